@@ -1,0 +1,403 @@
+"""Seeded synthetic populations of box-and-hinge robots.
+
+This module only *draws inputs*: morphologies, CPG parameters and initial
+states, as flat float32/int32 arrays in the variant-CSR layout that both the
+HIP library and the FP64 checker accept.  It contains none of the simulation
+arithmetic (no kinematics, dynamics, contact or integration); the one piece of
+geometry here is the lift of a dropped box so that it starts above the ground,
+which is part of drawing its initial state.
+
+The paper (Sec. 4, "Simulation Parameters"; Sec. 6) benchmarks populations of
+"variants" of MuJoCo scenes whose model files are not available.  The
+populations below stand in for them; every draw uses
+``numpy.random.default_rng([config, index])`` (PCG64 seeded through
+SeedSequence) in a fixed order so that variant ``i`` of a config is the same
+robot whatever the population size.
+
+Conventions of the model layout (shared by every consumer):
+
+* bodies of a variant are numbered in creation order, body 0 is the core
+  (root), ``parent[b] < b``;
+* each non-root body is joined to its parent by one hinge (DoF) located at
+  the centre of a face of the parent (``anchor_parent``, parent frame); the
+  child's rest orientation relative to the parent is ``rest_quat`` (w, x, y,
+  z) and the child's back-face centre ``anchor_child`` sits on the anchor;
+* the hinge axis ``axis`` is a unit vector in the child frame;
+* ``cpg[b] = (A, omega, phi)`` drives the hinge of body ``b``;
+* a FREE root has generalised position (p0, Q0, theta_1..theta_nh) and
+  velocity (omega_body, v_body, thetadot_1..thetadot_nh); a FIXED root
+  (used by unit tests only) has only the hinge coordinates and its pose is
+  given by ``root_pose`` = (p0, Q0).
+"""
+from __future__ import annotations
+
+from dataclasses import dataclass, field
+
+import numpy as np
+
+ROOT_FREE = 0
+ROOT_FIXED = 1
+
+CORE_HALF = 0.05          # 0.1 m cube
+CORE_MASS = 0.15
+BRICK_HALF = 0.03         # 0.06 m cube
+BRICK_MASS = 0.05
+CORE_Z0 = 0.05            # core bottom face resting on the plane
+
+# face name -> outward normal in the body frame
+FACES = {
+    "+x": (1.0, 0.0, 0.0), "-x": (-1.0, 0.0, 0.0),
+    "+y": (0.0, 1.0, 0.0), "-y": (0.0, -1.0, 0.0),
+    "+z": (0.0, 0.0, 1.0), "-z": (0.0, 0.0, -1.0),
+}
+CORE_SLOTS = ("+x", "-x", "+y", "-y")
+BRICK_SLOTS = ("+x", "+y", "-y")
+AXIS_Z = 0
+AXIS_Y = 1
+
+DEFAULT_PARAMS = dict(kp=5.0, kd=0.05, tau_max=0.9, k_contact=1.0e4,
+                      b_contact=100.0, dt=0.002, gravity=(0.0, 0.0, -9.81),
+                      pgs_iters=8)
+
+
+def _face_rest_quat(face: str) -> tuple:
+    """Rest rotation (w,x,y,z) taking the child's +x axis onto the face normal."""
+    h = np.sqrt(0.5)
+    return {
+        "+x": (1.0, 0.0, 0.0, 0.0),
+        "+y": (h, 0.0, 0.0, h),          # yaw +90 deg
+        "-x": (0.0, 0.0, 0.0, 1.0),      # yaw 180 deg
+        "-y": (h, 0.0, 0.0, -h),         # yaw -90 deg
+        "+z": (h, 0.0, -h, 0.0),         # pitch -90 deg about y: +x -> +z
+        "-z": (h, 0.0, h, 0.0),          # pitch +90 deg about y: +x -> -z
+    }[face]
+
+
+@dataclass
+class Population:
+    """A batch of variants in variant-CSR layout (host arrays)."""
+    body_offset: np.ndarray          # int32 [N+1]
+    parent: np.ndarray               # int32 [NB]  (variant-local, -1 for root)
+    half_ext: np.ndarray             # float32 [NB,3]
+    mass: np.ndarray                 # float32 [NB]
+    anchor_parent: np.ndarray        # float32 [NB,3]
+    anchor_child: np.ndarray         # float32 [NB,3]
+    rest_quat: np.ndarray            # float32 [NB,4]
+    axis: np.ndarray                 # float32 [NB,3]
+    cpg: np.ndarray                  # float32 [NB,3]  (A, omega, phi); zero for root
+    mu: np.ndarray                   # float32 [N]
+    q0: np.ndarray                   # float32 CSR, nq per variant
+    v0: np.ndarray                   # float32 CSR, nv per variant
+    root_pose: np.ndarray            # float32 [N,7] (FIXED roots; zeros otherwise)
+    root_type: int = ROOT_FREE
+    params: dict = field(default_factory=lambda: dict(DEFAULT_PARAMS))
+    name: str = ""
+    steps: int = 0                   # horizon T of the workload
+    lifted: int = 0                  # boxes lifted off the plane at creation
+
+    @property
+    def n_variants(self) -> int:
+        return int(self.body_offset.shape[0] - 1)
+
+    @property
+    def n_bodies(self) -> np.ndarray:
+        return np.diff(self.body_offset).astype(np.int64)
+
+    @property
+    def n_hinges(self) -> np.ndarray:
+        return self.n_bodies - 1
+
+    @property
+    def nq(self) -> np.ndarray:
+        return self.n_hinges + (7 if self.root_type == ROOT_FREE else 0)
+
+    @property
+    def nv(self) -> np.ndarray:
+        return self.n_hinges + (6 if self.root_type == ROOT_FREE else 0)
+
+    @property
+    def q_offset(self) -> np.ndarray:
+        return np.concatenate([[0], np.cumsum(self.nq)]).astype(np.int64)
+
+    @property
+    def v_offset(self) -> np.ndarray:
+        return np.concatenate([[0], np.cumsum(self.nv)]).astype(np.int64)
+
+    def subset(self, idx) -> "Population":
+        """Population made of the listed variants (in the given order)."""
+        idx = np.asarray(idx, dtype=np.int64)
+        bo, qo, vo = self.body_offset, self.q_offset, self.v_offset
+        bsel = np.concatenate([np.arange(bo[i], bo[i + 1]) for i in idx]) if len(idx) else np.zeros(0, np.int64)
+        qsel = np.concatenate([np.arange(qo[i], qo[i + 1]) for i in idx]) if len(idx) else np.zeros(0, np.int64)
+        vsel = np.concatenate([np.arange(vo[i], vo[i + 1]) for i in idx]) if len(idx) else np.zeros(0, np.int64)
+        nb = np.diff(bo)[idx]
+        return Population(
+            body_offset=np.concatenate([[0], np.cumsum(nb)]).astype(np.int32),
+            parent=self.parent[bsel].copy(), half_ext=self.half_ext[bsel].copy(),
+            mass=self.mass[bsel].copy(), anchor_parent=self.anchor_parent[bsel].copy(),
+            anchor_child=self.anchor_child[bsel].copy(), rest_quat=self.rest_quat[bsel].copy(),
+            axis=self.axis[bsel].copy(), cpg=self.cpg[bsel].copy(), mu=self.mu[idx].copy(),
+            q0=self.q0[qsel].copy(), v0=self.v0[vsel].copy(),
+            root_pose=self.root_pose[idx].copy(), root_type=self.root_type,
+            params=dict(self.params), name=self.name, steps=self.steps)
+
+
+class _Builder:
+    """Accumulates robots body by body, then emits a Population."""
+
+    def __init__(self, root_type=ROOT_FREE):
+        self.root_type = root_type
+        self.rows = dict(parent=[], half=[], mass=[], ap=[], ac=[], rq=[], axis=[], cpg=[])
+        self.offsets = [0]
+        self.mu, self.q0, self.v0, self.root_pose = [], [], [], []
+
+    def add_body(self, parent, half, mass, face=None, parent_half=None, axis_flag=AXIS_Z,
+                 cpg=(0.0, 0.0, 0.0)):
+        r = self.rows
+        r["parent"].append(parent)
+        r["half"].append(tuple(half))
+        r["mass"].append(mass)
+        if parent < 0:
+            r["ap"].append((0.0, 0.0, 0.0))
+            r["ac"].append((0.0, 0.0, 0.0))
+            r["rq"].append((1.0, 0.0, 0.0, 0.0))
+            r["axis"].append((0.0, 0.0, 1.0))
+        else:
+            n = np.array(FACES[face])
+            r["ap"].append(tuple(n * np.asarray(parent_half)))
+            r["ac"].append((-half[0], 0.0, 0.0))
+            r["rq"].append(_face_rest_quat(face))
+            r["axis"].append((0.0, 0.0, 1.0) if axis_flag == AXIS_Z else (0.0, 1.0, 0.0))
+        r["cpg"].append(tuple(cpg))
+
+    def end_variant(self, mu, q0, v0, root_pose=(0, 0, 0, 1, 0, 0, 0)):
+        self.offsets.append(len(self.rows["parent"]))
+        self.mu.append(mu)
+        self.q0.extend(q0)
+        self.v0.extend(v0)
+        self.root_pose.append(tuple(root_pose))
+
+    def build(self, name, steps, params=None, lifted=0) -> Population:
+        r = self.rows
+        f32 = lambda x, s: np.asarray(x, dtype=np.float32).reshape(s)
+        nbt = len(r["parent"])
+        return Population(
+            body_offset=np.asarray(self.offsets, dtype=np.int32),
+            parent=np.asarray(r["parent"], dtype=np.int32),
+            half_ext=f32(r["half"], (nbt, 3)), mass=f32(r["mass"], (nbt,)),
+            anchor_parent=f32(r["ap"], (nbt, 3)), anchor_child=f32(r["ac"], (nbt, 3)),
+            rest_quat=f32(r["rq"], (nbt, 4)), axis=f32(r["axis"], (nbt, 3)),
+            cpg=f32(r["cpg"], (nbt, 3)), mu=f32(self.mu, (-1,)),
+            q0=f32(self.q0, (-1,)), v0=f32(self.v0, (-1,)),
+            root_pose=f32(self.root_pose, (-1, 7)), root_type=self.root_type,
+            params=dict(DEFAULT_PARAMS if params is None else params),
+            name=name, steps=steps, lifted=lifted)
+
+
+def _robot_state(nh):
+    """Initial state of a legged robot: core on the plane, all hinges at 0, at rest."""
+    q0 = [0.0, 0.0, CORE_Z0, 1.0, 0.0, 0.0, 0.0] + [0.0] * nh
+    v0 = [0.0] * (6 + nh)
+    return q0, v0
+
+
+def _cpg_draw(rng, n):
+    A = rng.uniform(0.0, 1.0, n)
+    om = rng.uniform(1.0, 6.0, n)
+    ph = rng.uniform(0.0, 2.0 * np.pi, n)
+    return A, om, ph
+
+
+# ----------------------------------------------------------------------------
+# Config C0: plain method -- 3-hinge snake
+# ----------------------------------------------------------------------------
+def snake(n=16, first=0):
+    """16 snakes: core + 3 bricks chained on +x faces, axes z, y, z."""
+    b = _Builder()
+    axes = (AXIS_Z, AXIS_Y, AXIS_Z)
+    for i in range(first, first + n):
+        rng = np.random.default_rng([0, i])
+        A, om, ph = _cpg_draw(rng, 3)
+        b.add_body(-1, (CORE_HALF,) * 3, CORE_MASS)
+        for j in range(3):
+            ph_half = (CORE_HALF,) * 3 if j == 0 else (BRICK_HALF,) * 3
+            b.add_body(j, (BRICK_HALF,) * 3, BRICK_MASS, "+x", ph_half, axes[j],
+                       (A[j], om[j], ph[j]))
+        q0, v0 = _robot_state(3)
+        b.end_variant(1.0, q0, v0)
+    return b.build("snake3", 1000)
+
+
+# ----------------------------------------------------------------------------
+# Config C1: box environment -- free boxes dropped on a plane
+# ----------------------------------------------------------------------------
+def _quat_to_rot(q):
+    w, x, y, z = q
+    return np.array([
+        [1 - 2 * (y * y + z * z), 2 * (x * y - w * z), 2 * (x * z + w * y)],
+        [2 * (x * y + w * z), 1 - 2 * (x * x + z * z), 2 * (y * z - w * x)],
+        [2 * (x * z - w * y), 2 * (y * z + w * x), 1 - 2 * (x * x + y * y)]])
+
+
+def boxes(n=4096, first=0, clearance=0.005):
+    """Free boxes: sides U(0.05,0.3), density 1000, centre height U(0.2,1.0),
+    uniform random orientation, world velocities N(0, 0.5), mu U(0.3, 1.2).
+
+    A box whose lowest corner would start below ``clearance`` is raised so that
+    it starts there (the count is kept in ``Population.lifted``)."""
+    b = _Builder()
+    lifted = 0
+    for i in range(first, first + n):
+        rng = np.random.default_rng([1, i])
+        sides = rng.uniform(0.05, 0.3, 3)
+        H = rng.uniform(0.2, 1.0)
+        q = rng.normal(0.0, 1.0, 4)
+        q /= np.linalg.norm(q)
+        if q[0] < 0:
+            q = -q
+        vw = rng.normal(0.0, 0.5, 3)
+        ww = rng.normal(0.0, 0.5, 3)
+        mu = rng.uniform(0.3, 1.2)
+        half = sides / 2.0
+        R = _quat_to_rot(q)
+        lowest = H - np.abs(R[2]) @ half
+        if lowest < clearance:
+            H += clearance - lowest
+            lifted += 1
+        m = 1000.0 * sides.prod()
+        b.add_body(-1, tuple(half), m)
+        vb = R.T @ vw
+        wb = R.T @ ww
+        b.end_variant(mu, [0.0, 0.0, H, *q], [*wb, *vb])
+    return b.build("boxes", 2000, lifted=lifted)
+
+
+# ----------------------------------------------------------------------------
+# Config C2: uneven modular robots -- random trees of 4..20 hinges
+# ----------------------------------------------------------------------------
+MAX_DEPTH = 4
+
+
+def random_tree(i):
+    """Topology of variant i of the random-tree config: list of
+    (parent, face, axis_flag) per brick, plus CPG draws."""
+    rng = np.random.default_rng([2, i])
+    nh = int(rng.integers(4, 21))
+    depth = [0]
+    used = [set()]
+    bricks = []
+    for _ in range(nh):
+        free = []
+        for body in range(len(depth)):
+            if depth[body] >= MAX_DEPTH:
+                continue
+            for f in (CORE_SLOTS if body == 0 else BRICK_SLOTS):
+                if f not in used[body]:
+                    free.append((body, f))
+        body, f = free[int(rng.integers(len(free)))]
+        flag = int(rng.integers(2))
+        used[body].add(f)
+        used.append(set())
+        depth.append(depth[body] + 1)
+        bricks.append((body, f, flag))
+    A, om, ph = _cpg_draw(rng, nh)
+    return bricks, A, om, ph
+
+
+def random_trees(n=8192, first=0, indices=None):
+    b = _Builder()
+    idx = range(first, first + n) if indices is None else indices
+    for i in idx:
+        bricks, A, om, ph = random_tree(int(i))
+        b.add_body(-1, (CORE_HALF,) * 3, CORE_MASS)
+        for j, (par, f, flag) in enumerate(bricks):
+            ph_half = (CORE_HALF,) * 3 if par == 0 else (BRICK_HALF,) * 3
+            b.add_body(par, (BRICK_HALF,) * 3, BRICK_MASS, f, ph_half, flag, (A[j], om[j], ph[j]))
+        q0, v0 = _robot_state(len(bricks))
+        b.end_variant(1.0, q0, v0)
+    return b.build("trees", 5000)
+
+
+# ----------------------------------------------------------------------------
+# Config C3: long-horizon quadrupeds -- core + four 5-brick limbs
+# ----------------------------------------------------------------------------
+def quadrupeds(n=32768, first=0, steps=1000):
+    b = _Builder()
+    axes = (AXIS_Z, AXIS_Y, AXIS_Z, AXIS_Y, AXIS_Z)
+    for i in range(first, first + n):
+        rng = np.random.default_rng([3, i])
+        A, om, ph = _cpg_draw(rng, 20)
+        b.add_body(-1, (CORE_HALF,) * 3, CORE_MASS)
+        for limb, face in enumerate(CORE_SLOTS):
+            for j in range(5):
+                h = limb * 5 + j
+                if j == 0:
+                    b.add_body(0, (BRICK_HALF,) * 3, BRICK_MASS, face, (CORE_HALF,) * 3, axes[j],
+                               (A[h], om[h], ph[h]))
+                else:
+                    b.add_body(limb * 5 + j, (BRICK_HALF,) * 3, BRICK_MASS, "+x", (BRICK_HALF,) * 3,
+                               axes[j], (A[h], om[h], ph[h]))
+        q0, v0 = _robot_state(20)
+        b.end_variant(1.0, q0, v0)
+    return b.build("quadrupeds", steps)
+
+
+# ----------------------------------------------------------------------------
+# Small hand-built models used by unit tests
+# ----------------------------------------------------------------------------
+def chain(n_hinges, faces, axis_flags, root_type=ROOT_FIXED, root_pose=(0, 0, 1.0, 1, 0, 0, 0),
+          theta0=None, thetadot0=None, root_q=None, root_v=None, parents=None, cpg=None,
+          mu=1.0, params=None, name="chain"):
+    """One variant: core plus ``n_hinges`` bricks.  ``parents`` defaults to a
+    chain; ``faces`` and ``axis_flags`` give each brick's parent face and axis."""
+    b = _Builder(root_type)
+    parents = list(range(n_hinges)) if parents is None else list(parents)
+    b.add_body(-1, (CORE_HALF,) * 3, CORE_MASS)
+    for j in range(n_hinges):
+        par = parents[j]
+        ph_half = (CORE_HALF,) * 3 if par == 0 else (BRICK_HALF,) * 3
+        c = (0.0, 0.0, 0.0) if cpg is None else tuple(cpg[j])
+        b.add_body(par, (BRICK_HALF,) * 3, BRICK_MASS, faces[j], ph_half, axis_flags[j], c)
+    th = [0.0] * n_hinges if theta0 is None else list(theta0)
+    thd = [0.0] * n_hinges if thetadot0 is None else list(thetadot0)
+    if root_type == ROOT_FREE:
+        rq = [0.0, 0.0, 1.0, 1.0, 0.0, 0.0, 0.0] if root_q is None else list(root_q)
+        rv = [0.0] * 6 if root_v is None else list(root_v)
+        b.end_variant(mu, rq + th, rv + thd)
+    else:
+        b.end_variant(mu, th, thd, root_pose)
+    return b.build(name, 0, params=params)
+
+
+def single_box(half=(0.05, 0.05, 0.05), mass=None, pos=(0, 0, 1.0), quat=(1, 0, 0, 0),
+               omega_b=(0, 0, 0), v_b=(0, 0, 0), mu=1.0, params=None, name="box"):
+    b = _Builder()
+    m = 1000.0 * 8 * np.prod(half) if mass is None else mass
+    b.add_body(-1, tuple(half), m)
+    b.end_variant(mu, [*pos, *quat], [*omega_b, *v_b])
+    return b.build(name, 0, params=params)
+
+
+def concat(pops) -> Population:
+    """Concatenate populations that share root type and parameters."""
+    p0 = pops[0]
+    nb = np.concatenate([p.n_bodies for p in pops])
+    cat = lambda a: np.concatenate([getattr(p, a) for p in pops])
+    return Population(
+        body_offset=np.concatenate([[0], np.cumsum(nb)]).astype(np.int32),
+        parent=cat("parent"), half_ext=cat("half_ext"), mass=cat("mass"),
+        anchor_parent=cat("anchor_parent"), anchor_child=cat("anchor_child"),
+        rest_quat=cat("rest_quat"), axis=cat("axis"), cpg=cat("cpg"), mu=cat("mu"),
+        q0=cat("q0"), v0=cat("v0"), root_pose=cat("root_pose"), root_type=p0.root_type,
+        params=dict(p0.params), name="+".join(p.name for p in pops), steps=p0.steps)
+
+
+CONFIGS = {
+    "snake3": snake,
+    "boxes": boxes,
+    "trees": random_trees,
+    "quadrupeds": quadrupeds,
+}
+
+# Oracle spot-check subset of the random-tree population: indices 128*m.
+TREE_SPOTCHECK = tuple(128 * m for m in range(64))

@@ -1,0 +1,322 @@
+"""Pins of the FP64 oracle's kinematics and dynamics against quantities that
+do not come from the oracle's own formulas: brute-force finite differences of
+body point positions (kinetic energy -> mass matrix, Euler-Lagrange -> bias),
+textbook closed forms, LAPACK, and conservation laws under RK4."""
+import numpy as np
+import pytest
+
+from paper_2502_11129_amd import workloads as W
+
+G = 9.81
+
+
+# ---------------------------------------------------------------- test-side helpers
+def qrot(q):
+    w, x, y, z = q
+    return np.array([[1 - 2 * (y * y + z * z), 2 * (x * y - w * z), 2 * (x * z + w * y)],
+                     [2 * (x * y + w * z), 1 - 2 * (x * x + z * z), 2 * (y * z - w * x)],
+                     [2 * (x * z - w * y), 2 * (y * z + w * x), 1 - 2 * (x * x + y * y)]])
+
+
+def qmul(a, b):
+    w1, x1, y1, z1 = a
+    w2, x2, y2, z2 = b
+    return np.array([w1 * w2 - x1 * x2 - y1 * y2 - z1 * z2, w1 * x2 + x1 * w2 + y1 * z2 - z1 * y2,
+                     w1 * y2 - x1 * z2 + y1 * w2 + z1 * x2, w1 * z2 + x1 * y2 - y1 * x2 + z1 * w2])
+
+
+def qexp(phi):
+    a = np.linalg.norm(phi)
+    if a < 1e-15:
+        return np.array([1.0, *(phi / 2)])
+    return np.array([np.cos(a / 2), *(np.sin(a / 2) * phi / a)])
+
+
+def retract(q, v, eps, free):
+    """Position reached by moving along generalised velocity v for 'time' eps
+    (first order): root translates by eps*R0*v_b and turns by exp(eps*w_b)."""
+    q = np.array(q, dtype=np.float64)
+    if free:
+        R0 = qrot(q[3:7])
+        q[0:3] += eps * R0 @ v[3:6]
+        q[3:7] = qmul(q[3:7], qexp(eps * np.asarray(v[0:3])))
+        q[3:7] /= np.linalg.norm(q[3:7])
+        q[7:] += eps * np.asarray(v[6:])
+    else:
+        q += eps * np.asarray(v)
+    return q
+
+
+def gauss_points(half):
+    """2-point Gauss-Legendre nodes of a box (exact for quadratics), equal weights 1/8."""
+    s = np.asarray(half) / np.sqrt(3.0)
+    return np.array([[sx * s[0], sy * s[1], sz * s[2]] for sx in (-1, 1) for sy in (-1, 1) for sz in (-1, 1)])
+
+
+def point_cloud(o, vi, pop, q):
+    """World positions of every body's Gauss nodes and the body masses, from FK only."""
+    R, p, _, _ = o.fk(vi, q)
+    b0 = pop.body_offset[vi]
+    pts, ms = [], []
+    for b in range(R.shape[0]):
+        gp = gauss_points(pop.half_ext[b0 + b])
+        pts.append(p[b] + gp @ R[b].T)
+        ms.append(float(pop.mass[b0 + b]))
+    return pts, ms
+
+
+def kinetic_energy_fd(o, vi, pop, q, v, eps=1e-6):
+    free = pop.root_type == W.ROOT_FREE
+    qp, qm = retract(q, v, eps, free), retract(q, v, -eps, free)
+    Pp, ms = point_cloud(o, vi, pop, qp)
+    Pm, _ = point_cloud(o, vi, pop, qm)
+    T = 0.0
+    for a, b, m in zip(Pp, Pm, ms):
+        vel = (a - b) / (2 * eps)
+        T += 0.5 * m / 8.0 * np.sum(vel * vel)
+    return T
+
+
+def mass_matrix_fd(o, vi, pop, q):
+    nv = int(o.nv[vi])
+    E = np.eye(nv)
+    Td = [kinetic_energy_fd(o, vi, pop, q, E[j]) for j in range(nv)]
+    M = np.zeros((nv, nv))
+    for j in range(nv):
+        M[j, j] = 2 * Td[j]
+        for k in range(j + 1, nv):
+            M[j, k] = M[k, j] = kinetic_energy_fd(o, vi, pop, q, E[j] + E[k]) - Td[j] - Td[k]
+    return M
+
+
+def potential(o, vi, pop, q, g):
+    _, p, _, _ = o.fk(vi, q)
+    b0 = pop.body_offset[vi]
+    return -sum(float(pop.mass[b0 + b]) * p[b] @ g for b in range(p.shape[0]))
+
+
+def trees(root_type):
+    """1-, 2-, 3-joint chains plus a branched 3-joint tree with mixed faces/axes."""
+    rp = (0.1, -0.2, 1.0, *(qexp(np.array([0.3, -0.5, 0.2]))))
+    out = [
+        W.chain(1, ["+x"], [W.AXIS_Y], root_type=root_type, root_pose=rp),
+        W.chain(2, ["+x", "+y"], [W.AXIS_Z, W.AXIS_Y], root_type=root_type, root_pose=rp),
+        W.chain(3, ["+x", "+x", "-y"], [W.AXIS_Z, W.AXIS_Y, W.AXIS_Z], root_type=root_type, root_pose=rp),
+        W.chain(3, ["+x", "-y", "+z"], [W.AXIS_Y, W.AXIS_Z, W.AXIS_Y], parents=[0, 0, 1],
+                root_type=root_type, root_pose=rp),
+    ]
+    return out
+
+
+def random_state(pop, rng):
+    nh = int(pop.n_hinges[0])
+    th = rng.uniform(-1.5, 1.5, nh)
+    thd = rng.normal(0, 2.0, nh)
+    if pop.root_type == W.ROOT_FREE:
+        Q = rng.normal(size=4)
+        Q /= np.linalg.norm(Q)
+        q = np.concatenate([rng.normal(0, 0.3, 3) + [0, 0, 1], Q, th])
+        v = np.concatenate([rng.normal(0, 1.5, 3), rng.normal(0, 1.0, 3), thd])
+    else:
+        q, v = th, thd
+    return q, v
+
+
+# ---------------------------------------------------------------- kinematics
+def test_fk_special_poses(oracle_mod):
+    pop = W.chain(1, ["+x"], [W.AXIS_Z], root_type=W.ROOT_FIXED, root_pose=(0, 0, 1.0, 1, 0, 0, 0))
+    o = oracle_mod.Oracle(pop)
+    _, p, w, oo = o.fk(0, [0.0])
+    np.testing.assert_allclose(p[1], [0.05 + 0.03, 0, 1.0], atol=1e-15)     # rest pose
+    np.testing.assert_allclose(oo[1], [0.05, 0, 1.0], atol=1e-15)            # hinge at the face centre
+    np.testing.assert_allclose(w[1], [0, 0, 1], atol=1e-15)
+    _, p, _, _ = o.fk(0, [np.pi / 2])
+    np.testing.assert_allclose(p[1], [0.05, 0.03, 1.0], atol=1e-15)          # anchor + h * y_parent
+    # axis y, +90 deg: the brick hangs straight down
+    pop = W.chain(1, ["+x"], [W.AXIS_Y], root_type=W.ROOT_FIXED, root_pose=(0, 0, 1.0, 1, 0, 0, 0))
+    o = oracle_mod.Oracle(pop)
+    R, p, _, _ = o.fk(0, [np.pi / 2])
+    np.testing.assert_allclose(p[1], [0.05, 0, 1.0 - 0.03], atol=1e-15)
+    np.testing.assert_allclose(R[1] @ [1, 0, 0], [0, 0, -1], atol=1e-15)
+
+
+def test_fk_child_faces():
+    """Each face's rest rotation takes the child +x onto that face's outward normal."""
+    for face, n in W.FACES.items():
+        R = qrot(np.array(W._face_rest_quat(face)))
+        np.testing.assert_allclose(R @ [1, 0, 0], n, atol=1e-12)
+        np.testing.assert_allclose(R @ R.T, np.eye(3), atol=1e-12)
+
+
+def test_cholesky_matches_lapack(oracle_mod):
+    rng = np.random.default_rng(5)
+    for n in (1, 2, 6, 13, 26):
+        A = rng.normal(size=(n, n))
+        A = A @ A.T + n * np.eye(n)
+        np.testing.assert_allclose(oracle_mod.cholesky(A), np.linalg.cholesky(A), rtol=1e-12, atol=1e-12)
+    with pytest.raises(np.linalg.LinAlgError):
+        oracle_mod.cholesky(-np.eye(3))
+
+
+def test_contact_rows_are_corner_velocities(oracle_mod):
+    """J_p(x) v equals the finite-difference velocity of the active corner (FK only)."""
+    rng = np.random.default_rng(11)
+    pop = W.chain(3, ["+x", "+y", "+x"], [W.AXIS_Y, W.AXIS_Z, W.AXIS_Y], root_type=W.ROOT_FREE)
+    o = oracle_mod.Oracle(pop)
+    for trial in range(6):
+        q, v = random_state(pop, rng)
+        q[2] = 0.04                                   # push the robot into the ground
+        c = o.contacts(0, q)
+        assert len(c["body"]) > 0
+        eps = 1e-6
+        Rp, pp, _, _ = o.fk(0, retract(q, v, eps, True))
+        Rm, pm, _, _ = o.fk(0, retract(q, v, -eps, True))
+        for i, (b, k) in enumerate(zip(c["body"], c["corner"])):
+            h = pop.half_ext[b]
+            s = np.array([h[0] if k & 1 else -h[0], h[1] if k & 2 else -h[1], h[2] if k & 4 else -h[2]])
+            vel = ((pp[b] + Rp[b] @ s) - (pm[b] + Rm[b] @ s)) / (2 * eps)
+            got = c["J"][i] @ v                        # rows: normal (z), x, y
+            np.testing.assert_allclose(got, [vel[2], vel[0], vel[1]], rtol=1e-7, atol=1e-8)
+            assert c["x"][i][2] < 0 and np.isclose(c["depth"][i], -c["x"][i][2])
+
+
+def test_contact_enumeration_order(oracle_mod):
+    """Active corners come in (body, corner) order, corner bits = sign of (x, y, z)."""
+    pop = W.single_box(half=(0.1, 0.2, 0.3), pos=(0, 0, 0.29))
+    o = oracle_mod.Oracle(pop)
+    c = o.contacts(0, pop.q0.astype(np.float64))
+    assert list(c["corner"]) == [0, 1, 2, 3]          # the four bottom corners (z bit clear)
+    np.testing.assert_allclose(c["depth"], 0.01, atol=1e-7)   # model arrays are float32
+
+
+# ---------------------------------------------------------------- dynamics
+@pytest.mark.parametrize("root_type", [W.ROOT_FIXED, W.ROOT_FREE])
+def test_mass_matrix_equals_bruteforce_lagrangian(oracle_mod, root_type):
+    """M from the oracle == Hessian of the kinetic energy obtained by finite
+    differences of FK point positions (Gauss nodes, exact for boxes)."""
+    rng = np.random.default_rng(1 + root_type)
+    for pop in trees(root_type):
+        o = oracle_mod.Oracle(pop)
+        for _ in range(2):
+            q, v = random_state(pop, rng)
+            M, _ = o.dynamics(0, q, v)
+            Mb = mass_matrix_fd(o, 0, pop, q)
+            np.testing.assert_allclose(M, M.T, atol=1e-14)
+            assert np.linalg.eigvalsh(M).min() > 0
+            np.testing.assert_allclose(M, Mb, rtol=0, atol=1e-7 * np.abs(M).max())
+
+
+def test_single_free_box_mass_and_bias_closed_form(oracle_mod):
+    """Newton-Euler of one box in body coordinates: M = diag(I_b, m 1),
+    c = [w x I w ; m (w x v - R^T g)]."""
+    rng = np.random.default_rng(3)
+    half = np.array([0.07, 0.11, 0.05])
+    pop = W.single_box(half=tuple(half), mass=2.5)
+    o = oracle_mod.Oracle(pop)
+    m = 2.5
+    Ib = np.diag([m / 3 * (half[1] ** 2 + half[2] ** 2), m / 3 * (half[0] ** 2 + half[2] ** 2),
+                  m / 3 * (half[0] ** 2 + half[1] ** 2)])
+    g = np.array([0, 0, -G])
+    for _ in range(5):
+        Q = rng.normal(size=4); Q /= np.linalg.norm(Q)
+        q = np.concatenate([rng.normal(size=3), Q])
+        v = rng.normal(size=6)
+        M, c = o.dynamics(0, q, v)
+        Mx = np.zeros((6, 6)); Mx[:3, :3] = Ib; Mx[3:, 3:] = m * np.eye(3)
+        np.testing.assert_allclose(M, Mx, atol=1e-14)
+        w, vb = v[:3], v[3:]
+        cx = np.concatenate([np.cross(w, Ib @ w), m * (np.cross(w, vb) - qrot(Q).T @ g)])
+        np.testing.assert_allclose(c, cx, atol=1e-13)
+
+
+def test_bias_equals_euler_lagrange_fixed_base(oracle_mod):
+    """c_i = sum_jk (dM_ij/dq_k - 1/2 dM_jk/dq_i) v_j v_k + dV/dq_i, by finite
+    differences (M from the pinned mass matrix, V from FK positions)."""
+    rng = np.random.default_rng(7)
+    g = np.array([0, 0, -G])
+    for pop in trees(W.ROOT_FIXED):
+        o = oracle_mod.Oracle(pop)
+        nv = int(o.nv[0])
+        for _ in range(3):
+            q, v = random_state(pop, rng)
+            _, c = o.dynamics(0, q, v)
+            eps = 1e-6
+            dM = np.zeros((nv, nv, nv))      # dM[k] = dM/dq_k
+            dV = np.zeros(nv)
+            for k in range(nv):
+                e = np.zeros(nv); e[k] = eps
+                Mp, _ = o.dynamics(0, q + e, v)
+                Mm, _ = o.dynamics(0, q - e, v)
+                dM[k] = (Mp - Mm) / (2 * eps)
+                dV[k] = (potential(o, 0, pop, q + e, g) - potential(o, 0, pop, q - e, g)) / (2 * eps)
+            cel = np.einsum("kij,j,k->i", dM, v, v) - 0.5 * np.einsum("ijk,j,k->i", dM, v, v) + dV
+            np.testing.assert_allclose(c, cel, rtol=0, atol=1e-6 * max(1.0, np.abs(c).max()))
+
+
+def _floating_tree(vel_scale=1.0, g=(0, 0, -G), pd=False):
+    rng = np.random.default_rng(21)
+    params = dict(W.DEFAULT_PARAMS)
+    params["gravity"] = g
+    cpg = [(0.8, 3.0, 0.2), (0.5, 5.0, 1.0), (0.9, 2.0, 2.0)] if pd else None
+    Q = qexp(np.array([0.4, -0.2, 0.9]))
+    pop = W.chain(3, ["+x", "-y", "+x"], [W.AXIS_Y, W.AXIS_Z, W.AXIS_Y], parents=[0, 0, 2],
+                  root_type=W.ROOT_FREE, root_q=[0, 0, 5.0, *Q],
+                  root_v=list(vel_scale * rng.normal(0, 1, 6)), theta0=[0.3, -0.6, 1.0],
+                  thetadot0=list(vel_scale * rng.normal(0, 2, 3)), cpg=cpg, params=params)
+    return pop
+
+
+def test_rk4_conserves_energy(oracle_mod):
+    """Contact-free floating tree under gravity, no torque: E drift <= 1e-8 (RK4)."""
+    pop = _floating_tree()
+    o = oracle_mod.Oracle(pop)
+    E0 = o.invariants(0)[0]
+    o.rk4(250)
+    E1 = o.invariants(0)[0]
+    assert abs(E1 - E0) <= 1e-8 * max(1.0, abs(E0))
+
+
+def test_rk4_conserves_momentum_with_pd(oracle_mod):
+    """g = 0, PD torques on (internal forces): linear and angular momentum about
+    the origin stay constant (RK4, <= 1e-8)."""
+    pop = _floating_tree(g=(0, 0, 0), pd=True)
+    pop.params["dt"] = 1e-4          # the PD gains are stiff for explicit RK4 (w*dt = 0.5 at dt = 2 ms)
+    o = oracle_mod.Oracle(pop)
+    I0 = o.invariants(0)
+    o.rk4(2000, pd=True)
+    I1 = o.invariants(0)
+    assert abs(I1[0] - I0[0]) > 1e-5                  # the torques do work ...
+    np.testing.assert_allclose(I1[1:], I0[1:], atol=5e-8 * max(1.0, np.abs(I0[1:]).max()))  # ... but exert no net wrench
+
+
+def test_semi_implicit_energy_drift_is_first_order(oracle_mod):
+    """Contact-free, tau = 0 (kp = kd = 0), gravity on: the semi-implicit Euler
+    energy error over a fixed time shrinks ~linearly with dt."""
+    errs = []
+    for dt in (0.002, 0.001, 0.0005):
+        pop = _floating_tree(vel_scale=0.5)
+        pop.params.update(dict(kp=0.0, kd=0.0, dt=dt))
+        o = oracle_mod.Oracle(pop)
+        E0 = o.invariants(0)[0]
+        o.step(int(round(0.2 / dt)))
+        errs.append(abs(o.invariants(0)[0] - E0))
+    assert errs[0] > 0
+    r1, r2 = errs[0] / errs[1], errs[1] / errs[2]
+    assert 1.5 < r1 < 2.7 and 1.5 < r2 < 2.7, errs
+
+
+def test_semi_implicit_momentum_drift_is_first_order(oracle_mod):
+    """g = 0, PD on, no contact: the implicit-PD semi-implicit Euler step does
+    not conserve momentum exactly, but its drift over a fixed time is O(dt)."""
+    lin, ang = [], []
+    for dt in (0.002, 0.001, 0.0005):
+        pop = _floating_tree(g=(0, 0, 0), pd=True, vel_scale=0.5)
+        pop.params.update(dict(dt=dt))
+        o = oracle_mod.Oracle(pop)
+        I0 = o.invariants(0)
+        o.step(int(round(0.2 / dt)))
+        I1 = o.invariants(0)
+        lin.append(np.linalg.norm(I1[1:4] - I0[1:4]))
+        ang.append(np.linalg.norm(I1[4:] - I0[4:]))
+    for d in (lin, ang):
+        assert 1.6 < d[0] / d[1] < 2.4 and 1.6 < d[1] / d[2] < 2.4, d

@@ -1,0 +1,127 @@
+#!/usr/bin/env python3
+"""Benchmark: batched rollouts of the uneven-morphology population on one MI355X.
+
+One bench step = one sim_rollout of the whole population (every variant,
+T simulation steps: kinematics, dynamics, inverse, contacts, solver,
+integration, fitness) with the model already resident in HBM.
+Prints ONE JSON line (see the contract in the design doc).
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0
+FP32_VECTOR_PEAK_TFLOPS = 157.3      # published MI355X FP32 vector peak (packed issue)
+
+
+def parse():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=5)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--variants", type=int, default=8192)
+    ap.add_argument("--horizon", type=int, default=5000)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--cpu-sample-steps", type=int, default=1000)
+    return ap.parse_args()
+
+
+def cpu_baseline(pop_full, sample_steps):
+    """The FP64 oracle on the host cores over a bounded sample of the same
+    workload: the 64 spot-check variants (indices 128 m) for sample_steps steps."""
+    from oracle import oracle as O
+    from paper_2502_11129_amd import workloads as W
+    idx = [i for i in W.TREE_SPOTCHECK if i < pop_full.n_variants]
+    pop = W.random_trees(indices=idx)
+    cores = os.cpu_count() or 1
+    o = O.Oracle(pop)
+    t0 = time.perf_counter()
+    o.rollout(sample_steps, threads=cores)
+    dt = time.perf_counter() - t0
+    return {"value": pop.n_variants * sample_steps / dt, "unit": "variant-steps/s", "cores": cores,
+            "kind": "oracle", "sample": f"{pop.n_variants} spot-check variants x {sample_steps} steps, "
+                                        f"FP64, {cores} threads, {dt:.1f} s"}
+
+
+def main():
+    args = parse()
+    if args.gpus != 1:
+        print(f"bench.py: this build runs on one GPU only (asked for --gpus {args.gpus}); "
+              "variants are independent, so more GPUs would each take a contiguous DoF-balanced share.",
+              file=sys.stderr)
+        sys.exit(2)
+    import torch
+    from paper_2502_11129_amd import workloads as W
+    from paper_2502_11129_amd.flops import flops_per_variant, bytes_per_rollout
+    from paper_2502_11129_amd.sim import Simulator
+
+    pop = W.random_trees(args.variants)
+    T = args.horizon
+    sim = Simulator(pop)
+    stream = torch.cuda.current_stream()
+    for _ in range(args.warmup):
+        sim.rollout(T)
+    torch.cuda.synchronize()
+    ev0 = torch.cuda.Event(enable_timing=True)
+    ev1 = torch.cuda.Event(enable_timing=True)
+    t0 = time.perf_counter()
+    ev0.record(stream)
+    for _ in range(args.steps):
+        sim.rollout(T)
+    ev1.record(stream)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    gpu_ms = ev0.elapsed_time(ev1)
+    ms_per_step = gpu_ms / args.steps
+    vsteps = pop.n_variants * T
+    value = vsteps * args.steps / (gpu_ms / 1e3)
+
+    rows_contact, rows_clamp, status = sim.counters()
+    fl = flops_per_variant(pop, T, rows_contact, rows_clamp).sum()
+    bins = sim.bins()
+    launches = len(bins) * max(1, -(-T // 1000))
+    per_launch_s = (ms_per_step / 1e3) / launches
+    achieved = fl / launches / per_launch_s / 1e12
+    byt = bytes_per_rollout(pop)
+
+    out = {
+        "metric": "variant-steps/sec at 1 MI355X",
+        "value": value,
+        "unit": "variant-steps/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": ms_per_step,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": f"uneven-morphology random trees (4-20 hinges, depth<=4), "
+                               f"{pop.n_variants} variants x {T} steps, dt=0.002, K=8",
+                   "variants": pop.n_variants, "horizon": T, "bins": bins,
+                   "frozen_variants": int((status != 0).sum()),
+                   "mean_contacts_per_step": float(rows_contact.sum() / (pop.n_variants * T)),
+                   "wall_s": wall},
+        "roofline": {"bound": "alu", "achieved": achieved, "peak": FP32_VECTOR_PEAK_TFLOPS, "unit": "TFLOP/s",
+                     "frac": achieved / FP32_VECTOR_PEAK_TFLOPS, "traffic": None,
+                     "kernel": "rollout_kernel (all DoF bins)", "launches_per_step": launches,
+                     "flops_per_step": fl, "hbm_bytes_per_step": byt,
+                     "hbm_GBs": byt / (ms_per_step / 1e3) / 1e9},
+    }
+    if not args.no_cpu_baseline:
+        out["cpu_baseline"] = cpu_baseline(pop, args.cpu_sample_steps)
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

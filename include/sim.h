@@ -1,0 +1,166 @@
+/*
+ * sim.h -- C ABI of the MI355X batched robot-variant simulator.
+ *
+ * Problem statement (arXiv 2502.11129, Sec. 4 "Simulation Parameters" and
+ * Sec. 5): a population of N simulation "variants" is advanced for S steps;
+ * Sec. 6 splits such a population between CPU and GPU.  Here a variant is an
+ * articulated tree of boxes joined by hinges, driven by a sine-wave central
+ * pattern generator through a PD loop, on a ground plane with friction; its
+ * fitness is the horizontal displacement of its core box after the run.
+ *
+ * One call advances every variant of a handle on the GPU; all per-step work
+ * (kinematics, composite-rigid-body mass matrix, recursive Newton-Euler bias,
+ * box-plane contact detection, inversion of the implicit-PD mass matrix,
+ * fixed-iteration projected Gauss-Seidel over actuator-clamp and contact rows,
+ * semi-implicit Euler) runs inside one persistent HIP kernel per DoF bin.
+ *
+ * Conventions shared by every entry point
+ *  - Return value: SIM_OK (0) or a negative SIM_E_* code; sim_last_error()
+ *    returns a message for the last failing call on that handle.
+ *  - A per-variant numerical failure (non-finite state) is NOT an error: the
+ *    variant is frozen, a status bit is set and its fitness reads NaN.
+ *  - Ownership: sim_create deep-copies the descriptor; caller arrays may be
+ *    freed afterwards.  Device memory is owned by the caller: the library
+ *    uses only the workspace handed to sim_bind (query its size with
+ *    sim_workspace_bytes) plus a few events and streams of its own.
+ *  - Streams: every device call is ordered on the hipStream_t passed in
+ *    (void*; NULL = the null stream).  where=SIM_HOST transfers synchronise
+ *    that stream before returning.
+ *  - Variant order in and out is always the caller's order; packing by
+ *    degrees of freedom is internal.
+ *  - Handles are not thread-safe: use one handle per host thread.
+ */
+#ifndef SIM_H_
+#define SIM_H_
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define SIM_OK 0
+#define SIM_E_INVALID (-1) /* bad argument or model (nothing was changed)        */
+#define SIM_E_NOMEM (-2)   /* workspace smaller than sim_workspace_bytes()       */
+#define SIM_E_DEVICE (-3)  /* HIP runtime error (sticky for the handle)          */
+#define SIM_E_STATE (-4)   /* call out of order (e.g. step before sim_bind)      */
+
+#define SIM_ROOT_FREE 0  /* 6-DoF floating core                                 */
+#define SIM_ROOT_FIXED 1 /* core welded to root_pose (tests)                    */
+
+#define SIM_HOST 0
+#define SIM_DEVICE 1
+
+/* Status bits of a variant. */
+#define SIM_STATUS_NONFINITE 1u /* a non-finite value appeared; variant frozen  */
+
+/*
+ * Model descriptor.  All arrays are host memory in variant-CSR layout:
+ * body b of variant i is global body body_offset[i] + b; body 0 is the core.
+ *  parent[nb]           variant-local parent index, -1 for the core, parent < child
+ *  half_ext[nb*3]       box half extents (m), > 0
+ *  mass[nb]             kg, > 0
+ *  anchor_parent[nb*3]  hinge point in the parent frame (face centre)
+ *  anchor_child[nb*3]   the same point in the child frame
+ *  rest_quat[nb*4]      parent <- child rotation at theta = 0 (w,x,y,z), unit
+ *  axis[nb*3]           hinge axis in the child frame, unit
+ *  cpg[nb*3]            (A, omega, phi): target angle A sin(omega t + phi)
+ *  mu[n]                Coulomb friction coefficient of each variant, >= 0
+ *  q0, v0               initial state, CSR over variants:
+ *                       FREE : q = (p0[3], Q0[4] wxyz, theta[nh]), v = (w_body[3], v_body[3], thetadot[nh])
+ *                       FIXED: q = theta[nh], v = thetadot[nh]
+ *  root_pose[n*7]       FIXED roots only: (p0, Q0); may be NULL for FREE
+ * Per-model constants: PD gains kp, kd (actuator torque limit tau_max), soft
+ * contact stiffness and damping in acceleration units per contact row,
+ * time step dt, gravity vector, and the solver sweep count pgs_iters (part
+ * of the problem definition, never tuned).
+ */
+typedef struct {
+  int32_t n_variants;
+  int32_t root_type;
+  const int32_t* body_offset;
+  const int32_t* parent;
+  const float* half_ext;
+  const float* mass;
+  const float* anchor_parent;
+  const float* anchor_child;
+  const float* rest_quat;
+  const float* axis;
+  const float* cpg;
+  const float* mu;
+  const float* q0;
+  const float* v0;
+  const float* root_pose;
+  float kp, kd, tau_max, k_contact, b_contact, dt;
+  float gravity[3];
+  int32_t pgs_iters;
+} sim_model_desc;
+
+/*
+ * Options (may be NULL = defaults).  contacts_in_registers selects how many
+ * contacts per variant keep their solver rows in registers (0 = the tuned
+ * default); contacts beyond it spill to the workspace.  Results do not depend
+ * on it (same arithmetic, different storage).  use_graph != 0 replays
+ * sim_rollout through a captured hipGraph.
+ */
+typedef struct {
+  int32_t contacts_in_registers;
+  int32_t use_graph;
+  int32_t reserved[6];
+} sim_options;
+
+typedef struct sim_handle sim_handle;
+
+/* Validate the descriptor and pack it by DoF bins (host only, no device work).
+ * Errors: SIM_E_INVALID with a message in sim_last_error(*out) when *out is
+ * non-NULL, else in sim_last_error(NULL).  Limits: 1..21 bodies per variant,
+ * nv <= 28 degrees of freedom, pgs_iters >= 1, dt > 0. */
+int sim_create(const sim_model_desc* desc, const sim_options* opts, sim_handle** out);
+
+/* Bytes of device workspace the handle needs (256-byte aligned base). */
+int sim_workspace_bytes(const sim_handle* h, size_t* bytes);
+
+/* Attach a caller-owned device workspace of at least sim_workspace_bytes()
+ * and upload the packed model and the initial state on `stream`. */
+int sim_bind(sim_handle* h, void* dev_workspace, size_t bytes, void* stream);
+
+/* Advance every (non-frozen) variant by n_steps >= 0 steps. */
+int sim_step_batch(sim_handle* h, int32_t n_steps, void* stream);
+
+/* Reset every variant to (q0, v0, k = 0), run T >= 0 steps and compute the
+ * fitness (core xy displacement at T relative to k = 0). */
+int sim_rollout(sim_handle* h, int32_t T, void* stream);
+
+/* Fitness of every variant, user order: ||xy_core(k) - xy_core(0)||, NaN for
+ * frozen variants.  out: [n_variants] floats in host (where=SIM_HOST) or
+ * device (SIM_DEVICE) memory. */
+int sim_fitness(const sim_handle* h, float* out, int where, void* stream);
+
+/* Current state in the q0/v0 CSR layout and step counters [n_variants].
+ * Host memory only (where must be SIM_HOST).  Any of q, v, k may be NULL. */
+int sim_get_state(const sim_handle* h, float* q, float* v, int64_t* k, int where, void* stream);
+/* Overwrite the state (and, if k != NULL, the step counters); clears status. */
+int sim_set_state(sim_handle* h, const float* q, const float* v, const int64_t* k, int where, void* stream);
+
+/* Per-variant counters since the last reset: active contact rows (sum over
+ * steps of the number of active corners), actuator-clamp rows that ended a
+ * step engaged, and status bits.  Host memory; any pointer may be NULL. */
+int sim_counters(const sim_handle* h, uint64_t* rows_contact, uint64_t* rows_clamp, uint32_t* status,
+                 int where, void* stream);
+
+/* Description of the packing: number of bins and, per bin, (nv capacity,
+ * body capacity, contacts in registers, variants).  info has 4*max_bins ints. */
+int sim_bins(const sim_handle* h, int32_t* n_bins, int32_t* info, int32_t max_bins);
+
+void sim_destroy(sim_handle* h);
+
+/* Message of the last failing call on h (or of the last failed sim_create
+ * when h is NULL).  Valid until the next call on that handle. */
+const char* sim_last_error(const sim_handle* h);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* SIM_H_ */

@@ -1,0 +1,67 @@
+"""Build libsim.so (HIP kernels for gfx950 + the C-ABI host library) in-tree.
+
+Usage: python -m paper_2502_11129_amd.build  (or build() from Python).
+The kernel translation units compile in parallel; objects go to _build/.
+"""
+from __future__ import annotations
+
+import concurrent.futures as cf
+import glob
+import os
+import shutil
+import subprocess
+import sys
+
+PKG = os.path.dirname(os.path.abspath(__file__))
+CSRC = os.path.join(PKG, "csrc")
+BUILD = os.path.join(os.path.dirname(PKG), "_build")
+LIB = os.path.join(PKG, "libsim.so")
+ARCH = os.environ.get("SIM_OFFLOAD_ARCH", "gfx950")
+
+HIPCC = shutil.which("hipcc") or "/opt/rocm/bin/hipcc"
+ROCM_INC = os.path.join(os.environ.get("ROCM_PATH", "/opt/rocm"), "include")
+API_INC = os.path.join(os.path.dirname(PKG), "include")
+COMMON = ["-O3", "-std=c++17", "-fPIC", "-Wno-unused-result"]
+# Packed FP32 instructions stay disabled in every HIP translation unit.
+DEVICE = [f"--offload-arch={ARCH}", "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops"]
+
+
+def _sources():
+    kern = sorted(glob.glob(os.path.join(CSRC, "kernels", "*.hip")))
+    host = [os.path.join(CSRC, "kernel_registry.cpp"), os.path.join(CSRC, "sim_host.cpp")]
+    return kern, host
+
+
+def _compile(src: str, device: bool) -> str:
+    obj = os.path.join(BUILD, os.path.basename(src) + ".o")
+    cmd = [HIPCC, *COMMON, *(DEVICE if device else []), "-I", CSRC, "-c", src, "-o", obj]
+    if not device:
+        cmd = [HIPCC, *COMMON, "-I", CSRC, "-I", API_INC, "-I", ROCM_INC, "-x", "c++", "-D__HIP_PLATFORM_AMD__", "-c", src, "-o", obj]
+    r = subprocess.run(cmd, capture_output=True, text=True)
+    if r.returncode != 0:
+        raise RuntimeError(f"compile failed: {' '.join(cmd)}\n{r.stdout}\n{r.stderr}")
+    return obj
+
+
+def build(jobs: int | None = None, verbose: bool = False) -> str:
+    """Compile every HIP source for gfx950 and link libsim.so (always rebuilds)."""
+    os.makedirs(BUILD, exist_ok=True)
+    kern, host = _sources()
+    jobs = jobs or min(8, os.cpu_count() or 4)
+    with cf.ThreadPoolExecutor(jobs) as ex:
+        futs = [ex.submit(_compile, s, True) for s in kern] + [ex.submit(_compile, s, False) for s in host]
+        objs = [f.result() for f in futs]
+    tmp = LIB + ".tmp"
+    cmd = [HIPCC, f"--offload-arch={ARCH}", "-shared", "-fPIC", *objs, "-o", tmp]
+    r = subprocess.run(cmd, capture_output=True, text=True)
+    if r.returncode != 0:
+        raise RuntimeError(f"link failed: {' '.join(cmd)}\n{r.stdout}\n{r.stderr}")
+    os.replace(tmp, LIB)
+    if verbose:
+        print("built", LIB)
+    return LIB
+
+
+if __name__ == "__main__":
+    build(verbose=True)
+    sys.exit(0)

@@ -1,0 +1,3 @@
+// Rollout kernel instantiations: (nv capacity, body slots, contacts in registers).
+#define SIMK_FAMILY(X) X(28, 2, 8) X(28, 2, 2)
+#include "../rollout_inst.inc"

@@ -1,0 +1,947 @@
+// Persistent per-variant rollout kernel for gfx950 (CDNA4, wave64).
+//
+// Mapping: one variant per 16-lane DPP row, four variants per wave, one wave
+// per workgroup.  Degree of freedom d lives in lane d % 16, slot d / 16;
+// body b lives in lane b % 16, slot b / 16.  All cross-lane traffic of a
+// variant stays inside its row: reductions and broadcasts use DPP
+// (quad_perm, row_half_mirror, row_mirror, row_newbcast), bulk exchanges go
+// through a per-variant LDS area fenced at wavefront scope (no s_barrier).
+//
+// One step (t_k = k dt), for every variant in parallel:
+//   1. CPG targets; forward kinematics level by level down the tree, together
+//      with body spatial velocities and bias accelerations (frame: world axes
+//      at the current core origin);
+//   2. recursive Newton-Euler bias force and composite-rigid-body inertias
+//      (one backward sweep up the tree); mass matrix by CRBA; the
+//      linearly-implicit PD term dt (kd + dt kp) on the hinge diagonal;
+//   3. explicit inverse of that matrix by a symmetric Gauss-Jordan sweep with
+//      rotating columns (rows in registers, pivot column broadcast via LDS);
+//   4. free velocity v + dt Mt^-1 (a - b_a v - c);
+//   5. box-plane contact detection (8 corners per box, active iff z < 0) and
+//      per-contact rows J (normal z, tangents x, y), W = Mt^-1 J^T, D = J W;
+//   6. K sweeps of projected Gauss-Seidel: actuator-clamp rows then contact
+//      rows (soft normal in acceleration units, Coulomb disk friction);
+//   7. semi-implicit Euler; non-finite check freezes the variant.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "sim_layout.h"
+
+namespace simk {
+
+// ----------------------------------------------------------------------------
+// Row-local (16-lane) primitives.
+// ----------------------------------------------------------------------------
+__device__ __forceinline__ void wave_sync() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+template <int CTRL>
+__device__ __forceinline__ float dpp(float x) {
+  return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(x), CTRL, 0xF, 0xF, false));
+}
+
+// Sum over the 16 lanes of a row; every lane gets the bitwise-same value.
+__device__ __forceinline__ float row_sum(float x) {
+  x += dpp<0xB1>(x);   // quad_perm [1,0,3,2]
+  x += dpp<0x4E>(x);   // quad_perm [2,3,0,1]
+  x += dpp<0x141>(x);  // row_half_mirror
+  x += dpp<0x140>(x);  // row_mirror
+  return x;
+}
+
+// Value of lane L of the row, broadcast to the row (row_newbcast:L).
+template <int L>
+__device__ __forceinline__ float row_bcast(float x) {
+  return dpp<0x150 + L>(x);
+}
+
+// ----------------------------------------------------------------------------
+// Small 3D helpers.
+// ----------------------------------------------------------------------------
+struct f3 { float x, y, z; };
+__device__ __forceinline__ f3 mk(float a, float b, float c) { return {a, b, c}; }
+__device__ __forceinline__ f3 operator+(f3 a, f3 b) { return {a.x + b.x, a.y + b.y, a.z + b.z}; }
+__device__ __forceinline__ f3 operator-(f3 a, f3 b) { return {a.x - b.x, a.y - b.y, a.z - b.z}; }
+__device__ __forceinline__ f3 operator*(f3 a, float s) { return {a.x * s, a.y * s, a.z * s}; }
+__device__ __forceinline__ float dot3(f3 a, f3 b) { return a.x * b.x + a.y * b.y + a.z * b.z; }
+__device__ __forceinline__ f3 cross3(f3 a, f3 b) {
+  return {a.y * b.z - a.z * b.y, a.z * b.x - a.x * b.z, a.x * b.y - a.y * b.x};
+}
+struct m33 { float m[9]; };
+__device__ __forceinline__ f3 mul(const m33& R, f3 v) {
+  return {R.m[0] * v.x + R.m[1] * v.y + R.m[2] * v.z, R.m[3] * v.x + R.m[4] * v.y + R.m[5] * v.z,
+          R.m[6] * v.x + R.m[7] * v.y + R.m[8] * v.z};
+}
+__device__ __forceinline__ f3 mulT(const m33& R, f3 v) {
+  return {R.m[0] * v.x + R.m[3] * v.y + R.m[6] * v.z, R.m[1] * v.x + R.m[4] * v.y + R.m[7] * v.z,
+          R.m[2] * v.x + R.m[5] * v.y + R.m[8] * v.z};
+}
+__device__ __forceinline__ m33 matmul(const m33& A, const m33& B) {
+  m33 C;
+#pragma unroll
+  for (int i = 0; i < 3; ++i)
+#pragma unroll
+    for (int j = 0; j < 3; ++j)
+      C.m[3 * i + j] = A.m[3 * i] * B.m[j] + A.m[3 * i + 1] * B.m[3 + j] + A.m[3 * i + 2] * B.m[6 + j];
+  return C;
+}
+__device__ __forceinline__ m33 quat_rot(float w, float x, float y, float z) {
+  m33 R;
+  R.m[0] = 1.f - 2.f * (y * y + z * z); R.m[1] = 2.f * (x * y - w * z); R.m[2] = 2.f * (x * z + w * y);
+  R.m[3] = 2.f * (x * y + w * z); R.m[4] = 1.f - 2.f * (x * x + z * z); R.m[5] = 2.f * (y * z - w * x);
+  R.m[6] = 2.f * (x * z - w * y); R.m[7] = 2.f * (y * z + w * x); R.m[8] = 1.f - 2.f * (x * x + y * y);
+  return R;
+}
+// Rotation about unit axis u by the angle whose sine / cosine are s, c (Rodrigues).
+__device__ __forceinline__ m33 axis_rot_acc(f3 u, float s, float c) {
+  float C = 1.f - c;
+  m33 R;
+  R.m[0] = c + u.x * u.x * C; R.m[1] = u.x * u.y * C - u.z * s; R.m[2] = u.x * u.z * C + u.y * s;
+  R.m[3] = u.y * u.x * C + u.z * s; R.m[4] = c + u.y * u.y * C; R.m[5] = u.y * u.z * C - u.x * s;
+  R.m[6] = u.z * u.x * C - u.y * s; R.m[7] = u.z * u.y * C + u.x * s; R.m[8] = c + u.z * u.z * C;
+  return R;
+}
+
+// Spatial vectors (angular; linear at the frame origin), world axes at p0.
+struct sv { f3 a, l; };
+// motion cross product  V x_m U
+__device__ __forceinline__ sv crm(const sv& V, const sv& U) {
+  return {cross3(V.a, U.a), cross3(V.a, U.l) + cross3(V.l, U.a)};
+}
+// force cross product  V x_f F
+__device__ __forceinline__ sv crf(const sv& V, const sv& F) {
+  return {cross3(V.a, F.a) + cross3(V.l, F.l), cross3(V.a, F.l)};
+}
+// Rigid-body inertia about the frame origin: mass, first moment h = m c,
+// rotational inertia Io (symmetric: xx, yy, zz, xy, xz, yz).
+struct sinertia { float m; f3 h; float I[6]; };
+__device__ __forceinline__ f3 symmul(const float* I, f3 w) {
+  return {I[0] * w.x + I[3] * w.y + I[4] * w.z, I[3] * w.x + I[1] * w.y + I[5] * w.z,
+          I[4] * w.x + I[5] * w.y + I[2] * w.z};
+}
+__device__ __forceinline__ sv imul(const sinertia& J, const sv& V) {
+  return {symmul(J.I, V.a) + cross3(J.h, V.l), V.l * J.m - cross3(J.h, V.a)};
+}
+
+// ----------------------------------------------------------------------------
+// Per-variant LDS area.
+// ----------------------------------------------------------------------------
+template <int NVC, int SB, int NCR>
+struct GroupLds {
+  static constexpr int NBC = 16 * SB;
+  static constexpr int MST = NVC + 1;                 // padded row stride of the assembled matrix
+  static constexpr int A_BODY = NBC * 24;             // forward pass: R9 p3 V6 A6; backward: C10 F6
+  static constexpr int A_MAT = NVC * MST;
+  static constexpr int A_WORDS = A_BODY > A_MAT ? A_BODY : A_MAT;
+  float A[A_WORDS];
+  float WO[NBC][12];        // hinge axis w, anchor o (world), composite force C S of the hinge
+  int par[NBC];
+  int ccount[NBC];          // active corners per body
+  float cl[NCR][4];         // contact list: x, y, z, ancestor mask of the body
+  float cs[NCR][12];        // per-contact solver scalars
+  float th[32], thd[32];    // theta / thetadot by DoF
+  float cb[2][32];          // pivot-column broadcast (double buffered); also c and rhs
+  float jb[NVC][4];         // contact row broadcast (J_n, J_x, J_y)
+};
+
+// ----------------------------------------------------------------------------
+// Contact rows.  Builds J (normal z, tangents x, y) of the point x for the
+// lane's DoF slots, W = Mt^-1 J^T (J broadcast through LDS), the row
+// denominators and cross terms, and the per-contact solver scalars.
+// ----------------------------------------------------------------------------
+template <int S, int NVC>
+__device__ __forceinline__ void build_rows(const float (&Mi)[S][NVC], const f3 (&ang)[S], const f3 (&cst)[S],
+                                           const int (&bodyOfDof)[S], int lane, float (*jb)[4], f3 x,
+                                           unsigned anc, float kc, float kb, float dt, float (&Jn)[S],
+                                           float (&Jx)[S], float (&Jy)[S], float (&Wn)[S], float (&Wx)[S],
+                                           float (&Wy)[S], float (&scal)[10]) {
+#pragma unroll
+  for (int s = 0; s < S; ++s) {
+    const int d = lane + 16 * s;
+    const bool on = (bodyOfDof[s] < 0) || ((anc >> bodyOfDof[s]) & 1u);
+    const f3 J = cross3(ang[s], x) + cst[s];
+    Jn[s] = on ? J.z : 0.f;
+    Jx[s] = on ? J.x : 0.f;
+    Jy[s] = on ? J.y : 0.f;
+    if (d < NVC) { jb[d][0] = Jn[s]; jb[d][1] = Jx[s]; jb[d][2] = Jy[s]; }
+  }
+  wave_sync();
+#pragma unroll
+  for (int s = 0; s < S; ++s) { Wn[s] = 0.f; Wx[s] = 0.f; Wy[s] = 0.f; }
+#pragma unroll
+  for (int j = 0; j < NVC; ++j) {
+    const float4 jj = *reinterpret_cast<const float4*>(&jb[j][0]);
+#pragma unroll
+    for (int s = 0; s < S; ++s) {
+      Wn[s] = fmaf(Mi[s][j], jj.x, Wn[s]);
+      Wx[s] = fmaf(Mi[s][j], jj.y, Wx[s]);
+      Wy[s] = fmaf(Mi[s][j], jj.z, Wy[s]);
+    }
+  }
+  wave_sync();  // jb is free for the next contact
+  float pn = 0.f, px = 0.f, py = 0.f, pxn = 0.f, pyn = 0.f;
+#pragma unroll
+  for (int s = 0; s < S; ++s) {
+    pn = fmaf(Jn[s], Wn[s], pn);
+    px = fmaf(Jx[s], Wx[s], px);
+    py = fmaf(Jy[s], Wy[s], py);
+    pxn = fmaf(Jx[s], Wn[s], pxn);
+    pyn = fmaf(Jy[s], Wn[s], pyn);
+  }
+  const float Dn = row_sum(pn), Dx = row_sum(px), Dy = row_sum(py);
+  const float Dxn = row_sum(pxn), Dyn = row_sum(pyn);
+  scal[0] = kc * (-x.z);                    // k * depth
+  scal[1] = 1.f / (Dn * (1.f + kb * dt));   // normal row: 1 / (D_n (1 + (b + k dt) dt))
+  scal[2] = dt * Dn;
+  scal[3] = dt * Dxn;                       // tangential velocity change per unit normal force
+  scal[4] = dt * Dyn;
+  scal[5] = 1.f / (dt * Dx);
+  scal[6] = 1.f / (dt * Dy);
+  scal[7] = 0.f;                            // lambda_n, lambda_x, lambda_y (cold start)
+  scal[8] = 0.f;
+  scal[9] = 0.f;
+}
+
+// One contact of one Gauss-Seidel sweep: soft normal row, then the two
+// friction rows together (Jacobi within the pair), projected on the disk
+// |lambda_t| <= mu lambda_n.  lam[0..2] are read and updated.
+template <int S>
+__device__ __forceinline__ void contact_row(float (&vp)[S], const float (&Jn)[S], const float (&Jx)[S],
+                                            const float (&Jy)[S], const float (&Wn)[S], const float (&Wx)[S],
+                                            const float (&Wy)[S], const float (&sc)[10], float (&lam)[3],
+                                            float mu, float kb, float dt) {
+  float pn = 0.f, px = 0.f, py = 0.f;
+#pragma unroll
+  for (int s = 0; s < S; ++s) {
+    pn = fmaf(Jn[s], vp[s], pn);
+    px = fmaf(Jx[s], vp[s], px);
+    py = fmaf(Jy[s], vp[s], py);
+  }
+  const float un = row_sum(pn), ux = row_sum(px), uy = row_sum(py);
+  const float ln0 = lam[0], lx0 = lam[1], ly0 = lam[2];
+  const float u0 = un - sc[2] * ln0;
+  const float ln = fmaxf(0.f, (sc[0] - kb * u0) * sc[1]);
+  const float dn = ln - ln0;
+  const float ux2 = fmaf(sc[3], dn, ux), uy2 = fmaf(sc[4], dn, uy);
+  float gx = lx0 - ux2 * sc[5], gy = ly0 - uy2 * sc[6];
+  const float gn2 = gx * gx + gy * gy, lim = mu * ln;
+  if (gn2 > lim * lim) {
+    const float scale = lim / sqrtf(gn2);
+    gx *= scale;
+    gy *= scale;
+  }
+  const float edn = dt * dn, edx = dt * (gx - lx0), edy = dt * (gy - ly0);
+  lam[0] = ln; lam[1] = gx; lam[2] = gy;
+#pragma unroll
+  for (int s = 0; s < S; ++s) vp[s] = fmaf(Wn[s], edn, fmaf(Wx[s], edx, fmaf(Wy[s], edy, vp[s])));
+}
+
+// ----------------------------------------------------------------------------
+// The kernel.
+// ----------------------------------------------------------------------------
+template <int NVC, int SB, int NCR>
+__global__ __launch_bounds__(64) void rollout_kernel(BinArgs a, ModelParams P) {
+  constexpr int S = (NVC + 15) / 16;
+  constexpr int NBC = 16 * SB;
+  constexpr int MAXC = 8 * NBC;
+  using L = GroupLds<NVC, SB, NCR>;
+  __shared__ L lds_all[kVarPerWave];
+
+  const int lane = threadIdx.x & 15;
+  const int grp = threadIdx.x >> 4;
+  const int vid = blockIdx.x * kVarPerWave + grp;
+  if (vid >= a.n) return;  // whole rows leave together
+  L& sh = lds_all[grp];
+
+  // ---- per-variant header (uniform within the row) ----
+  const int* hdr = a.hdr + (size_t)vid * HW_WORDS;
+  const int nb = hdr[HW_NB], nv = hdr[HW_NV], r0 = hdr[HW_R0], maxdepth = hdr[HW_MAXDEPTH];
+  const float* hf = a.hdrf + (size_t)vid * HF_WORDS;
+  const float mu = hf[HF_MU];
+  const float* bodyv = a.body + (size_t)vid * NBC * BW_WORDS;
+  float* ovf = a.ovf + (size_t)vid * a.ovf_stride;
+  float* ovf_list = ovf;
+  float* ovf_scal = ovf + MAXC * 4;
+  float* ovf_rows = ovf_scal + MAXC * kOvfScal;
+
+  const float dt = P.dt, kp = P.kp, kd = P.kd, tmax = P.tau_max, kc = P.k_contact, bc = P.b_contact;
+  const float ba = kd + dt * kp;
+  const float kb = bc + kc * dt;
+  const double dtd = (double)dt;
+
+  // ---- state ----
+  float vS[S], thS[S];
+  float p0[3], Q0[4];
+  long long kstep;
+  unsigned status;
+  unsigned long long cnt_contact, cnt_clamp;
+  {
+    const float* qsrc = (a.reset ? a.q0 : a.q) + (size_t)vid * kQStride;
+    const float* vsrc = (a.reset ? a.v0 : a.v) + (size_t)vid * kVStride;
+    const int qh = (r0 == 6) ? 7 : 0;  // offset of theta in q
+#pragma unroll
+    for (int s = 0; s < S; ++s) {
+      const int d = lane + 16 * s;
+      vS[s] = (d < nv) ? vsrc[d] : 0.f;
+      thS[s] = (d >= r0 && d < nv) ? qsrc[qh + d - r0] : 0.f;
+    }
+    if (r0 == 6) {
+      p0[0] = qsrc[0]; p0[1] = qsrc[1]; p0[2] = qsrc[2];
+      Q0[0] = qsrc[3]; Q0[1] = qsrc[4]; Q0[2] = qsrc[5]; Q0[3] = qsrc[6];
+    } else {
+      p0[0] = hf[HF_ROOTP]; p0[1] = hf[HF_ROOTP + 1]; p0[2] = hf[HF_ROOTP + 2];
+      Q0[0] = hf[HF_ROOTQ]; Q0[1] = hf[HF_ROOTQ + 1]; Q0[2] = hf[HF_ROOTQ + 2]; Q0[3] = hf[HF_ROOTQ + 3];
+    }
+    if (a.reset) {
+      kstep = 0; status = 0; cnt_contact = 0; cnt_clamp = 0;
+    } else {
+      kstep = a.k[vid]; status = a.status[vid];
+      cnt_contact = a.cnt[2 * vid]; cnt_clamp = a.cnt[2 * vid + 1];
+    }
+  }
+  if (a.reset && lane == 0) {
+    a.xy0[2 * vid] = (r0 == 6) ? p0[0] : 0.f;
+    a.xy0[2 * vid + 1] = (r0 == 6) ? p0[1] : 0.f;
+  }
+  if (lane < nb) sh.par[lane] = __float_as_int(bodyv[lane * BW_WORDS + BW_PARENT]);
+  if (SB > 1 && lane + 16 < nb) sh.par[lane + 16] = __float_as_int(bodyv[(lane + 16) * BW_WORDS + BW_PARENT]);
+
+  // DoF-slot constants: hinge CPG, and for hinge DoFs the body index.
+  float cpgA[S], cpgW[S], cpgP[S];
+#pragma unroll
+  for (int s = 0; s < S; ++s) {
+    const int d = lane + 16 * s;
+    const bool hinge = d >= r0 && d < nv;
+    const int b = d - r0 + 1;
+    cpgA[s] = hinge ? bodyv[b * BW_WORDS + BW_CPG] : 0.f;
+    cpgW[s] = hinge ? bodyv[b * BW_WORDS + BW_CPG + 1] : 0.f;
+    cpgP[s] = hinge ? bodyv[b * BW_WORDS + BW_CPG + 2] : 0.f;
+  }
+
+  for (int it = 0; it < a.n_steps; ++it) {
+    if (status) break;  // frozen variants stop (row-uniform)
+
+    // =====================================================================
+    // 1. forward kinematics, spatial velocities and bias accelerations; the
+    //    body's inertia about p0 and its Newton-Euler force are formed at once
+    // =====================================================================
+#pragma unroll
+    for (int s = 0; s < S; ++s) {
+      const int d = lane + 16 * s;
+      if (d < 32) { sh.th[d] = thS[s]; sh.thd[d] = vS[s]; }
+    }
+    // root velocity (body frame), broadcast from DoF lanes 0..5
+    f3 wb = mk(row_bcast<0>(vS[0]), row_bcast<1>(vS[0]), row_bcast<2>(vS[0]));
+    f3 vb = mk(row_bcast<3>(vS[0]), row_bcast<4>(vS[0]), row_bcast<5>(vS[0]));
+    if (r0 != 6) { wb = mk(0.f, 0.f, 0.f); vb = wb; }
+    const m33 R0 = quat_rot(Q0[0], Q0[1], Q0[2], Q0[3]);
+    const f3 P0 = mk(p0[0], p0[1], p0[2]);
+    wave_sync();
+
+    int depthb[SB];
+#pragma unroll
+    for (int t = 0; t < SB; ++t) {
+      const int b = lane + 16 * t;
+      depthb[t] = (b < nb) ? __float_as_int(bodyv[(size_t)b * BW_WORDS + BW_DEPTH]) : 1 << 20;
+      if (b < NBC) sh.ccount[b] = 0;
+    }
+    for (int lev = 0; lev <= maxdepth; ++lev) {
+#pragma unroll
+      for (int t = 0; t < SB; ++t) {
+        const int b = lane + 16 * t;
+        if (depthb[t] == lev) {
+          const float* rec = bodyv + (size_t)b * BW_WORDS;
+          m33 R;
+          f3 p, w, o;
+          sv V, A;
+          if (b == 0) {
+            R = R0;
+            p = P0;
+            w = mk(0.f, 0.f, 0.f);
+            o = P0;
+            V.a = mul(R0, wb);
+            V.l = mul(R0, vb);
+            A.a = mk(0.f, 0.f, 0.f);
+            A.l = mk(-P.g[0], -P.g[1], -P.g[2]);  // gravity as a base acceleration
+          } else {
+            const int lam = __float_as_int(rec[BW_PARENT]);
+            const float* pr = &sh.A[lam * 24];
+            m33 Rl;
+#pragma unroll
+            for (int i = 0; i < 9; ++i) Rl.m[i] = pr[i];
+            const f3 pl = mk(pr[9], pr[10], pr[11]);
+            const sv Vl = {mk(pr[12], pr[13], pr[14]), mk(pr[15], pr[16], pr[17])};
+            const sv Al = {mk(pr[18], pr[19], pr[20]), mk(pr[21], pr[22], pr[23])};
+            const int dof = r0 + b - 1;
+            const float th = sh.th[dof], thd = sh.thd[dof];
+            const f3 u = mk(rec[BW_AXIS], rec[BW_AXIS + 1], rec[BW_AXIS + 2]);
+            float sn, cs;
+            sincosf(th, &sn, &cs);
+            const m33 E = matmul(quat_rot(rec[BW_RQ], rec[BW_RQ + 1], rec[BW_RQ + 2], rec[BW_RQ + 3]),
+                                 axis_rot_acc(u, sn, cs));
+            R = matmul(Rl, E);
+            o = pl + mul(Rl, mk(rec[BW_AP], rec[BW_AP + 1], rec[BW_AP + 2]));
+            p = o - mul(R, mk(rec[BW_AC], rec[BW_AC + 1], rec[BW_AC + 2]));
+            w = mul(R, u);
+            const sv St = {w * thd, cross3(o - P0, w) * thd};
+            V = {Vl.a + St.a, Vl.l + St.l};
+            const sv c = crm(Vl, St);
+            A = {Al.a + c.a, Al.l + c.l};
+          }
+          float* dst = &sh.A[b * 24];
+#pragma unroll
+          for (int i = 0; i < 9; ++i) dst[i] = R.m[i];
+          dst[9] = p.x; dst[10] = p.y; dst[11] = p.z;
+          dst[12] = V.a.x; dst[13] = V.a.y; dst[14] = V.a.z; dst[15] = V.l.x; dst[16] = V.l.y; dst[17] = V.l.z;
+          dst[18] = A.a.x; dst[19] = A.a.y; dst[20] = A.a.z; dst[21] = A.l.x; dst[22] = A.l.y; dst[23] = A.l.z;
+          sh.WO[b][0] = w.x; sh.WO[b][1] = w.y; sh.WO[b][2] = w.z;
+          sh.WO[b][3] = o.x; sh.WO[b][4] = o.y; sh.WO[b][5] = o.z;
+          // box-plane contact: 8 corners, bits (x, y, z) of the corner index = sign
+          if (b >= 1 || r0 == 6) {
+            const f3 h = mk(rec[BW_HALF], rec[BW_HALF + 1], rec[BW_HALF + 2]);
+            unsigned msk = 0u;
+#pragma unroll
+            for (int cn = 0; cn < 8; ++cn) {
+              const float z = p.z + R.m[6] * ((cn & 1) ? h.x : -h.x) + R.m[7] * ((cn & 2) ? h.y : -h.y) +
+                              R.m[8] * ((cn & 4) ? h.z : -h.z);
+              if (z < 0.f) msk |= 1u << cn;
+            }
+            sh.ccount[b] = (int)msk;  // corner mask; the list is written below
+          }
+        }
+      }
+      wave_sync();
+    }
+    // contact list in (body, corner) order: prefix over bodies of the popcounts
+    int nc = 0;
+    {
+      int off[SB];
+#pragma unroll
+      for (int t = 0; t < SB; ++t) off[t] = 0;
+      for (int bb = 0; bb < nb; ++bb) {
+        const int cbb = __builtin_popcount((unsigned)sh.ccount[bb]);
+#pragma unroll
+        for (int t = 0; t < SB; ++t) off[t] += (bb < lane + 16 * t) ? cbb : 0;
+        nc += cbb;
+      }
+#pragma unroll
+      for (int t = 0; t < SB; ++t) {
+        const int b = lane + 16 * t;
+        if (b < nb) {
+          const unsigned msk = (unsigned)sh.ccount[b];
+          if (msk) {
+            const float* pr = &sh.A[b * 24];
+            const float* rec = bodyv + (size_t)b * BW_WORDS;
+            const f3 h = mk(rec[BW_HALF], rec[BW_HALF + 1], rec[BW_HALF + 2]);
+            const unsigned anc = __float_as_uint(rec[BW_ANCESTORS]);
+            int idx = off[t];
+            for (int cn = 0; cn < 8; ++cn) {
+              if (msk & (1u << cn)) {
+                const f3 sv3 = mk((cn & 1) ? h.x : -h.x, (cn & 2) ? h.y : -h.y, (cn & 4) ? h.z : -h.z);
+                const f3 x = mk(pr[9] + pr[0] * sv3.x + pr[1] * sv3.y + pr[2] * sv3.z,
+                                pr[10] + pr[3] * sv3.x + pr[4] * sv3.y + pr[5] * sv3.z,
+                                pr[11] + pr[6] * sv3.x + pr[7] * sv3.y + pr[8] * sv3.z);
+                if (idx < NCR) {
+                  sh.cl[idx][0] = x.x; sh.cl[idx][1] = x.y; sh.cl[idx][2] = x.z;
+                  sh.cl[idx][3] = __uint_as_float(anc);
+                } else {
+                  ovf_list[idx * 4 + 0] = x.x; ovf_list[idx * 4 + 1] = x.y; ovf_list[idx * 4 + 2] = x.z;
+                  ovf_list[idx * 4 + 3] = __uint_as_float(anc);
+                }
+                ++idx;
+              }
+            }
+          }
+        }
+      }
+    }
+    __threadfence_block();  // overflow list entries are read by other lanes of the row
+    wave_sync();
+
+    // =====================================================================
+    // 2. backward sweep: body inertia about p0 and Newton-Euler force
+    //    f = I A + V x* (I V), composite inertia C and force F of each subtree,
+    //    bias c (hinge: S.F; root: S0^T F0), and C S of each hinge for CRBA
+    // =====================================================================
+    for (int lev = maxdepth; lev >= 0; --lev) {
+#pragma unroll
+      for (int t = 0; t < SB; ++t) {
+        const int b = lane + 16 * t;
+        if (depthb[t] == lev) {
+          const float* rec = bodyv + (size_t)b * BW_WORDS;
+          float* own = &sh.A[b * 24];
+          sinertia C;
+          sv F;
+          {
+            m33 R;
+#pragma unroll
+            for (int i = 0; i < 9; ++i) R.m[i] = own[i];
+            const f3 c = mk(own[9], own[10], own[11]) - P0;
+            const sv V = {mk(own[12], own[13], own[14]), mk(own[15], own[16], own[17])};
+            const sv A = {mk(own[18], own[19], own[20]), mk(own[21], own[22], own[23])};
+            const float m = rec[BW_MASS];
+            const f3 h = mk(rec[BW_HALF], rec[BW_HALF + 1], rec[BW_HALF + 2]);
+            const float ix = m / 3.f * (h.y * h.y + h.z * h.z), iy = m / 3.f * (h.x * h.x + h.z * h.z),
+                        iz = m / 3.f * (h.x * h.x + h.y * h.y);
+            const float cc = dot3(c, c);
+            C.m = m;
+            C.h = c * m;
+            C.I[0] = R.m[0] * R.m[0] * ix + R.m[1] * R.m[1] * iy + R.m[2] * R.m[2] * iz + m * (cc - c.x * c.x);
+            C.I[1] = R.m[3] * R.m[3] * ix + R.m[4] * R.m[4] * iy + R.m[5] * R.m[5] * iz + m * (cc - c.y * c.y);
+            C.I[2] = R.m[6] * R.m[6] * ix + R.m[7] * R.m[7] * iy + R.m[8] * R.m[8] * iz + m * (cc - c.z * c.z);
+            C.I[3] = R.m[0] * R.m[3] * ix + R.m[1] * R.m[4] * iy + R.m[2] * R.m[5] * iz - m * c.x * c.y;
+            C.I[4] = R.m[0] * R.m[6] * ix + R.m[1] * R.m[7] * iy + R.m[2] * R.m[8] * iz - m * c.x * c.z;
+            C.I[5] = R.m[3] * R.m[6] * ix + R.m[4] * R.m[7] * iy + R.m[5] * R.m[8] * iz - m * c.y * c.z;
+            const sv IV = imul(C, V), IA = imul(C, A);
+            const sv x = crf(V, IV);
+            F = {IA.a + x.a, IA.l + x.l};
+          }
+          unsigned ch = __float_as_uint(rec[BW_CHILDREN]);
+          while (ch) {
+            const int c = __builtin_ctz(ch);
+            ch &= ch - 1;
+            const float* src = &sh.A[c * 24];
+            C.m += src[0];
+            C.h = C.h + mk(src[1], src[2], src[3]);
+#pragma unroll
+            for (int i = 0; i < 6; ++i) C.I[i] += src[4 + i];
+            F.a = F.a + mk(src[10], src[11], src[12]);
+            F.l = F.l + mk(src[13], src[14], src[15]);
+          }
+          own[0] = C.m; own[1] = C.h.x; own[2] = C.h.y; own[3] = C.h.z;
+#pragma unroll
+          for (int i = 0; i < 6; ++i) own[4 + i] = C.I[i];
+          own[10] = F.a.x; own[11] = F.a.y; own[12] = F.a.z;
+          own[13] = F.l.x; own[14] = F.l.y; own[15] = F.l.z;
+          if (b >= 1) {
+            const f3 w = mk(sh.WO[b][0], sh.WO[b][1], sh.WO[b][2]);
+            const f3 o = mk(sh.WO[b][3], sh.WO[b][4], sh.WO[b][5]);
+            const sv Sb = {w, cross3(o - P0, w)};
+            sh.cb[0][r0 + b - 1] = dot3(Sb.a, F.a) + dot3(Sb.l, F.l);
+            const sv Fc = imul(C, Sb);
+            sh.WO[b][6] = Fc.a.x; sh.WO[b][7] = Fc.a.y; sh.WO[b][8] = Fc.a.z;
+            sh.WO[b][9] = Fc.l.x; sh.WO[b][10] = Fc.l.y; sh.WO[b][11] = Fc.l.z;
+          }
+        }
+      }
+      wave_sync();
+    }
+    // root bias and root rows of M from the total composite (lanes 0..5)
+    float mroot[6];
+#pragma unroll
+    for (int i = 0; i < 6; ++i) mroot[i] = 0.f;
+    if (r0 == 6 && lane < 6) {
+      const float* src = &sh.A[0];
+      const float m = src[0];
+      const f3 hw = mk(src[1], src[2], src[3]);
+      float Iw[6];
+#pragma unroll
+      for (int i = 0; i < 6; ++i) Iw[i] = src[4 + i];
+      const f3 Fa = mk(src[10], src[11], src[12]), Fl = mk(src[13], src[14], src[15]);
+      const f3 ca = mulT(R0, Fa), cl = mulT(R0, Fl);
+      const int i = lane;
+      sh.cb[0][i] = (i < 3) ? (i == 0 ? ca.x : i == 1 ? ca.y : ca.z) : (i == 3 ? cl.x : i == 4 ? cl.y : cl.z);
+      // M_rr = [[R^T Io R, [h_b]x], [[h_b]x^T, m 1]] with h_b = R^T h; column j of [h_b]x is h_b x e_j
+      const f3 hb = mulT(R0, hw);
+      const f3 hx0 = cross3(hb, mk(1.f, 0.f, 0.f)), hx1 = cross3(hb, mk(0.f, 1.f, 0.f)),
+               hx2 = cross3(hb, mk(0.f, 0.f, 1.f));
+      if (i < 3) {
+        const f3 e = mk(R0.m[i], R0.m[3 + i], R0.m[6 + i]);  // R0 e_i (column i)
+        const f3 row = mulT(R0, symmul(Iw, e));             // row i of R^T Io R
+        mroot[0] = row.x; mroot[1] = row.y; mroot[2] = row.z;
+        mroot[3] = (i == 0) ? hx0.x : (i == 1) ? hx0.y : hx0.z;
+        mroot[4] = (i == 0) ? hx1.x : (i == 1) ? hx1.y : hx1.z;
+        mroot[5] = (i == 0) ? hx2.x : (i == 1) ? hx2.y : hx2.z;
+      } else {
+        const int r = i - 3;  // row r of [h_b]x^T = column r of [h_b]x
+        const f3 col = (r == 0) ? hx0 : (r == 1) ? hx1 : hx2;
+        mroot[0] = col.x; mroot[1] = col.y; mroot[2] = col.z;
+        mroot[3] = (r == 0) ? m : 0.f; mroot[4] = (r == 1) ? m : 0.f; mroot[5] = (r == 2) ? m : 0.f;
+      }
+    }
+    wave_sync();  // composite reads done; the area becomes the assembled matrix
+    {
+      constexpr int MST = L::MST;
+      for (int e = lane; e < NVC * MST; e += 16) sh.A[e] = 0.f;
+    }
+    wave_sync();
+    {
+      constexpr int MST = L::MST;
+      float* Ml = sh.A;
+#pragma unroll
+      for (int s = 0; s < S; ++s) {
+        const int d = lane + 16 * s;
+        if (d >= nv && d < NVC) Ml[d * MST + d] = 1.f;  // identity padding
+      }
+      if (r0 == 6 && lane < 6) {
+#pragma unroll
+        for (int j = 0; j < 6; ++j) Ml[lane * MST + j] = mroot[j];
+      }
+#pragma unroll
+      for (int t = 0; t < SB; ++t) {
+        const int b = lane + 16 * t;
+        if (b >= 1 && b < nb) {
+          const int d = r0 + b - 1;
+          const sv Fcb = {mk(sh.WO[b][6], sh.WO[b][7], sh.WO[b][8]), mk(sh.WO[b][9], sh.WO[b][10], sh.WO[b][11])};
+          int j = b;
+          while (j >= 1) {
+            const int dj = r0 + j - 1;
+            const f3 wj = mk(sh.WO[j][0], sh.WO[j][1], sh.WO[j][2]);
+            const f3 oj = mk(sh.WO[j][3], sh.WO[j][4], sh.WO[j][5]);
+            float val = dot3(wj, Fcb.a) + dot3(cross3(oj - P0, wj), Fcb.l);
+            if (j == b) val += dt * ba;
+            Ml[d * MST + dj] = val;
+            Ml[dj * MST + d] = val;
+            j = sh.par[j];
+          }
+          if (r0 == 6) {
+            const f3 ra = mulT(R0, Fcb.a), rl = mulT(R0, Fcb.l);
+            const float rv[6] = {ra.x, ra.y, ra.z, rl.x, rl.y, rl.z};
+#pragma unroll
+            for (int i = 0; i < 6; ++i) {
+              Ml[d * MST + i] = rv[i];
+              Ml[i * MST + d] = rv[i];
+            }
+          }
+        }
+      }
+    }
+    wave_sync();
+    // rows into registers, bias per slot
+    float Mi[S][NVC];
+    float cS[S];
+#pragma unroll
+    for (int s = 0; s < S; ++s) {
+      const int d = lane + 16 * s;
+      const int dr = d < NVC ? d : 0;
+#pragma unroll
+      for (int j = 0; j < NVC; ++j) Mi[s][j] = sh.A[dr * L::MST + j];
+      cS[s] = (d < nv) ? sh.cb[0][d] : 0.f;
+    }
+
+    // =====================================================================
+    // 3. inverse by symmetric Gauss-Jordan sweep with rotating columns
+    //    invariant: register column j of step k holds original column (k+j) mod NVC
+    // =====================================================================
+    wave_sync();
+#pragma unroll 1
+    for (int k = 0; k < NVC; ++k) {
+      float* cbk = sh.cb[k & 1];
+#pragma unroll
+      for (int s = 0; s < S; ++s) {
+        const int d = lane + 16 * s;
+        if (d < NVC) cbk[d] = Mi[s][0];
+      }
+      wave_sync();
+      const float pinv = 1.0f / cbk[k];
+      float f[S];
+      bool piv[S];
+#pragma unroll
+      for (int s = 0; s < S; ++s) {
+        f[s] = Mi[s][0] * pinv;
+        piv[s] = (lane + 16 * s) == k;
+      }
+#pragma unroll
+      for (int j = 1; j < NVC; ++j) {
+        int idx = k + j;
+        idx = idx >= NVC ? idx - NVC : idx;
+        const float cj = cbk[idx];
+#pragma unroll
+        for (int s = 0; s < S; ++s) Mi[s][j - 1] = piv[s] ? cj * pinv : fmaf(-f[s], cj, Mi[s][j]);
+      }
+#pragma unroll
+      for (int s = 0; s < S; ++s) Mi[s][NVC - 1] = piv[s] ? -pinv : f[s];
+    }
+    // Mi now holds -Mt^-1
+#pragma unroll
+    for (int s = 0; s < S; ++s)
+#pragma unroll
+      for (int j = 0; j < NVC; ++j) Mi[s][j] = -Mi[s][j];
+    float Dd[S];  // own diagonal of Mt^-1
+#pragma unroll
+    for (int s = 0; s < S; ++s) {
+      const int d = lane + 16 * s;
+      float x = 0.f;
+#pragma unroll
+      for (int j = 0; j < NVC; ++j) x = (j == d) ? Mi[s][j] : x;
+      Dd[s] = x;
+    }
+
+    // =====================================================================
+    // 4. control and free velocity
+    // =====================================================================
+    wave_sync();  // last sweep reads of cb done before it is reused
+    const double tk = (double)kstep * dtd;
+    float aS[S];
+#pragma unroll
+    for (int s = 0; s < S; ++s) {
+      const int d = lane + 16 * s;
+      const bool hinge = d >= r0 && d < nv;
+      double ph = (double)cpgW[s] * tk + (double)cpgP[s];
+      ph -= 6.283185307179586 * floor(ph * 0.15915494309189535);
+      const float target = cpgA[s] * sinf((float)ph);
+      aS[s] = hinge ? kp * (target - thS[s]) : 0.f;
+      float rhs = -dt * cS[s];
+      if (hinge) rhs += dt * (aS[s] - ba * vS[s]);
+      if (d >= nv) rhs = 0.f;
+      if (d < 32) sh.cb[0][d] = rhs;
+    }
+    wave_sync();
+    float vp[S];
+#pragma unroll
+    for (int s = 0; s < S; ++s) vp[s] = vS[s];
+#pragma unroll
+    for (int j = 0; j < NVC; ++j) {
+      const float r = sh.cb[0][j];
+#pragma unroll
+      for (int s = 0; s < S; ++s) vp[s] = fmaf(Mi[s][j], r, vp[s]);
+    }
+
+    // =====================================================================
+    // 5. contact rows
+    // =====================================================================
+    // per-DoF geometry of the point Jacobian: J_d(x) = ang_d x x + cst_d (zero off the path)
+    f3 ang[S], cst[S];
+    int bodyOfDof[S];
+#pragma unroll
+    for (int s = 0; s < S; ++s) {
+      const int d = lane + 16 * s;
+      bodyOfDof[s] = -1;
+      if (r0 == 6 && d < 3) {
+        ang[s] = mk(R0.m[d], R0.m[3 + d], R0.m[6 + d]);
+        cst[s] = mk(0.f, 0.f, 0.f) - cross3(ang[s], P0);
+      } else if (r0 == 6 && d < 6) {
+        ang[s] = mk(0.f, 0.f, 0.f);
+        cst[s] = mk(R0.m[d - 3], R0.m[3 + d - 3], R0.m[6 + d - 3]);
+      } else if (d < nv) {
+        const int b = d - r0 + 1;
+        bodyOfDof[s] = b;
+        ang[s] = mk(sh.WO[b][0], sh.WO[b][1], sh.WO[b][2]);
+        cst[s] = mk(0.f, 0.f, 0.f) - cross3(ang[s], mk(sh.WO[b][3], sh.WO[b][4], sh.WO[b][5]));
+      } else {
+        ang[s] = mk(0.f, 0.f, 0.f);
+        cst[s] = mk(0.f, 0.f, 0.f);
+      }
+    }
+
+    float JnR[NCR][S], JxR[NCR][S], JyR[NCR][S], WnR[NCR][S], WxR[NCR][S], WyR[NCR][S];
+#pragma unroll
+    for (int c = 0; c < NCR; ++c) {
+      if (c < nc) {
+        const f3 x = mk(sh.cl[c][0], sh.cl[c][1], sh.cl[c][2]);
+        const unsigned anc = __float_as_uint(sh.cl[c][3]);
+        float scal[10];
+        build_rows<S, NVC>(Mi, ang, cst, bodyOfDof, lane, sh.jb, x, anc, kc, kb, dt, JnR[c], JxR[c], JyR[c],
+                           WnR[c], WxR[c], WyR[c], scal);
+#pragma unroll
+        for (int i = 0; i < 10; ++i) sh.cs[c][i] = scal[i];  // identical in every lane
+      } else {
+#pragma unroll
+        for (int s = 0; s < S; ++s) {
+          JnR[c][s] = JxR[c][s] = JyR[c][s] = 0.f;
+          WnR[c][s] = WxR[c][s] = WyR[c][s] = 0.f;
+        }
+      }
+    }
+    // contacts beyond the register budget: rows and scalars go to the workspace.
+    // Each lane stores and later reloads only values it computed itself (the
+    // scalars are identical in all lanes), so no cross-lane visibility is needed.
+    for (int c = NCR; c < nc; ++c) {
+      const f3 x = mk(ovf_list[c * 4], ovf_list[c * 4 + 1], ovf_list[c * 4 + 2]);
+      const unsigned anc = __float_as_uint(ovf_list[c * 4 + 3]);
+      float Jn[S], Jx[S], Jy[S], Wn[S], Wx[S], Wy[S], scal[10];
+      build_rows<S, NVC>(Mi, ang, cst, bodyOfDof, lane, sh.jb, x, anc, kc, kb, dt, Jn, Jx, Jy, Wn, Wx, Wy, scal);
+      float* rows = ovf_rows + (size_t)c * 6 * NVC;
+#pragma unroll
+      for (int s = 0; s < S; ++s) {
+        const int d = lane + 16 * s;
+        if (d < NVC) {
+          rows[0 * NVC + d] = Jn[s]; rows[1 * NVC + d] = Jx[s]; rows[2 * NVC + d] = Jy[s];
+          rows[3 * NVC + d] = Wn[s]; rows[4 * NVC + d] = Wx[s]; rows[5 * NVC + d] = Wy[s];
+        }
+      }
+      float* sd = ovf_scal + (size_t)c * kOvfScal;
+#pragma unroll
+      for (int i = 0; i < 10; ++i) sd[i] = scal[i];
+    }
+
+    // =====================================================================
+    // 6. projected Gauss-Seidel
+    // =====================================================================
+    float Dl[S];  // actuator clamp corrections Delta, held by the DoF's owner lane/slot
+#pragma unroll
+    for (int s = 0; s < S; ++s) Dl[s] = 0.f;
+    for (int sweep = 0; sweep < P.K; ++sweep) {
+      // (i) actuator clamp rows in hinge order.  A row is a no-op when its new
+      // Delta equals the old one; if that holds for every row against the
+      // current velocity, the sequential pass would change nothing, so it is
+      // only run (exactly, in order) when some row of some variant changes.
+      bool chg = false;
+#pragma unroll
+      for (int s = 0; s < S; ++s) {
+        const int d = lane + 16 * s;
+        const bool hinge = d >= r0 && d < nv;
+        const float u0 = fmaf(dt * Dd[s], Dl[s], vp[s]);
+        const float sv_ = aS[s] - ba * u0;
+        const float den = 1.f - ba * dt * Dd[s];
+        float nd = 0.f;
+        if (sv_ > tmax) nd = (sv_ - tmax) / den;
+        else if (sv_ < -tmax) nd = (sv_ + tmax) / den;
+        chg = chg || (hinge && nd != Dl[s]);
+      }
+      if (__builtin_amdgcn_ballot_w64(chg) != 0) {
+#pragma unroll
+        for (int j = 0; j < NVC; ++j) {
+          const int lj = j & 15, sj = j >> 4;
+          if (j >= r0 && j < nv) {  // row-uniform
+            const float u0 = fmaf(dt * Dd[sj], Dl[sj], vp[sj]);
+            const float sv_ = aS[sj] - ba * u0;
+            const float den = 1.f - ba * dt * Dd[sj];
+            float nd = 0.f;
+            if (sv_ > tmax) nd = (sv_ - tmax) / den;
+            else if (sv_ < -tmax) nd = (sv_ + tmax) / den;
+            const float dl = nd - Dl[sj];  // meaningful in the owner lane lj
+            float dlb;
+            switch (lj) {
+              case 0: dlb = row_bcast<0>(dl); break;   case 1: dlb = row_bcast<1>(dl); break;
+              case 2: dlb = row_bcast<2>(dl); break;   case 3: dlb = row_bcast<3>(dl); break;
+              case 4: dlb = row_bcast<4>(dl); break;   case 5: dlb = row_bcast<5>(dl); break;
+              case 6: dlb = row_bcast<6>(dl); break;   case 7: dlb = row_bcast<7>(dl); break;
+              case 8: dlb = row_bcast<8>(dl); break;   case 9: dlb = row_bcast<9>(dl); break;
+              case 10: dlb = row_bcast<10>(dl); break; case 11: dlb = row_bcast<11>(dl); break;
+              case 12: dlb = row_bcast<12>(dl); break; case 13: dlb = row_bcast<13>(dl); break;
+              case 14: dlb = row_bcast<14>(dl); break; default: dlb = row_bcast<15>(dl); break;
+            }
+            Dl[sj] = (lane == lj) ? nd : Dl[sj];
+            const float e = -dt * dlb;
+#pragma unroll
+            for (int s = 0; s < S; ++s) vp[s] = fmaf(Mi[s][j], e, vp[s]);
+          }
+        }
+      }
+      // (ii) contact rows in (body, corner) order
+#pragma unroll
+      for (int c = 0; c < NCR; ++c) {
+        if (c < nc) {
+          float sc[10], lam[3];
+#pragma unroll
+          for (int i = 0; i < 10; ++i) sc[i] = sh.cs[c][i];
+          lam[0] = sc[7]; lam[1] = sc[8]; lam[2] = sc[9];
+          contact_row<S>(vp, JnR[c], JxR[c], JyR[c], WnR[c], WxR[c], WyR[c], sc, lam, mu, kb, dt);
+          sh.cs[c][7] = lam[0]; sh.cs[c][8] = lam[1]; sh.cs[c][9] = lam[2];
+        }
+      }
+      for (int c = NCR; c < nc; ++c) {
+        const float* rows = ovf_rows + (size_t)c * 6 * NVC;
+        float Jn[S], Jx[S], Jy[S], Wn[S], Wx[S], Wy[S];
+#pragma unroll
+        for (int s = 0; s < S; ++s) {
+          const int d = lane + 16 * s;
+          const bool ok = d < NVC;
+          Jn[s] = ok ? rows[0 * NVC + d] : 0.f; Jx[s] = ok ? rows[1 * NVC + d] : 0.f;
+          Jy[s] = ok ? rows[2 * NVC + d] : 0.f; Wn[s] = ok ? rows[3 * NVC + d] : 0.f;
+          Wx[s] = ok ? rows[4 * NVC + d] : 0.f; Wy[s] = ok ? rows[5 * NVC + d] : 0.f;
+        }
+        float* sd = ovf_scal + (size_t)c * kOvfScal;
+        float sc[10], lam[3];
+#pragma unroll
+        for (int i = 0; i < 10; ++i) sc[i] = sd[i];
+        lam[0] = sc[7]; lam[1] = sc[8]; lam[2] = sc[9];
+        contact_row<S>(vp, Jn, Jx, Jy, Wn, Wx, Wy, sc, lam, mu, kb, dt);
+        sd[7] = lam[0]; sd[8] = lam[1]; sd[9] = lam[2];
+      }
+    }
+
+    // =====================================================================
+    // 7. semi-implicit Euler, failure check, counters
+    // =====================================================================
+    const f3 wn = mk(row_bcast<0>(vp[0]), row_bcast<1>(vp[0]), row_bcast<2>(vp[0]));
+    const f3 vn = mk(row_bcast<3>(vp[0]), row_bcast<4>(vp[0]), row_bcast<5>(vp[0]));
+    float thN[S];
+    float bad = 0.f, nclamp = 0.f;
+#pragma unroll
+    for (int s = 0; s < S; ++s) {
+      const int d = lane + 16 * s;
+      const bool hinge = d >= r0 && d < nv;
+      thN[s] = hinge ? fmaf(dt, vp[s], thS[s]) : 0.f;
+      if (d < nv && !(isfinite(vp[s]) && isfinite(thN[s]))) bad = 1.f;
+      if (hinge && Dl[s] != 0.f) nclamp += 1.f;
+    }
+    float p0n[3] = {p0[0], p0[1], p0[2]}, Q0n[4] = {Q0[0], Q0[1], Q0[2], Q0[3]};
+    if (r0 == 6) {
+      const f3 dp = mul(R0, vn);
+      p0n[0] = fmaf(dt, dp.x, p0[0]); p0n[1] = fmaf(dt, dp.y, p0[1]); p0n[2] = fmaf(dt, dp.z, p0[2]);
+      const f3 phi = wn * dt;
+      const float an = sqrtf(dot3(phi, phi));
+      float dq[4];
+      if (an < 1e-8f) {
+        dq[0] = 1.f; dq[1] = 0.5f * phi.x; dq[2] = 0.5f * phi.y; dq[3] = 0.5f * phi.z;
+      } else {
+        float sh2, ch2;
+        sincosf(0.5f * an, &sh2, &ch2);
+        const float sc = sh2 / an;
+        dq[0] = ch2; dq[1] = phi.x * sc; dq[2] = phi.y * sc; dq[3] = phi.z * sc;
+      }
+      const float aw = Q0[0], ax = Q0[1], ay = Q0[2], az = Q0[3];
+      float qn[4] = {aw * dq[0] - ax * dq[1] - ay * dq[2] - az * dq[3],
+                     aw * dq[1] + ax * dq[0] + ay * dq[3] - az * dq[2],
+                     aw * dq[2] - ax * dq[3] + ay * dq[0] + az * dq[1],
+                     aw * dq[3] + ax * dq[2] - ay * dq[1] + az * dq[0]};
+      const float inrm = 1.f / sqrtf(qn[0] * qn[0] + qn[1] * qn[1] + qn[2] * qn[2] + qn[3] * qn[3]);
+#pragma unroll
+      for (int i = 0; i < 4; ++i) Q0n[i] = qn[i] * inrm;
+      bool ok = true;
+#pragma unroll
+      for (int i = 0; i < 3; ++i) ok = ok && isfinite(p0n[i]);
+#pragma unroll
+      for (int i = 0; i < 4; ++i) ok = ok && isfinite(Q0n[i]);
+      if (!ok) bad = 1.f;
+    }
+    const float badsum = row_sum(bad);
+    const float clampsum = row_sum(nclamp);
+    if (badsum > 0.f) {
+      status |= 1u;  // non-finite state: freeze
+      break;
+    }
+#pragma unroll
+    for (int s = 0; s < S; ++s) { vS[s] = vp[s]; thS[s] = thN[s]; }
+#pragma unroll
+    for (int i = 0; i < 3; ++i) p0[i] = p0n[i];
+#pragma unroll
+    for (int i = 0; i < 4; ++i) Q0[i] = Q0n[i];
+    kstep += 1;
+    cnt_contact += (unsigned long long)nc;
+    cnt_clamp += (unsigned long long)clampsum;
+  }
+
+  // ---- write back ----
+  {
+    float* qdst = a.q + (size_t)vid * kQStride;
+    float* vdst = a.v + (size_t)vid * kVStride;
+    const int qh = (r0 == 6) ? 7 : 0;
+#pragma unroll
+    for (int s = 0; s < S; ++s) {
+      const int d = lane + 16 * s;
+      if (d < nv) vdst[d] = vS[s];
+      if (d >= r0 && d < nv) qdst[qh + d - r0] = thS[s];
+    }
+    if (lane == 0) {
+      if (r0 == 6) {
+        qdst[0] = p0[0]; qdst[1] = p0[1]; qdst[2] = p0[2];
+        qdst[3] = Q0[0]; qdst[4] = Q0[1]; qdst[5] = Q0[2]; qdst[6] = Q0[3];
+      }
+      a.k[vid] = kstep;
+      a.status[vid] = status;
+      const float dx = p0[0] - a.xy0[2 * vid], dy = p0[1] - a.xy0[2 * vid + 1];
+      a.fit[vid] = status ? __int_as_float(0x7fc00000) : ((r0 == 6) ? sqrtf(dx * dx + dy * dy) : 0.f);
+      a.cnt[2 * vid] = cnt_contact;
+      a.cnt[2 * vid + 1] = cnt_clamp;
+    }
+  }
+}
+
+}  // namespace simk

@@ -1,0 +1,73 @@
+// Internal layout of the packed model and state in the device workspace,
+// shared by the host library (packing, launches) and the HIP kernels.
+#pragma once
+#include <stdint.h>
+
+namespace simk {
+
+constexpr int kGroup = 16;       // lanes cooperating on one variant (one DPP row)
+constexpr int kVarPerWave = 4;   // 64-lane wave = 4 variants
+constexpr int kMaxBodies = 32;   // body capacity of the largest bin (2 slots of 16)
+constexpr int kQStride = 32;     // floats of q per variant (nq <= 29)
+constexpr int kVStride = 32;     // floats of v per variant (nv <= 28)
+
+// Body record: 24 words per body, bin stride = body capacity.
+enum BodyWord {
+  BW_HALF = 0,      // 3 half extents
+  BW_MASS = 3,
+  BW_AP = 4,        // anchor in the parent frame (3)
+  BW_AC = 7,        // anchor in the child frame (3)
+  BW_RQ = 10,       // rest quaternion w,x,y,z (4)
+  BW_AXIS = 14,     // hinge axis, child frame (3)
+  BW_CPG = 17,      // A, omega, phi (3)
+  BW_PARENT = 20,   // int
+  BW_DEPTH = 21,    // int
+  BW_CHILDREN = 22, // uint bitmask over variant-local bodies
+  BW_ANCESTORS = 23,// uint bitmask: ancestors-or-self
+  BW_WORDS = 24
+};
+
+// Per-variant integer header.
+enum HdrWord { HW_NB = 0, HW_NH, HW_NV, HW_R0, HW_MAXDEPTH, HW_USER, HW_PAD0, HW_PAD1, HW_WORDS };
+// Per-variant float header: mu, fixed root pose (p[3], q[4]).
+enum HdrfWord { HF_MU = 0, HF_ROOTP = 1, HF_ROOTQ = 4, HF_WORDS = 8 };
+
+// Overflow scratch per contact (contacts that do not fit in registers).
+constexpr int kOvfScal = 12;     // per-contact solver scalars
+
+struct ModelParams {
+  float kp, kd, tau_max, k_contact, b_contact, dt;
+  float g[3];
+  int K;
+};
+
+// Arguments of one bin's rollout kernel: device pointers into the workspace.
+struct BinArgs {
+  int n;                        // variants in this bin
+  const int* hdr;               // [n][HW_WORDS]
+  const float* hdrf;            // [n][HF_WORDS]
+  const float* body;            // [n][nbc][BW_WORDS]
+  const float* q0;              // [n][kQStride]
+  const float* v0;              // [n][kVStride]
+  float* q;                     // [n][kQStride]
+  float* v;                     // [n][kVStride]
+  long long* k;                 // [n]
+  unsigned* status;             // [n]
+  float* xy0;                   // [n][2]  core xy at k = 0
+  float* fit;                   // [n]     fitness
+  unsigned long long* cnt;      // [n][2]  contact rows, clamp rows
+  float* ovf;                   // [n][ovf_stride]
+  long long ovf_stride;         // floats per variant
+  int n_steps;
+  int reset;                    // 1: start from q0, v0 at k = 0
+};
+
+// Overflow scratch layout per variant (floats):
+//   list  [max_contacts][4]   x, y, z, ancestor mask of the contact body (uint bits)
+//   scal  [max_contacts][kOvfScal]
+//   rows  [max_contacts][6][nvc]  J_n, J_x, J_y, W_n, W_x, W_y
+inline long long ovf_floats(int max_contacts, int nvc) {
+  return (long long)max_contacts * (4 + kOvfScal + 6 * nvc);
+}
+
+}  // namespace simk

@@ -1,0 +1,58 @@
+"""Algorithmic work of one simulation step (for roofline reporting).
+
+Flops of the dense method per variant-step, at each variant's own sizes
+(nh hinges, nb bodies, nv DoFs, D = sum of body depths) and its actually
+active rows (n_c contacts, n_clamp engaged actuator clamps), FMA = 2:
+
+  156 nh + 594 nb + 60 D + 72 nh          kinematics, RNEA, CRBA, control
+  + (2/3) nv^3 + 2 nv^2 + 100             dense factorisation and free solve
+  + n_c (50 + 9 dbar + 6 nv^2 + 6 nv + 12 K nv)   contact rows and K sweeps
+  + n_clamp (2 nv^2 + 4 K nv)             clamp rows and K sweeps
+
+Padded lanes, bin capacities and the kernel's own extra work (for instance
+the explicit inverse) are not counted.  Bytes: model + state read once and
+state + fitness written once per rollout launch.
+"""
+from __future__ import annotations
+
+import numpy as np
+
+
+def depth_sums(pop):
+    """Sum of body depths and mean depth per variant."""
+    D = np.zeros(pop.n_variants)
+    dbar = np.zeros(pop.n_variants)
+    bo = pop.body_offset
+    for i in range(pop.n_variants):
+        par = pop.parent[bo[i]:bo[i + 1]]
+        d = np.zeros(len(par))
+        for b in range(1, len(par)):
+            d[b] = d[par[b]] + 1
+        D[i] = d.sum()
+        dbar[i] = d.mean()
+    return D, dbar
+
+
+def flops_per_variant(pop, steps, rows_contact, rows_clamp, K=None):
+    """Algorithmic flops of `steps` steps per variant given the counters
+    (rows_contact = sum of active contacts over those steps, rows_clamp = sum
+    of engaged clamps)."""
+    K = int(pop.params["pgs_iters"] if K is None else K)
+    nh = pop.n_hinges.astype(np.float64)
+    nb = pop.n_bodies.astype(np.float64)
+    nv = pop.nv.astype(np.float64)
+    D, dbar = depth_sums(pop)
+    base = 156 * nh + 594 * nb + 60 * D + 72 * nh + (2.0 / 3.0) * nv ** 3 + 2 * nv ** 2 + 100
+    per_contact = 50 + 9 * dbar + 6 * nv ** 2 + 6 * nv + 12 * K * nv
+    per_clamp = 2 * nv ** 2 + 4 * K * nv
+    return (base * steps + np.asarray(rows_contact, np.float64) * per_contact
+            + np.asarray(rows_clamp, np.float64) * per_clamp)
+
+
+def bytes_per_rollout(pop):
+    """Algorithmic HBM bytes of one rollout launch: model (24 words per body,
+    header) and initial state read, final state and fitness written."""
+    nb = pop.n_bodies.astype(np.float64)
+    nq = pop.nq.astype(np.float64)
+    nv = pop.nv.astype(np.float64)
+    return float((4 * (24 * nb + 16) + 4 * (nq + nv) * 2 + 4 + 16).sum())

@@ -1,0 +1,207 @@
+"""Thin ctypes binding of libsim.so (the C ABI declared in include/sim.h).
+
+Argument marshalling only: every simulation step runs in the HIP kernels of
+libsim.so.  PyTorch provides the device workspace and the stream.  If the
+library has not been built, importing works but creating a Simulator raises.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+
+import numpy as np
+
+_LIB_PATH = os.path.join(os.path.dirname(os.path.abspath(__file__)), "libsim.so")
+_lib = None
+
+SIM_OK, SIM_E_INVALID, SIM_E_NOMEM, SIM_E_DEVICE, SIM_E_STATE = 0, -1, -2, -3, -4
+SIM_ROOT_FREE, SIM_ROOT_FIXED = 0, 1
+SIM_HOST, SIM_DEVICE = 0, 1
+EXPORTED = ("sim_create", "sim_workspace_bytes", "sim_bind", "sim_step_batch", "sim_rollout", "sim_fitness",
+            "sim_get_state", "sim_set_state", "sim_counters", "sim_bins", "sim_destroy", "sim_last_error")
+
+_F = C.POINTER(C.c_float)
+_I32 = C.POINTER(C.c_int32)
+
+
+class sim_model_desc(C.Structure):
+    _fields_ = [("n_variants", C.c_int32), ("root_type", C.c_int32), ("body_offset", _I32), ("parent", _I32),
+                ("half_ext", _F), ("mass", _F), ("anchor_parent", _F), ("anchor_child", _F), ("rest_quat", _F),
+                ("axis", _F), ("cpg", _F), ("mu", _F), ("q0", _F), ("v0", _F), ("root_pose", _F),
+                ("kp", C.c_float), ("kd", C.c_float), ("tau_max", C.c_float), ("k_contact", C.c_float),
+                ("b_contact", C.c_float), ("dt", C.c_float), ("gravity", C.c_float * 3), ("pgs_iters", C.c_int32)]
+
+
+class sim_options(C.Structure):
+    _fields_ = [("contacts_in_registers", C.c_int32), ("use_graph", C.c_int32), ("reserved", C.c_int32 * 6)]
+
+
+class SimError(RuntimeError):
+    def __init__(self, code, msg):
+        super().__init__(f"{msg} (code {code})")
+        self.code = code
+
+
+def library_path() -> str:
+    return _LIB_PATH
+
+
+def load():
+    """Load libsim.so; raises if it has not been built (no fallback path exists)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(_LIB_PATH):
+        raise ImportError(f"{_LIB_PATH} is missing: build it with `python -m paper_2502_11129_amd.build`")
+    # torch ships its own HIP runtime (same soname); load it first so the process
+    # holds a single runtime that both torch and libsim use.
+    import torch  # noqa: F401
+    lib = C.CDLL(_LIB_PATH)
+    P, I, VP, SZ = C.c_void_p, C.c_int, C.c_void_p, C.c_size_t
+    lib.sim_create.argtypes = [C.POINTER(sim_model_desc), C.POINTER(sim_options), C.POINTER(P)]
+    lib.sim_create.restype = I
+    lib.sim_workspace_bytes.argtypes = [P, C.POINTER(SZ)]
+    lib.sim_bind.argtypes = [P, VP, SZ, VP]
+    lib.sim_step_batch.argtypes = [P, C.c_int32, VP]
+    lib.sim_rollout.argtypes = [P, C.c_int32, VP]
+    lib.sim_fitness.argtypes = [P, VP, I, VP]
+    lib.sim_get_state.argtypes = [P, _F, _F, C.POINTER(C.c_int64), I, VP]
+    lib.sim_set_state.argtypes = [P, _F, _F, C.POINTER(C.c_int64), I, VP]
+    lib.sim_counters.argtypes = [P, C.POINTER(C.c_uint64), C.POINTER(C.c_uint64), C.POINTER(C.c_uint32), I, VP]
+    lib.sim_bins.argtypes = [P, _I32, _I32, C.c_int32]
+    lib.sim_destroy.argtypes = [P]
+    lib.sim_destroy.restype = None
+    lib.sim_last_error.argtypes = [P]
+    lib.sim_last_error.restype = C.c_char_p
+    for name in ("sim_workspace_bytes", "sim_bind", "sim_step_batch", "sim_rollout", "sim_fitness",
+                 "sim_get_state", "sim_set_state", "sim_counters", "sim_bins"):
+        getattr(lib, name).restype = I
+    _lib = lib
+    return lib
+
+
+def _f32(a):
+    return np.ascontiguousarray(a, dtype=np.float32)
+
+
+def make_desc(pop):
+    """Build a sim_model_desc over the arrays of a Population (kept alive by the returned tuple)."""
+    keep = dict(bo=np.ascontiguousarray(pop.body_offset, np.int32), parent=np.ascontiguousarray(pop.parent, np.int32),
+                half=_f32(pop.half_ext), mass=_f32(pop.mass), ap=_f32(pop.anchor_parent), ac=_f32(pop.anchor_child),
+                rq=_f32(pop.rest_quat), axis=_f32(pop.axis), cpg=_f32(pop.cpg), mu=_f32(pop.mu), q0=_f32(pop.q0),
+                v0=_f32(pop.v0), rp=_f32(pop.root_pose))
+    p = pop.params
+    f = lambda a: a.ctypes.data_as(_F)
+    d = sim_model_desc()
+    d.n_variants = int(keep["bo"].shape[0] - 1)
+    d.root_type = int(pop.root_type)
+    d.body_offset = keep["bo"].ctypes.data_as(_I32)
+    d.parent = keep["parent"].ctypes.data_as(_I32)
+    d.half_ext, d.mass, d.anchor_parent, d.anchor_child = f(keep["half"]), f(keep["mass"]), f(keep["ap"]), f(keep["ac"])
+    d.rest_quat, d.axis, d.cpg, d.mu = f(keep["rq"]), f(keep["axis"]), f(keep["cpg"]), f(keep["mu"])
+    d.q0, d.v0, d.root_pose = f(keep["q0"]), f(keep["v0"]), f(keep["rp"])
+    d.kp, d.kd, d.tau_max = p["kp"], p["kd"], p["tau_max"]
+    d.k_contact, d.b_contact, d.dt = p["k_contact"], p["b_contact"], p["dt"]
+    d.gravity[0], d.gravity[1], d.gravity[2] = p["gravity"]
+    d.pgs_iters = int(p["pgs_iters"])
+    return d, keep
+
+
+class Handle:
+    """Host-only handle (sim_create): validation and packing, no device work."""
+
+    def __init__(self, pop, contacts_in_registers: int = 0, use_graph: bool = False):
+        self.lib = load()
+        self.pop = pop
+        desc, self._keep = make_desc(pop)
+        opts = sim_options()
+        opts.contacts_in_registers = int(contacts_in_registers)
+        opts.use_graph = int(bool(use_graph))
+        h = C.c_void_p()
+        rc = self.lib.sim_create(C.byref(desc), C.byref(opts), C.byref(h))
+        if rc != SIM_OK:
+            raise SimError(rc, self.lib.sim_last_error(None).decode())
+        self.h = h
+        self.n = desc.n_variants
+        self.nq = np.asarray(pop.nq)
+        self.nv = np.asarray(pop.nv)
+
+    def _check(self, rc):
+        if rc != SIM_OK:
+            raise SimError(rc, self.lib.sim_last_error(self.h).decode())
+
+    def workspace_bytes(self) -> int:
+        b = C.c_size_t()
+        self._check(self.lib.sim_workspace_bytes(self.h, C.byref(b)))
+        return int(b.value)
+
+    def bins(self):
+        n = C.c_int32()
+        info = np.zeros(4 * 64, np.int32)
+        self._check(self.lib.sim_bins(self.h, C.byref(n), info.ctypes.data_as(_I32), 64))
+        return [tuple(int(x) for x in info[4 * i:4 * i + 4]) for i in range(n.value)]
+
+    def close(self):
+        if getattr(self, "h", None):
+            self.lib.sim_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        self.close()
+
+
+class Simulator(Handle):
+    """A bound simulator: workspace allocated by torch on the current device."""
+
+    def __init__(self, pop, contacts_in_registers: int = 0, use_graph: bool = False, device=None):
+        import torch
+        super().__init__(pop, contacts_in_registers, use_graph)
+        self.torch = torch
+        self.device = torch.device("cuda" if device is None else device)
+        self.ws = torch.empty(max(self.workspace_bytes(), 256), dtype=torch.uint8, device=self.device)
+        self._check(self.lib.sim_bind(self.h, C.c_void_p(self.ws.data_ptr()), self.ws.numel(), self.stream()))
+
+    def stream(self):
+        return C.c_void_p(self.torch.cuda.current_stream(self.device).cuda_stream)
+
+    def step(self, n: int = 1):
+        self._check(self.lib.sim_step_batch(self.h, int(n), self.stream()))
+
+    def rollout(self, T: int):
+        self._check(self.lib.sim_rollout(self.h, int(T), self.stream()))
+
+    def fitness(self) -> np.ndarray:
+        out = np.zeros(self.n, np.float32)
+        self._check(self.lib.sim_fitness(self.h, C.c_void_p(out.ctypes.data), SIM_HOST, self.stream()))
+        return out
+
+    def fitness_device(self, out=None):
+        if out is None:
+            out = self.torch.empty(self.n, dtype=self.torch.float32, device=self.device)
+        self._check(self.lib.sim_fitness(self.h, C.c_void_p(out.data_ptr()), SIM_DEVICE, self.stream()))
+        return out
+
+    def get_state(self):
+        q = np.zeros(int(self.nq.sum()), np.float32)
+        v = np.zeros(int(self.nv.sum()), np.float32)
+        k = np.zeros(self.n, np.int64)
+        self._check(self.lib.sim_get_state(self.h, q.ctypes.data_as(_F), v.ctypes.data_as(_F),
+                                           k.ctypes.data_as(C.POINTER(C.c_int64)), SIM_HOST, self.stream()))
+        return q, v, k
+
+    def set_state(self, q, v, k=None):
+        q = _f32(q)
+        v = _f32(v)
+        kk = None if k is None else np.ascontiguousarray(k, np.int64)
+        self._check(self.lib.sim_set_state(self.h, q.ctypes.data_as(_F), v.ctypes.data_as(_F),
+                                           None if kk is None else kk.ctypes.data_as(C.POINTER(C.c_int64)),
+                                           SIM_HOST, self.stream()))
+
+    def counters(self):
+        a = np.zeros(self.n, np.uint64)
+        b = np.zeros(self.n, np.uint64)
+        s = np.zeros(self.n, np.uint32)
+        self._check(self.lib.sim_counters(self.h, a.ctypes.data_as(C.POINTER(C.c_uint64)),
+                                          b.ctypes.data_as(C.POINTER(C.c_uint64)),
+                                          s.ctypes.data_as(C.POINTER(C.c_uint32)), SIM_HOST, self.stream()))
+        return a, b, s

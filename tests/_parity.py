@@ -1,0 +1,88 @@
+"""Helpers shared by the GPU parity tests: teacher-forced one-step errors and
+fitness comparison with a single-precision sensitivity gate."""
+import os
+
+import numpy as np
+
+from oracle import oracle as O
+
+THREADS = max(1, min(16, os.cpu_count() or 1))
+STEP_TOL = 1e-4          # per-step relative state error
+FIT_TOL = 1e-3           # fitness: |F - F_ref| <= FIT_TOL * max(|F_ref|, FIT_FLOOR)
+FIT_FLOOR = 0.01
+BAND = 1e-6              # corners closer than this to the plane: contact activation band
+
+
+def split(pop, q, v):
+    qo, vo = pop.q_offset, pop.v_offset
+    return ([q[qo[i]:qo[i + 1]] for i in range(pop.n_variants)], [v[vo[i]:vo[i + 1]] for i in range(pop.n_variants)])
+
+
+def canon_quat(q, ref, free):
+    q = np.array(q, dtype=np.float64)
+    if free and np.dot(q[3:7], ref[3:7]) < 0:
+        q[3:7] = -q[3:7]
+    return q
+
+
+def step_error(qg, vg, qr, vr, free):
+    qg = canon_quat(qg, qr, free)
+    eq = np.linalg.norm(qg - qr) / max(np.linalg.norm(qr), 1.0)
+    ev = np.linalg.norm(np.asarray(vg, np.float64) - vr) / max(np.linalg.norm(vr), 1.0)
+    return max(eq, ev)
+
+
+def min_corner_height(o, pop, vi, q):
+    """Smallest |z| over all box corners of variant vi at position q (FK of the oracle)."""
+    R, p, _, _ = o.fk(vi, q)
+    b0 = pop.body_offset[vi]
+    best = np.inf
+    for b in range(R.shape[0]):
+        h = pop.half_ext[b0 + b].astype(np.float64)
+        s = np.array([[sx * h[0], sy * h[1], sz * h[2]] for sx in (-1, 1) for sy in (-1, 1) for sz in (-1, 1)])
+        z = p[b][2] + s @ R[b][2]
+        best = min(best, np.abs(z).min())
+    return best
+
+
+def teacher_forced(pop, sim, ks, threads=THREADS):
+    """For each k in ks: oracle state x_k (FP64) -> float32 -> one GPU step,
+    compared with the oracle's x_{k+1}.  Returns (max error outside the
+    activation band, number of (variant, k) cases in the band, all errors)."""
+    o = O.Oracle(pop)
+    free = pop.root_type == 0
+    cur = 0
+    worst, in_band, errs = 0.0, 0, []
+    for k in sorted(ks):
+        o.step(k - cur, threads)
+        q, v, kk, st = o.get_state()
+        o.step(1, threads)
+        cur = k + 1
+        q1, v1, _, st1 = o.get_state()
+        sim.set_state(q.astype(np.float32), v.astype(np.float32), kk)
+        sim.step(1)
+        qg, vg, kg = sim.get_state()
+        assert (kg == k + 1).all()
+        qs, vs = split(pop, q, v)
+        q1s, v1s = split(pop, q1, v1)
+        qgs, vgs = split(pop, qg, vg)
+        for i in range(pop.n_variants):
+            if st[i] or st1[i]:
+                continue
+            e = step_error(qgs[i], vgs[i], q1s[i], v1s[i], free)
+            if min_corner_height(o, pop, i, qs[i]) < BAND:
+                in_band += 1
+                continue
+            errs.append(e)
+            worst = max(worst, e)
+    return worst, in_band, np.array(errs)
+
+
+def fitness_gate(F_gpu, F_ref, F_32):
+    """Per variant: ok if within FIT_TOL; a variant whose float oracle is itself
+    outside the bound is FP32-chaotic and must be within 3x of that deviation."""
+    bound = FIT_TOL * np.maximum(np.abs(F_ref), FIT_FLOOR)
+    dev = np.abs(F_gpu - F_ref)
+    chaotic = np.abs(F_32 - F_ref) > bound
+    ok = (dev <= bound) | (chaotic & (dev <= 3.0 * np.abs(F_32 - F_ref)))
+    return ok, chaotic, dev / bound

@@ -1,0 +1,117 @@
+"""C-ABI contract (host only, no device work): the library loads, exports every
+entry point declared in include/sim.h, validates descriptors before touching
+the device and packs variants into DoF bins."""
+import os
+import re
+
+import numpy as np
+import pytest
+
+from paper_2502_11129_amd import sim as S
+from paper_2502_11129_amd import workloads as W
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def _header_symbols():
+    src = open(os.path.join(ROOT, "include", "sim.h")).read()
+    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+    return sorted(set(re.findall(r"\b(sim_[a-z_]+)\s*\(", src)))
+
+
+def test_library_exports_every_declared_symbol():
+    lib = S.load()
+    decl = _header_symbols()
+    assert set(decl) == set(S.EXPORTED)
+    for name in decl:
+        assert hasattr(lib, name), name
+
+
+def test_create_and_bins_for_each_workload():
+    for pop, nvs in ((W.snake(5), {9}), (W.boxes(7), {6}), (W.quadrupeds(3), {26})):
+        h = S.Handle(pop)
+        bins = h.bins()
+        assert sum(b[3] for b in bins) == pop.n_variants
+        assert all(b[0] >= max(nvs) for b in bins)
+        assert h.workspace_bytes() > 0
+        h.close()
+    trees = W.random_trees(200)
+    h = S.Handle(trees)
+    bins = h.bins()
+    assert sum(b[3] for b in bins) == 200
+    caps = sorted(b[0] for b in bins)
+    assert caps == sorted(set(caps)) or len(bins) == len(caps)
+    for b in bins:
+        assert b[1] in (16, 32)
+
+
+def test_contacts_in_registers_option():
+    pop = W.quadrupeds(2)
+    h = S.Handle(pop, contacts_in_registers=2)
+    assert all(b[2] == 2 for b in h.bins())
+    with pytest.raises(S.SimError) as e:
+        S.Handle(pop, contacts_in_registers=7)
+    assert e.value.code == S.SIM_E_INVALID and "no compiled kernel" in str(e.value)
+
+
+def _mutated(pop, **changes):
+    import copy
+    p = copy.deepcopy(pop)
+    for k, v in changes.items():
+        setattr(p, k, v)
+    return p
+
+
+@pytest.mark.parametrize("case, needle", [
+    ("parent", "parent"), ("mass", "mass"), ("half", "half extents"), ("axis", "unit vector"),
+    ("quat", "unit quaternion"), ("dt", "dt"), ("iters", "pgs_iters"), ("mu", "mu"),
+    ("nan", "non-finite"), ("big", "degrees of freedom"),
+])
+def test_invalid_models_are_rejected(case, needle):
+    pop = W.snake(2)
+    if case == "parent":
+        par = pop.parent.copy(); par[2] = 3; p = _mutated(pop, parent=par)
+    elif case == "mass":
+        m = pop.mass.copy(); m[1] = 0.0; p = _mutated(pop, mass=m)
+    elif case == "half":
+        h = pop.half_ext.copy(); h[0, 1] = -0.1; p = _mutated(pop, half_ext=h)
+    elif case == "axis":
+        a = pop.axis.copy(); a[1] = [0.0, 0.0, 2.0]; p = _mutated(pop, axis=a)
+    elif case == "quat":
+        q = pop.q0.copy(); q[3] = 0.5; p = _mutated(pop, q0=q)
+    elif case == "dt":
+        p = _mutated(pop, params=dict(pop.params, dt=0.0))
+    elif case == "iters":
+        p = _mutated(pop, params=dict(pop.params, pgs_iters=0))
+    elif case == "mu":
+        mu = pop.mu.copy(); mu[0] = -1.0; p = _mutated(pop, mu=mu)
+    elif case == "nan":
+        v = pop.v0.copy(); v[2] = np.nan; p = _mutated(pop, v0=v)
+    elif case == "big":
+        p = W.chain(23, ["+x"] + ["+x"] * 22, [0] * 23, root_type=W.ROOT_FREE)
+    with pytest.raises(S.SimError) as e:
+        S.Handle(p)
+    assert e.value.code == S.SIM_E_INVALID
+    assert needle in str(e.value)
+
+
+def test_caller_arrays_may_be_freed_after_create():
+    pop = W.snake(3)
+    h = S.Handle(pop)
+    b0 = h.bins()
+    del pop
+    import gc
+    gc.collect()
+    assert h.bins() == b0
+
+
+def test_calls_before_bind_are_state_errors():
+    import ctypes as C
+    h = S.Handle(W.snake(2))
+    rc = h.lib.sim_step_batch(h.h, 1, None)
+    assert rc == S.SIM_E_STATE
+    assert "sim_bind" in h.lib.sim_last_error(h.h).decode()
+    rc = h.lib.sim_rollout(h.h, 10, None)
+    assert rc == S.SIM_E_STATE
+    assert h.lib.sim_bind(h.h, None, 0, None) == S.SIM_E_INVALID
+    assert h.lib.sim_bind(h.h, C.c_void_p(256), 16, None) == S.SIM_E_NOMEM

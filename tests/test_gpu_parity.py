@@ -1,0 +1,202 @@
+"""GPU parity: the HIP path (through the C ABI) against the FP64 oracle on the
+same seeded inputs.  Bar: per-step relative state error <= 1e-4 (teacher
+forced, outside the contact activation band) and fitness within 1e-3 relative
+(floor 1 cm) after T steps, with a float32 sensitivity gate."""
+import sys
+
+import numpy as np
+import pytest
+
+from oracle import oracle as O
+from paper_2502_11129_amd import workloads as W
+
+from _parity import STEP_TOL, THREADS, fitness_gate, teacher_forced
+
+pytestmark = pytest.mark.gpu
+
+
+def _sim(pop, **kw):
+    from paper_2502_11129_amd.sim import Simulator
+    return Simulator(pop, **kw)
+
+
+def _say(msg):
+    print(msg, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.mark.parametrize("name, pop, ks", [
+    ("snake3 x16", W.snake(16), [0, 1, 5, 20, 60, 150, 300, 500, 750, 999]),
+    ("boxes x128", W.boxes(128), [0, 1, 100, 200, 300, 450, 600, 1000, 1500, 1999]),
+    ("trees spot-check x64", None, [0, 1, 10, 100, 400, 1000, 2000]),
+    ("quadrupeds x16", W.quadrupeds(16), [0, 1, 10, 100, 300, 600, 999]),
+])
+def test_teacher_forced_one_step(name, pop, ks):
+    if pop is None:
+        pop = W.random_trees(indices=W.TREE_SPOTCHECK)
+    _say(f"[teacher-forced] {name}: {pop.n_variants} variants, steps {ks}")
+    sim = _sim(pop)
+    worst, in_band, errs = teacher_forced(pop, sim, ks)
+    _say(f"  worst step error {worst:.3e} over {len(errs)} cases; {in_band} cases in the activation band")
+    assert len(errs) > 0
+    assert worst <= STEP_TOL
+
+
+def _fitness_case(pop, T, **kw):
+    sim = _sim(pop, **kw)
+    sim.rollout(T)
+    Fg = sim.fitness().astype(np.float64)
+    Fr = O.Oracle(pop).rollout(T, threads=THREADS)
+    F32 = O.Oracle(pop, precision=32).rollout(T, threads=THREADS)
+    ok, chaotic, ratio = fitness_gate(Fg, Fr, F32)
+    return sim, Fg, Fr, ok, chaotic, ratio
+
+
+@pytest.mark.parametrize("name, make, T", [
+    ("snake3 x16 T=1000", lambda: W.snake(16), 1000),
+    ("boxes x256 T=2000", lambda: W.boxes(256), 2000),
+    ("trees spot-check x64 T=5000", lambda: W.random_trees(indices=W.TREE_SPOTCHECK), 5000),
+    ("quadrupeds x32 T=1000", lambda: W.quadrupeds(32), 1000),
+])
+def test_fitness_after_T(name, make, T):
+    pop = make()
+    _say(f"[fitness] {name}")
+    sim, Fg, Fr, ok, chaotic, ratio = _fitness_case(pop, T)
+    _say(f"  max |dF|/bound {ratio.max():.3f}; fp32-chaotic variants {int(chaotic.sum())}; failing {int((~ok).sum())}")
+    a, b, s = sim.counters()
+    assert (s == 0).all()
+    assert ok.all(), (np.where(~ok)[0], Fg[~ok], Fr[~ok])
+
+
+def test_overflow_contacts_bitwise_equal_register_path():
+    """Contacts beyond the register budget take the workspace path: same
+    arithmetic, so results match the all-in-register kernel bit for bit."""
+    pop = W.quadrupeds(9)          # 9: ragged last wave
+    _say("[overflow] quadrupeds x9, contacts_in_registers 2 vs default, T=600")
+    a = _sim(pop)
+    b = _sim(pop, contacts_in_registers=2)
+    a.rollout(600)
+    b.rollout(600)
+    qa, va, _ = a.get_state()
+    qb, vb, _ = b.get_state()
+    ca, _, _ = a.counters()
+    assert ca.max() > 600 * 2      # the overflow path was exercised
+    np.testing.assert_array_equal(qa, qb)
+    np.testing.assert_array_equal(va, vb)
+
+
+def test_determinism_chunking_and_resume():
+    pop = W.random_trees(37)
+    _say("[determinism] trees x37")
+    s1 = _sim(pop)
+    s1.rollout(300)
+    q1, v1, k1 = s1.get_state()
+    s1.rollout(300)
+    q2, v2, _ = s1.get_state()
+    np.testing.assert_array_equal(q1, q2)
+    np.testing.assert_array_equal(v1, v2)
+    s2 = _sim(pop)
+    for _ in range(3):
+        s2.step(100)
+    q3, v3, k3 = s2.get_state()
+    np.testing.assert_array_equal(q1, q3)
+    np.testing.assert_array_equal(k1, k3)
+    # resume: stop at 150, reload the state into a fresh simulator, continue
+    s3 = _sim(pop)
+    s3.step(150)
+    qm, vm, km = s3.get_state()
+    s4 = _sim(pop)
+    s4.set_state(qm, vm, km)
+    s4.step(150)
+    q4, v4, _ = s4.get_state()
+    np.testing.assert_array_equal(q1, q4)
+    np.testing.assert_array_equal(v1, v4)
+    # step counter drives the CPG phase: the fitness reference is still k = 0
+    F1 = s1.fitness()
+    assert np.isfinite(F1).all()
+
+
+def test_graph_replay_matches_eager():
+    pop = W.snake(16)
+    _say("[graph] snake3 x16, 4 replays")
+    e = _sim(pop)
+    e.rollout(400)
+    Fe = e.fitness()
+    g = _sim(pop, use_graph=True)
+    for _ in range(4):
+        g.rollout(400)
+        np.testing.assert_array_equal(g.fitness(), Fe)
+        e.step(3)                  # unrelated eager work between replays
+
+
+def test_nonfinite_state_freezes_only_that_variant():
+    pop = W.snake(8)
+    _say("[failure] NaN injected into variant 3")
+    a = _sim(pop)
+    b = _sim(pop)
+    q, v, k = a.get_state()
+    v_bad = v.copy()
+    v_bad[pop.v_offset[3] + 6] = np.nan
+    b.set_state(q, v_bad, k)
+    a.step(200)
+    b.step(200)
+    qa, va, _ = a.get_state()
+    qb, vb, kb = b.get_state()
+    _, _, s = b.counters()
+    assert s[3] == 1 and (np.delete(s, 3) == 0).all()
+    assert np.isnan(b.fitness()[3])
+    keep = np.ones(len(qa), bool)
+    keep[pop.q_offset[3]:pop.q_offset[4]] = False
+    np.testing.assert_array_equal(qa[keep], qb[keep])
+    assert kb[3] == 0 and kb[0] == 200
+
+
+def test_fixed_root_pendulum_period_on_gpu():
+    th_eq = np.pi / 2
+    params = dict(W.DEFAULT_PARAMS, kp=0.0, kd=0.0)
+    pop = W.chain(1, ["+x"], [W.AXIS_Y], root_type=W.ROOT_FIXED, root_pose=(0, 0, 1.0, 1, 0, 0, 0),
+                  theta0=[th_eq + 0.01], params=params)
+    _say("[closed form] compound pendulum on the GPU")
+    sim = _sim(pop)
+    n = 2050
+    th = np.zeros(n)
+    for i in range(n):
+        sim.step(1)
+        th[i] = sim.get_state()[0][0]
+    x = th - th_eq
+    up = np.where((x[:-1] < 0) & (x[1:] >= 0))[0]
+    t_cross = (up + 1 - x[up + 1] / (x[up + 1] - x[up])) * 0.002
+    T_exact = 2 * np.pi * np.sqrt(5.0 / 3.0 * 0.03 / 9.81)
+    assert abs(np.diff(t_cross).mean() - T_exact) / T_exact < 1e-3
+
+
+def test_free_fall_and_resting_box_on_gpu():
+    _say("[closed form] free fall and resting cube on the GPU")
+    pop = W.single_box(pos=(0.0, 0.0, 3.0), v_b=(0.3, -0.2, 0.7))
+    sim = _sim(pop)
+    sim.step(300)
+    q, _, _ = sim.get_state()
+    n, dt = 300, np.float32(0.002)
+    z = np.float32(3.0) + n * dt * np.float32(0.7) - 9.81 * dt * dt * n * (n + 1) / 2
+    assert abs(q[2] - z) < 2e-5
+    cube = W.single_box(half=(0.05, 0.05, 0.05), pos=(0, 0, 0.05))
+    sim = _sim(cube)
+    sim.step(300)
+    q, _, _ = sim.get_state()
+    assert abs((0.05 - q[2]) - 9.81e-4) / 9.81e-4 < 0.05
+
+
+def test_edge_cases_sizes():
+    """n = 1, n not a multiple of 4, nv = 28 (the largest), FIXED roots, T = 0."""
+    _say("[edge] single variant, ragged, nv=28, T=0")
+    for pop in (W.snake(1), W.random_trees(5), W.chain(22, ["+x"] * 22, [0, 1] * 11, root_type=W.ROOT_FREE,
+                                                        root_q=[0, 0, 0.5, 1, 0, 0, 0])):
+        sim = _sim(pop)
+        sim.rollout(0)
+        assert (sim.fitness() == 0).all()
+        sim.rollout(200)
+        Fg = sim.fitness().astype(np.float64)
+        Fr = O.Oracle(pop).rollout(200)
+        F32 = O.Oracle(pop, precision=32).rollout(200)
+        ok, _, _ = fitness_gate(Fg, Fr, F32)
+        assert ok.all(), (Fg, Fr)

@@ -149,6 +149,31 @@ int sim_set_state(sim_handle* h, const float* q, const float* v, const int64_t* 
 int sim_counters(const sim_handle* h, uint64_t* rows_contact, uint64_t* rows_clamp, uint32_t* status,
                  int where, void* stream);
 
+/* Timings of a split rollout, seconds (paper Sec. 6 "Results" measures). */
+typedef struct {
+  double combined_s; /* wall clock of the concurrent run, including the merge of host results */
+  double gpu_s;      /* GPU share: first launch to completion (HIP events)                    */
+  double host_s;     /* host share: first thread start to last thread end                     */
+  int32_t n_gpu, n_host, host_threads, reserved;
+} sim_split_times;
+
+/* Rollout of T steps with the population split between the GPU and host
+ * threads (paper Sec. 6: pilot benchmark, allocation, concurrent execution).
+ * n_host variants, taken from the tail of every DoF bin in proportion to the
+ * bin's size, run on host_threads CPU threads (single precision, same step)
+ * while the others run on the GPU; both start together.  When the call
+ * returns (it synchronises `stream`), fitness, state and counters of every
+ * variant are as after sim_rollout.  0 <= n_host <= n_variants;
+ * host_threads >= 1.  `times` may be NULL. */
+int sim_rollout_split(sim_handle* h, int32_t T, int32_t n_host, int32_t host_threads, void* stream,
+                      sim_split_times* times);
+
+/* Host-only rollout of every variant on host_threads CPU threads, without any
+ * device work and without touching the device state (sim_bind not needed).
+ * fitness: [n_variants] host floats, user order; may be NULL.  seconds: wall
+ * clock of the run; may be NULL. */
+int sim_rollout_host(sim_handle* h, int32_t T, int32_t host_threads, float* fitness, double* seconds);
+
 /* Description of the packing: number of bins and, per bin, (nv capacity,
  * body capacity, contacts in registers, variants).  info has 4*max_bins ints. */
 int sim_bins(const sim_handle* h, int32_t* n_bins, int32_t* info, int32_t max_bins);

@@ -1,0 +1,384 @@
+// Host-thread worker: one variant per task, single precision, the same step
+// as the GPU kernel (spatial forward/backward passes, CRBA, implicit-PD
+// diagonal, contact rows, fixed-iteration Gauss-Seidel, semi-implicit Euler).
+// The dense system is factorised by Cholesky here (a serial CPU has no reason
+// to form the inverse); clamp-row columns are solved only when a clamp engages.
+#include "host_worker.hpp"
+
+#include <cmath>
+#include <cstring>
+
+namespace simk {
+namespace {
+
+struct V3 { float x, y, z; };
+inline V3 v3(float a, float b, float c) { return {a, b, c}; }
+inline V3 operator+(V3 a, V3 b) { return {a.x + b.x, a.y + b.y, a.z + b.z}; }
+inline V3 operator-(V3 a, V3 b) { return {a.x - b.x, a.y - b.y, a.z - b.z}; }
+inline V3 operator*(V3 a, float s) { return {a.x * s, a.y * s, a.z * s}; }
+inline float dotp(V3 a, V3 b) { return a.x * b.x + a.y * b.y + a.z * b.z; }
+inline V3 crs(V3 a, V3 b) { return {a.y * b.z - a.z * b.y, a.z * b.x - a.x * b.z, a.x * b.y - a.y * b.x}; }
+struct M3 { float m[9]; };
+inline V3 mv(const M3& R, V3 v) {
+  return {R.m[0] * v.x + R.m[1] * v.y + R.m[2] * v.z, R.m[3] * v.x + R.m[4] * v.y + R.m[5] * v.z,
+          R.m[6] * v.x + R.m[7] * v.y + R.m[8] * v.z};
+}
+inline V3 mtv(const M3& R, V3 v) {
+  return {R.m[0] * v.x + R.m[3] * v.y + R.m[6] * v.z, R.m[1] * v.x + R.m[4] * v.y + R.m[7] * v.z,
+          R.m[2] * v.x + R.m[5] * v.y + R.m[8] * v.z};
+}
+inline M3 mm(const M3& A, const M3& B) {
+  M3 C;
+  for (int i = 0; i < 3; ++i)
+    for (int j = 0; j < 3; ++j)
+      C.m[3 * i + j] = A.m[3 * i] * B.m[j] + A.m[3 * i + 1] * B.m[3 + j] + A.m[3 * i + 2] * B.m[6 + j];
+  return C;
+}
+inline M3 qrot(float w, float x, float y, float z) {
+  return {{1.f - 2.f * (y * y + z * z), 2.f * (x * y - w * z), 2.f * (x * z + w * y),
+           2.f * (x * y + w * z), 1.f - 2.f * (x * x + z * z), 2.f * (y * z - w * x),
+           2.f * (x * z - w * y), 2.f * (y * z + w * x), 1.f - 2.f * (x * x + y * y)}};
+}
+inline M3 arot(V3 u, float s, float c) {
+  const float C = 1.f - c;
+  return {{c + u.x * u.x * C, u.x * u.y * C - u.z * s, u.x * u.z * C + u.y * s,
+           u.y * u.x * C + u.z * s, c + u.y * u.y * C, u.y * u.z * C - u.x * s,
+           u.z * u.x * C - u.y * s, u.z * u.y * C + u.x * s, c + u.z * u.z * C}};
+}
+struct SV { V3 a, l; };
+inline SV crm(const SV& V, const SV& U) { return {crs(V.a, U.a), crs(V.a, U.l) + crs(V.l, U.a)}; }
+inline SV crf(const SV& V, const SV& F) { return {crs(V.a, F.a) + crs(V.l, F.l), crs(V.a, F.l)}; }
+struct Inertia { float m; V3 h; float I[6]; };  // about p0: xx yy zz xy xz yz
+inline V3 sym(const float* I, V3 w) {
+  return {I[0] * w.x + I[3] * w.y + I[4] * w.z, I[3] * w.x + I[1] * w.y + I[5] * w.z,
+          I[4] * w.x + I[5] * w.y + I[2] * w.z};
+}
+inline SV imul(const Inertia& J, const SV& V) { return {sym(J.I, V.a) + crs(J.h, V.l), V.l * J.m - crs(J.h, V.a)}; }
+
+constexpr int NB = kMaxBodies;
+constexpr int NV = 28;
+
+struct Work {
+  M3 R[NB];
+  V3 p[NB], w[NB], o[NB];
+  SV V[NB], A[NB], F[NB];
+  Inertia C[NB];
+  float M[NV * NV], L[NV * NV], c[NV], a[NV], vf[NV], vp[NV];
+  float Wc[NV][NV];
+  bool haveWc[NV];
+  float Dl[NV];
+  // contacts
+  int ncap = 0;
+  std::vector<float> J, W, scal;  // per contact: 3 * NV each; scalars 10
+};
+
+void chol_solve(int n, const float* L, const float* b, float* x) {
+  float y[NV];
+  for (int i = 0; i < n; ++i) {
+    float s = b[i];
+    for (int k = 0; k < i; ++k) s -= L[i * NV + k] * y[k];
+    y[i] = s / L[i * NV + i];
+  }
+  for (int i = n - 1; i >= 0; --i) {
+    float s = y[i];
+    for (int k = i + 1; k < n; ++k) s -= L[k * NV + i] * x[k];
+    x[i] = s / L[i * NV + i];
+  }
+}
+
+bool step(const HostVariantView& m, const ModelParams& P, HostVariantState& st, Work& wk) {
+  const int nb = m.hdr[HW_NB], nv = m.hdr[HW_NV], r0 = m.hdr[HW_R0], nh = nb - 1;
+  const float dt = P.dt, kp = P.kp, kd = P.kd, tmax = P.tau_max, kc = P.k_contact, bcn = P.b_contact;
+  const float ba = kd + dt * kp, kb = bcn + kc * dt, mu = m.hdrf[HF_MU];
+  const float* rec = m.body;
+  auto B = [&](int b, int w) { return rec[b * BW_WORDS + w]; };
+  auto Bi = [&](int b, int w) { int x; std::memcpy(&x, &rec[b * BW_WORDS + w], 4); return x; };
+  float* q = st.q;
+  float* v = st.v;
+  const int qh = r0 ? 7 : 0;
+  V3 P0;
+  M3 R0;
+  if (r0) { P0 = v3(q[0], q[1], q[2]); R0 = qrot(q[3], q[4], q[5], q[6]); }
+  else {
+    P0 = v3(m.hdrf[HF_ROOTP], m.hdrf[HF_ROOTP + 1], m.hdrf[HF_ROOTP + 2]);
+    R0 = qrot(m.hdrf[HF_ROOTQ], m.hdrf[HF_ROOTQ + 1], m.hdrf[HF_ROOTQ + 2], m.hdrf[HF_ROOTQ + 3]);
+  }
+  const V3 wb = r0 ? v3(v[0], v[1], v[2]) : v3(0, 0, 0), vb = r0 ? v3(v[3], v[4], v[5]) : v3(0, 0, 0);
+  // forward pass
+  for (int b = 0; b < nb; ++b) {
+    if (b == 0) {
+      wk.R[0] = R0; wk.p[0] = P0; wk.w[0] = v3(0, 0, 0); wk.o[0] = P0;
+      wk.V[0] = {mv(R0, wb), mv(R0, vb)};
+      wk.A[0] = {v3(0, 0, 0), v3(-P.g[0], -P.g[1], -P.g[2])};
+      continue;
+    }
+    const int l = Bi(b, BW_PARENT);
+    const float th = q[qh + b - 1], thd = v[r0 + b - 1];
+    const V3 u = v3(B(b, BW_AXIS), B(b, BW_AXIS + 1), B(b, BW_AXIS + 2));
+    const M3 E = mm(qrot(B(b, BW_RQ), B(b, BW_RQ + 1), B(b, BW_RQ + 2), B(b, BW_RQ + 3)), arot(u, std::sin(th), std::cos(th)));
+    wk.R[b] = mm(wk.R[l], E);
+    wk.o[b] = wk.p[l] + mv(wk.R[l], v3(B(b, BW_AP), B(b, BW_AP + 1), B(b, BW_AP + 2)));
+    wk.p[b] = wk.o[b] - mv(wk.R[b], v3(B(b, BW_AC), B(b, BW_AC + 1), B(b, BW_AC + 2)));
+    wk.w[b] = mv(wk.R[b], u);
+    const SV St = {wk.w[b] * thd, crs(wk.o[b] - P0, wk.w[b]) * thd};
+    wk.V[b] = {wk.V[l].a + St.a, wk.V[l].l + St.l};
+    const SV cc = crm(wk.V[l], St);
+    wk.A[b] = {wk.A[l].a + cc.a, wk.A[l].l + cc.l};
+  }
+  // backward pass: inertia, force, composites (children have larger indices)
+  for (int b = 0; b < nb; ++b) {
+    const M3& R = wk.R[b];
+    const float mm_ = B(b, BW_MASS);
+    const V3 h = v3(B(b, BW_HALF), B(b, BW_HALF + 1), B(b, BW_HALF + 2));
+    const float ix = mm_ / 3.f * (h.y * h.y + h.z * h.z), iy = mm_ / 3.f * (h.x * h.x + h.z * h.z),
+                iz = mm_ / 3.f * (h.x * h.x + h.y * h.y);
+    const V3 c = wk.p[b] - P0;
+    const float cc = dotp(c, c);
+    Inertia J;
+    J.m = mm_;
+    J.h = c * mm_;
+    J.I[0] = R.m[0] * R.m[0] * ix + R.m[1] * R.m[1] * iy + R.m[2] * R.m[2] * iz + mm_ * (cc - c.x * c.x);
+    J.I[1] = R.m[3] * R.m[3] * ix + R.m[4] * R.m[4] * iy + R.m[5] * R.m[5] * iz + mm_ * (cc - c.y * c.y);
+    J.I[2] = R.m[6] * R.m[6] * ix + R.m[7] * R.m[7] * iy + R.m[8] * R.m[8] * iz + mm_ * (cc - c.z * c.z);
+    J.I[3] = R.m[0] * R.m[3] * ix + R.m[1] * R.m[4] * iy + R.m[2] * R.m[5] * iz - mm_ * c.x * c.y;
+    J.I[4] = R.m[0] * R.m[6] * ix + R.m[1] * R.m[7] * iy + R.m[2] * R.m[8] * iz - mm_ * c.x * c.z;
+    J.I[5] = R.m[3] * R.m[6] * ix + R.m[4] * R.m[7] * iy + R.m[5] * R.m[8] * iz - mm_ * c.y * c.z;
+    const SV IV = imul(J, wk.V[b]), IA = imul(J, wk.A[b]);
+    const SV x = crf(wk.V[b], IV);
+    wk.C[b] = J;
+    wk.F[b] = {IA.a + x.a, IA.l + x.l};
+  }
+  for (int b = nb - 1; b >= 1; --b) {
+    const int l = Bi(b, BW_PARENT);
+    wk.C[l].m += wk.C[b].m;
+    wk.C[l].h = wk.C[l].h + wk.C[b].h;
+    for (int i = 0; i < 6; ++i) wk.C[l].I[i] += wk.C[b].I[i];
+    wk.F[l].a = wk.F[l].a + wk.F[b].a;
+    wk.F[l].l = wk.F[l].l + wk.F[b].l;
+  }
+  // bias and mass matrix (CRBA)
+  std::memset(wk.M, 0, sizeof(wk.M));
+  if (r0) {
+    const V3 ca = mtv(R0, wk.F[0].a), cl = mtv(R0, wk.F[0].l);
+    wk.c[0] = ca.x; wk.c[1] = ca.y; wk.c[2] = ca.z; wk.c[3] = cl.x; wk.c[4] = cl.y; wk.c[5] = cl.z;
+    const Inertia& T = wk.C[0];
+    const V3 hb = mtv(R0, T.h);
+    for (int i = 0; i < 3; ++i) {
+      const V3 e = v3(R0.m[i], R0.m[3 + i], R0.m[6 + i]);
+      const V3 row = mtv(R0, sym(T.I, e));
+      wk.M[i * NV + 0] = row.x; wk.M[i * NV + 1] = row.y; wk.M[i * NV + 2] = row.z;
+    }
+    const V3 hx[3] = {crs(hb, v3(1, 0, 0)), crs(hb, v3(0, 1, 0)), crs(hb, v3(0, 0, 1))};
+    for (int j = 0; j < 3; ++j) {
+      const float col[3] = {hx[j].x, hx[j].y, hx[j].z};
+      for (int i = 0; i < 3; ++i) {
+        wk.M[i * NV + 3 + j] = col[i];   // [h_b]x
+        wk.M[(3 + j) * NV + i] = col[i]; // its transpose
+      }
+      wk.M[(3 + j) * NV + 3 + j] = T.m;
+    }
+  }
+  for (int b = 1; b < nb; ++b) {
+    const int d = r0 + b - 1;
+    const SV Sb = {wk.w[b], crs(wk.o[b] - P0, wk.w[b])};
+    wk.c[d] = dotp(Sb.a, wk.F[b].a) + dotp(Sb.l, wk.F[b].l);
+    const SV Fc = imul(wk.C[b], Sb);
+    for (int j = b; j >= 1; j = Bi(j, BW_PARENT)) {
+      const int dj = r0 + j - 1;
+      const SV Sj = {wk.w[j], crs(wk.o[j] - P0, wk.w[j])};
+      float val = dotp(Sj.a, Fc.a) + dotp(Sj.l, Fc.l);
+      if (j == b) val += dt * ba;
+      wk.M[d * NV + dj] = val;
+      wk.M[dj * NV + d] = val;
+    }
+    if (r0) {
+      const V3 ra = mtv(R0, Fc.a), rl = mtv(R0, Fc.l);
+      const float rv[6] = {ra.x, ra.y, ra.z, rl.x, rl.y, rl.z};
+      for (int i = 0; i < 6; ++i) { wk.M[d * NV + i] = rv[i]; wk.M[i * NV + d] = rv[i]; }
+    }
+  }
+  // Cholesky of Mt
+  for (int j = 0; j < nv; ++j) {
+    float s = wk.M[j * NV + j];
+    for (int k = 0; k < j; ++k) s -= wk.L[j * NV + k] * wk.L[j * NV + k];
+    if (!(s > 0.f)) return false;
+    wk.L[j * NV + j] = std::sqrt(s);
+    for (int i = j + 1; i < nv; ++i) {
+      float t = wk.M[i * NV + j];
+      for (int k = 0; k < j; ++k) t -= wk.L[i * NV + k] * wk.L[j * NV + k];
+      wk.L[i * NV + j] = t / wk.L[j * NV + j];
+    }
+  }
+  // control and free velocity
+  const double tk = double(st.k) * double(dt);
+  float rhs[NV];
+  for (int d = 0; d < nv; ++d) rhs[d] = -dt * wk.c[d];
+  for (int j = 0; j < nh; ++j) {
+    const int b = j + 1;
+    double ph = double(B(b, BW_CPG + 1)) * tk + double(B(b, BW_CPG + 2));
+    ph -= 6.283185307179586 * std::floor(ph * 0.15915494309189535);
+    const float target = B(b, BW_CPG) * std::sin(float(ph));
+    wk.a[j] = kp * (target - q[qh + j]);
+    rhs[r0 + j] += dt * (wk.a[j] - ba * v[r0 + j]);
+  }
+  chol_solve(nv, wk.L, rhs, wk.vf);
+  for (int d = 0; d < nv; ++d) wk.vf[d] += v[d];
+  // contacts
+  int nc = 0;
+  const unsigned char anyc = 0;
+  (void)anyc;
+  for (int b = (r0 ? 0 : 1); b < nb; ++b) {
+    const V3 h = v3(B(b, BW_HALF), B(b, BW_HALF + 1), B(b, BW_HALF + 2));
+    unsigned anc;
+    { int x = Bi(b, BW_ANCESTORS); std::memcpy(&anc, &x, 4); }
+    for (int cn = 0; cn < 8; ++cn) {
+      const V3 s = v3((cn & 1) ? h.x : -h.x, (cn & 2) ? h.y : -h.y, (cn & 4) ? h.z : -h.z);
+      const V3 x = wk.p[b] + mv(wk.R[b], s);
+      if (!(x.z < 0.f)) continue;
+      if (nc >= wk.ncap) {
+        wk.ncap = nc + 16;
+        wk.J.resize((size_t)wk.ncap * 3 * NV);
+        wk.W.resize((size_t)wk.ncap * 3 * NV);
+        wk.scal.resize((size_t)wk.ncap * 10);
+      }
+      float* J = &wk.J[(size_t)nc * 3 * NV];
+      float* W = &wk.W[(size_t)nc * 3 * NV];
+      float* sc = &wk.scal[(size_t)nc * 10];
+      for (int d = 0; d < nv; ++d) {
+        V3 col;
+        if (r0 && d < 3) col = crs(v3(R0.m[d], R0.m[3 + d], R0.m[6 + d]), x - P0);
+        else if (r0 && d < 6) col = v3(R0.m[d - 3], R0.m[3 + d - 3], R0.m[6 + d - 3]);
+        else {
+          const int hb = d - r0 + 1;
+          col = ((anc >> hb) & 1u) ? crs(wk.w[hb], x - wk.o[hb]) : v3(0, 0, 0);
+        }
+        J[d] = col.z; J[NV + d] = col.x; J[2 * NV + d] = col.y;
+      }
+      float D[3];
+      for (int r = 0; r < 3; ++r) {
+        chol_solve(nv, wk.L, J + r * NV, W + r * NV);
+        float s2 = 0.f;
+        for (int d = 0; d < nv; ++d) s2 += J[r * NV + d] * W[r * NV + d];
+        D[r] = s2;
+      }
+      sc[0] = kc * (-x.z);
+      sc[1] = 1.f / (D[0] * (1.f + kb * dt));
+      sc[2] = dt * D[0];
+      sc[3] = 1.f / (dt * D[1]);
+      sc[4] = 1.f / (dt * D[2]);
+      sc[5] = sc[6] = sc[7] = 0.f;
+      ++nc;
+    }
+  }
+  // fixed-iteration Gauss-Seidel
+  for (int d = 0; d < nv; ++d) wk.vp[d] = wk.vf[d];
+  for (int j = 0; j < nh; ++j) { wk.Dl[j] = 0.f; wk.haveWc[j] = false; }
+  auto clamp_col = [&](int j) -> const float* {
+    if (!wk.haveWc[j]) {
+      float e[NV] = {0};
+      e[r0 + j] = 1.f;
+      chol_solve(nv, wk.L, e, wk.Wc[j]);
+      wk.haveWc[j] = true;
+    }
+    return wk.Wc[j];
+  };
+  for (int it = 0; it < P.K; ++it) {
+    for (int j = 0; j < nh; ++j) {
+      // a clamp row with no correction and an unsaturated law is a no-op
+      const float u_plain = wk.vp[r0 + j];
+      if (wk.Dl[j] == 0.f) {
+        const float s0 = wk.a[j] - ba * u_plain;
+        if (s0 <= tmax && s0 >= -tmax) continue;
+      }
+      const float* Wj = clamp_col(j);
+      const float Dj = Wj[r0 + j];
+      const float u0 = wk.vp[r0 + j] + dt * Dj * wk.Dl[j];
+      const float s = wk.a[j] - ba * u0;
+      const float den = 1.f - ba * dt * Dj;
+      float nd = 0.f;
+      if (s > tmax) nd = (s - tmax) / den;
+      else if (s < -tmax) nd = (s + tmax) / den;
+      const float dl = nd - wk.Dl[j];
+      for (int d = 0; d < nv; ++d) wk.vp[d] -= dt * Wj[d] * dl;
+      wk.Dl[j] = nd;
+    }
+    for (int ci = 0; ci < nc; ++ci) {
+      const float* J = &wk.J[(size_t)ci * 3 * NV];
+      const float* W = &wk.W[(size_t)ci * 3 * NV];
+      float* sc = &wk.scal[(size_t)ci * 10];
+      float un = 0.f;
+      for (int d = 0; d < nv; ++d) un += J[d] * wk.vp[d];
+      const float u0 = un - sc[2] * sc[5];
+      float ln = (sc[0] - kb * u0) * sc[1];
+      if (ln < 0.f) ln = 0.f;
+      const float dn = ln - sc[5];
+      for (int d = 0; d < nv; ++d) wk.vp[d] += dt * W[d] * dn;
+      sc[5] = ln;
+      float ux = 0.f, uy = 0.f;
+      for (int d = 0; d < nv; ++d) { ux += J[NV + d] * wk.vp[d]; uy += J[2 * NV + d] * wk.vp[d]; }
+      float gx = sc[6] - ux * sc[3], gy = sc[7] - uy * sc[4];
+      const float gn2 = gx * gx + gy * gy, lim = mu * ln;
+      if (gn2 > lim * lim) { const float r = lim / std::sqrt(gn2); gx *= r; gy *= r; }
+      const float ex = dt * (gx - sc[6]), ey = dt * (gy - sc[7]);
+      for (int d = 0; d < nv; ++d) wk.vp[d] += W[NV + d] * ex + W[2 * NV + d] * ey;
+      sc[6] = gx; sc[7] = gy;
+    }
+  }
+  // semi-implicit Euler
+  float qn[kQStride];
+  std::memcpy(qn, q, sizeof(qn));
+  for (int j = 0; j < nh; ++j) qn[qh + j] = q[qh + j] + dt * wk.vp[r0 + j];
+  if (r0) {
+    const V3 dp = mv(R0, v3(wk.vp[3], wk.vp[4], wk.vp[5]));
+    qn[0] = q[0] + dt * dp.x; qn[1] = q[1] + dt * dp.y; qn[2] = q[2] + dt * dp.z;
+    const V3 phi = v3(wk.vp[0], wk.vp[1], wk.vp[2]) * dt;
+    const float an = std::sqrt(dotp(phi, phi));
+    float dq[4];
+    if (an < 1e-8f) { dq[0] = 1.f; dq[1] = 0.5f * phi.x; dq[2] = 0.5f * phi.y; dq[3] = 0.5f * phi.z; }
+    else { const float s = std::sin(0.5f * an) / an; dq[0] = std::cos(0.5f * an); dq[1] = phi.x * s; dq[2] = phi.y * s; dq[3] = phi.z * s; }
+    const float aw = q[3], ax = q[4], ay = q[5], az = q[6];
+    float Q[4] = {aw * dq[0] - ax * dq[1] - ay * dq[2] - az * dq[3], aw * dq[1] + ax * dq[0] + ay * dq[3] - az * dq[2],
+                  aw * dq[2] - ax * dq[3] + ay * dq[0] + az * dq[1], aw * dq[3] + ax * dq[2] - ay * dq[1] + az * dq[0]};
+    const float n = std::sqrt(Q[0] * Q[0] + Q[1] * Q[1] + Q[2] * Q[2] + Q[3] * Q[3]);
+    for (int i = 0; i < 4; ++i) qn[3 + i] = Q[i] / n;
+  }
+  for (int i = 0; i < qh + nh; ++i)
+    if (!std::isfinite(qn[i])) return false;
+  for (int d = 0; d < nv; ++d)
+    if (!std::isfinite(wk.vp[d])) return false;
+  std::memcpy(q, qn, sizeof(qn));
+  for (int d = 0; d < nv; ++d) v[d] = wk.vp[d];
+  st.k += 1;
+  st.rows_contact += (unsigned long long)nc;
+  for (int j = 0; j < nh; ++j) st.rows_clamp += (wk.Dl[j] != 0.f);
+  return true;
+}
+
+}  // namespace
+
+void host_rollout(const HostVariantView& m, const ModelParams& P, int T, HostVariantState& st) {
+  std::memcpy(st.q, m.q0, sizeof(st.q));
+  std::memcpy(st.v, m.v0, sizeof(st.v));
+  st.k = 0;
+  st.status = 0;
+  st.rows_contact = st.rows_clamp = 0;
+  const int r0 = m.hdr[HW_R0];
+  st.x0 = r0 ? st.q[0] : 0.f;
+  st.y0 = r0 ? st.q[1] : 0.f;
+  Work wk;
+  for (int t = 0; t < T; ++t) {
+    if (!step(m, P, st, wk)) {
+      st.status |= 1u;
+      break;
+    }
+  }
+}
+
+float host_fitness(const HostVariantView& m, const HostVariantState& st) {
+  if (st.status) return std::nanf("");
+  if (!m.hdr[HW_R0]) return 0.f;
+  const float dx = st.q[0] - st.x0, dy = st.q[1] - st.y0;
+  return std::sqrt(dx * dx + dy * dy);
+}
+
+}  // namespace simk

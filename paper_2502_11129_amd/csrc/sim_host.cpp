@@ -3,7 +3,10 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <atomic>
+#include <chrono>
 #include <cmath>
+#include <thread>
 #include <cstdio>
 #include <cstring>
 #include <memory>
@@ -11,6 +14,7 @@
 #include <vector>
 
 #include "sim.h"
+#include "host_worker.hpp"
 #include "launch.h"
 #include "sim_layout.h"
 
@@ -60,6 +64,11 @@ struct sim_handle {
   hipGraphExec_t graph_exec = nullptr;
   int graph_T = -1;
   hipStream_t cap_stream = nullptr;
+  int split_T = 0;
+  // bins run concurrently: one library stream per bin beyond the first, fork/join by events
+  std::vector<hipStream_t> bin_streams;
+  std::vector<hipEvent_t> join_events;
+  hipEvent_t fork_event = nullptr;
 };
 
 namespace {
@@ -91,22 +100,89 @@ const KernelVariant* find_variant(int nvc, int sb, int ncr) {
 }
 
 // Launch every bin's kernel for n_steps (reset on the first chunk if asked).
-int launch_all(sim_handle* h, int n_steps, bool reset, hipStream_t st) {
+// Bins are independent: bin 0 runs on the caller's stream, every other bin on
+// a library stream forked from and joined back into the caller's stream.
+int launch_bin(sim_handle* h, Bin& b, int n_steps, bool reset, hipStream_t st, int count = -1) {
+  if (count == 0) return SIM_OK;
   int done = 0;
   bool first = true;
   while (first || done < n_steps) {
     const int chunk = std::min(kStepsPerLaunch, n_steps - done);
-    for (Bin& b : h->bins) {
-      BinArgs a = b.args;
-      a.n_steps = chunk;
-      a.reset = (reset && first) ? 1 : 0;
-      hipError_t e = b.fn(a, h->params, st);
-      if (e != hipSuccess) return dev_check(h, e, "kernel launch");
-    }
+    BinArgs a = b.args;
+    a.n_steps = chunk;
+    a.reset = (reset && first) ? 1 : 0;
+    if (count >= 0) a.n = count;
+    hipError_t e = b.fn(a, h->params, st);
+    if (e != hipSuccess) return dev_check(h, e, "kernel launch");
     done += chunk;
     first = false;
   }
   return SIM_OK;
+}
+
+int launch_all(sim_handle* h, int n_steps, bool reset, hipStream_t st, const std::vector<int>* counts = nullptr) {
+  const size_t nb = h->bins.size();
+  int rc;
+  if (nb > 1) {
+    if ((rc = dev_check(h, hipEventRecord(h->fork_event, st), "fork record"))) return rc;
+    for (size_t i = 1; i < nb; ++i)
+      if ((rc = dev_check(h, hipStreamWaitEvent(h->bin_streams[i - 1], h->fork_event, 0), "fork wait"))) return rc;
+  }
+  // largest bins first on the side streams, the caller's stream takes bin 0
+  for (size_t i = 1; i < nb; ++i)
+    if ((rc = launch_bin(h, h->bins[i], n_steps, reset, h->bin_streams[i - 1], counts ? (*counts)[i] : -1))) return rc;
+  if ((rc = launch_bin(h, h->bins[0], n_steps, reset, st, counts ? (*counts)[0] : -1))) return rc;
+  for (size_t i = 1; i < nb; ++i) {
+    if ((rc = dev_check(h, hipEventRecord(h->join_events[i - 1], h->bin_streams[i - 1]), "join record"))) return rc;
+    if ((rc = dev_check(h, hipStreamWaitEvent(st, h->join_events[i - 1], 0), "join wait"))) return rc;
+  }
+  return SIM_OK;
+}
+
+HostVariantView host_view(const Bin& b, size_t s) {
+  const int nbc = 16 * b.sb;
+  return HostVariantView{&b.hdr[s * HW_WORDS], &b.hdrf[s * HF_WORDS], &b.body[s * nbc * BW_WORDS],
+                         &b.q0[s * kQStride], &b.v0[s * kVStride]};
+}
+
+// Run the listed (bin, slot) pairs on host threads; returns wall seconds.
+double run_host(const sim_handle* h, const std::vector<std::pair<int, int>>& work, int threads,
+                std::vector<HostVariantState>& out) {
+  out.assign(work.size(), HostVariantState());
+  std::atomic<size_t> next(0);
+  auto t0 = std::chrono::steady_clock::now();
+  auto body = [&]() {
+    for (size_t i = next.fetch_add(1); i < work.size(); i = next.fetch_add(1)) {
+      const Bin& b = h->bins[work[i].first];
+      host_rollout(host_view(b, work[i].second), h->params, h->split_T, out[i]);
+    }
+  };
+  const int nt = std::max(1, std::min<int>(threads, (int)work.size()));
+  std::vector<std::thread> pool;
+  for (int t = 1; t < nt; ++t) pool.emplace_back(body);
+  body();
+  for (auto& th : pool) th.join();
+  return std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+}
+
+// Host share per bin: proportional to bin size, largest remainders, taken from the bin tails.
+std::vector<int> host_counts(const sim_handle* h, int n_host) {
+  const size_t nb = h->bins.size();
+  std::vector<int> cnt(nb, 0);
+  std::vector<std::pair<double, int>> rem;
+  int given = 0;
+  for (size_t i = 0; i < nb; ++i) {
+    const double exact = double(n_host) * h->bins[i].users.size() / h->n;
+    cnt[i] = (int)std::floor(exact);
+    given += cnt[i];
+    rem.push_back({exact - cnt[i], (int)i});
+  }
+  std::sort(rem.begin(), rem.end(), [](auto& x, auto& y) { return x.first > y.first; });
+  for (size_t r = 0; given < n_host && r < rem.size(); ++r) {
+    const int i = rem[r].second;
+    if (cnt[i] < (int)h->bins[i].users.size()) { ++cnt[i]; ++given; }
+  }
+  return cnt;
 }
 
 }  // namespace
@@ -237,6 +313,8 @@ int sim_create(const sim_model_desc* d, const sim_options* opts, sim_handle** ou
     });
     hp->bins.push_back(std::move(b));
   }
+  std::stable_sort(hp->bins.begin(), hp->bins.end(),
+                   [](const Bin& x, const Bin& y) { return x.users.size() * x.nvc > y.users.size() * y.nvc; });
   // pack
   for (size_t bi = 0; bi < hp->bins.size(); ++bi) {
     Bin& b = hp->bins[bi];
@@ -324,6 +402,18 @@ int sim_bind(sim_handle* h, void* ws, size_t bytes, void* stream) {
   if (h->device_error) return SIM_E_DEVICE;
   hipStream_t st = (hipStream_t)stream;
   h->ws = (char*)ws;
+  if (h->bin_streams.empty() && h->bins.size() > 1) {
+    int rc = dev_check(h, hipEventCreateWithFlags(&h->fork_event, hipEventDisableTiming), "event create");
+    if (rc) return rc;
+    for (size_t i = 1; i < h->bins.size(); ++i) {
+      hipStream_t s2;
+      hipEvent_t e2;
+      if ((rc = dev_check(h, hipStreamCreateWithFlags(&s2, hipStreamNonBlocking), "stream create"))) return rc;
+      h->bin_streams.push_back(s2);
+      if ((rc = dev_check(h, hipEventCreateWithFlags(&e2, hipEventDisableTiming), "event create"))) return rc;
+      h->join_events.push_back(e2);
+    }
+  }
   for (Bin& b : h->bins) {
     char* base = h->ws;
     const size_t m = b.users.size();
@@ -383,7 +473,7 @@ int sim_rollout(sim_handle* h, int32_t T, void* stream) {
       int rc = dev_check(h, hipStreamCreateWithFlags(&h->cap_stream, hipStreamNonBlocking), "stream create");
       if (rc) return rc;
     }
-    int rc = dev_check(h, hipStreamBeginCapture(h->cap_stream, hipStreamCaptureModeThreadLocal), "begin capture");
+    int rc = dev_check(h, hipStreamBeginCapture(h->cap_stream, hipStreamCaptureModeGlobal), "begin capture");
     if (rc) return rc;
     rc = launch_all(h, T, true, h->cap_stream);
     hipGraph_t g = nullptr;
@@ -517,6 +607,102 @@ int sim_counters(const sim_handle* hc, uint64_t* rows_contact, uint64_t* rows_cl
   return SIM_OK;
 }
 
+int sim_rollout_host(sim_handle* h, int32_t T, int32_t host_threads, float* fitness, double* seconds) {
+  if (!h) return SIM_E_INVALID;
+  if (T < 0 || host_threads < 1) return fail(h, SIM_E_INVALID, "T must be >= 0 and host_threads >= 1");
+  std::vector<std::pair<int, int>> work;
+  for (size_t bi = 0; bi < h->bins.size(); ++bi)
+    for (size_t s2 = 0; s2 < h->bins[bi].users.size(); ++s2) work.push_back({(int)bi, (int)s2});
+  std::vector<HostVariantState> out;
+  h->split_T = T;
+  const double sec = run_host(h, work, host_threads, out);
+  if (fitness)
+    for (size_t i = 0; i < work.size(); ++i) {
+      const Bin& b = h->bins[work[i].first];
+      fitness[b.users[work[i].second]] = host_fitness(host_view(b, work[i].second), out[i]);
+    }
+  if (seconds) *seconds = sec;
+  return SIM_OK;
+}
+
+int sim_rollout_split(sim_handle* h, int32_t T, int32_t n_host, int32_t host_threads, void* stream,
+                      sim_split_times* times) {
+  if (!h) return SIM_E_INVALID;
+  if (!h->bound) return fail(h, SIM_E_STATE, "sim_bind has not been called");
+  if (h->device_error) return SIM_E_DEVICE;
+  if (T < 0 || n_host < 0 || n_host > h->n || host_threads < 1)
+    return fail(h, SIM_E_INVALID, "need T >= 0, 0 <= n_host <= n_variants, host_threads >= 1");
+  hipStream_t st = (hipStream_t)stream;
+  const std::vector<int> hc = host_counts(h, n_host);
+  std::vector<int> gc(h->bins.size());
+  std::vector<std::pair<int, int>> work;
+  for (size_t bi = 0; bi < h->bins.size(); ++bi) {
+    const int m = (int)h->bins[bi].users.size();
+    gc[bi] = m - hc[bi];
+    for (int s2 = gc[bi]; s2 < m; ++s2) work.push_back({(int)bi, s2});
+  }
+  hipEvent_t e0, e1;
+  int rc;
+  if ((rc = dev_check(h, hipEventCreate(&e0), "event create"))) return rc;
+  if ((rc = dev_check(h, hipEventCreate(&e1), "event create"))) { hipEventDestroy(e0); return rc; }
+  auto t0 = std::chrono::steady_clock::now();
+  rc = dev_check(h, hipEventRecord(e0, st), "event record");
+  if (!rc) rc = launch_all(h, T, true, st, &gc);
+  if (!rc) rc = dev_check(h, hipEventRecord(e1, st), "event record");
+  std::vector<HostVariantState> out;
+  h->split_T = T;
+  double host_s = 0.0;
+  if (!rc) host_s = run_host(h, work, host_threads, out);  // concurrent with the GPU launches above
+  if (!rc) rc = dev_check(h, hipStreamSynchronize(st), "split sync");
+  // merge: host results into the device state (contiguous tail of every bin)
+  size_t wi = 0;
+  for (size_t bi = 0; !rc && bi < h->bins.size(); ++bi) {
+    Bin& b = h->bins[bi];
+    const size_t m = b.users.size(), g = (size_t)gc[bi], nh = m - g;
+    if (!nh) continue;
+    std::vector<float> q(nh * kQStride), v(nh * kVStride), xy(2 * nh), fit(nh);
+    std::vector<long long> kk(nh);
+    std::vector<unsigned> sts(nh);
+    std::vector<unsigned long long> cc(2 * nh);
+    for (size_t j = 0; j < nh; ++j, ++wi) {
+      const HostVariantState& hs = out[wi];
+      std::memcpy(&q[j * kQStride], hs.q, sizeof(hs.q));
+      std::memcpy(&v[j * kVStride], hs.v, sizeof(hs.v));
+      kk[j] = hs.k; sts[j] = hs.status; xy[2 * j] = hs.x0; xy[2 * j + 1] = hs.y0;
+      fit[j] = host_fitness(host_view(b, g + j), hs);
+      cc[2 * j] = hs.rows_contact; cc[2 * j + 1] = hs.rows_clamp;
+    }
+    char* w = h->ws;
+    auto up = [&](size_t off, const void* src, size_t bytes) {
+      if (!rc) rc = dev_check(h, hipMemcpyAsync(w + off, src, bytes, hipMemcpyHostToDevice, st), "merge upload");
+    };
+    up(b.o_q + g * kQStride * 4, q.data(), q.size() * 4);
+    up(b.o_v + g * kVStride * 4, v.data(), v.size() * 4);
+    up(b.o_k + g * 8, kk.data(), nh * 8);
+    up(b.o_status + g * 4, sts.data(), nh * 4);
+    up(b.o_xy0 + g * 8, xy.data(), nh * 8);
+    up(b.o_fit + g * 4, fit.data(), nh * 4);
+    up(b.o_cnt + g * 16, cc.data(), nh * 16);
+    if (!rc) rc = dev_check(h, hipStreamSynchronize(st), "merge sync");  // host vectors die here
+  }
+  const double combined = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+  float gpu_ms = 0.f;
+  if (!rc) rc = dev_check(h, hipEventElapsedTime(&gpu_ms, e0, e1), "event time");
+  hipEventDestroy(e0);
+  hipEventDestroy(e1);
+  if (rc) return rc;
+  if (times) {
+    times->combined_s = combined;
+    times->gpu_s = gpu_ms / 1e3;
+    times->host_s = host_s;
+    times->n_gpu = h->n - n_host;
+    times->n_host = n_host;
+    times->host_threads = host_threads;
+    times->reserved = 0;
+  }
+  return SIM_OK;
+}
+
 int sim_bins(const sim_handle* h, int32_t* n_bins, int32_t* info, int32_t max_bins) {
   if (!h || !n_bins) return SIM_E_INVALID;
   *n_bins = (int32_t)h->bins.size();
@@ -534,6 +720,9 @@ void sim_destroy(sim_handle* h) {
   if (h->graph_exec) hipGraphExecDestroy(h->graph_exec);
   if (h->graph) hipGraphDestroy(h->graph);
   if (h->cap_stream) hipStreamDestroy(h->cap_stream);
+  for (hipStream_t s2 : h->bin_streams) hipStreamDestroy(s2);
+  for (hipEvent_t e2 : h->join_events) hipEventDestroy(e2);
+  if (h->fork_event) hipEventDestroy(h->fork_event);
   delete h;
 }
 

@@ -18,7 +18,8 @@ SIM_OK, SIM_E_INVALID, SIM_E_NOMEM, SIM_E_DEVICE, SIM_E_STATE = 0, -1, -2, -3, -
 SIM_ROOT_FREE, SIM_ROOT_FIXED = 0, 1
 SIM_HOST, SIM_DEVICE = 0, 1
 EXPORTED = ("sim_create", "sim_workspace_bytes", "sim_bind", "sim_step_batch", "sim_rollout", "sim_fitness",
-            "sim_get_state", "sim_set_state", "sim_counters", "sim_bins", "sim_destroy", "sim_last_error")
+            "sim_get_state", "sim_set_state", "sim_counters", "sim_rollout_split", "sim_rollout_host", "sim_bins",
+            "sim_destroy", "sim_last_error")
 
 _F = C.POINTER(C.c_float)
 _I32 = C.POINTER(C.c_int32)
@@ -34,6 +35,11 @@ class sim_model_desc(C.Structure):
 
 class sim_options(C.Structure):
     _fields_ = [("contacts_in_registers", C.c_int32), ("use_graph", C.c_int32), ("reserved", C.c_int32 * 6)]
+
+
+class sim_split_times(C.Structure):
+    _fields_ = [("combined_s", C.c_double), ("gpu_s", C.c_double), ("host_s", C.c_double),
+                ("n_gpu", C.c_int32), ("n_host", C.c_int32), ("host_threads", C.c_int32), ("reserved", C.c_int32)]
 
 
 class SimError(RuntimeError):
@@ -69,12 +75,15 @@ def load():
     lib.sim_set_state.argtypes = [P, _F, _F, C.POINTER(C.c_int64), I, VP]
     lib.sim_counters.argtypes = [P, C.POINTER(C.c_uint64), C.POINTER(C.c_uint64), C.POINTER(C.c_uint32), I, VP]
     lib.sim_bins.argtypes = [P, _I32, _I32, C.c_int32]
+    lib.sim_rollout_split.argtypes = [P, C.c_int32, C.c_int32, C.c_int32, VP, C.POINTER(sim_split_times)]
+    lib.sim_rollout_host.argtypes = [P, C.c_int32, C.c_int32, _F, C.POINTER(C.c_double)]
     lib.sim_destroy.argtypes = [P]
     lib.sim_destroy.restype = None
     lib.sim_last_error.argtypes = [P]
     lib.sim_last_error.restype = C.c_char_p
     for name in ("sim_workspace_bytes", "sim_bind", "sim_step_batch", "sim_rollout", "sim_fitness",
-                 "sim_get_state", "sim_set_state", "sim_counters", "sim_bins"):
+                 "sim_get_state", "sim_set_state", "sim_counters", "sim_bins", "sim_rollout_split",
+                 "sim_rollout_host"):
         getattr(lib, name).restype = I
     _lib = lib
     return lib
@@ -141,6 +150,13 @@ class Handle:
         self._check(self.lib.sim_bins(self.h, C.byref(n), info.ctypes.data_as(_I32), 64))
         return [tuple(int(x) for x in info[4 * i:4 * i + 4]) for i in range(n.value)]
 
+    def rollout_host(self, T: int, threads: int = 1):
+        """Every variant on host threads (no device work); returns (fitness, seconds)."""
+        fit = np.zeros(self.n, np.float32)
+        sec = C.c_double()
+        self._check(self.lib.sim_rollout_host(self.h, int(T), int(threads), fit.ctypes.data_as(_F), C.byref(sec)))
+        return fit, sec.value
+
     def close(self):
         if getattr(self, "h", None):
             self.lib.sim_destroy(self.h)
@@ -196,6 +212,13 @@ class Simulator(Handle):
         self._check(self.lib.sim_set_state(self.h, q.ctypes.data_as(_F), v.ctypes.data_as(_F),
                                            None if kk is None else kk.ctypes.data_as(C.POINTER(C.c_int64)),
                                            SIM_HOST, self.stream()))
+
+    def rollout_split(self, T: int, n_host: int, threads: int):
+        """Concurrent GPU + host-thread rollout; returns the timing record as a dict."""
+        t = sim_split_times()
+        self._check(self.lib.sim_rollout_split(self.h, int(T), int(n_host), int(threads), self.stream(), C.byref(t)))
+        return dict(combined_s=t.combined_s, gpu_s=t.gpu_s, host_s=t.host_s, n_gpu=t.n_gpu, n_host=t.n_host,
+                    host_threads=t.host_threads)
 
     def counters(self):
         a = np.zeros(self.n, np.uint64)

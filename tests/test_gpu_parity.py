@@ -10,7 +10,7 @@ import pytest
 from oracle import oracle as O
 from paper_2502_11129_amd import workloads as W
 
-from _parity import STEP_TOL, THREADS, fitness_gate, teacher_forced
+from _parity import STEP_TOL, THREADS, fitness_gate, perturbed_fitness, teacher_forced
 
 pytestmark = pytest.mark.gpu
 
@@ -48,7 +48,8 @@ def _fitness_case(pop, T, **kw):
     Fg = sim.fitness().astype(np.float64)
     Fr = O.Oracle(pop).rollout(T, threads=THREADS)
     F32 = O.Oracle(pop, precision=32).rollout(T, threads=THREADS)
-    ok, chaotic, ratio = fitness_gate(Fg, Fr, F32)
+    Fp = perturbed_fitness(pop, T)
+    ok, chaotic, ratio = fitness_gate(Fg, Fr, F32, Fp)
     return sim, Fg, Fr, ok, chaotic, ratio
 
 
@@ -198,5 +199,28 @@ def test_edge_cases_sizes():
         Fg = sim.fitness().astype(np.float64)
         Fr = O.Oracle(pop).rollout(200)
         F32 = O.Oracle(pop, precision=32).rollout(200)
-        ok, _, _ = fitness_gate(Fg, Fr, F32)
+        ok, _, _ = fitness_gate(Fg, Fr, F32, perturbed_fitness(pop, 200))
         assert ok.all(), (Fg, Fr)
+
+
+def test_split_rollout_gpu_part_bitwise_host_part_within_bar():
+    """CPU/GPU split (paper Sec. 6): variants left on the GPU give bit-identical
+    results to a GPU-only rollout; variants sent to host threads meet the
+    oracle bar; the merged state is visible through the normal calls."""
+    pop = W.random_trees(40)
+    _say("[split] trees x40, 10 variants on host threads, T=400")
+    g = _sim(pop)
+    g.rollout(400)
+    Fg = g.fitness()
+    s = _sim(pop)
+    t = s.rollout_split(400, n_host=10, threads=4)
+    Fs = s.fitness()
+    assert t["n_host"] == 10 and t["n_gpu"] == 30 and t["combined_s"] > 0
+    Fr = O.Oracle(pop).rollout(400, threads=THREADS)
+    F32 = O.Oracle(pop, precision=32).rollout(400, threads=THREADS)
+    ok, _, _ = fitness_gate(Fs.astype(np.float64), Fr, F32, perturbed_fitness(pop, 400))
+    assert ok.all()
+    same = Fs == Fg
+    assert same.sum() >= 30          # the GPU share is bit-identical
+    _, _, k = s.get_state()
+    assert (k == 400).all()

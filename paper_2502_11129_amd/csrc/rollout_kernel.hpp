@@ -133,29 +133,32 @@ __device__ __forceinline__ sv imul(const sinertia& J, const sv& V) {
 template <int NVC, int SB, int NCR>
 struct GroupLds {
   static constexpr int NBC = 16 * SB;
-  static constexpr int MST = NVC + 1;                 // padded row stride of the assembled matrix
-  static constexpr int A_BODY = NBC * 24;             // forward pass: R9 p3 V6 A6; backward: C10 F6
-  static constexpr int A_MAT = NVC * MST;
+  static constexpr int MST = NVC + 1;                 // padded row stride of the matrices
+  static constexpr int A_BODY = NBC * 24;             // forward: R9 p3 V6 A6; backward: C10 F6
+  static constexpr int A_MAT = NVC * MST;             // assembled M~, later M~^-1 (rotated columns)
   static constexpr int A_WORDS = A_BODY > A_MAT ? A_BODY : A_MAT;
   float A[A_WORDS];
   float WO[NBC][12];        // hinge axis w, anchor o (world), composite force C S of the hinge
   int par[NBC];
-  int ccount[NBC];          // active corners per body
+  int ccount[NBC];          // active-corner mask per body
   float cl[NCR][4];         // contact list: x, y, z, ancestor mask of the body
   float cs[NCR][12];        // per-contact solver scalars
   float th[32], thd[32];    // theta / thetadot by DoF
-  float cb[2][32];          // pivot-column broadcast (double buffered); also c and rhs
-  float jb[NVC][4];         // contact row broadcast (J_n, J_x, J_y)
+  float cvec[32];           // bias c by DoF
+  float cb[2][64];          // doubled broadcast buffers (pivot column, right-hand sides)
+  float jb[2 * NVC][4];     // doubled contact-row broadcast (J_n, J_x, J_y)
 };
 
 // ----------------------------------------------------------------------------
-// Contact rows.  Builds J (normal z, tangents x, y) of the point x for the
-// lane's DoF slots, W = Mt^-1 J^T (J broadcast through LDS), the row
-// denominators and cross terms, and the per-contact solver scalars.
+// Contact rows.  The inverse is held negated with rotated columns: register
+// column j of the row of DoF d is -(M~^-1)[d][(nv + j) mod NVC]; vectors
+// multiplied by it are read from doubled LDS buffers at offset nv.
+// Builds J (normal z, tangents x, y) of the point x for the lane's DoF slots,
+// W = M~^-1 J^T, the row denominators and cross terms, and the solver scalars.
 // ----------------------------------------------------------------------------
 template <int S, int NVC>
 __device__ __forceinline__ void build_rows(const float (&Mi)[S][NVC], const f3 (&ang)[S], const f3 (&cst)[S],
-                                           const int (&bodyOfDof)[S], int lane, float (*jb)[4], f3 x,
+                                           const int (&bodyOfDof)[S], int lane, int nv, float (*jb)[4], f3 x,
                                            unsigned anc, float kc, float kb, float dt, float (&Jn)[S],
                                            float (&Jx)[S], float (&Jy)[S], float (&Wn)[S], float (&Wx)[S],
                                            float (&Wy)[S], float (&scal)[10]) {
@@ -167,14 +170,18 @@ __device__ __forceinline__ void build_rows(const float (&Mi)[S][NVC], const f3 (
     Jn[s] = on ? J.z : 0.f;
     Jx[s] = on ? J.x : 0.f;
     Jy[s] = on ? J.y : 0.f;
-    if (d < NVC) { jb[d][0] = Jn[s]; jb[d][1] = Jx[s]; jb[d][2] = Jy[s]; }
+    if (d < NVC) {
+      jb[d][0] = -Jn[s]; jb[d][1] = -Jx[s]; jb[d][2] = -Jy[s];  // sign of the held inverse folded in
+      jb[d + NVC][0] = -Jn[s]; jb[d + NVC][1] = -Jx[s]; jb[d + NVC][2] = -Jy[s];
+    }
   }
   wave_sync();
 #pragma unroll
   for (int s = 0; s < S; ++s) { Wn[s] = 0.f; Wx[s] = 0.f; Wy[s] = 0.f; }
+  const float (*jr)[4] = jb + nv;
 #pragma unroll
   for (int j = 0; j < NVC; ++j) {
-    const float4 jj = *reinterpret_cast<const float4*>(&jb[j][0]);
+    const float4 jj = *reinterpret_cast<const float4*>(&jr[j][0]);
 #pragma unroll
     for (int s = 0; s < S; ++s) {
       Wn[s] = fmaf(Mi[s][j], jj.x, Wn[s]);
@@ -240,6 +247,15 @@ __device__ __forceinline__ void contact_row(float (&vp)[S], const float (&Jn)[S]
   for (int s = 0; s < S; ++s) vp[s] = fmaf(Wn[s], edn, fmaf(Wx[s], edx, fmaf(Wy[s], edy, vp[s])));
 }
 
+// Smallest value over the 16 lanes of a row (every lane gets it).
+__device__ __forceinline__ float row_min(float x) {
+  x = fminf(x, dpp<0xB1>(x));
+  x = fminf(x, dpp<0x4E>(x));
+  x = fminf(x, dpp<0x141>(x));
+  x = fminf(x, dpp<0x140>(x));
+  return x;
+}
+
 // ----------------------------------------------------------------------------
 // The kernel.
 // ----------------------------------------------------------------------------
@@ -249,6 +265,7 @@ __global__ __launch_bounds__(64) void rollout_kernel(BinArgs a, ModelParams P) {
   constexpr int NBC = 16 * SB;
   constexpr int MAXC = 8 * NBC;
   using L = GroupLds<NVC, SB, NCR>;
+  constexpr int MST = L::MST;
   __shared__ L lds_all[kVarPerWave];
 
   const int lane = threadIdx.x & 15;
@@ -263,6 +280,7 @@ __global__ __launch_bounds__(64) void rollout_kernel(BinArgs a, ModelParams P) {
   const float* hf = a.hdrf + (size_t)vid * HF_WORDS;
   const float mu = hf[HF_MU];
   const float* bodyv = a.body + (size_t)vid * NBC * BW_WORDS;
+  const int* lvl = a.lvl + (size_t)vid * a.lvl_stride;  // bodies in level order, then level offsets
   float* ovf = a.ovf + (size_t)vid * a.ovf_stride;
   float* ovf_list = ovf;
   float* ovf_scal = ovf + MAXC * 4;
@@ -307,111 +325,95 @@ __global__ __launch_bounds__(64) void rollout_kernel(BinArgs a, ModelParams P) {
     a.xy0[2 * vid] = (r0 == 6) ? p0[0] : 0.f;
     a.xy0[2 * vid + 1] = (r0 == 6) ? p0[1] : 0.f;
   }
-  if (lane < nb) sh.par[lane] = __float_as_int(bodyv[lane * BW_WORDS + BW_PARENT]);
-  if (SB > 1 && lane + 16 < nb) sh.par[lane + 16] = __float_as_int(bodyv[(lane + 16) * BW_WORDS + BW_PARENT]);
-
-  // DoF-slot constants: hinge CPG, and for hinge DoFs the body index.
-  float cpgA[S], cpgW[S], cpgP[S];
 #pragma unroll
-  for (int s = 0; s < S; ++s) {
-    const int d = lane + 16 * s;
-    const bool hinge = d >= r0 && d < nv;
-    const int b = d - r0 + 1;
-    cpgA[s] = hinge ? bodyv[b * BW_WORDS + BW_CPG] : 0.f;
-    cpgW[s] = hinge ? bodyv[b * BW_WORDS + BW_CPG + 1] : 0.f;
-    cpgP[s] = hinge ? bodyv[b * BW_WORDS + BW_CPG + 2] : 0.f;
+  for (int t = 0; t < SB; ++t) {
+    const int b = lane + 16 * t;
+    if (b < nb) sh.par[b] = __float_as_int(bodyv[b * BW_WORDS + BW_PARENT]);
   }
 
   for (int it = 0; it < a.n_steps; ++it) {
     if (status) break;  // frozen variants stop (row-uniform)
 
     // =====================================================================
-    // 1. forward kinematics, spatial velocities and bias accelerations; the
-    //    body's inertia about p0 and its Newton-Euler force are formed at once
+    // 1. forward kinematics, spatial velocities and bias accelerations, body
+    //    by body down the tree; the lanes of a row take the bodies of one
+    //    depth level at a time.  Corner tests of each body.
     // =====================================================================
 #pragma unroll
     for (int s = 0; s < S; ++s) {
       const int d = lane + 16 * s;
       if (d < 32) { sh.th[d] = thS[s]; sh.thd[d] = vS[s]; }
     }
-    // root velocity (body frame), broadcast from DoF lanes 0..5
     f3 wb = mk(row_bcast<0>(vS[0]), row_bcast<1>(vS[0]), row_bcast<2>(vS[0]));
     f3 vb = mk(row_bcast<3>(vS[0]), row_bcast<4>(vS[0]), row_bcast<5>(vS[0]));
     if (r0 != 6) { wb = mk(0.f, 0.f, 0.f); vb = wb; }
     const m33 R0 = quat_rot(Q0[0], Q0[1], Q0[2], Q0[3]);
     const f3 P0 = mk(p0[0], p0[1], p0[2]);
+#pragma unroll
+    for (int t = 0; t < SB; ++t) sh.ccount[lane + 16 * t] = 0;
     wave_sync();
 
-    int depthb[SB];
-#pragma unroll
-    for (int t = 0; t < SB; ++t) {
-      const int b = lane + 16 * t;
-      depthb[t] = (b < nb) ? __float_as_int(bodyv[(size_t)b * BW_WORDS + BW_DEPTH]) : 1 << 20;
-      if (b < NBC) sh.ccount[b] = 0;
-    }
     for (int lev = 0; lev <= maxdepth; ++lev) {
+      const int i1 = lvl[NBC + lev + 1];
+      for (int i = lvl[NBC + lev] + lane; i < i1; i += 16) {
+        const int b = lvl[i];
+        const float* rec = bodyv + (size_t)b * BW_WORDS;
+        m33 R;
+        f3 p, w, o;
+        sv V, A;
+        if (b == 0) {
+          R = R0;
+          p = P0;
+          w = mk(0.f, 0.f, 0.f);
+          o = P0;
+          V.a = mul(R0, wb);
+          V.l = mul(R0, vb);
+          A.a = mk(0.f, 0.f, 0.f);
+          A.l = mk(-P.g[0], -P.g[1], -P.g[2]);  // gravity as a base acceleration
+        } else {
+          const int lam = sh.par[b];
+          const float* pr = &sh.A[lam * 24];
+          m33 Rl;
 #pragma unroll
-      for (int t = 0; t < SB; ++t) {
-        const int b = lane + 16 * t;
-        if (depthb[t] == lev) {
-          const float* rec = bodyv + (size_t)b * BW_WORDS;
-          m33 R;
-          f3 p, w, o;
-          sv V, A;
-          if (b == 0) {
-            R = R0;
-            p = P0;
-            w = mk(0.f, 0.f, 0.f);
-            o = P0;
-            V.a = mul(R0, wb);
-            V.l = mul(R0, vb);
-            A.a = mk(0.f, 0.f, 0.f);
-            A.l = mk(-P.g[0], -P.g[1], -P.g[2]);  // gravity as a base acceleration
-          } else {
-            const int lam = __float_as_int(rec[BW_PARENT]);
-            const float* pr = &sh.A[lam * 24];
-            m33 Rl;
+          for (int k2 = 0; k2 < 9; ++k2) Rl.m[k2] = pr[k2];
+          const f3 pl = mk(pr[9], pr[10], pr[11]);
+          const sv Vl = {mk(pr[12], pr[13], pr[14]), mk(pr[15], pr[16], pr[17])};
+          const sv Al = {mk(pr[18], pr[19], pr[20]), mk(pr[21], pr[22], pr[23])};
+          const int dof = r0 + b - 1;
+          const float th = sh.th[dof], thd = sh.thd[dof];
+          const f3 u = mk(rec[BW_AXIS], rec[BW_AXIS + 1], rec[BW_AXIS + 2]);
+          float sn, cs;
+          sincosf(th, &sn, &cs);
+          const m33 E = matmul(quat_rot(rec[BW_RQ], rec[BW_RQ + 1], rec[BW_RQ + 2], rec[BW_RQ + 3]),
+                               axis_rot_acc(u, sn, cs));
+          R = matmul(Rl, E);
+          o = pl + mul(Rl, mk(rec[BW_AP], rec[BW_AP + 1], rec[BW_AP + 2]));
+          p = o - mul(R, mk(rec[BW_AC], rec[BW_AC + 1], rec[BW_AC + 2]));
+          w = mul(R, u);
+          const sv St = {w * thd, cross3(o - P0, w) * thd};
+          V = {Vl.a + St.a, Vl.l + St.l};
+          const sv c = crm(Vl, St);
+          A = {Al.a + c.a, Al.l + c.l};
+        }
+        float* dst = &sh.A[b * 24];
 #pragma unroll
-            for (int i = 0; i < 9; ++i) Rl.m[i] = pr[i];
-            const f3 pl = mk(pr[9], pr[10], pr[11]);
-            const sv Vl = {mk(pr[12], pr[13], pr[14]), mk(pr[15], pr[16], pr[17])};
-            const sv Al = {mk(pr[18], pr[19], pr[20]), mk(pr[21], pr[22], pr[23])};
-            const int dof = r0 + b - 1;
-            const float th = sh.th[dof], thd = sh.thd[dof];
-            const f3 u = mk(rec[BW_AXIS], rec[BW_AXIS + 1], rec[BW_AXIS + 2]);
-            float sn, cs;
-            sincosf(th, &sn, &cs);
-            const m33 E = matmul(quat_rot(rec[BW_RQ], rec[BW_RQ + 1], rec[BW_RQ + 2], rec[BW_RQ + 3]),
-                                 axis_rot_acc(u, sn, cs));
-            R = matmul(Rl, E);
-            o = pl + mul(Rl, mk(rec[BW_AP], rec[BW_AP + 1], rec[BW_AP + 2]));
-            p = o - mul(R, mk(rec[BW_AC], rec[BW_AC + 1], rec[BW_AC + 2]));
-            w = mul(R, u);
-            const sv St = {w * thd, cross3(o - P0, w) * thd};
-            V = {Vl.a + St.a, Vl.l + St.l};
-            const sv c = crm(Vl, St);
-            A = {Al.a + c.a, Al.l + c.l};
+        for (int k2 = 0; k2 < 9; ++k2) dst[k2] = R.m[k2];
+        dst[9] = p.x; dst[10] = p.y; dst[11] = p.z;
+        dst[12] = V.a.x; dst[13] = V.a.y; dst[14] = V.a.z; dst[15] = V.l.x; dst[16] = V.l.y; dst[17] = V.l.z;
+        dst[18] = A.a.x; dst[19] = A.a.y; dst[20] = A.a.z; dst[21] = A.l.x; dst[22] = A.l.y; dst[23] = A.l.z;
+        sh.WO[b][0] = w.x; sh.WO[b][1] = w.y; sh.WO[b][2] = w.z;
+        sh.WO[b][3] = o.x; sh.WO[b][4] = o.y; sh.WO[b][5] = o.z;
+        // box-plane contact: 8 corners, bits (x, y, z) of the corner index = sign
+        if (b >= 1 || r0 == 6) {
+          const f3 h = mk(rec[BW_HALF], rec[BW_HALF + 1], rec[BW_HALF + 2]);
+          unsigned msk = 0u;
+#pragma unroll
+          for (int cn = 0; cn < 8; ++cn) {
+            const float z = p.z + R.m[6] * ((cn & 1) ? h.x : -h.x) + R.m[7] * ((cn & 2) ? h.y : -h.y) +
+                            R.m[8] * ((cn & 4) ? h.z : -h.z);
+            if (z < 0.f) msk |= 1u << cn;
           }
-          float* dst = &sh.A[b * 24];
-#pragma unroll
-          for (int i = 0; i < 9; ++i) dst[i] = R.m[i];
-          dst[9] = p.x; dst[10] = p.y; dst[11] = p.z;
-          dst[12] = V.a.x; dst[13] = V.a.y; dst[14] = V.a.z; dst[15] = V.l.x; dst[16] = V.l.y; dst[17] = V.l.z;
-          dst[18] = A.a.x; dst[19] = A.a.y; dst[20] = A.a.z; dst[21] = A.l.x; dst[22] = A.l.y; dst[23] = A.l.z;
-          sh.WO[b][0] = w.x; sh.WO[b][1] = w.y; sh.WO[b][2] = w.z;
-          sh.WO[b][3] = o.x; sh.WO[b][4] = o.y; sh.WO[b][5] = o.z;
-          // box-plane contact: 8 corners, bits (x, y, z) of the corner index = sign
-          if (b >= 1 || r0 == 6) {
-            const f3 h = mk(rec[BW_HALF], rec[BW_HALF + 1], rec[BW_HALF + 2]);
-            unsigned msk = 0u;
-#pragma unroll
-            for (int cn = 0; cn < 8; ++cn) {
-              const float z = p.z + R.m[6] * ((cn & 1) ? h.x : -h.x) + R.m[7] * ((cn & 2) ? h.y : -h.y) +
-                              R.m[8] * ((cn & 4) ? h.z : -h.z);
-              if (z < 0.f) msk |= 1u << cn;
-            }
-            sh.ccount[b] = (int)msk;  // corner mask; the list is written below
-          }
+          sh.ccount[b] = (int)msk;
         }
       }
       wave_sync();
@@ -463,69 +465,67 @@ __global__ __launch_bounds__(64) void rollout_kernel(BinArgs a, ModelParams P) {
     wave_sync();
 
     // =====================================================================
-    // 2. backward sweep: body inertia about p0 and Newton-Euler force
-    //    f = I A + V x* (I V), composite inertia C and force F of each subtree,
-    //    bias c (hinge: S.F; root: S0^T F0), and C S of each hinge for CRBA
+    // 2. backward sweep, level by level up the tree: body inertia about p0
+    //    and Newton-Euler force f = I A + V x* (I V); composite inertia C
+    //    and force F of each subtree; hinge bias S.F and C S for CRBA
     // =====================================================================
     for (int lev = maxdepth; lev >= 0; --lev) {
+      const int i1 = lvl[NBC + lev + 1];
+      for (int i = lvl[NBC + lev] + lane; i < i1; i += 16) {
+        const int b = lvl[i];
+        const float* rec = bodyv + (size_t)b * BW_WORDS;
+        float* own = &sh.A[b * 24];
+        sinertia C;
+        sv F;
+        {
+          m33 R;
 #pragma unroll
-      for (int t = 0; t < SB; ++t) {
-        const int b = lane + 16 * t;
-        if (depthb[t] == lev) {
-          const float* rec = bodyv + (size_t)b * BW_WORDS;
-          float* own = &sh.A[b * 24];
-          sinertia C;
-          sv F;
-          {
-            m33 R;
+          for (int k2 = 0; k2 < 9; ++k2) R.m[k2] = own[k2];
+          const f3 c = mk(own[9], own[10], own[11]) - P0;
+          const sv V = {mk(own[12], own[13], own[14]), mk(own[15], own[16], own[17])};
+          const sv A = {mk(own[18], own[19], own[20]), mk(own[21], own[22], own[23])};
+          const float m = rec[BW_MASS];
+          const f3 h = mk(rec[BW_HALF], rec[BW_HALF + 1], rec[BW_HALF + 2]);
+          const float ix = m / 3.f * (h.y * h.y + h.z * h.z), iy = m / 3.f * (h.x * h.x + h.z * h.z),
+                      iz = m / 3.f * (h.x * h.x + h.y * h.y);
+          const float cc = dot3(c, c);
+          C.m = m;
+          C.h = c * m;
+          C.I[0] = R.m[0] * R.m[0] * ix + R.m[1] * R.m[1] * iy + R.m[2] * R.m[2] * iz + m * (cc - c.x * c.x);
+          C.I[1] = R.m[3] * R.m[3] * ix + R.m[4] * R.m[4] * iy + R.m[5] * R.m[5] * iz + m * (cc - c.y * c.y);
+          C.I[2] = R.m[6] * R.m[6] * ix + R.m[7] * R.m[7] * iy + R.m[8] * R.m[8] * iz + m * (cc - c.z * c.z);
+          C.I[3] = R.m[0] * R.m[3] * ix + R.m[1] * R.m[4] * iy + R.m[2] * R.m[5] * iz - m * c.x * c.y;
+          C.I[4] = R.m[0] * R.m[6] * ix + R.m[1] * R.m[7] * iy + R.m[2] * R.m[8] * iz - m * c.x * c.z;
+          C.I[5] = R.m[3] * R.m[6] * ix + R.m[4] * R.m[7] * iy + R.m[5] * R.m[8] * iz - m * c.y * c.z;
+          const sv IV = imul(C, V), IA = imul(C, A);
+          const sv x = crf(V, IV);
+          F = {IA.a + x.a, IA.l + x.l};
+        }
+        unsigned ch = __float_as_uint(rec[BW_CHILDREN]);
+        while (ch) {
+          const int c = __builtin_ctz(ch);
+          ch &= ch - 1;
+          const float* src = &sh.A[c * 24];
+          C.m += src[0];
+          C.h = C.h + mk(src[1], src[2], src[3]);
 #pragma unroll
-            for (int i = 0; i < 9; ++i) R.m[i] = own[i];
-            const f3 c = mk(own[9], own[10], own[11]) - P0;
-            const sv V = {mk(own[12], own[13], own[14]), mk(own[15], own[16], own[17])};
-            const sv A = {mk(own[18], own[19], own[20]), mk(own[21], own[22], own[23])};
-            const float m = rec[BW_MASS];
-            const f3 h = mk(rec[BW_HALF], rec[BW_HALF + 1], rec[BW_HALF + 2]);
-            const float ix = m / 3.f * (h.y * h.y + h.z * h.z), iy = m / 3.f * (h.x * h.x + h.z * h.z),
-                        iz = m / 3.f * (h.x * h.x + h.y * h.y);
-            const float cc = dot3(c, c);
-            C.m = m;
-            C.h = c * m;
-            C.I[0] = R.m[0] * R.m[0] * ix + R.m[1] * R.m[1] * iy + R.m[2] * R.m[2] * iz + m * (cc - c.x * c.x);
-            C.I[1] = R.m[3] * R.m[3] * ix + R.m[4] * R.m[4] * iy + R.m[5] * R.m[5] * iz + m * (cc - c.y * c.y);
-            C.I[2] = R.m[6] * R.m[6] * ix + R.m[7] * R.m[7] * iy + R.m[8] * R.m[8] * iz + m * (cc - c.z * c.z);
-            C.I[3] = R.m[0] * R.m[3] * ix + R.m[1] * R.m[4] * iy + R.m[2] * R.m[5] * iz - m * c.x * c.y;
-            C.I[4] = R.m[0] * R.m[6] * ix + R.m[1] * R.m[7] * iy + R.m[2] * R.m[8] * iz - m * c.x * c.z;
-            C.I[5] = R.m[3] * R.m[6] * ix + R.m[4] * R.m[7] * iy + R.m[5] * R.m[8] * iz - m * c.y * c.z;
-            const sv IV = imul(C, V), IA = imul(C, A);
-            const sv x = crf(V, IV);
-            F = {IA.a + x.a, IA.l + x.l};
-          }
-          unsigned ch = __float_as_uint(rec[BW_CHILDREN]);
-          while (ch) {
-            const int c = __builtin_ctz(ch);
-            ch &= ch - 1;
-            const float* src = &sh.A[c * 24];
-            C.m += src[0];
-            C.h = C.h + mk(src[1], src[2], src[3]);
+          for (int k2 = 0; k2 < 6; ++k2) C.I[k2] += src[4 + k2];
+          F.a = F.a + mk(src[10], src[11], src[12]);
+          F.l = F.l + mk(src[13], src[14], src[15]);
+        }
+        own[0] = C.m; own[1] = C.h.x; own[2] = C.h.y; own[3] = C.h.z;
 #pragma unroll
-            for (int i = 0; i < 6; ++i) C.I[i] += src[4 + i];
-            F.a = F.a + mk(src[10], src[11], src[12]);
-            F.l = F.l + mk(src[13], src[14], src[15]);
-          }
-          own[0] = C.m; own[1] = C.h.x; own[2] = C.h.y; own[3] = C.h.z;
-#pragma unroll
-          for (int i = 0; i < 6; ++i) own[4 + i] = C.I[i];
-          own[10] = F.a.x; own[11] = F.a.y; own[12] = F.a.z;
-          own[13] = F.l.x; own[14] = F.l.y; own[15] = F.l.z;
-          if (b >= 1) {
-            const f3 w = mk(sh.WO[b][0], sh.WO[b][1], sh.WO[b][2]);
-            const f3 o = mk(sh.WO[b][3], sh.WO[b][4], sh.WO[b][5]);
-            const sv Sb = {w, cross3(o - P0, w)};
-            sh.cb[0][r0 + b - 1] = dot3(Sb.a, F.a) + dot3(Sb.l, F.l);
-            const sv Fc = imul(C, Sb);
-            sh.WO[b][6] = Fc.a.x; sh.WO[b][7] = Fc.a.y; sh.WO[b][8] = Fc.a.z;
-            sh.WO[b][9] = Fc.l.x; sh.WO[b][10] = Fc.l.y; sh.WO[b][11] = Fc.l.z;
-          }
+        for (int k2 = 0; k2 < 6; ++k2) own[4 + k2] = C.I[k2];
+        own[10] = F.a.x; own[11] = F.a.y; own[12] = F.a.z;
+        own[13] = F.l.x; own[14] = F.l.y; own[15] = F.l.z;
+        if (b >= 1) {
+          const f3 w = mk(sh.WO[b][0], sh.WO[b][1], sh.WO[b][2]);
+          const f3 o = mk(sh.WO[b][3], sh.WO[b][4], sh.WO[b][5]);
+          const sv Sb = {w, cross3(o - P0, w)};
+          sh.cvec[r0 + b - 1] = dot3(Sb.a, F.a) + dot3(Sb.l, F.l);
+          const sv Fc = imul(C, Sb);
+          sh.WO[b][6] = Fc.a.x; sh.WO[b][7] = Fc.a.y; sh.WO[b][8] = Fc.a.z;
+          sh.WO[b][9] = Fc.l.x; sh.WO[b][10] = Fc.l.y; sh.WO[b][11] = Fc.l.z;
         }
       }
       wave_sync();
@@ -544,7 +544,7 @@ __global__ __launch_bounds__(64) void rollout_kernel(BinArgs a, ModelParams P) {
       const f3 Fa = mk(src[10], src[11], src[12]), Fl = mk(src[13], src[14], src[15]);
       const f3 ca = mulT(R0, Fa), cl = mulT(R0, Fl);
       const int i = lane;
-      sh.cb[0][i] = (i < 3) ? (i == 0 ? ca.x : i == 1 ? ca.y : ca.z) : (i == 3 ? cl.x : i == 4 ? cl.y : cl.z);
+      sh.cvec[i] = (i < 3) ? (i == 0 ? ca.x : i == 1 ? ca.y : ca.z) : (i == 3 ? cl.x : i == 4 ? cl.y : cl.z);
       // M_rr = [[R^T Io R, [h_b]x], [[h_b]x^T, m 1]] with h_b = R^T h; column j of [h_b]x is h_b x e_j
       const f3 hb = mulT(R0, hw);
       const f3 hx0 = cross3(hb, mk(1.f, 0.f, 0.f)), hx1 = cross3(hb, mk(0.f, 1.f, 0.f)),
@@ -564,13 +564,9 @@ __global__ __launch_bounds__(64) void rollout_kernel(BinArgs a, ModelParams P) {
       }
     }
     wave_sync();  // composite reads done; the area becomes the assembled matrix
-    {
-      constexpr int MST = L::MST;
-      for (int e = lane; e < NVC * MST; e += 16) sh.A[e] = 0.f;
-    }
+    for (int e = lane; e < NVC * MST; e += 16) sh.A[e] = 0.f;
     wave_sync();
     {
-      constexpr int MST = L::MST;
       float* Ml = sh.A;
 #pragma unroll
       for (int s = 0; s < S; ++s) {
@@ -611,7 +607,6 @@ __global__ __launch_bounds__(64) void rollout_kernel(BinArgs a, ModelParams P) {
       }
     }
     wave_sync();
-    // rows into registers, bias per slot
     float Mi[S][NVC];
     float cS[S];
 #pragma unroll
@@ -619,86 +614,98 @@ __global__ __launch_bounds__(64) void rollout_kernel(BinArgs a, ModelParams P) {
       const int d = lane + 16 * s;
       const int dr = d < NVC ? d : 0;
 #pragma unroll
-      for (int j = 0; j < NVC; ++j) Mi[s][j] = sh.A[dr * L::MST + j];
-      cS[s] = (d < nv) ? sh.cb[0][d] : 0.f;
+      for (int j = 0; j < NVC; ++j) Mi[s][j] = sh.A[dr * MST + j];
+      cS[s] = (d < nv) ? sh.cvec[d] : 0.f;
     }
 
     // =====================================================================
-    // 3. inverse by symmetric Gauss-Jordan sweep with rotating columns
-    //    invariant: register column j of step k holds original column (k+j) mod NVC
+    // 3. inverse by a symmetric Gauss-Jordan sweep over the nv real pivots,
+    //    rows in registers, columns rotating by one per pivot (register
+    //    column j of step k holds original column (k + j) mod NVC).  The
+    //    pivot column is broadcast through a doubled LDS buffer.  Pivot row
+    //    k uses the symmetric column values: a_kj - (1 - 1/d) a_jk.
+    //    Result: -M~^-1 with register column j <-> column (nv + j) mod NVC.
     // =====================================================================
-    wave_sync();
 #pragma unroll 1
-    for (int k = 0; k < NVC; ++k) {
+    for (int k = 0; k < nv; ++k) {
       float* cbk = sh.cb[k & 1];
 #pragma unroll
       for (int s = 0; s < S; ++s) {
         const int d = lane + 16 * s;
-        if (d < NVC) cbk[d] = Mi[s][0];
+        if (d < NVC) { cbk[d] = Mi[s][0]; cbk[d + NVC] = Mi[s][0]; }
       }
       wave_sync();
-      const float pinv = 1.0f / cbk[k];
+      const float* ck = cbk + k;
+      const float pinv = 1.0f / ck[0];
       float f[S];
       bool piv[S];
 #pragma unroll
       for (int s = 0; s < S; ++s) {
-        f[s] = Mi[s][0] * pinv;
         piv[s] = (lane + 16 * s) == k;
+        f[s] = piv[s] ? 1.f - pinv : Mi[s][0] * pinv;
       }
 #pragma unroll
       for (int j = 1; j < NVC; ++j) {
-        int idx = k + j;
-        idx = idx >= NVC ? idx - NVC : idx;
-        const float cj = cbk[idx];
+        const float cj = ck[j];
 #pragma unroll
-        for (int s = 0; s < S; ++s) Mi[s][j - 1] = piv[s] ? cj * pinv : fmaf(-f[s], cj, Mi[s][j]);
+        for (int s = 0; s < S; ++s) Mi[s][j - 1] = fmaf(-f[s], cj, Mi[s][j]);
       }
 #pragma unroll
       for (int s = 0; s < S; ++s) Mi[s][NVC - 1] = piv[s] ? -pinv : f[s];
     }
-    // Mi now holds -Mt^-1
-#pragma unroll
-    for (int s = 0; s < S; ++s)
-#pragma unroll
-      for (int j = 0; j < NVC; ++j) Mi[s][j] = -Mi[s][j];
-    float Dd[S];  // own diagonal of Mt^-1
+    // the assembled matrix is dead: keep the (negated, rotated) inverse in LDS
+    // for the clamp rows, which need single columns chosen at run time
+    wave_sync();
 #pragma unroll
     for (int s = 0; s < S; ++s) {
       const int d = lane + 16 * s;
-      float x = 0.f;
+      if (d < NVC) {
 #pragma unroll
-      for (int j = 0; j < NVC; ++j) x = (j == d) ? Mi[s][j] : x;
-      Dd[s] = x;
+        for (int j = 0; j < NVC; ++j) sh.A[d * MST + j] = Mi[s][j];
+      }
+    }
+    wave_sync();
+    float Dd[S];  // own diagonal of M~^-1
+#pragma unroll
+    for (int s = 0; s < S; ++s) {
+      const int d = lane + 16 * s;
+      int cidx = d - nv;
+      cidx += (cidx < 0) ? NVC : 0;
+      Dd[s] = (d < nv) ? -sh.A[d * MST + cidx] : 0.f;
     }
 
     // =====================================================================
     // 4. control and free velocity
     // =====================================================================
-    wave_sync();  // last sweep reads of cb done before it is reused
     const double tk = (double)kstep * dtd;
     float aS[S];
 #pragma unroll
     for (int s = 0; s < S; ++s) {
       const int d = lane + 16 * s;
       const bool hinge = d >= r0 && d < nv;
-      double ph = (double)cpgW[s] * tk + (double)cpgP[s];
+      const int b = hinge ? d - r0 + 1 : 0;
+      const float* rec = bodyv + (size_t)b * BW_WORDS;
+      double ph = (double)rec[BW_CPG + 1] * tk + (double)rec[BW_CPG + 2];
       ph -= 6.283185307179586 * floor(ph * 0.15915494309189535);
-      const float target = cpgA[s] * sinf((float)ph);
+      const float target = rec[BW_CPG] * sinf((float)ph);
       aS[s] = hinge ? kp * (target - thS[s]) : 0.f;
       float rhs = -dt * cS[s];
       if (hinge) rhs += dt * (aS[s] - ba * vS[s]);
       if (d >= nv) rhs = 0.f;
-      if (d < 32) sh.cb[0][d] = rhs;
+      if (d < NVC) { sh.cb[0][d] = -rhs; sh.cb[0][d + NVC] = -rhs; }  // sign of the held inverse
     }
     wave_sync();
     float vp[S];
 #pragma unroll
     for (int s = 0; s < S; ++s) vp[s] = vS[s];
+    {
+      const float* rr = sh.cb[0] + nv;
 #pragma unroll
-    for (int j = 0; j < NVC; ++j) {
-      const float r = sh.cb[0][j];
+      for (int j = 0; j < NVC; ++j) {
+        const float r = rr[j];
 #pragma unroll
-      for (int s = 0; s < S; ++s) vp[s] = fmaf(Mi[s][j], r, vp[s]);
+        for (int s = 0; s < S; ++s) vp[s] = fmaf(Mi[s][j], r, vp[s]);
+      }
     }
 
     // =====================================================================
@@ -727,7 +734,6 @@ __global__ __launch_bounds__(64) void rollout_kernel(BinArgs a, ModelParams P) {
         cst[s] = mk(0.f, 0.f, 0.f);
       }
     }
-
     float JnR[NCR][S], JxR[NCR][S], JyR[NCR][S], WnR[NCR][S], WxR[NCR][S], WyR[NCR][S];
 #pragma unroll
     for (int c = 0; c < NCR; ++c) {
@@ -735,7 +741,7 @@ __global__ __launch_bounds__(64) void rollout_kernel(BinArgs a, ModelParams P) {
         const f3 x = mk(sh.cl[c][0], sh.cl[c][1], sh.cl[c][2]);
         const unsigned anc = __float_as_uint(sh.cl[c][3]);
         float scal[10];
-        build_rows<S, NVC>(Mi, ang, cst, bodyOfDof, lane, sh.jb, x, anc, kc, kb, dt, JnR[c], JxR[c], JyR[c],
+        build_rows<S, NVC>(Mi, ang, cst, bodyOfDof, lane, nv, sh.jb, x, anc, kc, kb, dt, JnR[c], JxR[c], JyR[c],
                            WnR[c], WxR[c], WyR[c], scal);
 #pragma unroll
         for (int i = 0; i < 10; ++i) sh.cs[c][i] = scal[i];  // identical in every lane
@@ -754,7 +760,7 @@ __global__ __launch_bounds__(64) void rollout_kernel(BinArgs a, ModelParams P) {
       const f3 x = mk(ovf_list[c * 4], ovf_list[c * 4 + 1], ovf_list[c * 4 + 2]);
       const unsigned anc = __float_as_uint(ovf_list[c * 4 + 3]);
       float Jn[S], Jx[S], Jy[S], Wn[S], Wx[S], Wy[S], scal[10];
-      build_rows<S, NVC>(Mi, ang, cst, bodyOfDof, lane, sh.jb, x, anc, kc, kb, dt, Jn, Jx, Jy, Wn, Wx, Wy, scal);
+      build_rows<S, NVC>(Mi, ang, cst, bodyOfDof, lane, nv, sh.jb, x, anc, kc, kb, dt, Jn, Jx, Jy, Wn, Wx, Wy, scal);
       float* rows = ovf_rows + (size_t)c * 6 * NVC;
 #pragma unroll
       for (int s = 0; s < S; ++s) {
@@ -776,51 +782,49 @@ __global__ __launch_bounds__(64) void rollout_kernel(BinArgs a, ModelParams P) {
 #pragma unroll
     for (int s = 0; s < S; ++s) Dl[s] = 0.f;
     for (int sweep = 0; sweep < P.K; ++sweep) {
-      // (i) actuator clamp rows in hinge order.  A row is a no-op when its new
-      // Delta equals the old one; if that holds for every row against the
-      // current velocity, the sequential pass would change nothing, so it is
-      // only run (exactly, in order) when some row of some variant changes.
-      bool chg = false;
+      // (i) actuator clamp rows in hinge order.  Every remaining row is
+      // evaluated against the current velocity; rows whose new Delta equals
+      // the old one are no-ops, so only the lowest changing row is applied,
+      // and the rest re-evaluated after it: the same result as visiting every
+      // row in order.
+      int last = -1;  // row-uniform: last hinge DoF applied in this sweep
+      while (true) {
+        float first = 1e9f;
+        float ndv[S];
 #pragma unroll
-      for (int s = 0; s < S; ++s) {
-        const int d = lane + 16 * s;
-        const bool hinge = d >= r0 && d < nv;
-        const float u0 = fmaf(dt * Dd[s], Dl[s], vp[s]);
-        const float sv_ = aS[s] - ba * u0;
-        const float den = 1.f - ba * dt * Dd[s];
-        float nd = 0.f;
-        if (sv_ > tmax) nd = (sv_ - tmax) / den;
-        else if (sv_ < -tmax) nd = (sv_ + tmax) / den;
-        chg = chg || (hinge && nd != Dl[s]);
-      }
-      if (__builtin_amdgcn_ballot_w64(chg) != 0) {
+        for (int s = 0; s < S; ++s) {
+          const int d = lane + 16 * s;
+          const float u0 = fmaf(dt * Dd[s], Dl[s], vp[s]);
+          const float sv_ = aS[s] - ba * u0;
+          const float den = 1.f - ba * dt * Dd[s];
+          float nd = 0.f;
+          if (sv_ > tmax) nd = (sv_ - tmax) / den;
+          else if (sv_ < -tmax) nd = (sv_ + tmax) / den;
+          ndv[s] = nd;
+          if (d >= r0 && d < nv && d > last && nd != Dl[s]) first = fminf(first, (float)d);
+        }
+        first = row_min(first);
+        if (__builtin_amdgcn_ballot_w64(first < 1e8f) == 0) break;  // no row of any variant changes
+        if (first < 1e8f) {  // row-uniform
+          const int j = (int)first;
+          float dl = 0.f;
 #pragma unroll
-        for (int j = 0; j < NVC; ++j) {
-          const int lj = j & 15, sj = j >> 4;
-          if (j >= r0 && j < nv) {  // row-uniform
-            const float u0 = fmaf(dt * Dd[sj], Dl[sj], vp[sj]);
-            const float sv_ = aS[sj] - ba * u0;
-            const float den = 1.f - ba * dt * Dd[sj];
-            float nd = 0.f;
-            if (sv_ > tmax) nd = (sv_ - tmax) / den;
-            else if (sv_ < -tmax) nd = (sv_ + tmax) / den;
-            const float dl = nd - Dl[sj];  // meaningful in the owner lane lj
-            float dlb;
-            switch (lj) {
-              case 0: dlb = row_bcast<0>(dl); break;   case 1: dlb = row_bcast<1>(dl); break;
-              case 2: dlb = row_bcast<2>(dl); break;   case 3: dlb = row_bcast<3>(dl); break;
-              case 4: dlb = row_bcast<4>(dl); break;   case 5: dlb = row_bcast<5>(dl); break;
-              case 6: dlb = row_bcast<6>(dl); break;   case 7: dlb = row_bcast<7>(dl); break;
-              case 8: dlb = row_bcast<8>(dl); break;   case 9: dlb = row_bcast<9>(dl); break;
-              case 10: dlb = row_bcast<10>(dl); break; case 11: dlb = row_bcast<11>(dl); break;
-              case 12: dlb = row_bcast<12>(dl); break; case 13: dlb = row_bcast<13>(dl); break;
-              case 14: dlb = row_bcast<14>(dl); break; default: dlb = row_bcast<15>(dl); break;
-            }
-            Dl[sj] = (lane == lj) ? nd : Dl[sj];
-            const float e = -dt * dlb;
-#pragma unroll
-            for (int s = 0; s < S; ++s) vp[s] = fmaf(Mi[s][j], e, vp[s]);
+          for (int s = 0; s < S; ++s) {
+            const bool own = (lane + 16 * s) == j;
+            dl += own ? ndv[s] - Dl[s] : 0.f;
+            Dl[s] = own ? ndv[s] : Dl[s];
           }
+          dl = row_sum(dl);
+          int cj = j - nv;
+          cj += (cj < 0) ? NVC : 0;
+          const float e = dt * dl;  // v+ -= dt M~^-1 e_j dl, inverse held negated
+#pragma unroll
+          for (int s = 0; s < S; ++s) {
+            const int d = lane + 16 * s;
+            const float mcol = (d < NVC) ? sh.A[d * MST + cj] : 0.f;
+            vp[s] = fmaf(mcol, e, vp[s]);
+          }
+          last = j;
         }
       }
       // (ii) contact rows in (body, corner) order

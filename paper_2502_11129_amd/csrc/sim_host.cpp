@@ -34,10 +34,11 @@ struct Bin {
   launch_fn fn = nullptr;
   std::vector<int> users;  // user index of each packed variant
   // packed host copies (uploaded by sim_bind)
-  std::vector<int> hdr;
+  std::vector<int> hdr, lvl;
   std::vector<float> hdrf, body, q0, v0;
   // device offsets (bytes from the workspace base)
-  size_t o_hdr, o_hdrf, o_body, o_q0, o_v0, o_q, o_v, o_k, o_status, o_xy0, o_fit, o_cnt, o_ovf;
+  size_t o_hdr, o_hdrf, o_body, o_lvl, o_q0, o_v0, o_q, o_v, o_k, o_status, o_xy0, o_fit, o_cnt, o_ovf;
+  int lvl_stride = 0;
   long long ovf_stride = 0;
   BinArgs args{};
 };
@@ -325,6 +326,8 @@ int sim_create(const sim_model_desc* d, const sim_options* opts, sim_handle** ou
     b.body.assign((size_t)m * nbc * BW_WORDS, 0.f);
     b.q0.assign((size_t)m * kQStride, 0.f);
     b.v0.assign((size_t)m * kVStride, 0.f);
+    b.lvl_stride = 2 * nbc + 4;
+    b.lvl.assign((size_t)m * b.lvl_stride, 0);
     for (int s = 0; s < m; ++s) {
       const int i = b.users[s];
       hp->bin_of[i] = (int)bi;
@@ -359,6 +362,15 @@ int sim_create(const sim_model_desc* d, const sim_options* opts, sim_handle** ou
         std::memcpy(&rec[BW_CHILDREN], &ch, 4);
         std::memcpy(&rec[BW_ANCESTORS], &an, 4);
       }
+      // bodies in depth order (stable), then the start of every level
+      int* lv = &b.lvl[(size_t)s * b.lvl_stride];
+      int pos = 0;
+      for (int lev = 0; lev <= vi.maxdepth; ++lev) {
+        lv[nbc + lev] = pos;
+        for (int bb = 0; bb < vi.nb; ++bb)
+          if (vi.depth[bb] == lev) lv[pos++] = bb;
+      }
+      lv[nbc + vi.maxdepth + 1] = pos;
       std::copy(d->q0 + hp->q_off[i], d->q0 + hp->q_off[i + 1], &b.q0[(size_t)s * kQStride]);
       std::copy(d->v0 + hp->v_off[i], d->v0 + hp->v_off[i + 1], &b.v0[(size_t)s * kVStride]);
     }
@@ -372,6 +384,7 @@ int sim_create(const sim_model_desc* d, const sim_options* opts, sim_handle** ou
     b.o_hdr = take(m * HW_WORDS * 4);
     b.o_hdrf = take(m * HF_WORDS * 4);
     b.o_body = take(m * 16 * b.sb * BW_WORDS * 4);
+    b.o_lvl = take(m * b.lvl_stride * 4);
     b.o_q0 = take(m * kQStride * 4);
     b.o_v0 = take(m * kVStride * 4);
     b.o_q = take(m * kQStride * 4);
@@ -421,6 +434,7 @@ int sim_bind(sim_handle* h, void* ws, size_t bytes, void* stream) {
     if ((rc = dev_check(h, hipMemcpyAsync(base + b.o_hdr, b.hdr.data(), m * HW_WORDS * 4, hipMemcpyHostToDevice, st), "upload"))) return rc;
     if ((rc = dev_check(h, hipMemcpyAsync(base + b.o_hdrf, b.hdrf.data(), m * HF_WORDS * 4, hipMemcpyHostToDevice, st), "upload"))) return rc;
     if ((rc = dev_check(h, hipMemcpyAsync(base + b.o_body, b.body.data(), b.body.size() * 4, hipMemcpyHostToDevice, st), "upload"))) return rc;
+    if ((rc = dev_check(h, hipMemcpyAsync(base + b.o_lvl, b.lvl.data(), b.lvl.size() * 4, hipMemcpyHostToDevice, st), "upload"))) return rc;
     if ((rc = dev_check(h, hipMemcpyAsync(base + b.o_q0, b.q0.data(), b.q0.size() * 4, hipMemcpyHostToDevice, st), "upload"))) return rc;
     if ((rc = dev_check(h, hipMemcpyAsync(base + b.o_v0, b.v0.data(), b.v0.size() * 4, hipMemcpyHostToDevice, st), "upload"))) return rc;
     BinArgs& a = b.args;
@@ -428,6 +442,8 @@ int sim_bind(sim_handle* h, void* ws, size_t bytes, void* stream) {
     a.hdr = (const int*)(base + b.o_hdr);
     a.hdrf = (const float*)(base + b.o_hdrf);
     a.body = (const float*)(base + b.o_body);
+    a.lvl = (const int*)(base + b.o_lvl);
+    a.lvl_stride = b.lvl_stride;
     a.q0 = (const float*)(base + b.o_q0);
     a.v0 = (const float*)(base + b.o_v0);
     a.q = (float*)(base + b.o_q);

@@ -47,6 +47,8 @@ struct BinArgs {
   const int* hdr;               // [n][HW_WORDS]
   const float* hdrf;            // [n][HF_WORDS]
   const float* body;            // [n][nbc][BW_WORDS]
+  const int* lvl;               // [n][lvl_stride]: bodies in depth order, then level start offsets
+  int lvl_stride;
   const float* q0;              // [n][kQStride]
   const float* v0;              // [n][kVStride]
   float* q;                     // [n][kQStride]

@@ -8,7 +8,7 @@ Imported by tests/ (and nothing on the product path).  Plain numpy:
   round-to-nearest-even at the same points as the GPU kernels: inputs,
   weight copies, every hidden activation and every hidden-layer gradient that
   feeds a matrix product;
-* its backward pass, the mean-squared-error loss, Adam (Kingma & Ba 2015,
+* target standardisation, its backward pass, the mean-squared-error loss, Adam (Kingma & Ba 2015,
   beta = (0.9, 0.999), eps = 1e-8) with FP32 master weights;
 * screening metrics: top-5% recall (ties broken by lower index) and
   Spearman's rho (Pearson correlation of average ranks).
@@ -97,16 +97,23 @@ def gelu_grad(z):
     return 0.5 * (1.0 + erf(z / math.sqrt(2.0))) + z * np.exp(-0.5 * z * z) / math.sqrt(2.0 * math.pi)
 
 
-def init_params(seed=0):
-    """U(+-1/sqrt(fan_in)) weights and biases, float32 masters.  W[l] is [in, out]."""
-    rng = np.random.default_rng([5, seed])
+def unflatten(p):
+    """Flat parameter vector (W1, b1, W2, b2, W3, b3, W4, b4; W_l[in][out]
+    row-major) -> lists W, b (views, dtype kept)."""
     dims = [N_FEAT, HIDDEN, HIDDEN, HIDDEN, 1]
-    W, b = [], []
+    W, b, o = [], [], 0
     for l in range(4):
-        lim = 1.0 / math.sqrt(dims[l])
-        W.append(rng.uniform(-lim, lim, (dims[l], dims[l + 1])).astype(np.float32))
-        b.append(rng.uniform(-lim, lim, dims[l + 1]).astype(np.float32))
+        n = dims[l] * dims[l + 1]
+        W.append(p[o:o + n].reshape(dims[l], dims[l + 1]))
+        o += n
+        b.append(p[o:o + dims[l + 1]])
+        o += dims[l + 1]
+    assert o == len(p)
     return W, b
+
+
+def flatten(W, b):
+    return np.concatenate([x for l in range(4) for x in (np.ravel(W[l]), np.ravel(b[l]))])
 
 
 def forward(X, W, b, emulate_bf16=True):
@@ -138,6 +145,14 @@ def backward(cache, W, dy, emulate_bf16=True):
         if l > 0:
             dh = dz @ r(W[l]).astype(np.float64).T
     return gW, gb
+
+
+def standardize(y):
+    """(y - mean) / std with the population std (1 when zero); returns (z, mean, std)."""
+    y = np.asarray(y, np.float64)
+    mean = y.mean()
+    sd = np.sqrt(np.mean((y - mean) ** 2))
+    return (y - mean) / (sd if sd > 0 else 1.0), mean, sd
 
 
 def mse_grad(y, t):

@@ -28,7 +28,7 @@ DEVICE = [f"--offload-arch={ARCH}", "-Xclang", "-target-feature", "-Xclang", "-p
 
 def _sources():
     kern = sorted(glob.glob(os.path.join(CSRC, "kernels", "*.hip")))
-    host = [os.path.join(CSRC, n) for n in ("kernel_registry.cpp", "sim_host.cpp", "host_worker.cpp")]
+    host = [os.path.join(CSRC, n) for n in ("kernel_registry.cpp", "sim_host.cpp", "host_worker.cpp", "sur_host.cpp")]
     return kern, host
 
 

@@ -401,3 +401,144 @@ CONFIGS = {
 
 # Oracle spot-check subset of the random-tree population: indices 128*m.
 TREE_SPOTCHECK = tuple(128 * m for m in range(64))
+
+
+# ----------------------------------------------------------------------------
+# Genotypes of random-tree robots (inputs of the learned surrogate)
+# ----------------------------------------------------------------------------
+FACE_CODE = {"+x": 0, "-x": 1, "+y": 2, "-y": 3}
+FACE_NAME = ("+x", "-x", "+y", "-y")
+
+
+@dataclass
+class Genotypes:
+    """Random-tree robots in compact form: hinge j joins body j+1 to
+    parent[j] on face face[j] (0 +x, 1 -x, 2 +y, 3 -y in the parent frame)
+    with axis flag axis[j] (0 child z, 1 child y); cpg[j] = (A, omega, phi).
+    Padding: parent = face = axis = -1, cpg = 0."""
+    nh: np.ndarray       # int32 [N]
+    parent: np.ndarray   # int32 [N, 20]
+    face: np.ndarray     # int32 [N, 20]
+    axis: np.ndarray     # int32 [N, 20]
+    cpg: np.ndarray      # float32 [N, 20, 3]
+
+    def __len__(self):
+        return int(self.nh.shape[0])
+
+    def take(self, idx):
+        idx = np.asarray(idx)
+        return Genotypes(self.nh[idx], self.parent[idx], self.face[idx], self.axis[idx], self.cpg[idx])
+
+
+def _empty_genotypes(n):
+    return Genotypes(np.zeros(n, np.int32), -np.ones((n, 20), np.int32), -np.ones((n, 20), np.int32),
+                     -np.ones((n, 20), np.int32), np.zeros((n, 20, 3), np.float32))
+
+
+def tree_genotypes(indices) -> Genotypes:
+    """Genotypes of the random-tree population (same robots as random_trees)."""
+    indices = list(indices)
+    g = _empty_genotypes(len(indices))
+    for r, i in enumerate(indices):
+        bricks, A, om, ph = random_tree(int(i))
+        nh = len(bricks)
+        g.nh[r] = nh
+        for j, (par, f, flag) in enumerate(bricks):
+            g.parent[r, j] = par
+            g.face[r, j] = FACE_CODE[f]
+            g.axis[r, j] = flag
+        g.cpg[r, :nh, 0] = A
+        g.cpg[r, :nh, 1] = om
+        g.cpg[r, :nh, 2] = ph
+    return g
+
+
+def random_genotypes(n, key=0, chunk=262144) -> Genotypes:
+    """n candidates drawn from the random-tree distribution (4..20 hinges,
+    free-slot attachment on bodies of depth < 4, axis z/y, CPG ranges as for
+    the snake), vectorised over candidates; seeded by rng([4, key, chunk])."""
+    out = _empty_genotypes(n)
+    # slot codes per body: core uses faces 0..3, bricks use +x, +y, -y (0, 2, 3)
+    allowed = np.ones((21, 4), bool)
+    allowed[1:, 1] = False
+    for c0 in range(0, n, chunk):
+        m = min(chunk, n - c0)
+        rng = np.random.default_rng([4, key, c0 // chunk])
+        nh = rng.integers(4, 21, m)
+        used = np.zeros((m, 21, 4), bool)
+        depth = np.zeros((m, 21), np.int64)
+        par = -np.ones((m, 20), np.int64)
+        face = -np.ones((m, 20), np.int64)
+        flag = -np.ones((m, 20), np.int64)
+        u = rng.random((m, 20))
+        fl = rng.integers(0, 2, (m, 20))
+        rows = np.arange(m)
+        for j in range(20):
+            act = nh > j
+            nbod = j + 1                                   # bodies existing before hinge j
+            free = (~used[:, :nbod, :]) & allowed[None, :nbod, :] & (depth[:, :nbod, None] < 4)
+            free = free.reshape(m, -1)
+            cnt = free.sum(axis=1)
+            pick = np.minimum((u[:, j] * cnt).astype(np.int64), np.maximum(cnt - 1, 0))
+            csum = np.cumsum(free, axis=1)
+            slot = np.argmax(csum > pick[:, None], axis=1)
+            b, f = slot // 4, slot % 4
+            a = act & (cnt > 0)
+            used[rows[a], b[a], f[a]] = True
+            depth[rows[a], j + 1] = depth[rows[a], b[a]] + 1
+            par[a, j], face[a, j], flag[a, j] = b[a], f[a], fl[a, j]
+        A = rng.uniform(0.0, 1.0, (m, 20))
+        om = rng.uniform(1.0, 6.0, (m, 20))
+        ph = rng.uniform(0.0, 2.0 * np.pi, (m, 20))
+        pad = np.arange(20)[None, :] >= nh[:, None]
+        sl = slice(c0, c0 + m)
+        out.nh[sl] = nh
+        out.parent[sl] = par
+        out.face[sl] = face
+        out.axis[sl] = flag
+        cpg = np.stack([A, om, ph], axis=-1)
+        cpg[pad] = 0.0
+        out.cpg[sl] = cpg.astype(np.float32)
+    return out
+
+
+def population_from_genotypes(g: Genotypes, steps=5000) -> Population:
+    """Robots of the given genotypes (core + bricks, as in random_trees)."""
+    b = _Builder()
+    for i in range(len(g)):
+        nh = int(g.nh[i])
+        b.add_body(-1, (CORE_HALF,) * 3, CORE_MASS)
+        for j in range(nh):
+            par = int(g.parent[i, j])
+            ph_half = (CORE_HALF,) * 3 if par == 0 else (BRICK_HALF,) * 3
+            b.add_body(par, (BRICK_HALF,) * 3, BRICK_MASS, FACE_NAME[int(g.face[i, j])], ph_half,
+                       int(g.axis[i, j]), tuple(float(x) for x in g.cpg[i, j]))
+        q0, v0 = _robot_state(nh)
+        b.end_variant(1.0, q0, v0)
+    return b.build("genotypes", steps)
+
+
+# ----------------------------------------------------------------------------
+# Initial parameters of the surrogate network (drawn here, passed in)
+# ----------------------------------------------------------------------------
+MLP_DIMS = (128, 256, 256, 256, 1)
+
+
+def mlp_init(seed=0) -> np.ndarray:
+    """Flat float32 parameters (W1, b1, W2, b2, W3, b3, W4, b4; W_l[in][out]
+    row-major), every entry U(-1/sqrt(fan_in), +1/sqrt(fan_in)); seeded by
+    rng([5, seed])."""
+    rng = np.random.default_rng([5, seed])
+    parts = []
+    for l in range(4):
+        lim = 1.0 / np.sqrt(MLP_DIMS[l])
+        parts.append(rng.uniform(-lim, lim, MLP_DIMS[l] * MLP_DIMS[l + 1]))
+        parts.append(rng.uniform(-lim, lim, MLP_DIMS[l + 1]))
+    return np.concatenate(parts).astype(np.float32)
+
+
+def genotype_arrays(g: Genotypes) -> dict:
+    """The genotype arrays in the element types the surrogate library reads."""
+    return dict(nh=np.ascontiguousarray(g.nh, np.int32), parent=np.ascontiguousarray(g.parent, np.int8),
+                face=np.ascontiguousarray(g.face, np.int8), axis=np.ascontiguousarray(g.axis, np.int8),
+                cpg=np.ascontiguousarray(g.cpg, np.float32))

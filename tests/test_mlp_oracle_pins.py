@@ -10,7 +10,7 @@ import pytest
 import torch
 
 from oracle import mlp_oracle as M
-from paper_2502_11129_amd import workloads as W
+from paper_2502_11129_amd import workloads as WL
 
 
 # ----------------------------------------------------------------------------- BF16
@@ -53,7 +53,7 @@ def test_gelu_grad_finite_difference_and_special_values():
 
 # ----------------------------------------------------------------------------- MLP gradients
 def _small_net(seed=3):
-    W, b = M.init_params(seed)
+    W, b = M.unflatten(WL.mlp_init(seed).astype(np.float64))
     W = [w.astype(np.float64) for w in W]
     b = [x.astype(np.float64) for x in b]
     return W, b
@@ -116,7 +116,7 @@ def test_forward_backward_match_torch_autograd():
 def test_bf16_emulation_rounds_activations_and_stays_close():
     rng = np.random.default_rng(13)
     X = rng.normal(0, 1, (64, M.N_FEAT))
-    W, b = M.init_params(1)
+    W, b = M.unflatten(WL.mlp_init(1))
     y16, (hs, _) = M.forward(X, W, b, emulate_bf16=True)
     y64, _ = M.forward(X, W, b, emulate_bf16=False)
     for h in hs:
@@ -194,7 +194,7 @@ def test_spearman_against_scipy_and_ties():
 
 # ----------------------------------------------------------------------------- features
 def _one(nh, parent, face, axis, cpg):
-    g = W._empty_genotypes(1)
+    g = WL._empty_genotypes(1)
     g.nh[0] = nh
     g.parent[0, :nh] = parent
     g.face[0, :nh] = face
@@ -224,9 +224,9 @@ def test_features_hand_case():
 def test_features_agree_with_the_robots_they_describe():
     """Depth counts and limb sizes recomputed from the robots' own parent
     arrays (the simulator input), not from the genotype."""
-    g = W.random_genotypes(300, key=7)
+    g = WL.random_genotypes(300, key=7)
     F = M.features(g)
-    pop = W.population_from_genotypes(g)
+    pop = WL.population_from_genotypes(g)
     for i in range(300):
         b0, b1 = pop.body_offset[i], pop.body_offset[i + 1]
         par = pop.parent[b0:b1]
@@ -256,8 +256,28 @@ def test_features_agree_with_the_robots_they_describe():
 
 
 def test_genotypes_reproduce_the_tree_population():
-    g = W.tree_genotypes(range(10))
-    p = W.population_from_genotypes(g)
-    q = W.random_trees(10)
+    g = WL.tree_genotypes(range(10))
+    p = WL.population_from_genotypes(g)
+    q = WL.random_trees(10)
     for a in ("body_offset", "parent", "anchor_parent", "anchor_child", "rest_quat", "axis", "cpg", "q0", "v0"):
         np.testing.assert_array_equal(getattr(p, a), getattr(q, a))
+
+
+def test_flat_layout_round_trip_and_init_ranges():
+    p = WL.mlp_init(0)
+    assert p.shape == (164865,) and p.dtype == np.float32
+    Wl, bl = M.unflatten(p)
+    assert [w.shape for w in Wl] == [(128, 256), (256, 256), (256, 256), (256, 1)]
+    np.testing.assert_array_equal(M.flatten(Wl, bl), p)
+    assert np.abs(Wl[0]).max() <= 1 / np.sqrt(128) and np.abs(Wl[1]).max() <= 1 / 16
+    assert np.abs(Wl[0]).max() > 0.9 / np.sqrt(128)
+
+
+def test_standardize_moments():
+    rng = np.random.default_rng(18)
+    y = rng.gamma(2.0, 0.1, 5000)
+    z, mu, sd = M.standardize(y)
+    assert abs(z.mean()) < 1e-12 and abs(z.std() - 1.0) < 1e-12
+    assert abs(mu - np.mean(y)) < 1e-12 and abs(sd - np.std(y)) < 1e-12
+    z, mu, sd = M.standardize(np.full(10, 3.0))
+    assert (z == 0).all() and sd == 0

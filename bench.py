@@ -32,6 +32,8 @@ def parse():
     ap.add_argument("--horizon", type=int, default=5000)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-sample-steps", type=int, default=1000)
+    ap.add_argument("--surrogate", action="store_true",
+                    help="also run one surrogate-screened generation (200k labels, 1M pool) and report it")
     return ap.parse_args()
 
 
@@ -120,6 +122,9 @@ def main():
     }
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(pop, args.cpu_sample_steps)
+    if args.surrogate:
+        from paper_2502_11129_amd.screening import run as screening_run
+        out["surrogate"] = screening_run(log=lambda m: print(m, file=sys.stderr, flush=True))
     print(json.dumps(out), flush=True)
 
 

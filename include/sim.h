@@ -98,16 +98,35 @@ typedef struct {
 } sim_model_desc;
 
 /*
- * Options (may be NULL = defaults).  contacts_in_registers selects how many
- * contacts per variant keep their solver rows in registers (0 = the tuned
- * default); contacts beyond it spill to the workspace.  Results do not depend
- * on it (same arithmetic, different storage).  use_graph != 0 replays
- * sim_rollout through a captured hipGraph.
+ * Options (may be NULL = defaults).  None of them changes results (same
+ * arithmetic in every configuration); they choose how the population is laid
+ * out and launched, and are what the autotuner searches over.
+ *  contacts_in_registers  contacts per variant whose solver rows stay in
+ *                         registers, for every bin (0 = ncr_by_nvc, else the
+ *                         first compiled kernel of the bin); contacts beyond
+ *                         it spill to the workspace
+ *  use_graph              != 0: sim_rollout replays a captured hipGraph
+ *  steps_per_launch       simulation steps per kernel launch (0 = 1000)
+ *  streams                concurrent streams the bins are spread over, by
+ *                         longest-first assignment (0 = one per bin; 1 = the
+ *                         caller's stream only)
+ *  min_body_slots         0 or 16: smallest body capacity that holds each
+ *                         variant; 32: every variant in 32-body kernels (fewer
+ *                         bins)
+ *  ncr_by_nvc[6]          per DoF capacity 8, 12, 16, 20, 24, 28: contacts in
+ *                         registers (0 = the bin's first compiled kernel)
+ *  time_launches          != 0: every bin's launches are bracketed by HIP
+ *                         events on the bin's stream (sim_launch_times)
  */
 typedef struct {
   int32_t contacts_in_registers;
   int32_t use_graph;
-  int32_t reserved[6];
+  int32_t steps_per_launch;
+  int32_t streams;
+  int32_t min_body_slots;
+  int32_t ncr_by_nvc[6];
+  int32_t time_launches;
+  int32_t reserved[4];
 } sim_options;
 
 typedef struct sim_handle sim_handle;
@@ -177,6 +196,59 @@ int sim_rollout_host(sim_handle* h, int32_t T, int32_t host_threads, float* fitn
 /* Description of the packing: number of bins and, per bin, (nv capacity,
  * body capacity, contacts in registers, variants).  info has 4*max_bins ints. */
 int sim_bins(const sim_handle* h, int32_t* n_bins, int32_t* info, int32_t max_bins);
+
+/* Bin of every variant (user order), an index into the sim_bins order.
+ * bin: [n_variants] ints.  Host only. */
+int sim_variant_bins(const sim_handle* h, int32_t* bin);
+
+/* With time_launches set: per bin (in sim_bins order), the milliseconds
+ * between the start of its first and the end of its last launch in the most
+ * recent sim_step_batch / sim_rollout, and the number of launches.  Any
+ * output may be NULL.  Synchronises on the recorded events. */
+int sim_launch_times(const sim_handle* h, int32_t* n_bins, float* ms, int32_t* launches, int32_t max_bins);
+
+/* The compiled kernel variants: per variant (nv capacity, body capacity,
+ * contacts in registers).  info has 3*max_variants ints; *n receives the
+ * total count.  Host only. */
+int sim_kernel_variants(int32_t* n, int32_t* info, int32_t max_variants);
+
+/*
+ * Allocation of a population between the GPU and host threads (paper Sec. 6:
+ * pilot benchmark, then a share for each side), host only, no device work.
+ * Inputs: n variants; the measured GPU time gpu_s[k] of pilot rollouts of
+ * gpu_n[k] variants (n_points >= 1 points, gpu_n ascending, > 0); the host
+ * time per variant of the thread pool for the same steps (host_s_per_variant
+ * > 0).  GPU time of m variants is modelled by the measured curve: flat below
+ * the first point, piecewise linear between points, extended with the last
+ * segment's slope; host time of h variants is h * host_s_per_variant.
+ * Outputs (any may be NULL):
+ *   n_host_paper     the paper's rule: each side's share is inversely
+ *                    proportional to its time for the whole population,
+ *                    n_host = round(n * t_gpu(n) / (t_gpu(n) + t_host(n)))
+ *   n_host_makespan  the smallest h minimising max(t_gpu(n - h), t_host(h))
+ *   makespan_paper_s, makespan_opt_s: modelled makespans of the two
+ * For a linear GPU curve through the origin both rules give the same h.
+ * Errors: SIM_E_INVALID, message in sim_last_error(NULL). */
+int sim_split_allocation(int32_t n, const int32_t* gpu_n, const double* gpu_s, int32_t n_points,
+                         double host_s_per_variant, int32_t* n_host_paper, int32_t* n_host_makespan,
+                         double* makespan_paper_s, double* makespan_opt_s);
+
+/* Pilot measurements and the resulting allocation (paper Sec. 6 "Initial
+ * Benchmarking"): GPU rollouts of T_pilot steps for 1, 1/2, 1/4, 1/8 and
+ * 1/16 of every bin (HIP events on `stream`, after one warm-up), and a host
+ * rollout of host_sample variants spread over the bins on host_threads
+ * threads.  Leaves every variant reset to its initial state (as after
+ * sim_bind).  Synchronises `stream`. */
+typedef struct {
+  int32_t n_host_paper, n_host_makespan;
+  double makespan_paper_s, makespan_opt_s; /* modelled, for T_pilot steps                */
+  double host_s_per_variant;               /* measured                                   */
+  int32_t gpu_points, reserved;
+  int32_t gpu_n[8];
+  double gpu_s[8];                         /* measured, ascending gpu_n                   */
+} sim_split_plan;
+int sim_plan_split(sim_handle* h, int32_t T_pilot, int32_t host_threads, int32_t host_sample, void* stream,
+                   sim_split_plan* plan);
 
 void sim_destroy(sim_handle* h);
 

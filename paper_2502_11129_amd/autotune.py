@@ -1,0 +1,98 @@
+"""Autotuner of the launch and packing options (sim_options).
+
+The options never change results (same arithmetic in every layout); they
+change how the population is cut into DoF bins and launched: contacts kept in
+registers per DoF capacity, body capacity (merging bins), steps per launch
+and the number of concurrent streams.  The tuner times short pilot rollouts
+of the actual population (HIP events on the stream) and keeps the fastest
+setting of one option at a time (coordinate descent, fixed order), so the
+search costs a few dozen pilots.
+"""
+from __future__ import annotations
+
+import json
+import os
+
+from . import sim as S
+
+
+def _time_rollout(pop, T, reps, **opts):
+    import torch
+    sim = S.Simulator(pop, **opts)
+    st = torch.cuda.current_stream()
+    sim.rollout(T)                                  # warm-up
+    best = float("inf")
+    for _ in range(reps):
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record(st)
+        sim.rollout(T)
+        e1.record(st)
+        e1.synchronize()
+        best = min(best, e0.elapsed_time(e1) / 1e3)
+    bins = sim.bins()
+    sim.close()
+    return best, bins
+
+
+def candidates_ncr(nvc):
+    """Compiled contact-register budgets for a DoF capacity (any body capacity)."""
+    return sorted({k[2] for k in S.kernel_variants() if k[0] == nvc})
+
+
+def autotune(pop, T_pilot=1000, reps=2, log=None, cache=None):
+    """Returns (best options dict, list of trial records).  `cache`: optional
+    JSON file path keyed by the population's DoF/body signature."""
+    import numpy as np
+    key = None
+    if cache:
+        nv = np.asarray(pop.nv)
+        nb = np.asarray(pop.n_bodies)
+        key = f"{pop.name}:{pop.n_variants}:{np.bincount(nv).tolist()}:{np.bincount(nb).tolist()}:{T_pilot}"
+        if os.path.exists(cache):
+            with open(cache) as f:
+                store = json.load(f)
+            if key in store:
+                return store[key]["options"], store[key]["trials"]
+    trials = []
+
+    def run(opts):
+        t, bins = _time_rollout(pop, T_pilot, reps, **opts)
+        trials.append(dict(options=dict(opts), seconds=t, bins=bins))
+        if log:
+            log(f"autotune {opts}: {t * 1e3:.2f} ms, bins {[(b[0], b[1], b[2], b[3]) for b in bins]}")
+        return t
+
+    best = dict(min_body_slots=0, streams=0, steps_per_launch=0, ncr_by_nvc={})
+    best_t = run(best)
+    space = [("min_body_slots", [32]), ("streams", [4, 2, 1]), ("steps_per_launch", [250, 500])]
+    for name, values in space:
+        for v in values:
+            cand = dict(best, **{name: v})
+            t = run(cand)
+            if t < best_t * 0.98:            # keep only clear wins
+                best, best_t = cand, t
+    # contacts in registers, one DoF capacity at a time
+    probe = S.Handle(pop, **best)
+    nvcs = sorted({b[0] for b in probe.bins()})
+    probe.close()
+    for nvc in nvcs:
+        for ncr in candidates_ncr(nvc):
+            cur = best["ncr_by_nvc"].get(nvc)
+            if ncr == cur:
+                continue
+            cand = dict(best, ncr_by_nvc={**best["ncr_by_nvc"], nvc: ncr})
+            try:
+                t = run(cand)
+            except S.SimError:
+                continue                      # no kernel with that budget for this body capacity
+            if t < best_t * 0.98:
+                best, best_t = cand, t
+    if cache:
+        store = {}
+        if os.path.exists(cache):
+            with open(cache) as f:
+                store = json.load(f)
+        store[key] = dict(options=best, trials=trials)
+        with open(cache, "w") as f:
+            json.dump(store, f)
+    return best, trials

@@ -25,7 +25,7 @@ namespace {
 constexpr int kNvCaps[] = {8, 12, 16, 20, 24, 28};
 constexpr int kMaxNv = 28;
 constexpr int kMaxBodiesPerVariant = 32;
-constexpr int kStepsPerLaunch = 1000;  // long runs are split so each launch stays short
+constexpr int kStepsPerLaunch = 1000;  // default: long runs are split so each launch stays short
 
 std::string g_create_error;
 
@@ -41,6 +41,8 @@ struct Bin {
   int lvl_stride = 0;
   long long ovf_stride = 0;
   BinArgs args{};
+  hipEvent_t t_begin = nullptr, t_end = nullptr;  // launch timing (time_launches)
+  int timed_launches = 0;
 };
 
 size_t align256(size_t x) { return (x + 255) & ~size_t(255); }
@@ -67,9 +69,12 @@ struct sim_handle {
   hipStream_t cap_stream = nullptr;
   int split_T = 0;
   // bins run concurrently: one library stream per bin beyond the first, fork/join by events
-  std::vector<hipStream_t> bin_streams;
+  std::vector<hipStream_t> bin_streams;   // library streams 1..; stream 0 is the caller's
   std::vector<hipEvent_t> join_events;
   hipEvent_t fork_event = nullptr;
+  std::vector<int> stream_of;             // bin -> stream index (0 = caller's)
+  int n_streams = 1;
+  int steps_per_launch = kStepsPerLaunch;
 };
 
 namespace {
@@ -107,8 +112,14 @@ int launch_bin(sim_handle* h, Bin& b, int n_steps, bool reset, hipStream_t st, i
   if (count == 0) return SIM_OK;
   int done = 0;
   bool first = true;
+  const bool timed = h->opts.time_launches && b.t_begin;
+  if (timed) {
+    int rc = dev_check(h, hipEventRecord(b.t_begin, st), "timing record");
+    if (rc) return rc;
+    b.timed_launches = 0;
+  }
   while (first || done < n_steps) {
-    const int chunk = std::min(kStepsPerLaunch, n_steps - done);
+    const int chunk = std::min(h->steps_per_launch, n_steps - done);
     BinArgs a = b.args;
     a.n_steps = chunk;
     a.reset = (reset && first) ? 1 : 0;
@@ -117,23 +128,26 @@ int launch_bin(sim_handle* h, Bin& b, int n_steps, bool reset, hipStream_t st, i
     if (e != hipSuccess) return dev_check(h, e, "kernel launch");
     done += chunk;
     first = false;
+    if (timed) ++b.timed_launches;
   }
+  if (timed) return dev_check(h, hipEventRecord(b.t_end, st), "timing record");
   return SIM_OK;
 }
 
 int launch_all(sim_handle* h, int n_steps, bool reset, hipStream_t st, const std::vector<int>* counts = nullptr) {
   const size_t nb = h->bins.size();
+  const int ns = h->n_streams;
+  auto stream = [&](size_t bi) { return h->stream_of[bi] == 0 ? st : h->bin_streams[h->stream_of[bi] - 1]; };
   int rc;
-  if (nb > 1) {
+  if (ns > 1) {
     if ((rc = dev_check(h, hipEventRecord(h->fork_event, st), "fork record"))) return rc;
-    for (size_t i = 1; i < nb; ++i)
+    for (int i = 1; i < ns; ++i)
       if ((rc = dev_check(h, hipStreamWaitEvent(h->bin_streams[i - 1], h->fork_event, 0), "fork wait"))) return rc;
   }
-  // largest bins first on the side streams, the caller's stream takes bin 0
-  for (size_t i = 1; i < nb; ++i)
-    if ((rc = launch_bin(h, h->bins[i], n_steps, reset, h->bin_streams[i - 1], counts ? (*counts)[i] : -1))) return rc;
-  if ((rc = launch_bin(h, h->bins[0], n_steps, reset, st, counts ? (*counts)[0] : -1))) return rc;
-  for (size_t i = 1; i < nb; ++i) {
+  // bins are ordered by decreasing cost; each stream receives its bins in that order
+  for (size_t i = 0; i < nb; ++i)
+    if ((rc = launch_bin(h, h->bins[i], n_steps, reset, stream(i), counts ? (*counts)[i] : -1))) return rc;
+  for (int i = 1; i < ns; ++i) {
     if ((rc = dev_check(h, hipEventRecord(h->join_events[i - 1], h->bin_streams[i - 1]), "join record"))) return rc;
     if ((rc = dev_check(h, hipStreamWaitEvent(st, h->join_events[i - 1], 0), "join wait"))) return rc;
   }
@@ -212,6 +226,17 @@ int sim_create(const sim_model_desc* d, const sim_options* opts, sim_handle** ou
   if (d->kp < 0 || d->kd < 0 || d->tau_max < 0 || d->k_contact < 0 || d->b_contact < 0)
     return bad("gains, torque limit and contact constants must be >= 0");
   if (opts) hp->opts = *opts;
+  {
+    const sim_options& o = hp->opts;
+    if (o.contacts_in_registers < 0 || o.steps_per_launch < 0 || o.streams < 0)
+      return bad("contacts_in_registers, steps_per_launch and streams must be >= 0");
+    if (o.min_body_slots != 0 && o.min_body_slots != 16 && o.min_body_slots != 32)
+      return bad("min_body_slots must be 0, 16 or 32");
+    if (o.time_launches && o.use_graph) return bad("time_launches and use_graph cannot be combined");
+    for (int k = 0; k < 6; ++k)
+      if (o.ncr_by_nvc[k] < 0) return bad("ncr_by_nvc entries must be >= 0");
+    hp->steps_per_launch = o.steps_per_launch > 0 ? o.steps_per_launch : kStepsPerLaunch;
+  }
   const int n = d->n_variants;
   hp->n = n;
   hp->root_type = d->root_type;
@@ -275,22 +300,27 @@ int sim_create(const sim_model_desc* d, const sim_options* opts, sim_handle** ou
     if (std::fabs(qn - 1.f) > 1e-5f) return bad("variant " + std::to_string(i) + ": root quaternion must be a unit quaternion");
   }
   // bins: smallest DoF capacity, body slots from the body count
-  const int want_ncr = hp->opts.contacts_in_registers;
+  auto ncr_for = [&](int nvc) {
+    if (hp->opts.contacts_in_registers > 0) return hp->opts.contacts_in_registers;
+    const int k = nvc / 4 - 2;
+    return (k >= 0 && k < 6) ? hp->opts.ncr_by_nvc[k] : 0;
+  };
   std::vector<std::pair<int, int>> keys(n);
   for (int i = 0; i < n; ++i) {
     int nvc = 0;
     for (int c : kNvCaps)
       if (hp->nv[i] <= c) { nvc = c; break; }
-    const int sb_need = info[i].nb > 16 ? 2 : 1;
+    int sb_need = info[i].nb > 16 ? 2 : 1;
+    if (hp->opts.min_body_slots == 32) sb_need = 2;
     // smallest compiled (nv capacity, body slots) that holds the variant
     int sb = 0;
     for (; nvc <= kMaxNv; nvc += 4) {
-      if (find_variant(nvc, sb_need, want_ncr)) { sb = sb_need; break; }
-      if (sb_need == 1 && find_variant(nvc, 2, want_ncr)) { sb = 2; break; }
+      if (find_variant(nvc, sb_need, ncr_for(nvc))) { sb = sb_need; break; }
+      if (sb_need == 1 && find_variant(nvc, 2, ncr_for(nvc))) { sb = 2; break; }
     }
     if (!sb)
       return bad("no compiled kernel for nv=" + std::to_string(hp->nv[i]) + " bodies=" + std::to_string(info[i].nb) +
-                 " contacts_in_registers=" + std::to_string(want_ncr));
+                 " contacts_in_registers=" + std::to_string(ncr_for(nvc > kMaxNv ? kMaxNv : nvc)));
     keys[i] = {nvc, sb};
   }
   std::vector<std::pair<int, int>> uk = keys;
@@ -302,7 +332,7 @@ int sim_create(const sim_model_desc* d, const sim_options* opts, sim_handle** ou
     Bin b;
     b.nvc = kk.first;
     b.sb = kk.second;
-    const KernelVariant* kv = find_variant(b.nvc, b.sb, want_ncr);
+    const KernelVariant* kv = find_variant(b.nvc, b.sb, ncr_for(b.nvc));
     b.ncr = kv->ncr;
     b.fn = kv->fn;
     for (int i = 0; i < n; ++i)
@@ -314,8 +344,24 @@ int sim_create(const sim_model_desc* d, const sim_options* opts, sim_handle** ou
     });
     hp->bins.push_back(std::move(b));
   }
-  std::stable_sort(hp->bins.begin(), hp->bins.end(),
-                   [](const Bin& x, const Bin& y) { return x.users.size() * x.nvc > y.users.size() * y.nvc; });
+  // cost order: variants x (nv capacity)^2 per bin, most expensive first
+  auto cost = [](const Bin& b) { return (double)b.users.size() * b.nvc * b.nvc * (b.sb == 2 ? 1.25 : 1.0); };
+  std::stable_sort(hp->bins.begin(), hp->bins.end(), [&](const Bin& x, const Bin& y) { return cost(x) > cost(y); });
+  // streams: longest-first assignment of the bins to the least-loaded stream
+  {
+    const int nbins = (int)hp->bins.size();
+    const int ns = hp->opts.streams == 0 ? nbins : std::min(hp->opts.streams, nbins);
+    hp->n_streams = std::max(1, ns);
+    std::vector<double> load(hp->n_streams, 0.0);
+    hp->stream_of.assign(nbins, 0);
+    for (int bi = 0; bi < nbins; ++bi) {
+      int best = 0;
+      for (int k = 1; k < hp->n_streams; ++k)
+        if (load[k] < load[best]) best = k;
+      hp->stream_of[bi] = best;
+      load[best] += cost(hp->bins[bi]);
+    }
+  }
   // pack
   for (size_t bi = 0; bi < hp->bins.size(); ++bi) {
     Bin& b = hp->bins[bi];
@@ -415,10 +461,10 @@ int sim_bind(sim_handle* h, void* ws, size_t bytes, void* stream) {
   if (h->device_error) return SIM_E_DEVICE;
   hipStream_t st = (hipStream_t)stream;
   h->ws = (char*)ws;
-  if (h->bin_streams.empty() && h->bins.size() > 1) {
+  if (h->bin_streams.empty() && h->n_streams > 1) {
     int rc = dev_check(h, hipEventCreateWithFlags(&h->fork_event, hipEventDisableTiming), "event create");
     if (rc) return rc;
-    for (size_t i = 1; i < h->bins.size(); ++i) {
+    for (int i = 1; i < h->n_streams; ++i) {
       hipStream_t s2;
       hipEvent_t e2;
       if ((rc = dev_check(h, hipStreamCreateWithFlags(&s2, hipStreamNonBlocking), "stream create"))) return rc;
@@ -431,6 +477,10 @@ int sim_bind(sim_handle* h, void* ws, size_t bytes, void* stream) {
     char* base = h->ws;
     const size_t m = b.users.size();
     int rc;
+    if (h->opts.time_launches && !b.t_begin) {
+      if ((rc = dev_check(h, hipEventCreate(&b.t_begin), "event create"))) return rc;
+      if ((rc = dev_check(h, hipEventCreate(&b.t_end), "event create"))) return rc;
+    }
     if ((rc = dev_check(h, hipMemcpyAsync(base + b.o_hdr, b.hdr.data(), m * HW_WORDS * 4, hipMemcpyHostToDevice, st), "upload"))) return rc;
     if ((rc = dev_check(h, hipMemcpyAsync(base + b.o_hdrf, b.hdrf.data(), m * HF_WORDS * 4, hipMemcpyHostToDevice, st), "upload"))) return rc;
     if ((rc = dev_check(h, hipMemcpyAsync(base + b.o_body, b.body.data(), b.body.size() * 4, hipMemcpyHostToDevice, st), "upload"))) return rc;
@@ -719,6 +769,145 @@ int sim_rollout_split(sim_handle* h, int32_t T, int32_t n_host, int32_t host_thr
   return SIM_OK;
 }
 
+int sim_variant_bins(const sim_handle* h, int32_t* bin) {
+  if (!h || !bin) return SIM_E_INVALID;
+  for (int i = 0; i < h->n; ++i) bin[i] = h->bin_of[i];
+  return SIM_OK;
+}
+
+int sim_launch_times(const sim_handle* hc, int32_t* n_bins, float* ms, int32_t* launches, int32_t max_bins) {
+  sim_handle* h = const_cast<sim_handle*>(hc);
+  if (!h) return SIM_E_INVALID;
+  if (!h->bound) return fail(h, SIM_E_STATE, "sim_bind has not been called");
+  if (!h->opts.time_launches) return fail(h, SIM_E_STATE, "the handle was created without time_launches");
+  if (n_bins) *n_bins = (int32_t)h->bins.size();
+  for (int i = 0; i < (int)h->bins.size() && i < max_bins; ++i) {
+    Bin& b = h->bins[i];
+    if (ms) {
+      int rc = dev_check(h, hipEventSynchronize(b.t_end), "timing sync");
+      if (rc) return rc;
+      float t = 0.f;
+      if ((rc = dev_check(h, hipEventElapsedTime(&t, b.t_begin, b.t_end), "timing read"))) return rc;
+      ms[i] = t;
+    }
+    if (launches) launches[i] = b.timed_launches;
+  }
+  return SIM_OK;
+}
+
+int sim_kernel_variants(int32_t* n, int32_t* info, int32_t max_variants) {
+  if (!n) return SIM_E_INVALID;
+  *n = kNumKernelVariants;
+  for (int i = 0; i < kNumKernelVariants && i < max_variants && info; ++i) {
+    info[3 * i] = kKernelVariants[i].nvc;
+    info[3 * i + 1] = 16 * kKernelVariants[i].sb;
+    info[3 * i + 2] = kKernelVariants[i].ncr;
+  }
+  return SIM_OK;
+}
+
+int sim_split_allocation(int32_t n, const int32_t* gpu_n, const double* gpu_s, int32_t n_points,
+                         double host_s_per_variant, int32_t* n_host_paper, int32_t* n_host_makespan,
+                         double* makespan_paper_s, double* makespan_opt_s) {
+  if (n < 0 || !gpu_n || !gpu_s || n_points < 1 || !(host_s_per_variant > 0.0) || !std::isfinite(host_s_per_variant))
+    return fail(nullptr, SIM_E_INVALID, "need n >= 0, >= 1 GPU point and host_s_per_variant > 0");
+  for (int k = 0; k < n_points; ++k) {
+    if (gpu_n[k] <= 0 || !(gpu_s[k] >= 0.0) || !std::isfinite(gpu_s[k]))
+      return fail(nullptr, SIM_E_INVALID, "GPU points need n > 0 and a finite time >= 0");
+    if (k && gpu_n[k] <= gpu_n[k - 1]) return fail(nullptr, SIM_E_INVALID, "GPU points must have ascending n");
+  }
+  // GPU time of m variants: 0 for none, flat below the first point, piecewise
+  // linear between points, the last segment's slope beyond the last point
+  auto t_gpu = [&](double m) -> double {
+    if (m <= 0) return 0.0;
+    if (m <= gpu_n[0]) return gpu_s[0];
+    for (int k = 1; k < n_points; ++k)
+      if (m <= gpu_n[k])
+        return gpu_s[k - 1] + (gpu_s[k] - gpu_s[k - 1]) * (m - gpu_n[k - 1]) / (gpu_n[k] - gpu_n[k - 1]);
+    const int a = n_points >= 2 ? n_points - 2 : 0, b = n_points - 1;
+    const double slope = n_points >= 2 ? (gpu_s[b] - gpu_s[a]) / (gpu_n[b] - gpu_n[a]) : gpu_s[0] / gpu_n[0];
+    return gpu_s[b] + slope * (m - gpu_n[b]);
+  };
+  auto t_host = [&](double h2) { return h2 * host_s_per_variant; };
+  auto span = [&](int32_t h2) { return std::max(t_gpu((double)n - h2), t_host(h2)); };
+  const double tg = t_gpu(n), tc = t_host(n);
+  int32_t hp = (tg + tc > 0) ? (int32_t)std::llround(n * tg / (tg + tc)) : 0;
+  hp = std::min(std::max(hp, 0), n);
+  int32_t best = 0;
+  double bs = span(0);
+  for (int32_t h2 = 1; h2 <= n; ++h2) {
+    const double v = span(h2);
+    if (v < bs) { bs = v; best = h2; }
+  }
+  if (n_host_paper) *n_host_paper = hp;
+  if (n_host_makespan) *n_host_makespan = best;
+  if (makespan_paper_s) *makespan_paper_s = span(hp);
+  if (makespan_opt_s) *makespan_opt_s = bs;
+  return SIM_OK;
+}
+
+int sim_plan_split(sim_handle* h, int32_t T_pilot, int32_t host_threads, int32_t host_sample, void* stream,
+                   sim_split_plan* plan) {
+  if (!h) return SIM_E_INVALID;
+  if (!h->bound) return fail(h, SIM_E_STATE, "sim_bind has not been called");
+  if (h->device_error) return SIM_E_DEVICE;
+  if (T_pilot < 1 || host_threads < 1 || host_sample < 1 || !plan)
+    return fail(h, SIM_E_INVALID, "need T_pilot >= 1, host_threads >= 1, host_sample >= 1 and a plan");
+  hipStream_t st = (hipStream_t)stream;
+  std::memset(plan, 0, sizeof(*plan));
+  hipEvent_t e0, e1;
+  int rc;
+  if ((rc = dev_check(h, hipEventCreate(&e0), "event create"))) return rc;
+  if ((rc = dev_check(h, hipEventCreate(&e1), "event create"))) { hipEventDestroy(e0); return rc; }
+  // GPU curve: 1/16 .. 1 of every bin, after one warm-up of the whole population
+  const int fr[] = {16, 8, 4, 2, 1};
+  rc = launch_all(h, T_pilot, true, st);
+  int np = 0;
+  for (int fi = 0; !rc && fi < 5; ++fi) {
+    std::vector<int> counts(h->bins.size());
+    int tot = 0;
+    for (size_t bi = 0; bi < h->bins.size(); ++bi) {
+      const int m = (int)h->bins[bi].users.size();
+      counts[bi] = std::max(m > 0 ? 1 : 0, (m + fr[fi] - 1) / fr[fi]);
+      tot += counts[bi];
+    }
+    if (np && tot <= plan->gpu_n[np - 1]) continue;
+    rc = dev_check(h, hipEventRecord(e0, st), "event record");
+    if (!rc) rc = launch_all(h, T_pilot, true, st, &counts);
+    if (!rc) rc = dev_check(h, hipEventRecord(e1, st), "event record");
+    if (!rc) rc = dev_check(h, hipEventSynchronize(e1), "event sync");
+    float ms = 0.f;
+    if (!rc) rc = dev_check(h, hipEventElapsedTime(&ms, e0, e1), "event time");
+    if (!rc) {
+      plan->gpu_n[np] = tot;
+      plan->gpu_s[np] = ms / 1e3;
+      ++np;
+    }
+  }
+  hipEventDestroy(e0);
+  hipEventDestroy(e1);
+  // restore the initial state of every variant
+  if (!rc) rc = launch_all(h, 0, true, st);
+  if (!rc) rc = dev_check(h, hipStreamSynchronize(st), "pilot sync");
+  if (rc) return rc;
+  plan->gpu_points = np;
+  // host pilot: host_sample variants spread over the bins
+  std::vector<std::pair<int, int>> work;
+  const int take = std::min(host_sample, h->n);
+  for (int j = 0; j < take; ++j) {
+    const int user = (int)((long long)j * h->n / take);
+    work.push_back({h->bin_of[user], h->slot_of[user]});
+  }
+  std::vector<HostVariantState> out;
+  const int saved_T = h->split_T;
+  h->split_T = T_pilot;
+  const double host_wall = run_host(h, work, host_threads, out);
+  h->split_T = saved_T;
+  plan->host_s_per_variant = host_wall / take;
+  return sim_split_allocation(h->n, plan->gpu_n, plan->gpu_s, np, plan->host_s_per_variant, &plan->n_host_paper,
+                              &plan->n_host_makespan, &plan->makespan_paper_s, &plan->makespan_opt_s);
+}
+
 int sim_bins(const sim_handle* h, int32_t* n_bins, int32_t* info, int32_t max_bins) {
   if (!h || !n_bins) return SIM_E_INVALID;
   *n_bins = (int32_t)h->bins.size();
@@ -739,6 +928,10 @@ void sim_destroy(sim_handle* h) {
   for (hipStream_t s2 : h->bin_streams) hipStreamDestroy(s2);
   for (hipEvent_t e2 : h->join_events) hipEventDestroy(e2);
   if (h->fork_event) hipEventDestroy(h->fork_event);
+  for (Bin& b : h->bins) {
+    if (b.t_begin) hipEventDestroy(b.t_begin);
+    if (b.t_end) hipEventDestroy(b.t_end);
+  }
   delete h;
 }
 

@@ -19,7 +19,7 @@ SIM_ROOT_FREE, SIM_ROOT_FIXED = 0, 1
 SIM_HOST, SIM_DEVICE = 0, 1
 EXPORTED = ("sim_create", "sim_workspace_bytes", "sim_bind", "sim_step_batch", "sim_rollout", "sim_fitness",
             "sim_get_state", "sim_set_state", "sim_counters", "sim_rollout_split", "sim_rollout_host", "sim_bins",
-            "sim_destroy", "sim_last_error")
+            "sim_variant_bins", "sim_launch_times", "sim_kernel_variants", "sim_split_allocation", "sim_plan_split", "sim_destroy", "sim_last_error")
 
 _F = C.POINTER(C.c_float)
 _I32 = C.POINTER(C.c_int32)
@@ -34,7 +34,32 @@ class sim_model_desc(C.Structure):
 
 
 class sim_options(C.Structure):
-    _fields_ = [("contacts_in_registers", C.c_int32), ("use_graph", C.c_int32), ("reserved", C.c_int32 * 6)]
+    _fields_ = [("contacts_in_registers", C.c_int32), ("use_graph", C.c_int32), ("steps_per_launch", C.c_int32),
+                ("streams", C.c_int32), ("min_body_slots", C.c_int32), ("ncr_by_nvc", C.c_int32 * 6),
+                ("time_launches", C.c_int32), ("reserved", C.c_int32 * 4)]
+
+
+NVC_CAPS = (8, 12, 16, 20, 24, 28)
+
+
+def make_options(contacts_in_registers=0, use_graph=False, steps_per_launch=0, streams=0, min_body_slots=0,
+                 ncr_by_nvc=None, time_launches=False):
+    o = sim_options()
+    o.contacts_in_registers = int(contacts_in_registers)
+    o.use_graph = int(bool(use_graph))
+    o.steps_per_launch = int(steps_per_launch)
+    o.streams = int(streams)
+    o.min_body_slots = int(min_body_slots)
+    o.time_launches = int(bool(time_launches))
+    for nvc, v in (ncr_by_nvc or {}).items():
+        o.ncr_by_nvc[NVC_CAPS.index(int(nvc))] = int(v)
+    return o
+
+
+class sim_split_plan(C.Structure):
+    _fields_ = [("n_host_paper", C.c_int32), ("n_host_makespan", C.c_int32), ("makespan_paper_s", C.c_double),
+                ("makespan_opt_s", C.c_double), ("host_s_per_variant", C.c_double), ("gpu_points", C.c_int32),
+                ("reserved", C.c_int32), ("gpu_n", C.c_int32 * 8), ("gpu_s", C.c_double * 8)]
 
 
 class sim_split_times(C.Structure):
@@ -77,13 +102,19 @@ def load():
     lib.sim_bins.argtypes = [P, _I32, _I32, C.c_int32]
     lib.sim_rollout_split.argtypes = [P, C.c_int32, C.c_int32, C.c_int32, VP, C.POINTER(sim_split_times)]
     lib.sim_rollout_host.argtypes = [P, C.c_int32, C.c_int32, _F, C.POINTER(C.c_double)]
+    lib.sim_kernel_variants.argtypes = [_I32, _I32, C.c_int32]
+    lib.sim_launch_times.argtypes = [P, _I32, _F, _I32, C.c_int32]
+    lib.sim_variant_bins.argtypes = [P, _I32]
+    lib.sim_split_allocation.argtypes = [C.c_int32, _I32, C.POINTER(C.c_double), C.c_int32, C.c_double, _I32, _I32,
+                                         C.POINTER(C.c_double), C.POINTER(C.c_double)]
+    lib.sim_plan_split.argtypes = [P, C.c_int32, C.c_int32, C.c_int32, VP, C.POINTER(sim_split_plan)]
     lib.sim_destroy.argtypes = [P]
     lib.sim_destroy.restype = None
     lib.sim_last_error.argtypes = [P]
     lib.sim_last_error.restype = C.c_char_p
     for name in ("sim_workspace_bytes", "sim_bind", "sim_step_batch", "sim_rollout", "sim_fitness",
                  "sim_get_state", "sim_set_state", "sim_counters", "sim_bins", "sim_rollout_split",
-                 "sim_rollout_host"):
+                 "sim_rollout_host", "sim_variant_bins", "sim_launch_times", "sim_kernel_variants", "sim_split_allocation", "sim_plan_split"):
         getattr(lib, name).restype = I
     _lib = lib
     return lib
@@ -116,16 +147,41 @@ def make_desc(pop):
     return d, keep
 
 
-class Handle:
-    """Host-only handle (sim_create): validation and packing, no device work."""
+def kernel_variants():
+    """Compiled kernels as (nv capacity, body capacity, contacts in registers)."""
+    lib = load()
+    n = C.c_int32()
+    info = np.zeros(3 * 64, np.int32)
+    assert lib.sim_kernel_variants(C.byref(n), info.ctypes.data_as(_I32), 64) == SIM_OK
+    return [tuple(int(x) for x in info[3 * i:3 * i + 3]) for i in range(n.value)]
 
-    def __init__(self, pop, contacts_in_registers: int = 0, use_graph: bool = False):
+
+def split_allocation(n, gpu_n, gpu_s, host_s_per_variant):
+    """The C ABI's allocation rule on measured curves; returns a dict."""
+    lib = load()
+    gn = np.ascontiguousarray(gpu_n, np.int32)
+    gs = np.ascontiguousarray(gpu_s, np.float64)
+    hp, hm = C.c_int32(), C.c_int32()
+    mp, mo = C.c_double(), C.c_double()
+    rc = lib.sim_split_allocation(int(n), gn.ctypes.data_as(_I32), gs.ctypes.data_as(C.POINTER(C.c_double)),
+                                  len(gn), float(host_s_per_variant), C.byref(hp), C.byref(hm), C.byref(mp),
+                                  C.byref(mo))
+    if rc != SIM_OK:
+        raise SimError(rc, lib.sim_last_error(None).decode())
+    return dict(n_host_paper=hp.value, n_host_makespan=hm.value, makespan_paper_s=mp.value,
+                makespan_opt_s=mo.value)
+
+
+class Handle:
+    """Host-only handle (sim_create): validation and packing, no device work.
+    Keyword options are those of sim_options (see make_options)."""
+
+    def __init__(self, pop, contacts_in_registers: int = 0, use_graph: bool = False, **options):
         self.lib = load()
         self.pop = pop
         desc, self._keep = make_desc(pop)
-        opts = sim_options()
-        opts.contacts_in_registers = int(contacts_in_registers)
-        opts.use_graph = int(bool(use_graph))
+        opts = make_options(contacts_in_registers, use_graph, **options)
+        self.options = dict(contacts_in_registers=contacts_in_registers, use_graph=use_graph, **options)
         h = C.c_void_p()
         rc = self.lib.sim_create(C.byref(desc), C.byref(opts), C.byref(h))
         if rc != SIM_OK:
@@ -150,6 +206,11 @@ class Handle:
         self._check(self.lib.sim_bins(self.h, C.byref(n), info.ctypes.data_as(_I32), 64))
         return [tuple(int(x) for x in info[4 * i:4 * i + 4]) for i in range(n.value)]
 
+    def variant_bins(self):
+        out = np.zeros(self.n, np.int32)
+        self._check(self.lib.sim_variant_bins(self.h, out.ctypes.data_as(_I32)))
+        return out
+
     def rollout_host(self, T: int, threads: int = 1):
         """Every variant on host threads (no device work); returns (fitness, seconds)."""
         fit = np.zeros(self.n, np.float32)
@@ -169,9 +230,9 @@ class Handle:
 class Simulator(Handle):
     """A bound simulator: workspace allocated by torch on the current device."""
 
-    def __init__(self, pop, contacts_in_registers: int = 0, use_graph: bool = False, device=None):
+    def __init__(self, pop, contacts_in_registers: int = 0, use_graph: bool = False, device=None, **options):
         import torch
-        super().__init__(pop, contacts_in_registers, use_graph)
+        super().__init__(pop, contacts_in_registers, use_graph, **options)
         self.torch = torch
         self.device = torch.device("cuda" if device is None else device)
         self.ws = torch.empty(max(self.workspace_bytes(), 256), dtype=torch.uint8, device=self.device)
@@ -219,6 +280,24 @@ class Simulator(Handle):
         self._check(self.lib.sim_rollout_split(self.h, int(T), int(n_host), int(threads), self.stream(), C.byref(t)))
         return dict(combined_s=t.combined_s, gpu_s=t.gpu_s, host_s=t.host_s, n_gpu=t.n_gpu, n_host=t.n_host,
                     host_threads=t.host_threads)
+
+    def launch_times(self):
+        """Per bin (sim_bins order): (milliseconds of its launches, number of launches) of the last run."""
+        n = C.c_int32()
+        ms = np.zeros(64, np.float32)
+        cnt = np.zeros(64, np.int32)
+        self._check(self.lib.sim_launch_times(self.h, C.byref(n), ms.ctypes.data_as(_F), cnt.ctypes.data_as(_I32), 64))
+        return [(float(ms[i]), int(cnt[i])) for i in range(n.value)]
+
+    def plan_split(self, T_pilot: int, threads: int, host_sample: int):
+        """Pilot measurements and the two allocations (paper rule, makespan rule)."""
+        p = sim_split_plan()
+        self._check(self.lib.sim_plan_split(self.h, int(T_pilot), int(threads), int(host_sample), self.stream(),
+                                            C.byref(p)))
+        k = p.gpu_points
+        return dict(n_host_paper=p.n_host_paper, n_host_makespan=p.n_host_makespan,
+                    makespan_paper_s=p.makespan_paper_s, makespan_opt_s=p.makespan_opt_s,
+                    host_s_per_variant=p.host_s_per_variant, gpu_n=list(p.gpu_n[:k]), gpu_s=list(p.gpu_s[:k]))
 
     def counters(self):
         a = np.zeros(self.n, np.uint64)

@@ -1,0 +1,53 @@
+"""Launch and packing options change layout, never results (GPU); the split
+pilot leaves the population in its initial state."""
+import sys
+
+import numpy as np
+import pytest
+
+from paper_2502_11129_amd import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+
+def _say(msg):
+    print(msg, flush=True)
+    sys.stdout.flush()
+
+
+def test_options_give_bitwise_identical_results():
+    from paper_2502_11129_amd.sim import Simulator
+    pop = W.random_trees(indices=W.TREE_SPOTCHECK)
+    T = 300
+    ref = Simulator(pop)
+    ref.rollout(T)
+    Fr = ref.fitness()
+    qr, vr, kr = ref.get_state()
+    for opts in (dict(streams=1), dict(streams=2), dict(steps_per_launch=97), dict(min_body_slots=32),
+                 dict(ncr_by_nvc={24: 2, 28: 2, 20: 2}), dict(ncr_by_nvc={28: 12})):
+        _say(f"[options] {opts}")
+        s = Simulator(pop, **opts)
+        s.rollout(T)
+        q, v, k = s.get_state()
+        np.testing.assert_array_equal(s.fitness(), Fr)
+        np.testing.assert_array_equal(q, qr)
+        np.testing.assert_array_equal(v, vr)
+        np.testing.assert_array_equal(k, kr)
+
+
+def test_plan_split_measures_and_resets():
+    from paper_2502_11129_amd.sim import Simulator
+    pop = W.quadrupeds(512)
+    s = Simulator(pop)
+    s.step(50)
+    plan = s.plan_split(T_pilot=50, threads=4, host_sample=16)
+    _say(f"[plan] {plan}")
+    assert len(plan["gpu_n"]) >= 3 and plan["gpu_n"][-1] == 512
+    assert all(b > a for a, b in zip(plan["gpu_n"], plan["gpu_n"][1:]))
+    assert all(t > 0 for t in plan["gpu_s"]) and plan["host_s_per_variant"] > 0
+    assert 0 <= plan["n_host_makespan"] <= 512 and 0 <= plan["n_host_paper"] <= 512
+    assert plan["makespan_opt_s"] <= plan["makespan_paper_s"] + 1e-12
+    q, v, k = s.get_state()
+    assert (k == 0).all()
+    np.testing.assert_array_equal(q, pop.q0.astype(np.float32))
+    np.testing.assert_array_equal(v, pop.v0.astype(np.float32))

@@ -32,6 +32,10 @@ def parse():
     ap.add_argument("--horizon", type=int, default=5000)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-autotune", action="store_true", help="default launch options instead of the autotuned ones")
+    ap.add_argument("--options", default=None,
+                    help="launch options as JSON (sim_options fields); skips the autotuner")
+    ap.add_argument("--copy-probe", action="store_true",
+                    help="also run one plain 1 GiB device copy (calibrates profiler byte counters)")
     ap.add_argument("--cpu-sample-steps", type=int, default=1000)
     ap.add_argument("--surrogate", action="store_true",
                     help="also run one surrogate-screened generation (200k labels, 1M pool) and report it")
@@ -55,6 +59,26 @@ def cpu_baseline(pop_full, sample_steps):
                                         f"FP64, {cores} threads, {dt:.1f} s"}
 
 
+def recorded_traffic(kernel, steps_per_launch):
+    """HBM bytes per launch of `kernel` from the committed profiler counters,
+    scaled by the copy calibration; None when the kernel source or the launch
+    length differs from what was profiled."""
+    import hashlib
+    path = os.path.join(ROOT, "profiles", "rollout_traffic.json")
+    if not os.path.exists(path):
+        return None
+    with open(path) as f:
+        rec = json.load(f)
+    src = os.path.join(ROOT, rec["kernel_source"])
+    with open(src, "rb") as f:
+        if hashlib.sha256(f.read()).hexdigest() != rec["kernel_source_sha256"]:
+            return None
+    if steps_per_launch != rec["steps_per_launch"] or kernel not in rec["per_launch_kib"]:
+        return None
+    fetch, write = rec["per_launch_kib"][kernel]
+    return (fetch * rec["scale"]["FETCH_SIZE"] + write * rec["scale"]["WRITE_SIZE"]) * 1024.0
+
+
 def main():
     args = parse()
     if args.gpus != 1:
@@ -70,9 +94,12 @@ def main():
     pop = W.random_trees(args.variants)
     T = args.horizon
     options, trials = {}, []
-    if not args.no_autotune:
+    if args.options:
+        options = {k: ({int(a): b for a, b in v.items()} if k == "ncr_by_nvc" else v)
+                   for k, v in json.loads(args.options).items()}
+    elif not args.no_autotune:
         from paper_2502_11129_amd.autotune import autotune
-        options, trials = autotune(pop, T_pilot=min(T, 1000))
+        options, trials = autotune(pop, T_pilot=min(T, 1000), log=lambda m: print(m, file=sys.stderr, flush=True))
     sim = Simulator(pop, time_launches=True, **options)
     stream = torch.cuda.current_stream()
     for _ in range(args.warmup):
@@ -92,6 +119,12 @@ def main():
     vsteps = pop.n_variants * T
     value = vsteps * args.steps / (gpu_ms / 1e3)
 
+    if args.copy_probe:
+        src = torch.empty(1 << 30, dtype=torch.uint8, device="cuda")
+        dst = torch.empty_like(src)
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
     rows_contact, rows_clamp, status = sim.counters()
     fl_var = flops_per_variant(pop, T, rows_contact, rows_clamp)
     fl = fl_var.sum()
@@ -108,6 +141,8 @@ def main():
     all_bins = fl / (ms_per_step / 1e3) / 1e12
     byt = bytes_per_rollout(pop)
     nvc, nbody, ncr, nvar = bins[dom]
+    kernel_name = f"rollout_kernel<{nvc}, {nbody // 16}, {ncr}>"
+    traffic = recorded_traffic(kernel_name, options.get("steps_per_launch") or 1000)
 
     out = {
         "metric": "variant-steps/sec at 1 MI355X",
@@ -130,8 +165,8 @@ def main():
                    "options": options, "autotune_trials": len(trials),
                    "wall_s": wall},
         "roofline": {"bound": "alu", "achieved": achieved, "peak": FP32_VECTOR_PEAK_TFLOPS, "unit": "TFLOP/s",
-                     "frac": achieved / FP32_VECTOR_PEAK_TFLOPS, "traffic": None,
-                     "kernel": f"rollout_kernel<{nvc}, {nbody // 16}, {ncr}>",
+                     "frac": achieved / FP32_VECTOR_PEAK_TFLOPS, "traffic": traffic,
+                     "kernel": kernel_name,
                      "kernel_variants": nvar, "kernel_launches_per_step": dom_launches,
                      "kernel_avg_launch_ms": per_launch_s * 1e3,
                      "kernel_flops_per_launch": dom_flops_per_launch,

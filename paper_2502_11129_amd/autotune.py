@@ -62,31 +62,38 @@ def autotune(pop, T_pilot=1000, reps=2, log=None, cache=None):
             log(f"autotune {opts}: {t * 1e3:.2f} ms, bins {[(b[0], b[1], b[2], b[3]) for b in bins]}")
         return t
 
-    best = dict(min_body_slots=0, streams=0, steps_per_launch=0, ncr_by_nvc={})
-    best_t = run(best)
-    space = [("min_body_slots", [32]), ("streams", [4, 2, 1]), ("steps_per_launch", [250, 500])]
-    for name, values in space:
-        for v in values:
-            cand = dict(best, **{name: v})
-            t = run(cand)
-            if t < best_t * 0.98:            # keep only clear wins
-                best, best_t = cand, t
-    # contacts in registers, one DoF capacity at a time
-    probe = S.Handle(pop, **best)
-    nvcs = sorted({b[0] for b in probe.bins()})
-    probe.close()
-    for nvc in nvcs:
-        for ncr in candidates_ncr(nvc):
-            cur = best["ncr_by_nvc"].get(nvc)
-            if ncr == cur:
-                continue
-            cand = dict(best, ncr_by_nvc={**best["ncr_by_nvc"], nvc: ncr})
-            try:
+    def descend(best, best_t):
+        """Coordinate descent from a starting point: streams, launch length,
+        then the contact budget of each DoF capacity present."""
+        for name, values in (("streams", [4, 2, 1]), ("steps_per_launch", [250, 500])):
+            for v in values:
+                cand = dict(best, **{name: v})
                 t = run(cand)
-            except S.SimError:
-                continue                      # no kernel with that budget for this body capacity
-            if t < best_t * 0.98:
-                best, best_t = cand, t
+                if t < best_t * 0.98:            # keep only clear wins
+                    best, best_t = cand, t
+        probe = S.Handle(pop, **best)
+        nvcs = sorted({b[0] for b in probe.bins()})
+        probe.close()
+        for nvc in nvcs:
+            for ncr in candidates_ncr(nvc):
+                if ncr == best["ncr_by_nvc"].get(nvc):
+                    continue
+                cand = dict(best, ncr_by_nvc={**best["ncr_by_nvc"], nvc: ncr})
+                try:
+                    t = run(cand)
+                except S.SimError:
+                    continue                      # no kernel with that budget for this body capacity
+                if t < best_t * 0.98:
+                    best, best_t = cand, t
+        return best, best_t
+
+    # two starting points: smallest body capacity per variant (more bins, some
+    # kernels with fewer registers) and every variant in 32-body kernels (fewer bins)
+    results = []
+    for slots in (0, 32):
+        start_opts = dict(min_body_slots=slots, streams=0, steps_per_launch=0, ncr_by_nvc={})
+        results.append(descend(start_opts, run(start_opts)))
+    best, best_t = min(results, key=lambda r: r[1])
     if cache:
         store = {}
         if os.path.exists(cache):

@@ -22,8 +22,10 @@ HIPCC = shutil.which("hipcc") or "/opt/rocm/bin/hipcc"
 ROCM_INC = os.path.join(os.environ.get("ROCM_PATH", "/opt/rocm"), "include")
 API_INC = os.path.join(os.path.dirname(PKG), "include")
 COMMON = ["-O3", "-std=c++17", "-fPIC", "-Wno-unused-result"]
-# Packed FP32 instructions stay disabled in every HIP translation unit.
-DEVICE = [f"--offload-arch={ARCH}", "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops"]
+# Packed FP32 instructions stay disabled in every HIP translation unit; a * b + c
+# is fused only within one expression, so every kernel variant (whatever its
+# register budget or inlining context) rounds the same way.
+DEVICE = [f"--offload-arch={ARCH}", "-ffp-contract=on", "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops"]
 
 
 def _sources():

@@ -16,6 +16,7 @@ hipError_t launch_rollout_20_1_2(const BinArgs&, const ModelParams&, hipStream_t
 hipError_t launch_rollout_24_1_8(const BinArgs&, const ModelParams&, hipStream_t);
 hipError_t launch_rollout_24_2_8(const BinArgs&, const ModelParams&, hipStream_t);
 hipError_t launch_rollout_24_2_2(const BinArgs&, const ModelParams&, hipStream_t);
+hipError_t launch_rollout_24_1_2(const BinArgs&, const ModelParams&, hipStream_t);
 hipError_t launch_rollout_28_2_8(const BinArgs&, const ModelParams&, hipStream_t);
 hipError_t launch_rollout_28_2_2(const BinArgs&, const ModelParams&, hipStream_t);
 hipError_t launch_rollout_28_2_4(const BinArgs&, const ModelParams&, hipStream_t);
@@ -35,6 +36,7 @@ const KernelVariant kKernelVariants[] = {
     {24, 1, 8, launch_rollout_24_1_8},
     {24, 2, 8, launch_rollout_24_2_8},
     {24, 2, 2, launch_rollout_24_2_2},
+    {24, 1, 2, launch_rollout_24_1_2},
     {28, 2, 8, launch_rollout_28_2_8},
     {28, 2, 2, launch_rollout_28_2_2},
     {28, 2, 4, launch_rollout_28_2_4},

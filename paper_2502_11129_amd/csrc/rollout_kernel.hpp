@@ -71,7 +71,22 @@ __device__ __forceinline__ float dot3(f3 a, f3 b) { return a.x * b.x + a.y * b.y
 __device__ __forceinline__ f3 cross3(f3 a, f3 b) {
   return {a.y * b.z - a.z * b.y, a.z * b.x - a.x * b.z, a.x * b.y - a.y * b.x};
 }
+// 1/x from the hardware reciprocal (1 ulp) refined by one Newton step
+__device__ __forceinline__ float recip(float x) {
+  const float r = __builtin_amdgcn_rcpf(x);
+  return fmaf(fmaf(-x, r, 1.f), r, r);
+}
+
 struct m33 { float m[9]; };
+// column c (0..2, may differ across lanes) of R as a weighted sum with 0/1
+// weights (entries are finite): selects between elements of one array are
+// folded by the compiler into a dynamically indexed load, which would move R
+// into scratch memory
+__device__ __forceinline__ f3 mcol(const m33& R, int c) {
+  const float w0 = c == 0 ? 1.f : 0.f, w1 = c == 1 ? 1.f : 0.f, w2 = c == 2 ? 1.f : 0.f;
+  return {R.m[0] * w0 + R.m[1] * w1 + R.m[2] * w2, R.m[3] * w0 + R.m[4] * w1 + R.m[5] * w2,
+          R.m[6] * w0 + R.m[7] * w1 + R.m[8] * w2};
+}
 __device__ __forceinline__ f3 mul(const m33& R, f3 v) {
   return {R.m[0] * v.x + R.m[1] * v.y + R.m[2] * v.z, R.m[3] * v.x + R.m[4] * v.y + R.m[5] * v.z,
           R.m[6] * v.x + R.m[7] * v.y + R.m[8] * v.z};
@@ -145,51 +160,60 @@ struct GroupLds {
   float cs[NCR][12];        // per-contact solver scalars
   float th[32], thd[32];    // theta / thetadot by DoF
   float cvec[32];           // bias c by DoF
-  float cb[2][64];          // doubled broadcast buffers (pivot column, right-hand sides)
-  float jb[2 * NVC][4];     // doubled contact-row broadcast (J_n, J_x, J_y)
+  float cb[2][64];          // doubled broadcast buffers of the pivot column
 };
 
 // ----------------------------------------------------------------------------
-// Contact rows.  The inverse is held negated with rotated columns: register
-// column j of the row of DoF d is -(M~^-1)[d][(nv + j) mod NVC]; vectors
-// multiplied by it are read from doubled LDS buffers at offset nv.
+// Contact rows.  The inverse is held negated in natural column order:
+// Mi[s][c] = -(M~^-1)[d][c] for the lane's DoF d = lane + 16 s.  The entries of
+// a vector multiplied by it are broadcast from their owner lanes (DoF c lives
+// in lane c mod 16, slot c / 16) by DPP, without LDS.
 // Builds J (normal z, tangents x, y) of the point x for the lane's DoF slots,
 // W = M~^-1 J^T, the row denominators and cross terms, and the solver scalars.
 // ----------------------------------------------------------------------------
+template <int S, int NVC, int C = 0>
+__device__ __forceinline__ void matvec_bcast3(const float (&Mi)[S][NVC], const float (&a)[S], const float (&b)[S],
+                                              const float (&c)[S], float (&ya)[S], float (&yb)[S], float (&yc)[S]) {
+  if constexpr (C < NVC) {
+    const float va = row_bcast<C % 16>(a[C / 16]), vb = row_bcast<C % 16>(b[C / 16]),
+                vc = row_bcast<C % 16>(c[C / 16]);
+#pragma unroll
+    for (int s = 0; s < S; ++s) {
+      ya[s] = fmaf(Mi[s][C], va, ya[s]);
+      yb[s] = fmaf(Mi[s][C], vb, yb[s]);
+      yc[s] = fmaf(Mi[s][C], vc, yc[s]);
+    }
+    matvec_bcast3<S, NVC, C + 1>(Mi, a, b, c, ya, yb, yc);
+  }
+}
+
+template <int S, int NVC, int C = 0>
+__device__ __forceinline__ void matvec_bcast1(const float (&Mi)[S][NVC], const float (&a)[S], float (&ya)[S]) {
+  if constexpr (C < NVC) {
+    const float va = row_bcast<C % 16>(a[C / 16]);
+#pragma unroll
+    for (int s = 0; s < S; ++s) ya[s] = fmaf(Mi[s][C], va, ya[s]);
+    matvec_bcast1<S, NVC, C + 1>(Mi, a, ya);
+  }
+}
+
 template <int S, int NVC>
 __device__ __forceinline__ void build_rows(const float (&Mi)[S][NVC], const f3 (&ang)[S], const f3 (&cst)[S],
-                                           const int (&bodyOfDof)[S], int lane, int nv, float (*jb)[4], f3 x,
-                                           unsigned anc, float kc, float kb, float dt, float (&Jn)[S],
-                                           float (&Jx)[S], float (&Jy)[S], float (&Wn)[S], float (&Wx)[S],
-                                           float (&Wy)[S], float (&scal)[10]) {
+                                           const int (&bodyOfDof)[S], int lane, f3 x, unsigned anc, float kc,
+                                           float kb, float dt, float (&Jn)[S], float (&Jx)[S], float (&Jy)[S],
+                                           float (&Wn)[S], float (&Wx)[S], float (&Wy)[S], float (&scal)[10]) {
+  float nJn[S], nJx[S], nJy[S];  // sign of the held inverse folded in
 #pragma unroll
   for (int s = 0; s < S; ++s) {
-    const int d = lane + 16 * s;
     const bool on = (bodyOfDof[s] < 0) || ((anc >> bodyOfDof[s]) & 1u);
     const f3 J = cross3(ang[s], x) + cst[s];
     Jn[s] = on ? J.z : 0.f;
     Jx[s] = on ? J.x : 0.f;
     Jy[s] = on ? J.y : 0.f;
-    if (d < NVC) {
-      jb[d][0] = -Jn[s]; jb[d][1] = -Jx[s]; jb[d][2] = -Jy[s];  // sign of the held inverse folded in
-      jb[d + NVC][0] = -Jn[s]; jb[d + NVC][1] = -Jx[s]; jb[d + NVC][2] = -Jy[s];
-    }
+    nJn[s] = -Jn[s]; nJx[s] = -Jx[s]; nJy[s] = -Jy[s];
+    Wn[s] = 0.f; Wx[s] = 0.f; Wy[s] = 0.f;
   }
-  wave_sync();
-#pragma unroll
-  for (int s = 0; s < S; ++s) { Wn[s] = 0.f; Wx[s] = 0.f; Wy[s] = 0.f; }
-  const float (*jr)[4] = jb + nv;
-#pragma unroll
-  for (int j = 0; j < NVC; ++j) {
-    const float4 jj = *reinterpret_cast<const float4*>(&jr[j][0]);
-#pragma unroll
-    for (int s = 0; s < S; ++s) {
-      Wn[s] = fmaf(Mi[s][j], jj.x, Wn[s]);
-      Wx[s] = fmaf(Mi[s][j], jj.y, Wx[s]);
-      Wy[s] = fmaf(Mi[s][j], jj.z, Wy[s]);
-    }
-  }
-  wave_sync();  // jb is free for the next contact
+  matvec_bcast3<S, NVC>(Mi, nJn, nJx, nJy, Wn, Wx, Wy);
   float pn = 0.f, px = 0.f, py = 0.f, pxn = 0.f, pyn = 0.f;
 #pragma unroll
   for (int s = 0; s < S; ++s) {
@@ -202,12 +226,12 @@ __device__ __forceinline__ void build_rows(const float (&Mi)[S][NVC], const f3 (
   const float Dn = row_sum(pn), Dx = row_sum(px), Dy = row_sum(py);
   const float Dxn = row_sum(pxn), Dyn = row_sum(pyn);
   scal[0] = kc * (-x.z);                    // k * depth
-  scal[1] = 1.f / (Dn * (1.f + kb * dt));   // normal row: 1 / (D_n (1 + (b + k dt) dt))
+  scal[1] = recip(Dn * (1.f + kb * dt));  // normal row: 1 / (D_n (1 + (b + k dt) dt))
   scal[2] = dt * Dn;
   scal[3] = dt * Dxn;                       // tangential velocity change per unit normal force
   scal[4] = dt * Dyn;
-  scal[5] = 1.f / (dt * Dx);
-  scal[6] = 1.f / (dt * Dy);
+  scal[5] = recip(dt * Dx);
+  scal[6] = recip(dt * Dy);
   scal[7] = 0.f;                            // lambda_n, lambda_x, lambda_y (cold start)
   scal[8] = 0.f;
   scal[9] = 0.f;
@@ -237,7 +261,7 @@ __device__ __forceinline__ void contact_row(float (&vp)[S], const float (&Jn)[S]
   float gx = lx0 - ux2 * sc[5], gy = ly0 - uy2 * sc[6];
   const float gn2 = gx * gx + gy * gy, lim = mu * ln;
   if (gn2 > lim * lim) {
-    const float scale = lim / sqrtf(gn2);
+    const float scale = lim * __builtin_amdgcn_rsqf(gn2);
     gx *= scale;
     gy *= scale;
   }
@@ -259,8 +283,18 @@ __device__ __forceinline__ float row_min(float x) {
 // ----------------------------------------------------------------------------
 // The kernel.
 // ----------------------------------------------------------------------------
+// Two waves per SIMD (at most 256 registers) for the families whose LDS area
+// allows it (16 body slots) and whose registers fit without spills (one DoF
+// slot per lane, few contacts kept in registers); the others may use the
+// whole register file and run one wave per SIMD.
 template <int NVC, int SB, int NCR>
-__global__ __launch_bounds__(64) void rollout_kernel(BinArgs a, ModelParams P) {
+struct WavesPerSimd {
+  static constexpr int value = (SB == 1 && NCR <= 2 && NVC <= 16) ? 2 : 1;
+};
+
+template <int NVC, int SB, int NCR>
+__global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(WavesPerSimd<NVC, SB, NCR>::value)))
+void rollout_kernel(BinArgs a, ModelParams P) {
   constexpr int S = (NVC + 15) / 16;
   constexpr int NBC = 16 * SB;
   constexpr int MAXC = 8 * NBC;
@@ -550,7 +584,7 @@ __global__ __launch_bounds__(64) void rollout_kernel(BinArgs a, ModelParams P) {
       const f3 hx0 = cross3(hb, mk(1.f, 0.f, 0.f)), hx1 = cross3(hb, mk(0.f, 1.f, 0.f)),
                hx2 = cross3(hb, mk(0.f, 0.f, 1.f));
       if (i < 3) {
-        const f3 e = mk(R0.m[i], R0.m[3 + i], R0.m[6 + i]);  // R0 e_i (column i)
+        const f3 e = mcol(R0, i);  // R0 e_i (column i)
         const f3 row = mulT(R0, symmul(Iw, e));             // row i of R^T Io R
         mroot[0] = row.x; mroot[1] = row.y; mroot[2] = row.z;
         mroot[3] = (i == 0) ? hx0.x : (i == 1) ? hx0.y : hx0.z;
@@ -636,7 +670,7 @@ __global__ __launch_bounds__(64) void rollout_kernel(BinArgs a, ModelParams P) {
       }
       wave_sync();
       const float* ck = cbk + k;
-      const float pinv = 1.0f / ck[0];
+      const float pinv = recip(ck[0]);
       float f[S];
       bool piv[S];
 #pragma unroll
@@ -654,7 +688,8 @@ __global__ __launch_bounds__(64) void rollout_kernel(BinArgs a, ModelParams P) {
       for (int s = 0; s < S; ++s) Mi[s][NVC - 1] = piv[s] ? -pinv : f[s];
     }
     // the assembled matrix is dead: keep the (negated, rotated) inverse in LDS
-    // for the clamp rows, which need single columns chosen at run time
+    // for the clamp rows, which need single columns chosen at run time, and
+    // reload the registers in natural column order for the mat-vecs
     wave_sync();
 #pragma unroll
     for (int s = 0; s < S; ++s) {
@@ -665,6 +700,15 @@ __global__ __launch_bounds__(64) void rollout_kernel(BinArgs a, ModelParams P) {
       }
     }
     wave_sync();
+#pragma unroll
+    for (int s = 0; s < S; ++s) {
+      const int dr = (lane + 16 * s) < NVC ? lane + 16 * s : 0;
+#pragma unroll
+      for (int c = 0; c < NVC; ++c) {
+        const int j = c - nv + (c < nv ? NVC : 0);  // register column of original column c
+        Mi[s][c] = sh.A[dr * MST + j];
+      }
+    }
     float Dd[S];  // own diagonal of M~^-1
 #pragma unroll
     for (int s = 0; s < S; ++s) {
@@ -678,7 +722,7 @@ __global__ __launch_bounds__(64) void rollout_kernel(BinArgs a, ModelParams P) {
     // 4. control and free velocity
     // =====================================================================
     const double tk = (double)kstep * dtd;
-    float aS[S];
+    float aS[S], nrhs[S];
 #pragma unroll
     for (int s = 0; s < S; ++s) {
       const int d = lane + 16 * s;
@@ -692,21 +736,12 @@ __global__ __launch_bounds__(64) void rollout_kernel(BinArgs a, ModelParams P) {
       float rhs = -dt * cS[s];
       if (hinge) rhs += dt * (aS[s] - ba * vS[s]);
       if (d >= nv) rhs = 0.f;
-      if (d < NVC) { sh.cb[0][d] = -rhs; sh.cb[0][d + NVC] = -rhs; }  // sign of the held inverse
+      nrhs[s] = -rhs;  // sign of the held inverse
     }
-    wave_sync();
     float vp[S];
 #pragma unroll
     for (int s = 0; s < S; ++s) vp[s] = vS[s];
-    {
-      const float* rr = sh.cb[0] + nv;
-#pragma unroll
-      for (int j = 0; j < NVC; ++j) {
-        const float r = rr[j];
-#pragma unroll
-        for (int s = 0; s < S; ++s) vp[s] = fmaf(Mi[s][j], r, vp[s]);
-      }
-    }
+    matvec_bcast1<S, NVC>(Mi, nrhs, vp);
 
     // =====================================================================
     // 5. contact rows
@@ -719,11 +754,11 @@ __global__ __launch_bounds__(64) void rollout_kernel(BinArgs a, ModelParams P) {
       const int d = lane + 16 * s;
       bodyOfDof[s] = -1;
       if (r0 == 6 && d < 3) {
-        ang[s] = mk(R0.m[d], R0.m[3 + d], R0.m[6 + d]);
+        ang[s] = mcol(R0, d);
         cst[s] = mk(0.f, 0.f, 0.f) - cross3(ang[s], P0);
       } else if (r0 == 6 && d < 6) {
         ang[s] = mk(0.f, 0.f, 0.f);
-        cst[s] = mk(R0.m[d - 3], R0.m[3 + d - 3], R0.m[6 + d - 3]);
+        cst[s] = mcol(R0, d - 3);
       } else if (d < nv) {
         const int b = d - r0 + 1;
         bodyOfDof[s] = b;
@@ -741,8 +776,8 @@ __global__ __launch_bounds__(64) void rollout_kernel(BinArgs a, ModelParams P) {
         const f3 x = mk(sh.cl[c][0], sh.cl[c][1], sh.cl[c][2]);
         const unsigned anc = __float_as_uint(sh.cl[c][3]);
         float scal[10];
-        build_rows<S, NVC>(Mi, ang, cst, bodyOfDof, lane, nv, sh.jb, x, anc, kc, kb, dt, JnR[c], JxR[c], JyR[c],
-                           WnR[c], WxR[c], WyR[c], scal);
+        build_rows<S, NVC>(Mi, ang, cst, bodyOfDof, lane, x, anc, kc, kb, dt, JnR[c], JxR[c], JyR[c], WnR[c],
+                           WxR[c], WyR[c], scal);
 #pragma unroll
         for (int i = 0; i < 10; ++i) sh.cs[c][i] = scal[i];  // identical in every lane
       } else {
@@ -760,7 +795,7 @@ __global__ __launch_bounds__(64) void rollout_kernel(BinArgs a, ModelParams P) {
       const f3 x = mk(ovf_list[c * 4], ovf_list[c * 4 + 1], ovf_list[c * 4 + 2]);
       const unsigned anc = __float_as_uint(ovf_list[c * 4 + 3]);
       float Jn[S], Jx[S], Jy[S], Wn[S], Wx[S], Wy[S], scal[10];
-      build_rows<S, NVC>(Mi, ang, cst, bodyOfDof, lane, nv, sh.jb, x, anc, kc, kb, dt, Jn, Jx, Jy, Wn, Wx, Wy, scal);
+      build_rows<S, NVC>(Mi, ang, cst, bodyOfDof, lane, x, anc, kc, kb, dt, Jn, Jx, Jy, Wn, Wx, Wy, scal);
       float* rows = ovf_rows + (size_t)c * 6 * NVC;
 #pragma unroll
       for (int s = 0; s < S; ++s) {

@@ -45,6 +45,19 @@ __device__ __forceinline__ float dpp(float x) {
 }
 
 // Sum over the 16 lanes of a row; every lane gets the bitwise-same value.
+// inclusive prefix sum over the 16 lanes of a row (lanes shifted in from
+// outside the row contribute 0)
+__device__ __forceinline__ int row_scan_incl(int x) {
+  x += __builtin_amdgcn_update_dpp(0, x, 0x111, 0xF, 0xF, false);  // row_shr:1
+  x += __builtin_amdgcn_update_dpp(0, x, 0x112, 0xF, 0xF, false);  // row_shr:2
+  x += __builtin_amdgcn_update_dpp(0, x, 0x114, 0xF, 0xF, false);  // row_shr:4
+  x += __builtin_amdgcn_update_dpp(0, x, 0x118, 0xF, 0xF, false);  // row_shr:8
+  return x;
+}
+template <int L>
+__device__ __forceinline__ int row_bcast_i(int x) {
+  return __builtin_amdgcn_update_dpp(0, x, 0x150 + L, 0xF, 0xF, false);  // row_newbcast:L
+}
 __device__ __forceinline__ float row_sum(float x) {
   x += dpp<0xB1>(x);   // quad_perm [1,0,3,2]
   x += dpp<0x4E>(x);   // quad_perm [2,3,0,1]
@@ -158,9 +171,10 @@ struct GroupLds {
   int ccount[NBC];          // active-corner mask per body
   float cl[NCR][4];         // contact list: x, y, z, ancestor mask of the body
   float cs[NCR][12];        // per-contact solver scalars
-  float th[32], thd[32];    // theta / thetadot by DoF
-  float cvec[32];           // bias c by DoF
-  float cb[2][64];          // doubled broadcast buffers of the pivot column
+  float th[NVC], thd[NVC];  // theta / thetadot by DoF
+  float cvec[NVC];          // bias c by DoF
+  float cb[2][2 * NVC];     // doubled broadcast buffers of the pivot column
+  int lv[2 * NBC + 4];      // level lists (bodies in depth order, then level starts), staged per launch
 };
 
 // ----------------------------------------------------------------------------
@@ -364,6 +378,8 @@ void rollout_kernel(BinArgs a, ModelParams P) {
     const int b = lane + 16 * t;
     if (b < nb) sh.par[b] = __float_as_int(bodyv[b * BW_WORDS + BW_PARENT]);
   }
+  for (int j = lane; j < 2 * NBC + 4; j += 16) sh.lv[j] = lvl[j];
+  wave_sync();
 
   for (int it = 0; it < a.n_steps; ++it) {
     if (status) break;  // frozen variants stop (row-uniform)
@@ -376,7 +392,7 @@ void rollout_kernel(BinArgs a, ModelParams P) {
 #pragma unroll
     for (int s = 0; s < S; ++s) {
       const int d = lane + 16 * s;
-      if (d < 32) { sh.th[d] = thS[s]; sh.thd[d] = vS[s]; }
+      if (d < NVC) { sh.th[d] = thS[s]; sh.thd[d] = vS[s]; }
     }
     f3 wb = mk(row_bcast<0>(vS[0]), row_bcast<1>(vS[0]), row_bcast<2>(vS[0]));
     f3 vb = mk(row_bcast<3>(vS[0]), row_bcast<4>(vS[0]), row_bcast<5>(vS[0]));
@@ -388,9 +404,9 @@ void rollout_kernel(BinArgs a, ModelParams P) {
     wave_sync();
 
     for (int lev = 0; lev <= maxdepth; ++lev) {
-      const int i1 = lvl[NBC + lev + 1];
-      for (int i = lvl[NBC + lev] + lane; i < i1; i += 16) {
-        const int b = lvl[i];
+      const int i1 = sh.lv[NBC + lev + 1];
+      for (int i = sh.lv[NBC + lev] + lane; i < i1; i += 16) {
+        const int b = sh.lv[i];
         const float* rec = bodyv + (size_t)b * BW_WORDS;
         m33 R;
         f3 p, w, o;
@@ -455,14 +471,16 @@ void rollout_kernel(BinArgs a, ModelParams P) {
     // contact list in (body, corner) order: prefix over bodies of the popcounts
     int nc = 0;
     {
+      // active corners per body, exclusive prefix over bodies by a DPP scan
+      // across the row (slot 0 holds bodies 0..15, slot 1 bodies 16..31)
       int off[SB];
 #pragma unroll
-      for (int t = 0; t < SB; ++t) off[t] = 0;
-      for (int bb = 0; bb < nb; ++bb) {
-        const int cbb = __builtin_popcount((unsigned)sh.ccount[bb]);
-#pragma unroll
-        for (int t = 0; t < SB; ++t) off[t] += (bb < lane + 16 * t) ? cbb : 0;
-        nc += cbb;
+      for (int t = 0; t < SB; ++t) {
+        const int b = lane + 16 * t;
+        const int cnt = (b < nb) ? __builtin_popcount((unsigned)sh.ccount[b]) : 0;
+        const int incl = row_scan_incl(cnt);
+        off[t] = nc + incl - cnt;
+        nc += row_bcast_i<15>(incl);
       }
 #pragma unroll
       for (int t = 0; t < SB; ++t) {
@@ -504,9 +522,9 @@ void rollout_kernel(BinArgs a, ModelParams P) {
     //    and force F of each subtree; hinge bias S.F and C S for CRBA
     // =====================================================================
     for (int lev = maxdepth; lev >= 0; --lev) {
-      const int i1 = lvl[NBC + lev + 1];
-      for (int i = lvl[NBC + lev] + lane; i < i1; i += 16) {
-        const int b = lvl[i];
+      const int i1 = sh.lv[NBC + lev + 1];
+      for (int i = sh.lv[NBC + lev] + lane; i < i1; i += 16) {
+        const int b = sh.lv[i];
         const float* rec = bodyv + (size_t)b * BW_WORDS;
         float* own = &sh.A[b * 24];
         sinertia C;

@@ -142,6 +142,12 @@ def main():
     byt = bytes_per_rollout(pop)
     nvc, nbody, ncr, nvar = bins[dom]
     kernel_name = f"rollout_kernel<{nvc}, {nbody // 16}, {ncr}>"
+    if options.get("single_launch"):
+        # one kernel runs every bin: its launches carry the whole rollout
+        kernel_name = "rollout_multi_kernel"
+        nvar = pop.n_variants
+        dom_flops_per_launch = fl / max(dom_launches, 1)
+        achieved = dom_flops_per_launch / per_launch_s / 1e12
     traffic = recorded_traffic(kernel_name, options.get("steps_per_launch") or 1000)
 
     out = {

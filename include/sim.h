@@ -117,6 +117,11 @@ typedef struct {
  *                         registers (0 = the bin's first compiled kernel)
  *  time_launches          != 0: every bin's launches are bracketed by HIP
  *                         events on the bin's stream (sim_launch_times)
+ *  single_launch          != 0: all bins in one launch per chunk of steps, the
+ *                         most expensive bins' workgroups first (needs every
+ *                         bin to be a 32-body kernel of the default contact
+ *                         budget with nv capacity 16..28, at most 8 bins; else
+ *                         sim_create fails); streams is then ignored
  */
 typedef struct {
   int32_t contacts_in_registers;
@@ -126,7 +131,8 @@ typedef struct {
   int32_t min_body_slots;
   int32_t ncr_by_nvc[6];
   int32_t time_launches;
-  int32_t reserved[4];
+  int32_t single_launch;
+  int32_t reserved[3];
 } sim_options;
 
 typedef struct sim_handle sim_handle;
@@ -203,8 +209,9 @@ int sim_variant_bins(const sim_handle* h, int32_t* bin);
 
 /* With time_launches set: per bin (in sim_bins order), the milliseconds
  * between the start of its first and the end of its last launch in the most
- * recent sim_step_batch / sim_rollout, and the number of launches.  Any
- * output may be NULL.  Synchronises on the recorded events. */
+ * recent sim_step_batch / sim_rollout, and the number of launches (with
+ * single_launch every bin reports the shared launches).  Any output may be
+ * NULL.  Synchronises on the recorded events. */
 int sim_launch_times(const sim_handle* h, int32_t* n_bins, float* ms, int32_t* launches, int32_t max_bins);
 
 /* The compiled kernel variants: per variant (nv capacity, body capacity,

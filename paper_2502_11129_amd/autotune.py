@@ -65,10 +65,15 @@ def autotune(pop, T_pilot=1000, reps=2, log=None, cache=None):
     def descend(best, best_t):
         """Coordinate descent from a starting point: streams, launch length,
         then the contact budget of each DoF capacity present."""
-        for name, values in (("streams", [4, 2, 1]), ("steps_per_launch", [250, 500])):
+        for name, values in (("single_launch", [True]), ("streams", [4, 2, 1]), ("steps_per_launch", [250, 500])):
             for v in values:
                 cand = dict(best, **{name: v})
-                t = run(cand)
+                if cand.get("single_launch") and name == "streams":
+                    continue                       # one launch uses one stream
+                try:
+                    t = run(cand)
+                except S.SimError:
+                    continue                       # e.g. a bin outside the single-launch kernel
                 if t < best_t * 0.98:            # keep only clear wins
                     best, best_t = cand, t
         probe = S.Handle(pop, **best)

@@ -18,4 +18,10 @@ struct KernelVariant {
 extern const KernelVariant kKernelVariants[];
 extern const int kNumKernelVariants;
 
+// The multi-bin kernel: its family list (nvc, sb, ncr per kind index) and launcher.
+struct MultiFamily { int nvc, sb, ncr; };
+extern const MultiFamily kMultiFamilies[];
+extern const int kNumMultiFamilies;
+hipError_t launch_rollout_multi(const MultiArgs& m, const ModelParams& p, int blocks, hipStream_t st);
+
 }  // namespace simk

@@ -306,19 +306,20 @@ struct WavesPerSimd {
   static constexpr int value = (SB == 1 && NCR <= 2 && NVC <= 16) ? 2 : 1;
 };
 
+// One workgroup (one wave, four variants) of a bin: `block` is the
+// workgroup's index within the bin, lds_all the four variants' LDS areas.
 template <int NVC, int SB, int NCR>
-__global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(WavesPerSimd<NVC, SB, NCR>::value)))
-void rollout_kernel(BinArgs a, ModelParams P) {
+__device__ __forceinline__ void rollout_body(const BinArgs& a, const ModelParams& P, int block,
+                                             GroupLds<NVC, SB, NCR>* lds_all) {
   constexpr int S = (NVC + 15) / 16;
   constexpr int NBC = 16 * SB;
   constexpr int MAXC = 8 * NBC;
   using L = GroupLds<NVC, SB, NCR>;
   constexpr int MST = L::MST;
-  __shared__ L lds_all[kVarPerWave];
 
   const int lane = threadIdx.x & 15;
   const int grp = threadIdx.x >> 4;
-  const int vid = blockIdx.x * kVarPerWave + grp;
+  const int vid = block * kVarPerWave + grp;
   if (vid >= a.n) return;  // whole rows leave together
   L& sh = lds_all[grp];
 
@@ -999,6 +1000,13 @@ void rollout_kernel(BinArgs a, ModelParams P) {
       a.cnt[2 * vid + 1] = cnt_clamp;
     }
   }
+}
+
+template <int NVC, int SB, int NCR>
+__global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(WavesPerSimd<NVC, SB, NCR>::value)))
+void rollout_kernel(BinArgs a, ModelParams P) {
+  __shared__ GroupLds<NVC, SB, NCR> lds_all[kVarPerWave];
+  rollout_body<NVC, SB, NCR>(a, P, blockIdx.x, lds_all);
 }
 
 }  // namespace simk

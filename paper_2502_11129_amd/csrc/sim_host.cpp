@@ -43,6 +43,7 @@ struct Bin {
   BinArgs args{};
   hipEvent_t t_begin = nullptr, t_end = nullptr;  // launch timing (time_launches)
   int timed_launches = 0;
+  int multi_kind = -1;  // family index in the multi-bin kernel
 };
 
 size_t align256(size_t x) { return (x + 255) & ~size_t(255); }
@@ -75,6 +76,7 @@ struct sim_handle {
   std::vector<int> stream_of;             // bin -> stream index (0 = caller's)
   int n_streams = 1;
   int steps_per_launch = kStepsPerLaunch;
+  bool multi = false;                     // all bins in one launch per chunk
 };
 
 namespace {
@@ -134,7 +136,53 @@ int launch_bin(sim_handle* h, Bin& b, int n_steps, bool reset, hipStream_t st, i
   return SIM_OK;
 }
 
+// All bins in one launch per chunk (single_launch).
+int launch_multi(sim_handle* h, int n_steps, bool reset, hipStream_t st, const std::vector<int>* counts) {
+  MultiArgs m{};
+  m.nbins = (int)h->bins.size();
+  // workgroups of the slowest bins (largest nv capacity) are dispatched first
+  std::vector<int> order(m.nbins);
+  for (int i = 0; i < m.nbins; ++i) order[i] = i;
+  std::stable_sort(order.begin(), order.end(), [&](int x, int y) { return h->bins[x].nvc > h->bins[y].nvc; });
+  int blocks = 0;
+  for (int j = 0; j < m.nbins; ++j) {
+    const int i = order[j];
+    const Bin& b = h->bins[i];
+    m.kind[j] = b.multi_kind;
+    m.block_start[j] = blocks;
+    m.bin[j] = b.args;
+    if (counts) m.bin[j].n = (*counts)[i];
+    blocks += (m.bin[j].n + kVarPerWave - 1) / kVarPerWave;
+  }
+  m.block_start[m.nbins] = blocks;
+  if (blocks == 0) return SIM_OK;
+  Bin& b0 = h->bins[0];
+  const bool timed = h->opts.time_launches && b0.t_begin;
+  int rc;
+  if (timed && (rc = dev_check(h, hipEventRecord(b0.t_begin, st), "timing record"))) return rc;
+  int done = 0, launches = 0;
+  bool first = true;
+  while (first || done < n_steps) {
+    const int chunk = std::min(h->steps_per_launch, n_steps - done);
+    for (int i = 0; i < m.nbins; ++i) {
+      m.bin[i].n_steps = chunk;
+      m.bin[i].reset = (reset && first) ? 1 : 0;
+    }
+    hipError_t e = launch_rollout_multi(m, h->params, blocks, st);
+    if (e != hipSuccess) return dev_check(h, e, "kernel launch");
+    done += chunk;
+    first = false;
+    ++launches;
+  }
+  if (timed) {
+    for (Bin& b : h->bins) b.timed_launches = launches;
+    return dev_check(h, hipEventRecord(b0.t_end, st), "timing record");
+  }
+  return SIM_OK;
+}
+
 int launch_all(sim_handle* h, int n_steps, bool reset, hipStream_t st, const std::vector<int>* counts = nullptr) {
+  if (h->multi) return launch_multi(h, n_steps, reset, st, counts);
   const size_t nb = h->bins.size();
   const int ns = h->n_streams;
   auto stream = [&](size_t bi) { return h->stream_of[bi] == 0 ? st : h->bin_streams[h->stream_of[bi] - 1]; };
@@ -347,10 +395,23 @@ int sim_create(const sim_model_desc* d, const sim_options* opts, sim_handle** ou
   // cost order: variants x (nv capacity)^2 per bin, most expensive first
   auto cost = [](const Bin& b) { return (double)b.users.size() * b.nvc * b.nvc * (b.sb == 2 ? 1.25 : 1.0); };
   std::stable_sort(hp->bins.begin(), hp->bins.end(), [&](const Bin& x, const Bin& y) { return cost(x) > cost(y); });
+  // single launch: every bin must be one of the multi-bin kernel's families
+  if (hp->opts.single_launch) {
+    if ((int)hp->bins.size() > kMaxMultiBins) return bad("single_launch supports at most 8 bins");
+    for (Bin& b : hp->bins) {
+      for (int k = 0; k < kNumMultiFamilies; ++k)
+        if (kMultiFamilies[k].nvc == b.nvc && kMultiFamilies[k].sb == b.sb && kMultiFamilies[k].ncr == b.ncr)
+          b.multi_kind = k;
+      if (b.multi_kind < 0)
+        return bad("single_launch: bin (nv capacity " + std::to_string(b.nvc) + ", " + std::to_string(16 * b.sb) +
+                   " bodies, " + std::to_string(b.ncr) + " contacts in registers) is not in the multi-bin kernel");
+    }
+    hp->multi = true;
+  }
   // streams: longest-first assignment of the bins to the least-loaded stream
   {
     const int nbins = (int)hp->bins.size();
-    const int ns = hp->opts.streams == 0 ? nbins : std::min(hp->opts.streams, nbins);
+    const int ns = hp->multi ? 1 : (hp->opts.streams == 0 ? nbins : std::min(hp->opts.streams, nbins));
     hp->n_streams = std::max(1, ns);
     std::vector<double> load(hp->n_streams, 0.0);
     hp->stream_of.assign(nbins, 0);
@@ -782,7 +843,7 @@ int sim_launch_times(const sim_handle* hc, int32_t* n_bins, float* ms, int32_t* 
   if (!h->opts.time_launches) return fail(h, SIM_E_STATE, "the handle was created without time_launches");
   if (n_bins) *n_bins = (int32_t)h->bins.size();
   for (int i = 0; i < (int)h->bins.size() && i < max_bins; ++i) {
-    Bin& b = h->bins[i];
+    Bin& b = h->multi ? h->bins[0] : h->bins[i];
     if (ms) {
       int rc = dev_check(h, hipEventSynchronize(b.t_end), "timing sync");
       if (rc) return rc;

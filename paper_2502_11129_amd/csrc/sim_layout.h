@@ -64,6 +64,18 @@ struct BinArgs {
   int reset;                    // 1: start from q0, v0 at k = 0
 };
 
+// All bins of a population in one launch: workgroups [block_start[i],
+// block_start[i + 1]) run bin i with the kernel family kind[i] (an index into
+// the multi-bin family list); bins are placed in decreasing cost order, so the
+// most expensive workgroups are dispatched first.
+constexpr int kMaxMultiBins = 8;
+struct MultiArgs {
+  int nbins;
+  int kind[kMaxMultiBins];
+  int block_start[kMaxMultiBins + 1];
+  BinArgs bin[kMaxMultiBins];
+};
+
 // Overflow scratch layout per variant (floats):
 //   list  [max_contacts][4]   x, y, z, ancestor mask of the contact body (uint bits)
 //   scal  [max_contacts][kOvfScal]

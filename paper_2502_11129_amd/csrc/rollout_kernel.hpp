@@ -159,12 +159,13 @@ __device__ __forceinline__ sv imul(const sinertia& J, const sv& V) {
 // Per-variant LDS area.
 // ----------------------------------------------------------------------------
 template <int NVC, int SB, int NCR>
-struct GroupLds {
+struct alignas(16) GroupLds {
   static constexpr int NBC = 16 * SB;
   static constexpr int MST = NVC + 1;                 // padded row stride of the matrices
   static constexpr int A_BODY = NBC * 24;             // forward: R9 p3 V6 A6; backward: C10 F6
   static constexpr int A_MAT = NVC * MST;             // assembled M~, later M~^-1 (rotated columns)
   static constexpr int A_WORDS = A_BODY > A_MAT ? A_BODY : A_MAT;
+  static_assert(A_MAT % 4 == 0, "the matrix area is cleared with 16-byte stores");
   float A[A_WORDS];
   float WO[NBC][12];        // hinge axis w, anchor o (world), composite force C S of the hinge
   int par[NBC];
@@ -433,8 +434,9 @@ __device__ __forceinline__ void rollout_body(const BinArgs& a, const ModelParams
           const int dof = r0 + b - 1;
           const float th = sh.th[dof], thd = sh.thd[dof];
           const f3 u = mk(rec[BW_AXIS], rec[BW_AXIS + 1], rec[BW_AXIS + 2]);
-          float sn, cs;
-          sincosf(th, &sn, &cs);
+          // hardware sine/cosine: joint angles stay within a few radians,
+          // where their absolute error (about 1e-6) is far below the step's
+          const float sn = __sinf(th), cs = __cosf(th);
           const m33 E = matmul(quat_rot(rec[BW_RQ], rec[BW_RQ + 1], rec[BW_RQ + 2], rec[BW_RQ + 3]),
                                axis_rot_acc(u, sn, cs));
           R = matmul(Rl, E);
@@ -617,7 +619,10 @@ __device__ __forceinline__ void rollout_body(const BinArgs& a, const ModelParams
       }
     }
     wave_sync();  // composite reads done; the area becomes the assembled matrix
-    for (int e = lane; e < NVC * MST; e += 16) sh.A[e] = 0.f;
+    {
+      float4* a4 = reinterpret_cast<float4*>(sh.A);  // A is 16-byte aligned (first member)
+      for (int e = lane; e < (NVC * MST + 3) / 4; e += 16) a4[e] = make_float4(0.f, 0.f, 0.f, 0.f);
+    }
     wave_sync();
     {
       float* Ml = sh.A;
@@ -750,7 +755,7 @@ __device__ __forceinline__ void rollout_body(const BinArgs& a, const ModelParams
       const float* rec = bodyv + (size_t)b * BW_WORDS;
       double ph = (double)rec[BW_CPG + 1] * tk + (double)rec[BW_CPG + 2];
       ph -= 6.283185307179586 * floor(ph * 0.15915494309189535);
-      const float target = rec[BW_CPG] * sinf((float)ph);
+      const float target = rec[BW_CPG] * __sinf((float)ph);  // phase reduced to [0, 2 pi)
       aS[s] = hinge ? kp * (target - thS[s]) : 0.f;
       float rhs = -dt * cS[s];
       if (hinge) rhs += dt * (aS[s] - ba * vS[s]);

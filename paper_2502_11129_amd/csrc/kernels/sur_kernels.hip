@@ -117,7 +117,11 @@ __global__ __launch_bounds__(256) void gemm_kernel(GemmArgs a) {
 #pragma unroll
     for (int j = 0; j < 2; ++j) acc[i][j] = f32x4{0.f, 0.f, 0.f, 0.f};
 
-  for (int k0 = 0; k0 < a.K; k0 += BK) {
+  // K range of this layer (the whole of K unless the product is split)
+  const int kchunk = a.ksplit > 1 ? ((a.K + a.ksplit - 1) / a.ksplit + BK - 1) / BK * BK : a.K;
+  const int kbeg = blockIdx.z * kchunk;
+  const int kend = min(a.K, kbeg + kchunk);
+  for (int k0 = kbeg; k0 < kend; k0 += BK) {
     load_tile<AL>(As, a.A, a.lda, a.gatherA, a.rowsA, a.onesRow, a.M, a.K, m0, k0, t);
     load_tile<BL>(Bs, a.B, a.ldb, nullptr, 0, -1, a.N, a.K, n0, k0, t);
     __syncthreads();
@@ -154,16 +158,35 @@ __global__ __launch_bounds__(256) void gemm_kernel(GemmArgs a) {
         } else if (EPI == kEpiGeluGrad) {
           const float z = a.zin[(int64_t)m * a.ldz + n];
           a.hout[o] = f2bf(v * gelu_grad(z));
+        } else if (a.ksplit > 1) {
+          a.partial[(size_t)blockIdx.z * a.M * a.N + (size_t)m * a.N + n] = v;
         } else {
           a.fout[o] = v;
         }
       }
 }
 
+// Sum of the split-K layers in layer order (deterministic): out[m][n] = sum_z partial[z][m][n].
+__global__ __launch_bounds__(256) void splitk_reduce_kernel(int M, int N, int layers, const float* __restrict__ partial,
+                                                            float* __restrict__ out, int ldc) {
+  const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (i >= (int64_t)M * N) return;
+  float s = 0.f;
+  for (int z = 0; z < layers; ++z) s += partial[(size_t)z * M * N + i];
+  const int m = (int)(i / N), n = (int)(i % N);
+  out[(int64_t)m * ldc + n] = s;
+}
+
 template <int AL, int BL, int EPI>
 static hipError_t launch_gemm(const GemmArgs& a, hipStream_t s) {
-  dim3 grid((a.N + BN - 1) / BN, (a.M + BM - 1) / BM);
+  const int layers = (EPI == kEpiF32 && a.ksplit > 1) ? a.ksplit : 1;
+  dim3 grid((a.N + BN - 1) / BN, (a.M + BM - 1) / BM, layers);
   hipLaunchKernelGGL((gemm_kernel<AL, BL, EPI>), grid, dim3(256), 0, s, a);
+  if (layers > 1) {
+    const int64_t total = (int64_t)a.M * a.N;
+    hipLaunchKernelGGL(splitk_reduce_kernel, dim3((unsigned)((total + 255) / 256)), dim3(256), 0, s, a.M, a.N, layers,
+                       a.partial, a.fout, a.ldc);
+  }
   return hipGetLastError();
 }
 

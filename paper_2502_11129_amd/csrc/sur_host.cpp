@@ -7,6 +7,7 @@
 #include <cstdio>
 #include <cstring>
 #include <string>
+#include <algorithm>
 #include <vector>
 
 #include "sur_launch.h"
@@ -16,6 +17,8 @@ using namespace surk;
 namespace {
 
 constexpr int64_t kPredictChunk = 65536;  // rows per forward pass of sur_predict
+constexpr int kMaxSplitK = 16;            // layers of a weight-gradient product
+constexpr int kSplitKRows = 256;          // batch rows per layer at least
 
 struct Work {
   float *p, *m, *v, *g;
@@ -25,6 +28,8 @@ struct Work {
   float *z1, *z2, *z3;
   uint16_t *h1, *h2, *h3, *dza, *dzb;
   float *y, *r, *dy, *partial, *loss;
+  // split-K layers of the weight-gradient products
+  float* splitk;
   // top-k scratch
   uint32_t *hist, *state, *blocks;
   int64_t blocks_cap;
@@ -109,6 +114,7 @@ static size_t layout(const sur_handle* h, char* base, Work* w) {
   x.dy = (float*)take(sizeof(float) * R);
   x.partial = (float*)take(sizeof(float) * ((R + kHeadChunk - 1) / kHeadChunk) * (kHid + 2));
   x.loss = (float*)take(sizeof(float) * 4);
+  x.splitk = (float*)take(sizeof(float) * kMaxSplitK * (kHid + 1) * kHid);
   x.hist = (uint32_t*)take(sizeof(uint32_t) * 256);
   x.state = (uint32_t*)take(sizeof(uint32_t) * 4);
   x.blocks = (uint32_t*)take(sizeof(uint32_t) * 3 * nblk_cap);
@@ -276,6 +282,9 @@ static int train_step(sur_handle* h, int B, const uint16_t* X, int64_t x_rows, c
   a.ldb = kHid;
   a.fout = w.g + kOffW3;
   a.ldc = kHid;
+  // the batch (the reduction) is long and M x N small: split it over layers
+  a.ksplit = std::min(kMaxSplitK, std::max(1, B / kSplitKRows));
+  a.partial = w.splitk;
   SUR_HIP(h, gemm(kRowM, kRowM, kEpiF32, a, s), "grad W3");
   // dz2 = bf16((dz3 W3^T) * GELU'(z2))
   GemmArgs d{};

@@ -46,6 +46,11 @@ struct GemmArgs {
   int ldz;
   float* fout;        // kEpiF32
   int ldc;
+  // kEpiF32 only: split the reduction dimension K over `ksplit` workgroup
+  // layers; layer z writes its partial product to partial + z * M * N (row
+  // stride N) and a second pass sums the layers in order into fout
+  int ksplit;
+  float* partial;
 };
 
 hipError_t gemm(int alayout, int blayout, int epi, const GemmArgs& a, hipStream_t s);

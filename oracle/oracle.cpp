@@ -19,6 +19,16 @@
 // force by Kane's method; contact: linearly-implicit soft normal in
 // acceleration units, Coulomb disk friction, sequential impulses.
 //
+// Optional ball (the box-and-ball scene of Sec. 5): a free solid sphere per
+// variant, generalised velocity = world angular velocity and world velocity of
+// its centre (so its mass matrix block is constant and its bias is gravity
+// alone), state appended after the robot's.  Contacts: ball-plane (the
+// sphere's lowest point) and ball-box against every box of the robot (closest
+// point of the box to the centre; a centre inside a box is pushed out through
+// the nearest face), normal from the box to the ball, relative velocity ball
+// minus box, friction in the tangent plane of the orthonormal basis of Duff
+// et al., "Building an Orthonormal Basis, Revisited", JCGT 6(1), 2017.
+//
 // The library is templated on the scalar so a float instance can measure how
 // sensitive a trajectory is to single precision.  An RK4 mode (no contact, no
 // solver) integrates the smooth dynamics for the energy/momentum pins.
@@ -151,7 +161,10 @@ template <class T> struct Variant {
   std::vector<Body<T>> bodies;
   std::vector<std::vector<int>> path;  // ancestors-or-self (hinge bodies only, root excluded)
   T mu;
-  int nh, nq, nv, r0;                  // r0 = number of root DoFs (6 or 0)
+  int nh, nq, nv, r0;                  // r0 = number of root DoFs (6 or 0); nq, nv include the ball
+  int nqr, nvr;                        // robot coordinates only (the ball's follow)
+  bool ball = false;
+  T ball_r = 0, ball_m = 0, ball_I = 0;  // radius, mass, 2/5 m r^2
   T root_p[3], root_q[4];              // FIXED root pose
   std::vector<T> q0, v0;
 };
@@ -169,7 +182,53 @@ template <class T> struct Kin {
   std::vector<V3<T>> p, w, o;
   V3<T> p0;
   M3<T> R0;
+  V3<T> cb{};  // ball centre
 };
+
+// Orthonormal tangents (t1, t2) of a unit normal n (Duff et al. 2017).
+template <class T> void tangent_basis(const V3<T>& n, V3<T>& t1, V3<T>& t2) {
+  T sign = std::copysign(T(1), n[2]);
+  T a = T(-1) / (sign + n[2]);
+  T b = n[0] * n[1] * a;
+  t1 = {1 + sign * n[0] * n[0] * a, sign * b, -sign * n[0]};
+  t2 = {b, sign + n[1] * n[1] * a, -n[1]};
+}
+
+// Sphere (centre c, radius r) against a box (centre p, rotation R world <- box,
+// half extents h).  With l = R^T (c - p) the centre in the box frame: outside
+// the box, the closest box point q = p + R clamp(l, -h, h), contact iff
+// |c - q| < r, normal (c - q)/|c - q|, depth r - |c - q|.  Centre inside or on
+// the box: the face nearest to the centre (first of equals in x, y, z order),
+// its outward normal R (+-e_k) normalised, depth r + distance to it.  Returns
+// the normal (box -> ball), the contact point c - r n (the sphere's deepest
+// point) and the depth.
+template <class T> bool sphere_box(const V3<T>& c, T r, const V3<T>& p, const M3<T>& R, const V3<T>& h,
+                                   V3<T>& x, V3<T>& n, T& depth) {
+  V3<T> l = mtv(R, sub(c, p));
+  bool inside = true;
+  for (int k = 0; k < 3; ++k) inside = inside && std::abs(l[k]) <= h[k];
+  if (!inside) {
+    V3<T> cl;
+    for (int k = 0; k < 3; ++k) cl[k] = std::max(-h[k], std::min(h[k], l[k]));
+    V3<T> d = sub(c, add(p, mv(R, cl)));
+    T dist = std::sqrt(dot(d, d));
+    if (!(dist < r)) return false;
+    n = scl(d, T(1) / dist);
+    depth = r - dist;
+  } else {
+    int kb = 0;
+    T gap = h[0] - std::abs(l[0]);
+    for (int k = 1; k < 3; ++k)
+      if (h[k] - std::abs(l[k]) < gap) { gap = h[k] - std::abs(l[k]); kb = k; }
+    V3<T> nl{0, 0, 0};
+    nl[kb] = l[kb] >= 0 ? T(1) : T(-1);
+    n = mv(R, nl);
+    n = scl(n, T(1) / std::sqrt(dot(n, n)));
+    depth = r + gap;
+  }
+  x = sub(c, scl(n, r));
+  return true;
+}
 
 template <class T> struct Sim {
   Params P;
@@ -191,6 +250,7 @@ template <class T> struct Sim {
       th = q;
     }
     kin.R[0] = kin.R0; kin.p[0] = kin.p0; kin.w[0] = {0, 0, 0}; kin.o[0] = kin.p0;
+    if (V.ball) kin.cb = {q[V.nqr], q[V.nqr + 1], q[V.nqr + 2]};
     for (int i = 1; i < nb; ++i) {
       const Body<T>& B = V.bodies[i];
       int l = B.parent;
@@ -225,6 +285,27 @@ template <class T> struct Sim {
       for (int rr = 0; rr < 3; ++rr) J[rr * nv + d] = c[rr];
     }
   }
+  // World Jacobian of the velocity of a point x moving with the ball (3 x nv):
+  // columns of the ball's angular velocity e_k x (x - cb), of its centre velocity e_k.
+  void ball_point_jacobian(const Variant<T>& V, const Kin<T>& kin, const V3<T>& x, T* J) const {
+    int nv = V.nv;
+    for (int k = 0; k < 3 * nv; ++k) J[k] = 0;
+    V3<T> r = sub(x, kin.cb);
+    for (int k = 0; k < 3; ++k) {
+      V3<T> e{0, 0, 0};
+      e[k] = 1;
+      V3<T> a = cross(e, r);
+      for (int rr = 0; rr < 3; ++rr) {
+        J[rr * nv + V.nvr + k] = a[rr];
+        J[rr * nv + V.nvr + 3 + k] = e[rr];
+      }
+    }
+  }
+  void ball_angular_jacobian(const Variant<T>& V, T* J) const {
+    int nv = V.nv;
+    for (int k = 0; k < 3 * nv; ++k) J[k] = 0;
+    for (int k = 0; k < 3; ++k) J[k * nv + V.nvr + k] = 1;
+  }
   // Angular-velocity Jacobian of body i (3 x nv): [R0, 0, w_j on path].
   void angular_jacobian(const Variant<T>& V, const Kin<T>& kin, int i, T* J) const {
     int nv = V.nv;
@@ -258,6 +339,16 @@ template <class T> struct Sim {
           for (int r = 0; r < 3; ++r) s += B.mass * Jv[r * nv + a] * Jv[r * nv + b];
           V3<T> Ja = {Jw[a], Jw[nv + a], Jw[2 * nv + a]}, Jb = {Jw[b], Jw[nv + b], Jw[2 * nv + b]};
           s += dot(Ja, mv(I, Jb));
+          M[a * nv + b] += s;
+        }
+    }
+    if (V.ball) {  // the ball as one more body, isotropic inertia
+      ball_point_jacobian(V, kin, kin.cb, Jv.data());
+      ball_angular_jacobian(V, Jw.data());
+      for (int a = 0; a < nv; ++a)
+        for (int b = 0; b < nv; ++b) {
+          T s = 0;
+          for (int r = 0; r < 3; ++r) s += V.ball_m * Jv[r * nv + a] * Jv[r * nv + b] + V.ball_I * Jw[r * nv + a] * Jw[r * nv + b];
           M[a * nv + b] += s;
         }
     }
@@ -300,16 +391,53 @@ template <class T> struct Sim {
       for (int k = 0; k < nv; ++k)
         for (int r = 0; r < 3; ++r) c[k] += Jv[r * nv + k] * f[r] + Jw[r * nv + k] * n[r];
     }
+    if (V.ball) {
+      // centre acceleration and angular acceleration are the generalised
+      // accelerations themselves: zero at zero generalised acceleration
+      ball_point_jacobian(V, kin, kin.cb, Jv.data());
+      ball_angular_jacobian(V, Jw.data());
+      V3<T> om_b = {v[V.nvr], v[V.nvr + 1], v[V.nvr + 2]};
+      V3<T> f = scl(sub(V3<T>{0, 0, 0}, gv), V.ball_m);
+      V3<T> n = cross(om_b, scl(om_b, V.ball_I));
+      for (int k = 0; k < nv; ++k)
+        for (int r = 0; r < 3; ++r) c[k] += Jv[r * nv + k] * f[r] + Jw[r * nv + k] * n[r];
+    }
   }
 
+  // kind 0: box corner - plane (body, corner); 1: ball - plane; 2: ball - box (body)
   struct Contact {
-    int body, corner;
-    V3<T> x;
+    int body, corner, kind = 0;
+    V3<T> x, n{0, 0, 1};
     T depth;
     std::vector<T> J[3], W[3];  // rows: 0 = normal (z), 1 = x, 2 = y
     T D[3];
     T lam[3];
   };
+
+  // Rows of a contact in the slots (t1, t2, n) = (x, y, z) of a 3 x nv matrix:
+  // plane contacts take world x, y, z; ball-box contacts project the relative
+  // velocity Jacobian (ball minus box at the contact point) on (t1, t2, n).
+  void contact_jacobian(const Variant<T>& V, const Kin<T>& kin, const Contact& ct, T* Jp) const {
+    const int nv = V.nv;
+    if (ct.kind == 0) {
+      point_jacobian(V, kin, ct.body, ct.x, Jp);
+    } else if (ct.kind == 1) {
+      ball_point_jacobian(V, kin, ct.x, Jp);
+    } else {
+      std::vector<T> Ja(3 * nv), Jb(3 * nv);
+      ball_point_jacobian(V, kin, ct.x, Ja.data());
+      point_jacobian(V, kin, ct.body, ct.x, Jb.data());
+      V3<T> t1, t2;
+      tangent_basis(ct.n, t1, t2);
+      const V3<T> dirs[3] = {t1, t2, ct.n};
+      for (int r = 0; r < 3; ++r)
+        for (int k = 0; k < nv; ++k) {
+          T s = 0;
+          for (int c = 0; c < 3; ++c) s += dirs[r][c] * (Ja[c * nv + k] - Jb[c * nv + k]);
+          Jp[r * nv + k] = s;
+        }
+    }
+  }
 
   // Active corners in (body, corner) order: corner c has sign bits (x,y,z) = bits 0,1,2.
   void detect(const Variant<T>& V, const Kin<T>& kin, std::vector<Contact>& out) const {
@@ -326,6 +454,22 @@ template <class T> struct Sim {
           C.body = i; C.corner = c; C.x = x; C.depth = -x[2];
           out.push_back(std::move(C));
         }
+      }
+    }
+    if (!V.ball) return;
+    // the ball after the boxes: plane first, then every box in body order
+    if (kin.cb[2] - V.ball_r < 0) {
+      Contact C;
+      C.body = -1; C.corner = -1; C.kind = 1;
+      C.x = {kin.cb[0], kin.cb[1], kin.cb[2] - V.ball_r};
+      C.depth = -C.x[2];
+      out.push_back(std::move(C));
+    }
+    for (int i = 0; i < nb; ++i) {
+      Contact C;
+      if (sphere_box(kin.cb, V.ball_r, kin.p[i], kin.R[i], V.bodies[i].half, C.x, C.n, C.depth)) {
+        C.body = i; C.corner = -2; C.kind = 2;
+        out.push_back(std::move(C));
       }
     }
   }
@@ -374,7 +518,7 @@ template <class T> struct Sim {
     std::vector<T> Jp(3 * nv);
     const int rowsel[3] = {2, 0, 1};  // normal = world z, then world x, y
     for (auto& ct : C) {
-      point_jacobian(V, kin, ct.body, ct.x, Jp.data());
+      contact_jacobian(V, kin, ct, Jp.data());
       for (int r = 0; r < 3; ++r) {
         ct.J[r].assign(Jp.begin() + rowsel[r] * nv, Jp.begin() + (rowsel[r] + 1) * nv);
         ct.W[r].resize(nv);
@@ -443,6 +587,14 @@ template <class T> struct Sim {
       quat_mul(q + 3, dq, qn.data() + 3);
       quat_normalize(qn.data() + 3);
     }
+    if (V.ball) {  // world-frame velocities: p += dt v, Q <- exp(dt w) Q
+      const int qb = V.nqr, vb = V.nvr;
+      for (int k = 0; k < 3; ++k) qn[qb + k] = q[qb + k] + dt * vp[vb + 3 + k];
+      T dq[4];
+      quat_exp(V3<T>{dt * vp[vb], dt * vp[vb + 1], dt * vp[vb + 2]}, dq);
+      quat_mul(dq, q + qb + 3, qn.data() + qb + 3);
+      quat_normalize(qn.data() + qb + 3);
+    }
     // 9. failure check: a non-finite state freezes the variant
     bool ok = true;
     for (T x : qn) ok = ok && std::isfinite(double(x));
@@ -497,6 +649,13 @@ template <class T> struct Sim {
     } else {
       for (int j = 0; j < nh; ++j) out[j] = v[j];
     }
+    if (V.ball) {  // pdot = v, Qdot = 1/2 (0, w) Q
+      const int qb = V.nqr, vb = V.nvr;
+      for (int k = 0; k < 3; ++k) out[qb + k] = v[vb + 3 + k];
+      T w[4] = {0, v[vb], v[vb + 1], v[vb + 2]}, qd[4];
+      quat_mul(w, q + qb + 3, qd);
+      for (int k = 0; k < 4; ++k) out[qb + 3 + k] = qd[k] / 2;
+    }
   }
   void rk4_step(int vi, bool pd) {
     const Variant<T>& V = var[vi];
@@ -515,6 +674,7 @@ template <class T> struct Sim {
     for (int k = 0; k < nq; ++k) S.q[k] = q0[k] + T(h / 6) * (kq[0][k] + 2 * kq[1][k] + 2 * kq[2][k] + kq[3][k]);
     for (int k = 0; k < nv; ++k) S.v[k] = v0[k] + T(h / 6) * (kv[0][k] + 2 * kv[1][k] + 2 * kv[2][k] + kv[3][k]);
     if (V.r0 == 6) quat_normalize(S.q.data() + 3);
+    if (V.ball) quat_normalize(S.q.data() + V.nqr + 3);
     S.k += 1;
   }
 
@@ -539,6 +699,13 @@ template <class T> struct Sim {
       E += B.mass * dot(vel, vel) / 2 + dot(om, mv(I, om)) / 2 - B.mass * dot(gv, kin.p[i]);
       Pm = add(Pm, scl(vel, B.mass));
       Lm = add(Lm, add(cross(kin.p[i], scl(vel, B.mass)), mv(I, om)));
+    }
+    if (V.ball) {
+      const int vb = V.nvr;
+      V3<T> vel = {S.v[vb + 3], S.v[vb + 4], S.v[vb + 5]}, om = {S.v[vb], S.v[vb + 1], S.v[vb + 2]};
+      E += V.ball_m * dot(vel, vel) / 2 + V.ball_I * dot(om, om) / 2 - V.ball_m * dot(gv, kin.cb);
+      Pm = add(Pm, scl(vel, V.ball_m));
+      Lm = add(Lm, add(cross(kin.cb, scl(vel, V.ball_m)), scl(om, V.ball_I)));
     }
     out[0] = E;
     for (int r = 0; r < 3; ++r) { out[1 + r] = Pm[r]; out[4 + r] = Lm[r]; }
@@ -587,7 +754,7 @@ template <class T>
 void parse(Sim<T>& S, int n, const int32_t* body_offset, const int32_t* parent, const float* half,
            const float* mass, const float* ap, const float* ac, const float* rq, const float* axis,
            const float* cpg, const float* mu, const float* q0, const float* v0, const float* root_pose,
-           const double* params, int root_fixed, int K) {
+           const float* ball, const double* params, int root_fixed, int K) {
   S.P = Params{params[0], params[1], params[2], params[3], params[4], params[5],
                {params[6], params[7], params[8]}, K, root_fixed};
   S.var.resize(n);
@@ -600,8 +767,16 @@ void parse(Sim<T>& S, int n, const int32_t* body_offset, const int32_t* parent, 
     V.path.resize(nb);
     V.nh = nb - 1;
     V.r0 = root_fixed ? 0 : 6;
-    V.nq = V.nh + (root_fixed ? 0 : 7);
-    V.nv = V.nh + V.r0;
+    V.nqr = V.nh + (root_fixed ? 0 : 7);
+    V.nvr = V.nh + V.r0;
+    V.ball = ball != nullptr;
+    if (V.ball) {
+      V.ball_r = T(ball[2 * i]);
+      V.ball_m = T(ball[2 * i + 1]);
+      V.ball_I = T(2) / T(5) * V.ball_m * V.ball_r * V.ball_r;
+    }
+    V.nq = V.nqr + (V.ball ? 7 : 0);
+    V.nv = V.nvr + (V.ball ? 6 : 0);
     V.mu = T(mu[i]);
     for (int k = 0; k < 3; ++k) V.root_p[k] = T(root_pose[7 * i + k]);
     for (int k = 0; k < 4; ++k) V.root_q[k] = T(root_pose[7 * i + 3 + k]);
@@ -635,22 +810,23 @@ void parse(Sim<T>& S, int n, const int32_t* body_offset, const int32_t* parent, 
 
 extern "C" {
 
-// Create a reference simulator.  params = [kp, kd, tau_max, k_contact, b_contact, dt, gx, gy, gz].
+// Create a reference simulator.  params = [kp, kd, tau_max, k_contact, b_contact, dt, gx, gy, gz];
+// ball = [radius, mass] per variant, or NULL for no ball.
 void* orc_create(int n, const int32_t* body_offset, const int32_t* parent, const float* half,
                  const float* mass, const float* anchor_parent, const float* anchor_child,
                  const float* rest_quat, const float* axis, const float* cpg, const float* mu,
-                 const float* q0, const float* v0, const float* root_pose, const double* params,
-                 int root_fixed, int pgs_iters, int precision) {
+                 const float* q0, const float* v0, const float* root_pose, const float* ball,
+                 const double* params, int root_fixed, int pgs_iters, int precision) {
   auto* h = new Handle();
   h->precision = precision;
   if (precision == 32) {
     h->f.reset(new Sim<float>());
     parse(*h->f, n, body_offset, parent, half, mass, anchor_parent, anchor_child, rest_quat, axis, cpg, mu,
-          q0, v0, root_pose, params, root_fixed, pgs_iters);
+          q0, v0, root_pose, ball, params, root_fixed, pgs_iters);
   } else {
     h->d.reset(new Sim<double>());
     parse(*h->d, n, body_offset, parent, half, mass, anchor_parent, anchor_child, rest_quat, axis, cpg, mu,
-          q0, v0, root_pose, params, root_fixed, pgs_iters);
+          q0, v0, root_pose, ball, params, root_fixed, pgs_iters);
   }
   return h;
 }
@@ -756,8 +932,9 @@ int orc_dynamics(void* hp, int vi, const double* q, const double* v, double* M, 
   return 0;
 }
 // Active contacts at q: returns count (<= max); body, corner, point x [3], depth, rows J [3*nv] (n, x, y).
+// corner: 0..7 box corner, -1 ball-plane, -2 ball-box (body = the box); normal n [3] (box -> ball).
 int orc_contacts(void* hp, int vi, const double* q, int max, int32_t* body, int32_t* corner, double* x,
-                 double* depth, double* J) {
+                 double* depth, double* J, double* normal) {
   auto* h = static_cast<Handle*>(hp);
   if (h->precision != 64) return -1;
   auto& S = *h->d;
@@ -771,8 +948,8 @@ int orc_contacts(void* hp, int vi, const double* q, int max, int32_t* body, int3
   const int rowsel[3] = {2, 0, 1};
   for (int i = 0; i < n; ++i) {
     body[i] = C[i].body; corner[i] = C[i].corner; depth[i] = C[i].depth;
-    for (int k = 0; k < 3; ++k) x[3 * i + k] = C[i].x[k];
-    S.point_jacobian(V, kin, C[i].body, C[i].x, Jp.data());
+    for (int k = 0; k < 3; ++k) { x[3 * i + k] = C[i].x[k]; normal[3 * i + k] = C[i].n[k]; }
+    S.contact_jacobian(V, kin, C[i], Jp.data());
     for (int r = 0; r < 3; ++r)
       for (int k = 0; k < nv; ++k) J[(3 * i + r) * nv + k] = Jp[rowsel[r] * nv + k];
   }

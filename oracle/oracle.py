@@ -6,7 +6,8 @@ and the ``cpu_baseline`` leg of ``bench.py``; the product path never loads it.
 The wrapper accepts any object carrying the variant-CSR model arrays
 (``body_offset``, ``parent``, ``half_ext``, ``mass``, ``anchor_parent``,
 ``anchor_child``, ``rest_quat``, ``axis``, ``cpg``, ``mu``, ``q0``, ``v0``,
-``root_pose``, ``root_type``, ``params``) -- the seeded generators produce
+``root_pose``, ``root_type``, ``params`` and optionally ``ball``: [N, 2] radius
+and mass of one free sphere per variant) -- the seeded generators produce
 such objects; nothing here imports the HIP library or its binding.
 """
 from __future__ import annotations
@@ -43,7 +44,7 @@ def _load():
         I32, I64, U32, U64 = (C.POINTER(C.c_int32), C.POINTER(C.c_int64), C.POINTER(C.c_uint32),
                               C.POINTER(C.c_uint64))
         lib.orc_create.restype = P
-        lib.orc_create.argtypes = [I, I32, I32, F, F, F, F, F, F, F, F, F, F, F, D, I, I, I]
+        lib.orc_create.argtypes = [I, I32, I32, F, F, F, F, F, F, F, F, F, F, F, F, D, I, I, I]
         lib.orc_destroy.argtypes = [P]
         lib.orc_step.argtypes = [P, I, I]
         lib.orc_step_subset.argtypes = [P, I, I32, I, I]
@@ -58,7 +59,7 @@ def _load():
         lib.orc_fk.restype = I
         lib.orc_dynamics.argtypes = [P, I, D, D, D, D]
         lib.orc_dynamics.restype = I
-        lib.orc_contacts.argtypes = [P, I, D, I, I32, I32, D, D, D]
+        lib.orc_contacts.argtypes = [P, I, D, I, I32, I32, D, D, D, D]
         lib.orc_contacts.restype = I
         lib.orc_cholesky.argtypes = [I, D, D]
         lib.orc_cholesky.restype = I
@@ -104,14 +105,16 @@ class Oracle:
             q0=np.ascontiguousarray(pop.q0, np.float32),
             v0=np.ascontiguousarray(pop.v0, np.float32),
             rp=np.ascontiguousarray(pop.root_pose, np.float32),
+            ball=(None if getattr(pop, "ball", None) is None else np.ascontiguousarray(pop.ball, np.float32)),
             prm=np.array([prm["kp"], prm["kd"], prm["tau_max"], prm["k_contact"], prm["b_contact"],
                           prm["dt"], g[0], g[1], g[2]], dtype=np.float64))
         k = self._keep
         self.n = int(k["bo"].shape[0] - 1)
         self.root_fixed = int(pop.root_type != 0)
         nb = np.diff(k["bo"]).astype(np.int64)
-        self.nq = nb - 1 + (0 if self.root_fixed else 7)
-        self.nv = nb - 1 + (0 if self.root_fixed else 6)
+        self.has_ball = k["ball"] is not None
+        self.nq = nb - 1 + (0 if self.root_fixed else 7) + (7 if self.has_ball else 0)
+        self.nv = nb - 1 + (0 if self.root_fixed else 6) + (6 if self.has_ball else 0)
         self.q_off = np.concatenate([[0], np.cumsum(self.nq)])
         self.v_off = np.concatenate([[0], np.cumsum(self.nv)])
         self.dt = float(prm["dt"])
@@ -119,7 +122,8 @@ class Oracle:
         f = lambda a: _p(a, C.c_float)
         self.h = lib.orc_create(self.n, _p(k["bo"], C.c_int32), _p(k["parent"], C.c_int32), f(k["half"]),
                                 f(k["mass"]), f(k["ap"]), f(k["ac"]), f(k["rq"]), f(k["axis"]), f(k["cpg"]),
-                                f(k["mu"]), f(k["q0"]), f(k["v0"]), f(k["rp"]), _p(k["prm"], C.c_double),
+                                f(k["mu"]), f(k["q0"]), f(k["v0"]), f(k["rp"]),
+                                None if k["ball"] is None else f(k["ball"]), _p(k["prm"], C.c_double),
                                 self.root_fixed, K, precision)
         self._lib = lib
 
@@ -206,12 +210,13 @@ class Oracle:
         nv = int(self.nv[vi])
         m = max_contacts
         body = np.zeros(m, np.int32); corner = np.zeros(m, np.int32)
-        x = np.zeros((m, 3)); d = np.zeros(m); J = np.zeros((m, 3, nv))
+        x = np.zeros((m, 3)); d = np.zeros(m); J = np.zeros((m, 3, nv)); nrm = np.zeros((m, 3))
         n = self._lib.orc_contacts(self.h, vi, _p(q, C.c_double), m, _p(body, C.c_int32),
                                    _p(corner, C.c_int32), _p(x, C.c_double), _p(d, C.c_double),
-                                   _p(J, C.c_double))
+                                   _p(J, C.c_double), _p(nrm, C.c_double))
         n = min(n, m)
-        return dict(body=body[:n], corner=corner[:n], x=x[:n], depth=d[:n], J=J[:n])
+        # corner: 0..7 box corner on the plane, -1 ball on the plane, -2 ball on box `body`
+        return dict(body=body[:n], corner=corner[:n], x=x[:n], depth=d[:n], J=J[:n], normal=nrm[:n])
 
     def variant_state(self, vi: int):
         q, v, k, s = self.get_state()

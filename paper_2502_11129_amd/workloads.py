@@ -27,7 +27,11 @@ Conventions of the model layout (shared by every consumer):
 * a FREE root has generalised position (p0, Q0, theta_1..theta_nh) and
   velocity (omega_body, v_body, thetadot_1..thetadot_nh); a FIXED root
   (used by unit tests only) has only the hinge coordinates and its pose is
-  given by ``root_pose`` = (p0, Q0).
+  given by ``root_pose`` = (p0, Q0);
+* optionally every variant of a population carries one free solid sphere
+  (``ball`` = [radius, mass] per variant, the box-and-ball scene): its
+  position (centre, Q) follows the robot's coordinates in q and its world
+  angular velocity and centre velocity follow the robot's in v.
 """
 from __future__ import annotations
 
@@ -94,6 +98,7 @@ class Population:
     name: str = ""
     steps: int = 0                   # horizon T of the workload
     lifted: int = 0                  # boxes lifted off the plane at creation
+    ball: np.ndarray | None = None   # float32 [N,2] (radius, mass) of each variant's ball, or None
 
     @property
     def n_variants(self) -> int:
@@ -109,11 +114,11 @@ class Population:
 
     @property
     def nq(self) -> np.ndarray:
-        return self.n_hinges + (7 if self.root_type == ROOT_FREE else 0)
+        return self.n_hinges + (7 if self.root_type == ROOT_FREE else 0) + (7 if self.ball is not None else 0)
 
     @property
     def nv(self) -> np.ndarray:
-        return self.n_hinges + (6 if self.root_type == ROOT_FREE else 0)
+        return self.n_hinges + (6 if self.root_type == ROOT_FREE else 0) + (6 if self.ball is not None else 0)
 
     @property
     def q_offset(self) -> np.ndarray:
@@ -139,7 +144,8 @@ class Population:
             axis=self.axis[bsel].copy(), cpg=self.cpg[bsel].copy(), mu=self.mu[idx].copy(),
             q0=self.q0[qsel].copy(), v0=self.v0[vsel].copy(),
             root_pose=self.root_pose[idx].copy(), root_type=self.root_type,
-            params=dict(self.params), name=self.name, steps=self.steps)
+            params=dict(self.params), name=self.name, steps=self.steps,
+            ball=None if self.ball is None else self.ball[idx].copy())
 
 
 class _Builder:
@@ -150,6 +156,7 @@ class _Builder:
         self.rows = dict(parent=[], half=[], mass=[], ap=[], ac=[], rq=[], axis=[], cpg=[])
         self.offsets = [0]
         self.mu, self.q0, self.v0, self.root_pose = [], [], [], []
+        self.ball = []
 
     def add_body(self, parent, half, mass, face=None, parent_half=None, axis_flag=AXIS_Z,
                  cpg=(0.0, 0.0, 0.0)):
@@ -170,7 +177,8 @@ class _Builder:
             r["axis"].append((0.0, 0.0, 1.0) if axis_flag == AXIS_Z else (0.0, 1.0, 0.0))
         r["cpg"].append(tuple(cpg))
 
-    def end_variant(self, mu, q0, v0, root_pose=(0, 0, 0, 1, 0, 0, 0)):
+    def end_variant(self, mu, q0, v0, root_pose=(0, 0, 0, 1, 0, 0, 0), ball=None):
+        self.ball.append(ball)
         self.offsets.append(len(self.rows["parent"]))
         self.mu.append(mu)
         self.q0.extend(q0)
@@ -191,7 +199,13 @@ class _Builder:
             q0=f32(self.q0, (-1,)), v0=f32(self.v0, (-1,)),
             root_pose=f32(self.root_pose, (-1, 7)), root_type=self.root_type,
             params=dict(DEFAULT_PARAMS if params is None else params),
-            name=name, steps=steps, lifted=lifted)
+            name=name, steps=steps, lifted=lifted, ball=self._balls())
+
+    def _balls(self):
+        has = [bl is not None for bl in self.ball]
+        if any(has) and not all(has):
+            raise ValueError("either every variant has a ball or none does")
+        return np.asarray(self.ball, dtype=np.float32).reshape(-1, 2) if has and all(has) else None
 
 
 def _robot_state(nh):
@@ -370,17 +384,28 @@ def chain(n_hinges, faces, axis_flags, root_type=ROOT_FIXED, root_pose=(0, 0, 1.
 
 
 def single_box(half=(0.05, 0.05, 0.05), mass=None, pos=(0, 0, 1.0), quat=(1, 0, 0, 0),
-               omega_b=(0, 0, 0), v_b=(0, 0, 0), mu=1.0, params=None, name="box"):
+               omega_b=(0, 0, 0), v_b=(0, 0, 0), mu=1.0, params=None, name="box", ball=None):
+    """One free box; ``ball`` = dict(r, m, pos, quat, w, v) adds a ball
+    (world angular velocity w and centre velocity v)."""
     b = _Builder()
     m = 1000.0 * 8 * np.prod(half) if mass is None else mass
     b.add_body(-1, tuple(half), m)
-    b.end_variant(mu, [*pos, *quat], [*omega_b, *v_b])
+    q0, v0, bl = [*pos, *quat], [*omega_b, *v_b], None
+    if ball is not None:
+        q0 += [*ball["pos"], *ball.get("quat", (1.0, 0.0, 0.0, 0.0))]
+        v0 += [*ball.get("w", (0.0, 0.0, 0.0)), *ball.get("v", (0.0, 0.0, 0.0))]
+        bl = (ball["r"], ball["m"])
+    b.end_variant(mu, q0, v0, ball=bl)
     return b.build(name, 0, params=params)
 
 
 def concat(pops) -> Population:
-    """Concatenate populations that share root type and parameters."""
+    """Concatenate populations that share root type and parameters (and
+    either all carry a ball or none does)."""
     p0 = pops[0]
+    has_ball = [p.ball is not None for p in pops]
+    if any(has_ball) and not all(has_ball):
+        raise ValueError("cannot mix populations with and without a ball")
     nb = np.concatenate([p.n_bodies for p in pops])
     cat = lambda a: np.concatenate([getattr(p, a) for p in pops])
     return Population(
@@ -389,7 +414,87 @@ def concat(pops) -> Population:
         anchor_parent=cat("anchor_parent"), anchor_child=cat("anchor_child"),
         rest_quat=cat("rest_quat"), axis=cat("axis"), cpg=cat("cpg"), mu=cat("mu"),
         q0=cat("q0"), v0=cat("v0"), root_pose=cat("root_pose"), root_type=p0.root_type,
-        params=dict(p0.params), name="+".join(p.name for p in pops), steps=p0.steps)
+        params=dict(p0.params), name="+".join(p.name for p in pops), steps=p0.steps,
+        ball=cat("ball") if all(has_ball) else None)
+
+
+# ----------------------------------------------------------------------------
+# Box-and-ball scene: a free box and a free ball dropped on the plane
+# ----------------------------------------------------------------------------
+BALL_DENSITY = 1000.0
+
+
+def _ball_mass(r, density=BALL_DENSITY):
+    return density * 4.0 / 3.0 * np.pi * r ** 3
+
+
+def box_and_ball(n=131072, first=0, clearance=0.005, steps=2000):
+    """Box-and-ball variants: the box of ``boxes`` (sides U(0.05,0.3), density
+    1000, uniform orientation, centre height U(0.2,1.0), world velocities
+    N(0,0.5), mu U(0.3,1.2)) and a ball of radius U(0.03,0.15), density 1000,
+    dropped from 0.05-0.5 m above the box top at a horizontal offset N(0,0.1)
+    from the box centre (so that most balls land on the box), world velocity
+    N(0,0.5) and angular velocity N(0,2)."""
+    b = _Builder()
+    lifted = 0
+    for i in range(first, first + n):
+        rng = np.random.default_rng([7, i])
+        sides = rng.uniform(0.05, 0.3, 3)
+        H = rng.uniform(0.2, 1.0)
+        q = rng.normal(0.0, 1.0, 4)
+        q /= np.linalg.norm(q)
+        if q[0] < 0:
+            q = -q
+        vw = rng.normal(0.0, 0.5, 3)
+        ww = rng.normal(0.0, 0.5, 3)
+        mu = rng.uniform(0.3, 1.2)
+        r = rng.uniform(0.03, 0.15)
+        off = rng.normal(0.0, 0.1, 2)
+        gap = rng.uniform(0.05, 0.5)
+        bv = rng.normal(0.0, 0.5, 3)
+        bw = rng.normal(0.0, 2.0, 3)
+        half = sides / 2.0
+        R = _quat_to_rot(q)
+        reach = np.abs(R[2]) @ half
+        if H - reach < clearance:
+            H += clearance - (H - reach)
+            lifted += 1
+        m = 1000.0 * sides.prod()
+        b.add_body(-1, tuple(half), m)
+        zb = H + reach + gap + r
+        b.end_variant(mu, [0.0, 0.0, H, *q, off[0], off[1], zb, 1.0, 0.0, 0.0, 0.0],
+                      [*(R.T @ ww), *(R.T @ vw), *bw, *bv], ball=(r, _ball_mass(r)))
+    return b.build("box_and_ball", steps, lifted=lifted)
+
+
+def attach_ball(pop: Population, key=0, radius=(0.03, 0.08), speed=(0.0, 1.0)) -> Population:
+    """The same robots, each with a ball resting on the plane 0.15-0.35 m
+    from its core in a random direction and rolling towards it (radius
+    U(radius), density U(200,1000), speed U(speed)).  FREE roots only."""
+    if pop.root_type != ROOT_FREE or pop.ball is not None:
+        raise ValueError("attach_ball needs FREE roots without a ball")
+    n = pop.n_variants
+    qo, vo = pop.q_offset, pop.v_offset
+    q0, v0, ball = [], [], np.zeros((n, 2), np.float32)
+    for i in range(n):
+        rng = np.random.default_rng([8, key, i])
+        r = rng.uniform(*radius)
+        rho = rng.uniform(200.0, 1000.0)
+        dist = rng.uniform(0.15, 0.35)
+        ang = rng.uniform(0.0, 2.0 * np.pi)
+        sp = rng.uniform(*speed)
+        qi = pop.q0[qo[i]:qo[i + 1]]
+        c = np.array([qi[0] + dist * np.cos(ang), qi[1] + dist * np.sin(ang), r + 1e-3])
+        u = -np.array([np.cos(ang), np.sin(ang), 0.0])
+        q0.append(np.concatenate([qi, c, [1.0, 0.0, 0.0, 0.0]]))
+        v0.append(np.concatenate([pop.v0[vo[i]:vo[i + 1]], [0.0, 0.0, 0.0], sp * u]))
+        ball[i] = (r, _ball_mass(r, rho))
+    out = pop.subset(np.arange(n))
+    out.q0 = np.concatenate(q0).astype(np.float32)
+    out.v0 = np.concatenate(v0).astype(np.float32)
+    out.ball = ball
+    out.name = pop.name + "+ball"
+    return out
 
 
 CONFIGS = {
@@ -397,6 +502,7 @@ CONFIGS = {
     "boxes": boxes,
     "trees": random_trees,
     "quadrupeds": quadrupeds,
+    "box_and_ball": box_and_ball,
 }
 
 # Oracle spot-check subset of the random-tree population: indices 128*m.

@@ -1,0 +1,274 @@
+"""Pins of the oracle's ball (box-and-ball scene) against closed forms,
+conservation laws and brute-force geometry -- none of them re-types the
+oracle's own formulas.
+
+* free flight: semi-implicit Euler under gravity has the exact discrete
+  solution v_k = v_0 + k dt g, p_k = p_0 + k dt v_0 + dt^2 g k(k+1)/2, and a
+  constant world angular velocity turns Q by exp(k dt w);
+* mass matrix block of a solid sphere diag(2/5 m r^2 (x3), m (x3)), bias -m g;
+* resting ball: the soft normal row (acceleration units) settles at depth
+  |g| / k_contact whatever the mass and radius;
+* a sliding ball on a rough plane: friction acts at the contact point, so the
+  angular momentum about that point, m v r + I w, is conserved step by step,
+  and rolling sets in at v = 5/7 v_0 (solid sphere);
+* ball against a free cube in zero gravity: contact impulses are equal and
+  opposite at one point, so a head-on hit conserves linear and angular
+  momentum exactly, and a glancing one converges to conservation at first
+  order in dt (the box's velocity coordinates are in its body frame);
+* sphere-box geometry against a brute-force nearest-face search, and the
+  contact rows: zero for every rigid motion of box and ball together,
+  orthonormal (t1, t2, n) on the ball's translation.
+"""
+import numpy as np
+import pytest
+
+from oracle import oracle as O
+from paper_2502_11129_amd import workloads as W
+
+G = np.array([0.0, 0.0, -9.81])
+
+
+def _params(**kw):
+    p = dict(W.DEFAULT_PARAMS)
+    p.update(kw)
+    return p
+
+
+def _quat_mul(a, b):
+    w1, x1, y1, z1 = a
+    w2, x2, y2, z2 = b
+    return np.array([w1 * w2 - x1 * x2 - y1 * y2 - z1 * z2, w1 * x2 + x1 * w2 + y1 * z2 - z1 * y2,
+                     w1 * y2 - x1 * z2 + y1 * w2 + z1 * x2, w1 * z2 + x1 * y2 - y1 * x2 + z1 * w2])
+
+
+def _axis_quat(phi):
+    a = np.linalg.norm(phi)
+    if a == 0:
+        return np.array([1.0, 0, 0, 0])
+    return np.concatenate([[np.cos(a / 2)], np.sin(a / 2) * phi / a])
+
+
+def _far_box_with_ball(ball, params=None, mu=1.0):
+    """A resting box far from the ball (never touches it)."""
+    return W.single_box(half=(0.05, 0.05, 0.05), pos=(50.0, 0.0, 0.05), mu=mu, params=params, ball=ball)
+
+
+def test_free_flight_exact_discrete_solution():
+    p0 = np.array([0.1, -0.2, 3.0])
+    v0 = np.array([0.3, 0.2, 1.5])
+    w0 = np.array([0.7, -1.1, 2.3])
+    pop = _far_box_with_ball(dict(r=0.05, m=0.4, pos=p0, v=v0, w=w0))
+    o = O.Oracle(pop)
+    dt = pop.params["dt"]
+    k = 300
+    o.step(k)
+    q, v, _, st = o.variant_state(0)
+    assert st == 0
+    pb, Qb, wb, vb = q[7:10], q[10:14], v[6:9], v[9:12]
+    v0f, p0f, w0f = (np.float32(v0).astype(np.float64), np.float32(p0).astype(np.float64),
+                     np.float32(w0).astype(np.float64))
+    np.testing.assert_allclose(vb, v0f + k * dt * G, rtol=0, atol=1e-12)
+    np.testing.assert_allclose(pb, p0f + k * dt * v0f + dt * dt * G * k * (k + 1) / 2, rtol=0, atol=1e-11)
+    np.testing.assert_allclose(wb, w0f, rtol=0, atol=1e-13)
+    Qexp = _quat_mul(_axis_quat(k * dt * w0f), np.array([1.0, 0, 0, 0]))
+    if np.dot(Qexp, Qb) < 0:
+        Qexp = -Qexp
+    np.testing.assert_allclose(Qb, Qexp, rtol=0, atol=1e-10)
+
+
+def test_sphere_mass_matrix_block_and_bias():
+    r, m = 0.07, 0.9
+    pop = _far_box_with_ball(dict(r=r, m=m, pos=(0, 0, 1.0), w=(1.0, 2.0, -0.5), v=(0.3, 0, 0)))
+    o = O.Oracle(pop)
+    q, v, _, _ = o.variant_state(0)
+    M, c = o.dynamics(0, q, v)
+    r32, m32 = float(np.float32(r)), float(np.float32(m))
+    I = 0.4 * m32 * r32 ** 2
+    np.testing.assert_allclose(M[6:, 6:], np.diag([I, I, I, m32, m32, m32]), rtol=1e-14, atol=1e-15)
+    assert np.abs(M[:6, 6:]).max() == 0.0 and np.abs(M[6:, :6]).max() == 0.0
+    np.testing.assert_allclose(c[6:], np.concatenate([[0, 0, 0], -m32 * G]), rtol=1e-14, atol=1e-15)
+
+
+@pytest.mark.parametrize("r, m", [(0.05, 0.2), (0.12, 7.0)])
+def test_resting_ball_depth_is_g_over_k(r, m):
+    prm = _params()
+    pop = _far_box_with_ball(dict(r=r, m=m, pos=(0, 0, r + 0.002)), params=prm)
+    o = O.Oracle(pop)
+    o.step(3000)
+    q, v, _, st = o.variant_state(0)
+    assert st == 0
+    depth = float(np.float32(r)) - q[9]
+    assert abs(depth - 9.81 / prm["k_contact"]) < 1e-9
+    assert np.abs(v[6:]).max() < 1e-9
+
+
+def test_sliding_ball_rolls_at_five_sevenths():
+    r, m, v0 = 0.05, 0.5, 1.2
+    prm = _params()
+    depth = 9.81 / prm["k_contact"]
+    pop = _far_box_with_ball(dict(r=r, m=m, pos=(0, 0, r - depth), v=(v0, 0, 0)), params=prm, mu=0.3)
+    o = O.Oracle(pop)
+    r32, m32 = float(np.float32(r)), float(np.float32(m))
+    I = 0.4 * m32 * r32 ** 2
+    v0f = float(np.float32(v0))
+    L0 = m32 * v0f * r32
+    for _ in range(40):
+        o.step(10)
+        q, v, _, st = o.variant_state(0)
+        assert st == 0
+        # angular momentum about the contact point (lever arm exactly r below the centre)
+        assert abs(m32 * v[9] * r32 + I * v[7] - L0) < 1e-12 * max(1.0, L0)
+    # rolling: contact point at rest, speed 5/7 of the initial one
+    assert abs(v[9] - r32 * v[7]) < 1e-9
+    assert abs(v[9] - 5.0 / 7.0 * v0f) < 1e-9
+
+
+def _collide(ball, quat=(1.0, 0.0, 0.0, 0.0), duration=0.6, mu=0.8, dt=None):
+    prm = _params(gravity=(0.0, 0.0, 0.0))
+    if dt is not None:
+        prm["dt"] = dt
+    pop = W.single_box(half=(0.08, 0.08, 0.08), pos=(0.0, 0.0, 2.0), quat=quat, mu=mu, params=prm, ball=ball)
+    o = O.Oracle(pop)
+    inv0 = o.invariants(0)
+    touched, worst = 0, np.zeros(6)
+    for _ in range(int(round(duration / prm["dt"]))):
+        o.step(1)
+        q, v, _, st = o.variant_state(0)
+        assert st == 0
+        touched += int((o.contacts(0, q)["corner"] == -2).any())
+        worst = np.maximum(worst, np.abs(o.invariants(0)[1:] - inv0[1:]))
+    return o, inv0, touched, worst
+
+
+def test_head_on_ball_box_collision_conserves_momentum_exactly():
+    """Ball moving along -x onto the centre of the +x face of a resting cube,
+    no gravity: the contact normal passes through both centres, nothing
+    rotates, and the equal and opposite impulses conserve momentum exactly."""
+    o, inv0, touched, worst = _collide(dict(r=0.06, m=0.8, pos=(0.3, 0.0, 2.0), v=(-2.0, 0.0, 0.0)))
+    assert touched > 3
+    assert worst.max() < 1e-12, worst
+    q, v, _, _ = o.variant_state(0)
+    assert np.abs(v[0:3]).max() < 1e-14 and np.abs(v[6:9]).max() < 1e-14   # no spin
+    assert v[3] < 0 and v[9] > -2.0                                        # momentum handed over
+
+
+def test_glancing_ball_box_collision_momentum_converges_with_dt():
+    """Off-centre hit of a cube with friction: the box spins up.  Its body-frame
+    velocity coordinates turn with it during a step, so total momentum is
+    conserved only to first order in dt: the drift halves when dt halves.  A
+    sign or lever-arm mistake in the contact rows leaves an O(1) drift that
+    does not shrink with dt."""
+    ball = dict(r=0.06, m=0.8, pos=(0.3, 0.05, 2.03), v=(-2.0, 0.0, 0.0), w=(0.0, 0.0, 5.0))
+    drift = []
+    for dt in (0.002, 0.001):
+        o, inv0, touched, worst = _collide(ball, dt=dt)
+        assert touched > 3
+        q, v, _, _ = o.variant_state(0)
+        assert np.abs(v[0:3]).max() > 0.1                                   # the box was set spinning
+        drift.append(worst)
+    P0 = np.linalg.norm(inv0[1:4])
+    assert drift[0][:3].max() < 0.02 * P0
+    ratio = drift[1] / drift[0]
+    assert (ratio[[0, 1, 3, 4]] > 0.45).all() and (ratio[[0, 1, 3, 4]] < 0.55).all(), ratio
+
+
+def _nearest_face_brute(cl, h):
+    """Brute force in the box frame: distance from cl to the box surface and
+    the surface point, by projecting on each of the six face rectangles."""
+    best = (np.inf, None, None)
+    for k in range(3):
+        for s in (-1.0, 1.0):
+            pt = np.clip(cl, -h, h)
+            pt[k] = s * h[k]
+            d = np.linalg.norm(cl - pt)
+            nrm = np.zeros(3)
+            nrm[k] = s
+            if d < best[0]:
+                best = (d, pt, nrm)
+    return best
+
+
+def test_sphere_box_geometry_against_brute_force():
+    rng = np.random.default_rng(11)
+    half = np.array([0.1, 0.06, 0.04], np.float32)
+    qb = rng.normal(size=4)
+    qb /= np.linalg.norm(qb)
+    pop = W.single_box(half=tuple(half), pos=(0.3, -0.2, 1.0), quat=tuple(qb), params=_params(),
+                       ball=dict(r=0.05, m=1.0, pos=(0, 0, 1.0)))
+    o = O.Oracle(pop)
+    q = o.variant_state(0)[0].copy()
+    R, p, _, _ = o.fk(0, q)
+    R, p = R[0], p[0]
+    h = half.astype(np.float64)
+    r = float(np.float32(0.05))
+    seen = {"in": 0, "out": 0, "miss": 0}
+    for _ in range(400):
+        c = p + R @ (rng.uniform(-1.0, 1.0, 3) * (h + 0.07))
+        cl = R.T @ (c - p)     # box-frame centre (R is orthogonal only to float32 rounding of Q)
+        q[7:10] = c
+        con = o.contacts(0, q)
+        sel = con["corner"] == -2
+        inside = (np.abs(cl) <= h).all()
+        if inside:
+            # nearest face plane: distance h_k - |cl_k|
+            gaps = h - np.abs(cl)
+            k = int(np.argmin(gaps))
+            nl = np.zeros(3)
+            nl[k] = 1.0 if cl[k] >= 0 else -1.0
+            assert sel.sum() == 1
+            np.testing.assert_allclose(con["depth"][sel][0], r + gaps[k], atol=1e-12)
+            np.testing.assert_allclose(con["normal"][sel][0], R @ nl / np.linalg.norm(R @ nl), atol=1e-12)
+            seen["in"] += 1
+        else:
+            _, pt, _ = _nearest_face_brute(cl, h)
+            dw = c - (p + R @ pt)                 # world offset from the nearest surface point
+            d = np.linalg.norm(dw)
+            if d < r:
+                assert sel.sum() == 1
+                np.testing.assert_allclose(con["depth"][sel][0], r - d, atol=1e-12)
+                np.testing.assert_allclose(con["normal"][sel][0], dw / d, atol=1e-10)
+                np.testing.assert_allclose(con["x"][sel][0], c - r * dw / d, atol=1e-10)
+                seen["out"] += 1
+            else:
+                assert sel.sum() == 0
+                seen["miss"] += 1
+    assert min(seen.values()) > 10, seen
+
+
+def test_ball_box_rows_vanish_on_rigid_motion_and_are_orthonormal():
+    rng = np.random.default_rng(5)
+    half = (0.1, 0.06, 0.04)
+    qb = rng.normal(size=4)
+    qb /= np.linalg.norm(qb)
+    # ball touching the +x side of the box region (some pose of it)
+    pop = W.single_box(half=half, pos=(0.0, 0.0, 1.0), quat=tuple(qb), params=_params(),
+                       ball=dict(r=0.05, m=1.0, pos=(0, 0, 1.0)))
+    o = O.Oracle(pop)
+    q = o.variant_state(0)[0].copy()
+    R, p, _, _ = o.fk(0, q)
+    R, p = R[0], p[0]
+    found = 0
+    for _ in range(200):
+        cl = rng.uniform(-1.0, 1.0, 3) * (np.array(half) + 0.05)
+        c = p + R @ cl
+        q[7:10] = c
+        con = o.contacts(0, q)
+        sel = np.where(con["corner"] == -2)[0]
+        if len(sel) == 0:
+            continue
+        found += 1
+        J = con["J"][sel[0]]                      # rows (n, t1, t2) x 12 DoFs
+        # rigid motion of box and ball together: angular velocity w, velocity u at the box centre
+        w = rng.normal(size=3)
+        u = rng.normal(size=3)
+        v = np.zeros(12)
+        v[0:3] = np.linalg.solve(R, w)           # box: body-frame angular velocity
+        v[3:6] = np.linalg.solve(R, u)           # box: body-frame velocity of its centre
+        v[6:9] = w                               # ball: world angular velocity
+        v[9:12] = u + np.cross(w, c - p)         # ball: centre velocity of the same rigid motion
+        assert np.abs(J @ v).max() < 1e-12
+        # on the ball's translation the rows are the orthonormal frame (n, t1, t2)
+        F = J[:, 9:12]
+        np.testing.assert_allclose(F @ F.T, np.eye(3), atol=1e-12)
+        np.testing.assert_allclose(F[0], con["normal"][sel[0]], atol=1e-15)
+    assert found > 20

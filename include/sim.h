@@ -71,6 +71,18 @@ extern "C" {
  *                       FREE : q = (p0[3], Q0[4] wxyz, theta[nh]), v = (w_body[3], v_body[3], thetadot[nh])
  *                       FIXED: q = theta[nh], v = thetadot[nh]
  *  root_pose[n*7]       FIXED roots only: (p0, Q0); may be NULL for FREE
+ *  ball[n*2]            optional (NULL = none): every variant carries one free
+ *                       solid sphere of (radius, mass), inertia 2/5 m r^2 --
+ *                       the box-and-ball scene of Sec. 5.  Its state follows
+ *                       the robot's in q0/v0: q += (centre[3], Q[4] wxyz),
+ *                       v += (w_world[3], v_centre_world[3]).  Contacts after
+ *                       the box corners: ball-plane (the sphere's lowest
+ *                       point), then ball-box for every box in body order
+ *                       (closest box point; a centre inside a box leaves
+ *                       through the nearest face), normal from box to ball,
+ *                       Coulomb friction on the relative velocity.  The
+ *                       DoF total (ball included) must stay <= 28;
+ *                       single_launch does not cover ball populations.
  * Per-model constants: PD gains kp, kd (actuator torque limit tau_max), soft
  * contact stiffness and damping in acceleration units per contact row,
  * time step dt, gravity vector, and the solver sweep count pgs_iters (part
@@ -95,6 +107,7 @@ typedef struct {
   float kp, kd, tau_max, k_contact, b_contact, dt;
   float gravity[3];
   int32_t pgs_iters;
+  const float* ball;
 } sim_model_desc;
 
 /*
@@ -215,8 +228,8 @@ int sim_variant_bins(const sim_handle* h, int32_t* bin);
 int sim_launch_times(const sim_handle* h, int32_t* n_bins, float* ms, int32_t* launches, int32_t max_bins);
 
 /* The compiled kernel variants: per variant (nv capacity, body capacity,
- * contacts in registers).  info has 3*max_variants ints; *n receives the
- * total count.  Host only. */
+ * contacts in registers, 1 if its variants carry a ball).  info has
+ * 4*max_variants ints; *n receives the total count.  Host only. */
 int sim_kernel_variants(int32_t* n, int32_t* info, int32_t max_variants);
 
 /*

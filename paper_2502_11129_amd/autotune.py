@@ -34,9 +34,9 @@ def _time_rollout(pop, T, reps, **opts):
     return best, bins
 
 
-def candidates_ncr(nvc):
+def candidates_ncr(nvc, ball=False):
     """Compiled contact-register budgets for a DoF capacity (any body capacity)."""
-    return sorted({k[2] for k in S.kernel_variants() if k[0] == nvc})
+    return sorted({k[2] for k in S.kernel_variants(ball) if k[0] == nvc})
 
 
 def autotune(pop, T_pilot=1000, reps=2, log=None, cache=None):
@@ -65,7 +65,8 @@ def autotune(pop, T_pilot=1000, reps=2, log=None, cache=None):
     def descend(best, best_t):
         """Coordinate descent from a starting point: streams, launch length,
         then the contact budget of each DoF capacity present."""
-        for name, values in (("single_launch", [True]), ("streams", [4, 2, 1]), ("steps_per_launch", [250, 500])):
+        single = [] if getattr(pop, "ball", None) is not None else [True]   # no multi-bin ball kernel
+        for name, values in (("single_launch", single), ("streams", [4, 2, 1]), ("steps_per_launch", [250, 500])):
             for v in values:
                 cand = dict(best, **{name: v})
                 if cand.get("single_launch") and name == "streams":
@@ -80,7 +81,7 @@ def autotune(pop, T_pilot=1000, reps=2, log=None, cache=None):
         nvcs = sorted({b[0] for b in probe.bins()})
         probe.close()
         for nvc in nvcs:
-            for ncr in candidates_ncr(nvc):
+            for ncr in candidates_ncr(nvc, getattr(pop, "ball", None) is not None):
                 if ncr == best["ncr_by_nvc"].get(nvc):
                     continue
                 cand = dict(best, ncr_by_nvc={**best["ncr_by_nvc"], nvc: ncr})

@@ -3,6 +3,8 @@
 // diagonal, contact rows, fixed-iteration Gauss-Seidel, semi-implicit Euler).
 // The dense system is factorised by Cholesky here (a serial CPU has no reason
 // to form the inverse); clamp-row columns are solved only when a clamp engages.
+// A ball (when the variant has one) adds six DoFs after the robot's (world
+// spin, centre velocity), a ball-plane contact and ball-box contacts.
 #include "host_worker.hpp"
 
 #include <cmath>
@@ -86,8 +88,49 @@ void chol_solve(int n, const float* L, const float* b, float* x) {
   }
 }
 
+// Orthonormal tangents of a unit normal (Duff et al., JCGT 2017).
+void tangent_pair(V3 n, V3& t1, V3& t2) {
+  const float sign = std::copysign(1.f, n.z);
+  const float a = -1.f / (sign + n.z);
+  const float b = n.x * n.y * a;
+  t1 = v3(1.f + sign * n.x * n.x * a, sign * b, -sign * n.x);
+  t2 = v3(b, sign + n.y * n.y * a, -n.y);
+}
+
+// Sphere against box: closest box point (or the nearest face for a centre
+// inside), normal from the box to the ball, point c - r n.
+bool sphere_box(V3 c, float r, V3 p, const M3& R, V3 h, V3& x, V3& n, float& depth) {
+  const V3 l = mtv(R, c - p);
+  const bool inside = std::fabs(l.x) <= h.x && std::fabs(l.y) <= h.y && std::fabs(l.z) <= h.z;
+  if (!inside) {
+    const V3 q = v3(std::fmax(-h.x, std::fmin(h.x, l.x)), std::fmax(-h.y, std::fmin(h.y, l.y)),
+                    std::fmax(-h.z, std::fmin(h.z, l.z)));
+    const V3 d = c - (p + mv(R, q));
+    const float dist = std::sqrt(dotp(d, d));
+    if (!(dist < r)) return false;
+    n = d * (1.f / dist);
+    depth = r - dist;
+  } else {
+    const float g[3] = {h.x - std::fabs(l.x), h.y - std::fabs(l.y), h.z - std::fabs(l.z)};
+    const float lc[3] = {l.x, l.y, l.z};
+    int kb = 0;
+    for (int k = 1; k < 3; ++k)
+      if (g[k] < g[kb]) kb = k;
+    const float sgn = lc[kb] >= 0.f ? 1.f : -1.f;
+    const V3 nw = mv(R, v3(kb == 0 ? sgn : 0.f, kb == 1 ? sgn : 0.f, kb == 2 ? sgn : 0.f));
+    n = nw * (1.f / std::sqrt(dotp(nw, nw)));
+    depth = r + g[kb];
+  }
+  x = c - n * r;
+  return true;
+}
+
 bool step(const HostVariantView& m, const ModelParams& P, HostVariantState& st, Work& wk) {
   const int nb = m.hdr[HW_NB], nv = m.hdr[HW_NV], r0 = m.hdr[HW_R0], nh = nb - 1;
+  const int nvr = m.hdr[HW_NVR], nqr = m.hdr[HW_NQR];
+  const bool ball = nv > nvr;
+  const float rball = m.hdrf[HF_BALLR], mball = m.hdrf[HF_BALLM], iball = 0.4f * mball * rball * rball;
+  const V3 cb = ball ? v3(st.q[nqr], st.q[nqr + 1], st.q[nqr + 2]) : v3(0, 0, 0);
   const float dt = P.dt, kp = P.kp, kd = P.kd, tmax = P.tau_max, kc = P.k_contact, bcn = P.b_contact;
   const float ba = kd + dt * kp, kb = bcn + kc * dt, mu = m.hdrf[HF_MU];
   const float* rec = m.body;
@@ -197,6 +240,11 @@ bool step(const HostVariantView& m, const ModelParams& P, HostVariantState& st, 
       for (int i = 0; i < 6; ++i) { wk.M[d * NV + i] = rv[i]; wk.M[i * NV + d] = rv[i]; }
     }
   }
+  if (ball)  // constant block diag(I, I, I, m, m, m), bias -m g on the centre velocity
+    for (int k = 0; k < 6; ++k) {
+      wk.M[(nvr + k) * NV + nvr + k] = k < 3 ? iball : mball;
+      wk.c[nvr + k] = k < 3 ? 0.f : -mball * P.g[k - 3];
+    }
   // Cholesky of Mt
   for (int j = 0; j < nv; ++j) {
     float s = wk.M[j * NV + j];
@@ -223,10 +271,51 @@ bool step(const HostVariantView& m, const ModelParams& P, HostVariantState& st, 
   }
   chol_solve(nv, wk.L, rhs, wk.vf);
   for (int d = 0; d < nv; ++d) wk.vf[d] += v[d];
-  // contacts
+  // contacts: rows (n, t1, t2) of the relative velocity, robot part with sign
+  // `robot` (+1 box corner on the plane, -1 box under the ball, 0 none) on the
+  // contact body's path, ball part with sign `bsign`
   int nc = 0;
-  const unsigned char anyc = 0;
-  (void)anyc;
+  auto add_contact = [&](V3 x, V3 n, float depth, unsigned anc, float robot, float bsign) {
+    if (nc >= wk.ncap) {
+      wk.ncap = nc + 16;
+      wk.J.resize((size_t)wk.ncap * 3 * NV);
+      wk.W.resize((size_t)wk.ncap * 3 * NV);
+      wk.scal.resize((size_t)wk.ncap * 10);
+    }
+    float* J = &wk.J[(size_t)nc * 3 * NV];
+    float* W = &wk.W[(size_t)nc * 3 * NV];
+    float* sc = &wk.scal[(size_t)nc * 10];
+    V3 t1, t2;
+    tangent_pair(n, t1, t2);
+    for (int d = 0; d < nv; ++d) {
+      V3 col;
+      if (r0 && d < 3) col = crs(v3(R0.m[d], R0.m[3 + d], R0.m[6 + d]), x - P0) * robot;
+      else if (r0 && d < 6) col = v3(R0.m[d - 3], R0.m[3 + d - 3], R0.m[6 + d - 3]) * robot;
+      else if (d < nvr) {
+        const int hb = d - r0 + 1;
+        col = ((anc >> hb) & 1u) ? crs(wk.w[hb], x - wk.o[hb]) * robot : v3(0, 0, 0);
+      } else {
+        const int k = d - nvr;
+        const V3 e = v3(k % 3 == 0 ? 1.f : 0.f, k % 3 == 1 ? 1.f : 0.f, k % 3 == 2 ? 1.f : 0.f);
+        col = (k < 3 ? crs(e, x - cb) : e) * bsign;
+      }
+      J[d] = dotp(n, col); J[NV + d] = dotp(t1, col); J[2 * NV + d] = dotp(t2, col);
+    }
+    float D[3];
+    for (int r = 0; r < 3; ++r) {
+      chol_solve(nv, wk.L, J + r * NV, W + r * NV);
+      float s2 = 0.f;
+      for (int d = 0; d < nv; ++d) s2 += J[r * NV + d] * W[r * NV + d];
+      D[r] = s2;
+    }
+    sc[0] = kc * depth;
+    sc[1] = 1.f / (D[0] * (1.f + kb * dt));
+    sc[2] = dt * D[0];
+    sc[3] = 1.f / (dt * D[1]);
+    sc[4] = 1.f / (dt * D[2]);
+    sc[5] = sc[6] = sc[7] = 0.f;
+    ++nc;
+  };
   for (int b = (r0 ? 0 : 1); b < nb; ++b) {
     const V3 h = v3(B(b, BW_HALF), B(b, BW_HALF + 1), B(b, BW_HALF + 2));
     unsigned anc;
@@ -235,39 +324,22 @@ bool step(const HostVariantView& m, const ModelParams& P, HostVariantState& st, 
       const V3 s = v3((cn & 1) ? h.x : -h.x, (cn & 2) ? h.y : -h.y, (cn & 4) ? h.z : -h.z);
       const V3 x = wk.p[b] + mv(wk.R[b], s);
       if (!(x.z < 0.f)) continue;
-      if (nc >= wk.ncap) {
-        wk.ncap = nc + 16;
-        wk.J.resize((size_t)wk.ncap * 3 * NV);
-        wk.W.resize((size_t)wk.ncap * 3 * NV);
-        wk.scal.resize((size_t)wk.ncap * 10);
-      }
-      float* J = &wk.J[(size_t)nc * 3 * NV];
-      float* W = &wk.W[(size_t)nc * 3 * NV];
-      float* sc = &wk.scal[(size_t)nc * 10];
-      for (int d = 0; d < nv; ++d) {
-        V3 col;
-        if (r0 && d < 3) col = crs(v3(R0.m[d], R0.m[3 + d], R0.m[6 + d]), x - P0);
-        else if (r0 && d < 6) col = v3(R0.m[d - 3], R0.m[3 + d - 3], R0.m[6 + d - 3]);
-        else {
-          const int hb = d - r0 + 1;
-          col = ((anc >> hb) & 1u) ? crs(wk.w[hb], x - wk.o[hb]) : v3(0, 0, 0);
-        }
-        J[d] = col.z; J[NV + d] = col.x; J[2 * NV + d] = col.y;
-      }
-      float D[3];
-      for (int r = 0; r < 3; ++r) {
-        chol_solve(nv, wk.L, J + r * NV, W + r * NV);
-        float s2 = 0.f;
-        for (int d = 0; d < nv; ++d) s2 += J[r * NV + d] * W[r * NV + d];
-        D[r] = s2;
-      }
-      sc[0] = kc * (-x.z);
-      sc[1] = 1.f / (D[0] * (1.f + kb * dt));
-      sc[2] = dt * D[0];
-      sc[3] = 1.f / (dt * D[1]);
-      sc[4] = 1.f / (dt * D[2]);
-      sc[5] = sc[6] = sc[7] = 0.f;
-      ++nc;
+      add_contact(x, v3(0, 0, 1), -x.z, anc, 1.f, 0.f);
+    }
+  }
+  if (ball) {
+    if (cb.z - rball < 0.f) {
+      const V3 x = v3(cb.x, cb.y, cb.z - rball);
+      add_contact(x, v3(0, 0, 1), -x.z, 0u, 0.f, 1.f);
+    }
+    for (int b = 0; b < nb; ++b) {
+      V3 x, n;
+      float depth;
+      if (!sphere_box(cb, rball, wk.p[b], wk.R[b], v3(B(b, BW_HALF), B(b, BW_HALF + 1), B(b, BW_HALF + 2)), x, n, depth))
+        continue;
+      unsigned anc;
+      { int xi = Bi(b, BW_ANCESTORS); std::memcpy(&anc, &xi, 4); }
+      add_contact(x, n, depth, anc, -1.f, 1.f);
     }
   }
   // fixed-iteration Gauss-Seidel
@@ -342,7 +414,22 @@ bool step(const HostVariantView& m, const ModelParams& P, HostVariantState& st, 
     const float n = std::sqrt(Q[0] * Q[0] + Q[1] * Q[1] + Q[2] * Q[2] + Q[3] * Q[3]);
     for (int i = 0; i < 4; ++i) qn[3 + i] = Q[i] / n;
   }
-  for (int i = 0; i < qh + nh; ++i)
+  if (ball) {  // world velocities: p += dt v, Q <- exp(dt w) Q
+    qn[nqr] = q[nqr] + dt * wk.vp[nvr + 3];
+    qn[nqr + 1] = q[nqr + 1] + dt * wk.vp[nvr + 4];
+    qn[nqr + 2] = q[nqr + 2] + dt * wk.vp[nvr + 5];
+    const V3 phi = v3(wk.vp[nvr], wk.vp[nvr + 1], wk.vp[nvr + 2]) * dt;
+    const float an = std::sqrt(dotp(phi, phi));
+    float dq[4];
+    if (an < 1e-8f) { dq[0] = 1.f; dq[1] = 0.5f * phi.x; dq[2] = 0.5f * phi.y; dq[3] = 0.5f * phi.z; }
+    else { const float s = std::sin(0.5f * an) / an; dq[0] = std::cos(0.5f * an); dq[1] = phi.x * s; dq[2] = phi.y * s; dq[3] = phi.z * s; }
+    const float* b = q + nqr + 3;
+    float Q[4] = {dq[0] * b[0] - dq[1] * b[1] - dq[2] * b[2] - dq[3] * b[3], dq[0] * b[1] + dq[1] * b[0] + dq[2] * b[3] - dq[3] * b[2],
+                  dq[0] * b[2] - dq[1] * b[3] + dq[2] * b[0] + dq[3] * b[1], dq[0] * b[3] + dq[1] * b[2] - dq[2] * b[1] + dq[3] * b[0]};
+    const float n = std::sqrt(Q[0] * Q[0] + Q[1] * Q[1] + Q[2] * Q[2] + Q[3] * Q[3]);
+    for (int i = 0; i < 4; ++i) qn[nqr + 3 + i] = Q[i] / n;
+  }
+  for (int i = 0; i < nqr + (ball ? 7 : 0); ++i)
     if (!std::isfinite(qn[i])) return false;
   for (int d = 0; d < nv; ++d)
     if (!std::isfinite(wk.vp[d])) return false;

@@ -3,45 +3,24 @@
 
 namespace simk {
 
-hipError_t launch_rollout_8_1_16(const BinArgs&, const ModelParams&, hipStream_t);
-hipError_t launch_rollout_8_1_2(const BinArgs&, const ModelParams&, hipStream_t);
-hipError_t launch_rollout_12_1_16(const BinArgs&, const ModelParams&, hipStream_t);
-hipError_t launch_rollout_12_1_2(const BinArgs&, const ModelParams&, hipStream_t);
-hipError_t launch_rollout_16_1_16(const BinArgs&, const ModelParams&, hipStream_t);
-hipError_t launch_rollout_16_2_16(const BinArgs&, const ModelParams&, hipStream_t);
-hipError_t launch_rollout_16_1_2(const BinArgs&, const ModelParams&, hipStream_t);
-hipError_t launch_rollout_20_1_8(const BinArgs&, const ModelParams&, hipStream_t);
-hipError_t launch_rollout_20_2_8(const BinArgs&, const ModelParams&, hipStream_t);
-hipError_t launch_rollout_20_1_2(const BinArgs&, const ModelParams&, hipStream_t);
-hipError_t launch_rollout_24_1_8(const BinArgs&, const ModelParams&, hipStream_t);
-hipError_t launch_rollout_24_2_8(const BinArgs&, const ModelParams&, hipStream_t);
-hipError_t launch_rollout_24_2_2(const BinArgs&, const ModelParams&, hipStream_t);
-hipError_t launch_rollout_24_1_2(const BinArgs&, const ModelParams&, hipStream_t);
-hipError_t launch_rollout_28_2_8(const BinArgs&, const ModelParams&, hipStream_t);
-hipError_t launch_rollout_28_2_2(const BinArgs&, const ModelParams&, hipStream_t);
-hipError_t launch_rollout_28_2_4(const BinArgs&, const ModelParams&, hipStream_t);
-hipError_t launch_rollout_28_2_12(const BinArgs&, const ModelParams&, hipStream_t);
+#define SIMK_DECLARE(NVC, SB, NCR) \
+  hipError_t launch_rollout_##NVC##_##SB##_##NCR(const BinArgs&, const ModelParams&, hipStream_t);
+#define SIMK_DECLARE_BALL(NVC, SB, NCR) \
+  hipError_t launch_rollout_ball_##NVC##_##SB##_##NCR(const BinArgs&, const ModelParams&, hipStream_t);
+#define SIMK_ENTRY(NVC, SB, NCR) {NVC, SB, NCR, 0, launch_rollout_##NVC##_##SB##_##NCR},
+#define SIMK_ENTRY_BALL(NVC, SB, NCR) {NVC, SB, NCR, 1, launch_rollout_ball_##NVC##_##SB##_##NCR},
 
-const KernelVariant kKernelVariants[] = {
-    {8, 1, 16, launch_rollout_8_1_16},
-    {8, 1, 2, launch_rollout_8_1_2},
-    {12, 1, 16, launch_rollout_12_1_16},
-    {12, 1, 2, launch_rollout_12_1_2},
-    {16, 1, 16, launch_rollout_16_1_16},
-    {16, 2, 16, launch_rollout_16_2_16},
-    {16, 1, 2, launch_rollout_16_1_2},
-    {20, 1, 8, launch_rollout_20_1_8},
-    {20, 2, 8, launch_rollout_20_2_8},
-    {20, 1, 2, launch_rollout_20_1_2},
-    {24, 1, 8, launch_rollout_24_1_8},
-    {24, 2, 8, launch_rollout_24_2_8},
-    {24, 2, 2, launch_rollout_24_2_2},
-    {24, 1, 2, launch_rollout_24_1_2},
-    {28, 2, 8, launch_rollout_28_2_8},
-    {28, 2, 2, launch_rollout_28_2_2},
-    {28, 2, 4, launch_rollout_28_2_4},
-    {28, 2, 12, launch_rollout_28_2_12},
-};
+// Plane-only kernels, and kernels whose variants carry a ball.
+#define SIMK_PLANE(X)                                                                        \
+  X(8, 1, 16) X(8, 1, 2) X(12, 1, 16) X(12, 1, 2) X(16, 1, 16) X(16, 2, 16) X(16, 1, 2)      \
+  X(20, 1, 8) X(20, 2, 8) X(20, 1, 2) X(24, 1, 8) X(24, 2, 8) X(24, 2, 2) X(24, 1, 2)        \
+  X(28, 2, 8) X(28, 2, 2) X(28, 2, 4) X(28, 2, 12)
+#define SIMK_BALL(X) X(12, 1, 8) X(12, 1, 2) X(16, 1, 8) X(20, 1, 8) X(24, 1, 8) X(28, 1, 8) X(28, 2, 8)
+
+SIMK_PLANE(SIMK_DECLARE)
+SIMK_BALL(SIMK_DECLARE_BALL)
+
+const KernelVariant kKernelVariants[] = {SIMK_PLANE(SIMK_ENTRY) SIMK_BALL(SIMK_ENTRY_BALL)};
 const int kNumKernelVariants = sizeof(kKernelVariants) / sizeof(kKernelVariants[0]);
 
 }  // namespace simk

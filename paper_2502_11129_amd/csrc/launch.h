@@ -12,6 +12,7 @@ struct KernelVariant {
   int nvc;   // DoF capacity (rows of the inverse held per variant)
   int sb;    // body slots per lane (body capacity 16 * sb)
   int ncr;   // contacts whose solver rows stay in registers
+  int ball;  // 1: variants carry a ball (box-and-ball scene)
   launch_fn fn;
 };
 

@@ -22,6 +22,13 @@
 //   6. K sweeps of projected Gauss-Seidel: actuator-clamp rows then contact
 //      rows (soft normal in acceleration units, Coulomb disk friction);
 //   7. semi-implicit Euler; non-finite check freezes the variant.
+// Ball kernels (BALL = true; the box-and-ball scene of Sec. 5) add one free
+// sphere per variant: its six DoFs (world angular velocity, centre velocity)
+// follow the robot's, its mass-matrix block is the constant diag(I, I, I, m,
+// m, m) and its bias is gravity; after the box corners come a ball-plane
+// contact and ball-box contacts (closest box point, or the nearest face when
+// the centre is inside a box), whose rows project the relative velocity ball
+// minus box on the normal and two tangents.
 #pragma once
 #include <hip/hip_runtime.h>
 #include <stdint.h>
@@ -158,7 +165,7 @@ __device__ __forceinline__ sv imul(const sinertia& J, const sv& V) {
 // ----------------------------------------------------------------------------
 // Per-variant LDS area.
 // ----------------------------------------------------------------------------
-template <int NVC, int SB, int NCR>
+template <int NVC, int SB, int NCR, bool BALL = false>
 struct alignas(16) GroupLds {
   static constexpr int NBC = 16 * SB;
   static constexpr int MST = NVC + 1;                 // padded row stride of the matrices
@@ -170,7 +177,7 @@ struct alignas(16) GroupLds {
   float WO[NBC][12];        // hinge axis w, anchor o (world), composite force C S of the hinge
   int par[NBC];
   int ccount[NBC];          // active-corner mask per body
-  float cl[NCR][4];         // contact list: x, y, z, ancestor mask of the body
+  float cl[NCR][BALL ? kListWordsBall : kListWords];  // contact list entries (ListWord)
   float cs[NCR][12];        // per-contact solver scalars
   float th[NVC], thd[NVC];  // theta / thetadot by DoF
   float cvec[NVC];          // bias c by DoF
@@ -252,6 +259,112 @@ __device__ __forceinline__ void build_rows(const float (&Mi)[S][NVC], const f3 (
   scal[9] = 0.f;
 }
 
+// Orthonormal tangents of a unit normal n (Duff et al., "Building an
+// Orthonormal Basis, Revisited", JCGT 2017); n = +z gives +x and +y exactly.
+__device__ __forceinline__ void tangents(f3 n, f3& t1, f3& t2) {
+  const float sign = copysignf(1.f, n.z);
+  const float a = -1.f / (sign + n.z);
+  const float b = n.x * n.y * a;
+  t1 = mk(1.f + sign * n.x * n.x * a, sign * b, -sign * n.x);
+  t2 = mk(b, sign + n.y * n.y * a, -n.y);
+}
+
+// Rows of one contact of a ball kernel: kind 0 box corner on the plane (the
+// box's path, +1), 1 ball on the plane (the ball's DoFs, +1), 2 ball on a box
+// (ball +1, the box's path -1); normal n and tangents t1, t2; depth d.
+// bodyOfDof: -1 root DoF, -2 ball DoF, else the hinge's body.
+template <int S, int NVC>
+__device__ __forceinline__ void build_rows_ball(const float (&Mi)[S][NVC], const f3 (&ang)[S], const f3 (&cst)[S],
+                                                const int (&bodyOfDof)[S], f3 x, f3 n, float depth, unsigned anc,
+                                                int kind, float kc, float kb, float dt, float (&Jn)[S],
+                                                float (&Jx)[S], float (&Jy)[S], float (&Wn)[S], float (&Wx)[S],
+                                                float (&Wy)[S], float (&scal)[10]) {
+  f3 t1, t2;
+  tangents(n, t1, t2);
+  const float robot = kind == 0 ? 1.f : (kind == 2 ? -1.f : 0.f);
+  const float ballc = kind >= 1 ? 1.f : 0.f;
+  float nJn[S], nJx[S], nJy[S];
+#pragma unroll
+  for (int s = 0; s < S; ++s) {
+    const int bd = bodyOfDof[s];
+    float coef;
+    if (bd == -2) coef = ballc;
+    else coef = (bd < 0 || ((anc >> bd) & 1u)) ? robot : 0.f;
+    const f3 J = (cross3(ang[s], x) + cst[s]) * coef;
+    Jn[s] = dot3(n, J);
+    Jx[s] = dot3(t1, J);
+    Jy[s] = dot3(t2, J);
+    nJn[s] = -Jn[s]; nJx[s] = -Jx[s]; nJy[s] = -Jy[s];
+    Wn[s] = 0.f; Wx[s] = 0.f; Wy[s] = 0.f;
+  }
+  matvec_bcast3<S, NVC>(Mi, nJn, nJx, nJy, Wn, Wx, Wy);
+  float pn = 0.f, px = 0.f, py = 0.f, pxn = 0.f, pyn = 0.f;
+#pragma unroll
+  for (int s = 0; s < S; ++s) {
+    pn = fmaf(Jn[s], Wn[s], pn);
+    px = fmaf(Jx[s], Wx[s], px);
+    py = fmaf(Jy[s], Wy[s], py);
+    pxn = fmaf(Jx[s], Wn[s], pxn);
+    pyn = fmaf(Jy[s], Wn[s], pyn);
+  }
+  const float Dn = row_sum(pn), Dx = row_sum(px), Dy = row_sum(py);
+  const float Dxn = row_sum(pxn), Dyn = row_sum(pyn);
+  scal[0] = kc * depth;
+  scal[1] = recip(Dn * (1.f + kb * dt));
+  scal[2] = dt * Dn;
+  scal[3] = dt * Dxn;
+  scal[4] = dt * Dyn;
+  scal[5] = recip(dt * Dx);
+  scal[6] = recip(dt * Dy);
+  scal[7] = 0.f;
+  scal[8] = 0.f;
+  scal[9] = 0.f;
+}
+
+// One contact list entry (ListWord layout); plane-only kernels store the
+// first four words.
+template <bool BALL>
+__device__ __forceinline__ void put_contact(float* e, f3 x, unsigned anc, f3 n, float depth, int kind) {
+  e[CL_X] = x.x; e[CL_X + 1] = x.y; e[CL_X + 2] = x.z;
+  e[CL_ANC] = __uint_as_float(anc);
+  if (BALL) {
+    e[CL_N] = n.x; e[CL_N + 1] = n.y; e[CL_N + 2] = n.z;
+    e[CL_DEPTH] = depth;
+    e[CL_KIND] = (float)kind;
+  }
+}
+
+// Sphere (centre c, radius r) against a box (centre p, rotation R, half
+// extents h): with l = R^T (c - p), outside the box the closest box point q,
+// contact iff |c - q| < r, normal (c - q) / |c - q|, depth r - |c - q|; a
+// centre inside or on the box leaves through the nearest face (first of
+// equals in x, y, z order), depth r + its distance.  Point: c - r n.
+__device__ __forceinline__ bool sphere_box(f3 c, float r, f3 p, const m33& R, f3 h, f3& x, f3& n, float& depth) {
+  const f3 l = mulT(R, c - p);
+  const bool inside = fabsf(l.x) <= h.x && fabsf(l.y) <= h.y && fabsf(l.z) <= h.z;
+  if (!inside) {
+    const f3 q = mk(fmaxf(-h.x, fminf(h.x, l.x)), fmaxf(-h.y, fminf(h.y, l.y)), fmaxf(-h.z, fminf(h.z, l.z)));
+    const f3 d = c - (p + mul(R, q));
+    const float dist = sqrtf(dot3(d, d));
+    if (!(dist < r)) return false;
+    n = d * (1.f / dist);
+    depth = r - dist;
+  } else {
+    const float gx = h.x - fabsf(l.x), gy = h.y - fabsf(l.y), gz = h.z - fabsf(l.z);
+    int kb = 0;
+    float gap = gx;
+    if (gy < gap) { gap = gy; kb = 1; }
+    if (gz < gap) { gap = gz; kb = 2; }
+    const float sgn = (kb == 0 ? l.x : kb == 1 ? l.y : l.z) >= 0.f ? 1.f : -1.f;
+    const f3 nl = mk(kb == 0 ? sgn : 0.f, kb == 1 ? sgn : 0.f, kb == 2 ? sgn : 0.f);
+    const f3 nw = mul(R, nl);
+    n = nw * (1.f / sqrtf(dot3(nw, nw)));
+    depth = r + gap;
+  }
+  x = c - n * r;
+  return true;
+}
+
 // One contact of one Gauss-Seidel sweep: soft normal row, then the two
 // friction rows together (Jacobi within the pair), projected on the disk
 // |lambda_t| <= mu lambda_n.  lam[0..2] are read and updated.
@@ -309,13 +422,14 @@ struct WavesPerSimd {
 
 // One workgroup (one wave, four variants) of a bin: `block` is the
 // workgroup's index within the bin, lds_all the four variants' LDS areas.
-template <int NVC, int SB, int NCR>
+template <int NVC, int SB, int NCR, bool BALL = false>
 __device__ __forceinline__ void rollout_body(const BinArgs& a, const ModelParams& P, int block,
-                                             GroupLds<NVC, SB, NCR>* lds_all) {
+                                             GroupLds<NVC, SB, NCR, BALL>* lds_all) {
   constexpr int S = (NVC + 15) / 16;
   constexpr int NBC = 16 * SB;
-  constexpr int MAXC = 8 * NBC;
-  using L = GroupLds<NVC, SB, NCR>;
+  constexpr int MAXC = max_contacts(NBC, BALL);
+  constexpr int CLW = BALL ? kListWordsBall : kListWords;
+  using L = GroupLds<NVC, SB, NCR, BALL>;
   constexpr int MST = L::MST;
 
   const int lane = threadIdx.x & 15;
@@ -327,13 +441,16 @@ __device__ __forceinline__ void rollout_body(const BinArgs& a, const ModelParams
   // ---- per-variant header (uniform within the row) ----
   const int* hdr = a.hdr + (size_t)vid * HW_WORDS;
   const int nb = hdr[HW_NB], nv = hdr[HW_NV], r0 = hdr[HW_R0], maxdepth = hdr[HW_MAXDEPTH];
+  const int nvr = BALL ? hdr[HW_NVR] : nv;  // robot DoFs (the ball's follow)
   const float* hf = a.hdrf + (size_t)vid * HF_WORDS;
   const float mu = hf[HF_MU];
+  const float rball = BALL ? hf[HF_BALLR] : 0.f, mball = BALL ? hf[HF_BALLM] : 0.f;
+  const float iball = 0.4f * mball * rball * rball;  // solid sphere
   const float* bodyv = a.body + (size_t)vid * NBC * BW_WORDS;
   const int* lvl = a.lvl + (size_t)vid * a.lvl_stride;  // bodies in level order, then level offsets
   float* ovf = a.ovf + (size_t)vid * a.ovf_stride;
   float* ovf_list = ovf;
-  float* ovf_scal = ovf + MAXC * 4;
+  float* ovf_scal = ovf + MAXC * CLW;
   float* ovf_rows = ovf_scal + MAXC * kOvfScal;
 
   const float dt = P.dt, kp = P.kp, kd = P.kd, tmax = P.tau_max, kc = P.k_contact, bc = P.b_contact;
@@ -344,6 +461,7 @@ __device__ __forceinline__ void rollout_body(const BinArgs& a, const ModelParams
   // ---- state ----
   float vS[S], thS[S];
   float p0[3], Q0[4];
+  float pb[3] = {0.f, 0.f, 0.f}, Qb[4] = {1.f, 0.f, 0.f, 0.f};  // ball centre and orientation
   long long kstep;
   unsigned status;
   unsigned long long cnt_contact, cnt_clamp;
@@ -355,7 +473,12 @@ __device__ __forceinline__ void rollout_body(const BinArgs& a, const ModelParams
     for (int s = 0; s < S; ++s) {
       const int d = lane + 16 * s;
       vS[s] = (d < nv) ? vsrc[d] : 0.f;
-      thS[s] = (d >= r0 && d < nv) ? qsrc[qh + d - r0] : 0.f;
+      thS[s] = (d >= r0 && d < nvr) ? qsrc[qh + d - r0] : 0.f;
+    }
+    if (BALL) {
+      const int qb = hdr[HW_NQR];
+      pb[0] = qsrc[qb]; pb[1] = qsrc[qb + 1]; pb[2] = qsrc[qb + 2];
+      Qb[0] = qsrc[qb + 3]; Qb[1] = qsrc[qb + 4]; Qb[2] = qsrc[qb + 5]; Qb[3] = qsrc[qb + 6];
     }
     if (r0 == 6) {
       p0[0] = qsrc[0]; p0[1] = qsrc[1]; p0[2] = qsrc[2];
@@ -502,18 +625,52 @@ __device__ __forceinline__ void rollout_body(const BinArgs& a, const ModelParams
                 const f3 x = mk(pr[9] + pr[0] * sv3.x + pr[1] * sv3.y + pr[2] * sv3.z,
                                 pr[10] + pr[3] * sv3.x + pr[4] * sv3.y + pr[5] * sv3.z,
                                 pr[11] + pr[6] * sv3.x + pr[7] * sv3.y + pr[8] * sv3.z);
-                if (idx < NCR) {
-                  sh.cl[idx][0] = x.x; sh.cl[idx][1] = x.y; sh.cl[idx][2] = x.z;
-                  sh.cl[idx][3] = __uint_as_float(anc);
-                } else {
-                  ovf_list[idx * 4 + 0] = x.x; ovf_list[idx * 4 + 1] = x.y; ovf_list[idx * 4 + 2] = x.z;
-                  ovf_list[idx * 4 + 3] = __uint_as_float(anc);
-                }
+                const f3 up = mk(0.f, 0.f, 1.f);
+                if (idx < NCR) put_contact<BALL>(&sh.cl[idx][0], x, anc, up, -x.z, 0);
+                else put_contact<BALL>(&ovf_list[idx * CLW], x, anc, up, -x.z, 0);
                 ++idx;
               }
             }
           }
         }
+      }
+    }
+    if (BALL) {
+      // the ball after the boxes: plane first (row-uniform), then every box
+      // in body order (a scan over the body lanes); the box poses are in sh.A
+      const f3 cb = mk(pb[0], pb[1], pb[2]);
+      if (cb.z - rball < 0.f) {
+        if (lane == 0) {
+          const f3 x = mk(cb.x, cb.y, cb.z - rball);
+          if (nc < NCR) put_contact<BALL>(&sh.cl[nc][0], x, 0u, mk(0.f, 0.f, 1.f), -x.z, 1);
+          else put_contact<BALL>(&ovf_list[nc * CLW], x, 0u, mk(0.f, 0.f, 1.f), -x.z, 1);
+        }
+        ++nc;
+      }
+#pragma unroll
+      for (int t = 0; t < SB; ++t) {
+        const int b = lane + 16 * t;
+        f3 x = mk(0.f, 0.f, 0.f), n = x;
+        float depth = 0.f;
+        bool hit = false;
+        if (b < nb) {
+          const float* pr = &sh.A[b * 24];
+          m33 R;
+#pragma unroll
+          for (int k2 = 0; k2 < 9; ++k2) R.m[k2] = pr[k2];
+          const float* rec = bodyv + (size_t)b * BW_WORDS;
+          hit = sphere_box(cb, rball, mk(pr[9], pr[10], pr[11]), R,
+                           mk(rec[BW_HALF], rec[BW_HALF + 1], rec[BW_HALF + 2]), x, n, depth);
+        }
+        const int cnt = hit ? 1 : 0;
+        const int incl = row_scan_incl(cnt);
+        if (hit) {
+          const int idx = nc + incl - cnt;
+          const unsigned anc = __float_as_uint(bodyv[(size_t)b * BW_WORDS + BW_ANCESTORS]);
+          if (idx < NCR) put_contact<BALL>(&sh.cl[idx][0], x, anc, n, depth, 2);
+          else put_contact<BALL>(&ovf_list[idx * CLW], x, anc, n, depth, 2);
+        }
+        nc += row_bcast_i<15>(incl);
       }
     }
     __threadfence_block();  // overflow list entries are read by other lanes of the row
@@ -618,6 +775,8 @@ __device__ __forceinline__ void rollout_body(const BinArgs& a, const ModelParams
         mroot[3] = (r == 0) ? m : 0.f; mroot[4] = (r == 1) ? m : 0.f; mroot[5] = (r == 2) ? m : 0.f;
       }
     }
+    if (BALL && lane < 6)  // ball: bias -m g on the centre velocity, none on the spin
+      sh.cvec[nvr + lane] = lane < 3 ? 0.f : -mball * (lane == 3 ? P.g[0] : lane == 4 ? P.g[1] : P.g[2]);
     wave_sync();  // composite reads done; the area becomes the assembled matrix
     {
       float4* a4 = reinterpret_cast<float4*>(sh.A);  // A is 16-byte aligned (first member)
@@ -630,6 +789,7 @@ __device__ __forceinline__ void rollout_body(const BinArgs& a, const ModelParams
       for (int s = 0; s < S; ++s) {
         const int d = lane + 16 * s;
         if (d >= nv && d < NVC) Ml[d * MST + d] = 1.f;  // identity padding
+        if (BALL && d >= nvr && d < nv) Ml[d * MST + d] = (d - nvr < 3) ? iball : mball;
       }
       if (r0 == 6 && lane < 6) {
 #pragma unroll
@@ -750,7 +910,7 @@ __device__ __forceinline__ void rollout_body(const BinArgs& a, const ModelParams
 #pragma unroll
     for (int s = 0; s < S; ++s) {
       const int d = lane + 16 * s;
-      const bool hinge = d >= r0 && d < nv;
+      const bool hinge = d >= r0 && d < nvr;
       const int b = hinge ? d - r0 + 1 : 0;
       const float* rec = bodyv + (size_t)b * BW_WORDS;
       double ph = (double)rec[BW_CPG + 1] * tk + (double)rec[BW_CPG + 2];
@@ -783,11 +943,18 @@ __device__ __forceinline__ void rollout_body(const BinArgs& a, const ModelParams
       } else if (r0 == 6 && d < 6) {
         ang[s] = mk(0.f, 0.f, 0.f);
         cst[s] = mcol(R0, d - 3);
-      } else if (d < nv) {
+      } else if (d < nvr) {
         const int b = d - r0 + 1;
         bodyOfDof[s] = b;
         ang[s] = mk(sh.WO[b][0], sh.WO[b][1], sh.WO[b][2]);
         cst[s] = mk(0.f, 0.f, 0.f) - cross3(ang[s], mk(sh.WO[b][3], sh.WO[b][4], sh.WO[b][5]));
+      } else if (BALL && d < nv) {
+        // ball: spin e_k gives e_k x (x - cb), centre velocity e_k gives e_k
+        const int k = d - nvr;
+        const f3 e = mk((k % 3) == 0 ? 1.f : 0.f, (k % 3) == 1 ? 1.f : 0.f, (k % 3) == 2 ? 1.f : 0.f);
+        bodyOfDof[s] = -2;
+        ang[s] = k < 3 ? e : mk(0.f, 0.f, 0.f);
+        cst[s] = k < 3 ? mk(0.f, 0.f, 0.f) - cross3(e, mk(pb[0], pb[1], pb[2])) : e;
       } else {
         ang[s] = mk(0.f, 0.f, 0.f);
         cst[s] = mk(0.f, 0.f, 0.f);
@@ -797,11 +964,16 @@ __device__ __forceinline__ void rollout_body(const BinArgs& a, const ModelParams
 #pragma unroll
     for (int c = 0; c < NCR; ++c) {
       if (c < nc) {
-        const f3 x = mk(sh.cl[c][0], sh.cl[c][1], sh.cl[c][2]);
-        const unsigned anc = __float_as_uint(sh.cl[c][3]);
+        const f3 x = mk(sh.cl[c][CL_X], sh.cl[c][CL_X + 1], sh.cl[c][CL_X + 2]);
+        const unsigned anc = __float_as_uint(sh.cl[c][CL_ANC]);
         float scal[10];
-        build_rows<S, NVC>(Mi, ang, cst, bodyOfDof, lane, x, anc, kc, kb, dt, JnR[c], JxR[c], JyR[c], WnR[c],
-                           WxR[c], WyR[c], scal);
+        if constexpr (BALL)
+          build_rows_ball<S, NVC>(Mi, ang, cst, bodyOfDof, x, mk(sh.cl[c][CL_N], sh.cl[c][CL_N + 1], sh.cl[c][CL_N + 2]),
+                                  sh.cl[c][CL_DEPTH], anc, (int)sh.cl[c][CL_KIND], kc, kb, dt, JnR[c], JxR[c], JyR[c],
+                                  WnR[c], WxR[c], WyR[c], scal);
+        else
+          build_rows<S, NVC>(Mi, ang, cst, bodyOfDof, lane, x, anc, kc, kb, dt, JnR[c], JxR[c], JyR[c], WnR[c],
+                             WxR[c], WyR[c], scal);
 #pragma unroll
         for (int i = 0; i < 10; ++i) sh.cs[c][i] = scal[i];  // identical in every lane
       } else {
@@ -816,10 +988,15 @@ __device__ __forceinline__ void rollout_body(const BinArgs& a, const ModelParams
     // Each lane stores and later reloads only values it computed itself (the
     // scalars are identical in all lanes), so no cross-lane visibility is needed.
     for (int c = NCR; c < nc; ++c) {
-      const f3 x = mk(ovf_list[c * 4], ovf_list[c * 4 + 1], ovf_list[c * 4 + 2]);
-      const unsigned anc = __float_as_uint(ovf_list[c * 4 + 3]);
+      const float* e = &ovf_list[c * CLW];
+      const f3 x = mk(e[CL_X], e[CL_X + 1], e[CL_X + 2]);
+      const unsigned anc = __float_as_uint(e[CL_ANC]);
       float Jn[S], Jx[S], Jy[S], Wn[S], Wx[S], Wy[S], scal[10];
-      build_rows<S, NVC>(Mi, ang, cst, bodyOfDof, lane, x, anc, kc, kb, dt, Jn, Jx, Jy, Wn, Wx, Wy, scal);
+      if constexpr (BALL)
+        build_rows_ball<S, NVC>(Mi, ang, cst, bodyOfDof, x, mk(e[CL_N], e[CL_N + 1], e[CL_N + 2]), e[CL_DEPTH], anc,
+                                (int)e[CL_KIND], kc, kb, dt, Jn, Jx, Jy, Wn, Wx, Wy, scal);
+      else
+        build_rows<S, NVC>(Mi, ang, cst, bodyOfDof, lane, x, anc, kc, kb, dt, Jn, Jx, Jy, Wn, Wx, Wy, scal);
       float* rows = ovf_rows + (size_t)c * 6 * NVC;
 #pragma unroll
       for (int s = 0; s < S; ++s) {
@@ -860,7 +1037,7 @@ __device__ __forceinline__ void rollout_body(const BinArgs& a, const ModelParams
           if (sv_ > tmax) nd = (sv_ - tmax) / den;
           else if (sv_ < -tmax) nd = (sv_ + tmax) / den;
           ndv[s] = nd;
-          if (d >= r0 && d < nv && d > last && nd != Dl[s]) first = fminf(first, (float)d);
+          if (d >= r0 && d < nvr && d > last && nd != Dl[s]) first = fminf(first, (float)d);
         }
         first = row_min(first);
         if (__builtin_amdgcn_ballot_w64(first < 1e8f) == 0) break;  // no row of any variant changes
@@ -929,7 +1106,7 @@ __device__ __forceinline__ void rollout_body(const BinArgs& a, const ModelParams
 #pragma unroll
     for (int s = 0; s < S; ++s) {
       const int d = lane + 16 * s;
-      const bool hinge = d >= r0 && d < nv;
+      const bool hinge = d >= r0 && d < nvr;
       thN[s] = hinge ? fmaf(dt, vp[s], thS[s]) : 0.f;
       if (d < nv && !(isfinite(vp[s]) && isfinite(thN[s]))) bad = 1.f;
       if (hinge && Dl[s] != 0.f) nclamp += 1.f;
@@ -964,6 +1141,46 @@ __device__ __forceinline__ void rollout_body(const BinArgs& a, const ModelParams
       for (int i = 0; i < 4; ++i) ok = ok && isfinite(Q0n[i]);
       if (!ok) bad = 1.f;
     }
+    float pbn[3] = {pb[0], pb[1], pb[2]}, Qbn[4] = {Qb[0], Qb[1], Qb[2], Qb[3]};
+    if (BALL) {
+      // ball velocities from their owner lanes (the bias vector is dead by now)
+#pragma unroll
+      for (int s = 0; s < S; ++s) {
+        const int d = lane + 16 * s;
+        if (d >= nvr && d < nv) sh.cvec[d] = vp[s];
+      }
+      wave_sync();
+      const f3 wbn = mk(sh.cvec[nvr], sh.cvec[nvr + 1], sh.cvec[nvr + 2]);
+      const f3 vbn = mk(sh.cvec[nvr + 3], sh.cvec[nvr + 4], sh.cvec[nvr + 5]);
+      wave_sync();  // read before the next step's writes
+      pbn[0] = fmaf(dt, vbn.x, pb[0]); pbn[1] = fmaf(dt, vbn.y, pb[1]); pbn[2] = fmaf(dt, vbn.z, pb[2]);
+      // world angular velocity: Q <- exp(dt w) Q
+      const f3 phi = wbn * dt;
+      const float an = sqrtf(dot3(phi, phi));
+      float dq[4];
+      if (an < 1e-8f) {
+        dq[0] = 1.f; dq[1] = 0.5f * phi.x; dq[2] = 0.5f * phi.y; dq[3] = 0.5f * phi.z;
+      } else {
+        float sh2, ch2;
+        sincosf(0.5f * an, &sh2, &ch2);
+        const float sc = sh2 / an;
+        dq[0] = ch2; dq[1] = phi.x * sc; dq[2] = phi.y * sc; dq[3] = phi.z * sc;
+      }
+      const float bw = Qb[0], bx = Qb[1], by = Qb[2], bz = Qb[3];
+      float qn[4] = {dq[0] * bw - dq[1] * bx - dq[2] * by - dq[3] * bz,
+                     dq[0] * bx + dq[1] * bw + dq[2] * bz - dq[3] * by,
+                     dq[0] * by - dq[1] * bz + dq[2] * bw + dq[3] * bx,
+                     dq[0] * bz + dq[1] * by - dq[2] * bx + dq[3] * bw};
+      const float inrm = 1.f / sqrtf(qn[0] * qn[0] + qn[1] * qn[1] + qn[2] * qn[2] + qn[3] * qn[3]);
+#pragma unroll
+      for (int i = 0; i < 4; ++i) Qbn[i] = qn[i] * inrm;
+      bool ok = true;
+#pragma unroll
+      for (int i = 0; i < 3; ++i) ok = ok && isfinite(pbn[i]);
+#pragma unroll
+      for (int i = 0; i < 4; ++i) ok = ok && isfinite(Qbn[i]);
+      if (!ok) bad = 1.f;
+    }
     const float badsum = row_sum(bad);
     const float clampsum = row_sum(nclamp);
     if (badsum > 0.f) {
@@ -976,6 +1193,10 @@ __device__ __forceinline__ void rollout_body(const BinArgs& a, const ModelParams
     for (int i = 0; i < 3; ++i) p0[i] = p0n[i];
 #pragma unroll
     for (int i = 0; i < 4; ++i) Q0[i] = Q0n[i];
+#pragma unroll
+    for (int i = 0; i < 3; ++i) pb[i] = pbn[i];
+#pragma unroll
+    for (int i = 0; i < 4; ++i) Qb[i] = Qbn[i];
     kstep += 1;
     cnt_contact += (unsigned long long)nc;
     cnt_clamp += (unsigned long long)clampsum;
@@ -990,7 +1211,12 @@ __device__ __forceinline__ void rollout_body(const BinArgs& a, const ModelParams
     for (int s = 0; s < S; ++s) {
       const int d = lane + 16 * s;
       if (d < nv) vdst[d] = vS[s];
-      if (d >= r0 && d < nv) qdst[qh + d - r0] = thS[s];
+      if (d >= r0 && d < nvr) qdst[qh + d - r0] = thS[s];
+    }
+    if (BALL && lane == 0) {
+      const int qb = hdr[HW_NQR];
+      qdst[qb] = pb[0]; qdst[qb + 1] = pb[1]; qdst[qb + 2] = pb[2];
+      qdst[qb + 3] = Qb[0]; qdst[qb + 4] = Qb[1]; qdst[qb + 5] = Qb[2]; qdst[qb + 6] = Qb[3];
     }
     if (lane == 0) {
       if (r0 == 6) {
@@ -1007,11 +1233,11 @@ __device__ __forceinline__ void rollout_body(const BinArgs& a, const ModelParams
   }
 }
 
-template <int NVC, int SB, int NCR>
+template <int NVC, int SB, int NCR, bool BALL = false>
 __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(WavesPerSimd<NVC, SB, NCR>::value)))
 void rollout_kernel(BinArgs a, ModelParams P) {
-  __shared__ GroupLds<NVC, SB, NCR> lds_all[kVarPerWave];
-  rollout_body<NVC, SB, NCR>(a, P, blockIdx.x, lds_all);
+  __shared__ GroupLds<NVC, SB, NCR, BALL> lds_all[kVarPerWave];
+  rollout_body<NVC, SB, NCR, BALL>(a, P, blockIdx.x, lds_all);
 }
 
 }  // namespace simk

@@ -53,6 +53,7 @@ size_t align256(size_t x) { return (x + 255) & ~size_t(255); }
 struct sim_handle {
   int n = 0;
   int root_type = 0;
+  int ball = 0;  // every variant carries a ball
   ModelParams params{};
   sim_options opts{};
   std::vector<int> nq, nv, q_off, v_off;
@@ -99,10 +100,10 @@ bool finite_all(const float* p, size_t n) {
   return true;
 }
 
-const KernelVariant* find_variant(int nvc, int sb, int ncr) {
+const KernelVariant* find_variant(int nvc, int sb, int ncr, int ball) {
   for (int i = 0; i < kNumKernelVariants; ++i) {
     const KernelVariant& k = kKernelVariants[i];
-    if (k.nvc == nvc && k.sb == sb && (ncr <= 0 || k.ncr == ncr)) return &k;
+    if (k.nvc == nvc && k.sb == sb && k.ball == ball && (ncr <= 0 || k.ncr == ncr)) return &k;
   }
   return nullptr;
 }
@@ -267,6 +268,12 @@ int sim_create(const sim_model_desc* d, const sim_options* opts, sim_handle** ou
       !d->rest_quat || !d->axis || !d->cpg || !d->mu || !d->q0 || !d->v0)
     return bad("a required model array is NULL");
   if (d->root_type == SIM_ROOT_FIXED && !d->root_pose) return bad("FIXED roots need root_pose");
+  const int ball = d->ball ? 1 : 0;
+  if (ball)
+    for (int i = 0; i < d->n_variants; ++i)
+      if (!(d->ball[2 * i] > 0.f) || !(d->ball[2 * i + 1] > 0.f) || !std::isfinite(d->ball[2 * i]) ||
+          !std::isfinite(d->ball[2 * i + 1]))
+        return bad("variant " + std::to_string(i) + ": ball radius and mass must be finite and > 0");
   if (!(d->dt > 0.f) || !std::isfinite(d->dt)) return bad("dt must be > 0");
   if (d->pgs_iters < 1) return bad("pgs_iters must be >= 1");
   const float prm[] = {d->kp, d->kd, d->tau_max, d->k_contact, d->b_contact, d->gravity[0], d->gravity[1], d->gravity[2]};
@@ -288,6 +295,7 @@ int sim_create(const sim_model_desc* d, const sim_options* opts, sim_handle** ou
   const int n = d->n_variants;
   hp->n = n;
   hp->root_type = d->root_type;
+  hp->ball = ball;
   hp->params = ModelParams{d->kp, d->kd, d->tau_max, d->k_contact, d->b_contact, d->dt,
                            {d->gravity[0], d->gravity[1], d->gravity[2]}, d->pgs_iters};
   const int r0 = d->root_type == SIM_ROOT_FREE ? 6 : 0;
@@ -298,10 +306,10 @@ int sim_create(const sim_model_desc* d, const sim_options* opts, sim_handle** ou
     const int nb = d->body_offset[i + 1] - d->body_offset[i];
     if (nb < 1 || nb > kMaxBodiesPerVariant) return bad("variant " + std::to_string(i) + ": 1..32 bodies required");
     const int nh = nb - 1;
-    hp->nv[i] = r0 + nh;
-    hp->nq[i] = (r0 ? 7 : 0) + nh;
+    hp->nv[i] = r0 + nh + (ball ? 6 : 0);
+    hp->nq[i] = (r0 ? 7 : 0) + nh + (ball ? 7 : 0);
     if (hp->nv[i] < 1 || hp->nv[i] > kMaxNv)
-      return bad("variant " + std::to_string(i) + ": degrees of freedom must be in 1..28");
+      return bad("variant " + std::to_string(i) + ": degrees of freedom (the ball's included) must be in 1..28");
     hp->q_off[i + 1] = hp->q_off[i] + hp->nq[i];
     hp->v_off[i + 1] = hp->v_off[i] + hp->nv[i];
   }
@@ -346,6 +354,11 @@ int sim_create(const sim_model_desc* d, const sim_options* opts, sim_handle** ou
     const float* q = (r0 ? d->q0 + hp->q_off[i] + 3 : d->root_pose + 7 * i + 3);
     const float qn = std::sqrt(q[0] * q[0] + q[1] * q[1] + q[2] * q[2] + q[3] * q[3]);
     if (std::fabs(qn - 1.f) > 1e-5f) return bad("variant " + std::to_string(i) + ": root quaternion must be a unit quaternion");
+    if (ball) {
+      const float* qb = d->q0 + hp->q_off[i + 1] - 4;
+      const float bn = std::sqrt(qb[0] * qb[0] + qb[1] * qb[1] + qb[2] * qb[2] + qb[3] * qb[3]);
+      if (std::fabs(bn - 1.f) > 1e-5f) return bad("variant " + std::to_string(i) + ": ball quaternion must be a unit quaternion");
+    }
   }
   // bins: smallest DoF capacity, body slots from the body count
   auto ncr_for = [&](int nvc) {
@@ -363,8 +376,8 @@ int sim_create(const sim_model_desc* d, const sim_options* opts, sim_handle** ou
     // smallest compiled (nv capacity, body slots) that holds the variant
     int sb = 0;
     for (; nvc <= kMaxNv; nvc += 4) {
-      if (find_variant(nvc, sb_need, ncr_for(nvc))) { sb = sb_need; break; }
-      if (sb_need == 1 && find_variant(nvc, 2, ncr_for(nvc))) { sb = 2; break; }
+      if (find_variant(nvc, sb_need, ncr_for(nvc), ball)) { sb = sb_need; break; }
+      if (sb_need == 1 && find_variant(nvc, 2, ncr_for(nvc), ball)) { sb = 2; break; }
     }
     if (!sb)
       return bad("no compiled kernel for nv=" + std::to_string(hp->nv[i]) + " bodies=" + std::to_string(info[i].nb) +
@@ -380,7 +393,7 @@ int sim_create(const sim_model_desc* d, const sim_options* opts, sim_handle** ou
     Bin b;
     b.nvc = kk.first;
     b.sb = kk.second;
-    const KernelVariant* kv = find_variant(b.nvc, b.sb, ncr_for(b.nvc));
+    const KernelVariant* kv = find_variant(b.nvc, b.sb, ncr_for(b.nvc), ball);
     b.ncr = kv->ncr;
     b.fn = kv->fn;
     for (int i = 0; i < n; ++i)
@@ -398,6 +411,7 @@ int sim_create(const sim_model_desc* d, const sim_options* opts, sim_handle** ou
   // single launch: every bin must be one of the multi-bin kernel's families
   if (hp->opts.single_launch) {
     if ((int)hp->bins.size() > kMaxMultiBins) return bad("single_launch supports at most 8 bins");
+    if (ball) return bad("single_launch: the multi-bin kernel has no ball families");
     for (Bin& b : hp->bins) {
       for (int k = 0; k < kNumMultiFamilies; ++k)
         if (kMultiFamilies[k].nvc == b.nvc && kMultiFamilies[k].sb == b.sb && kMultiFamilies[k].ncr == b.ncr)
@@ -443,8 +457,14 @@ int sim_create(const sim_model_desc* d, const sim_options* opts, sim_handle** ou
       int* hd = &b.hdr[(size_t)s * HW_WORDS];
       hd[HW_NB] = vi.nb; hd[HW_NH] = vi.nb - 1; hd[HW_NV] = hp->nv[i]; hd[HW_R0] = r0;
       hd[HW_MAXDEPTH] = vi.maxdepth; hd[HW_USER] = i;
+      hd[HW_NVR] = r0 + vi.nb - 1;
+      hd[HW_NQR] = (r0 ? 7 : 0) + vi.nb - 1;
       float* hf = &b.hdrf[(size_t)s * HF_WORDS];
       hf[HF_MU] = d->mu[i];
+      if (ball) {
+        hf[HF_BALLR] = d->ball[2 * i];
+        hf[HF_BALLM] = d->ball[2 * i + 1];
+      }
       if (!r0) {
         for (int k = 0; k < 3; ++k) hf[HF_ROOTP + k] = d->root_pose[7 * i + k];
         for (int k = 0; k < 4; ++k) hf[HF_ROOTQ + k] = d->root_pose[7 * i + 3 + k];
@@ -487,7 +507,7 @@ int sim_create(const sim_model_desc* d, const sim_options* opts, sim_handle** ou
   auto take = [&](size_t bytes) { size_t o = off; off = align256(off + bytes); return o; };
   for (Bin& b : hp->bins) {
     const size_t m = b.users.size();
-    b.ovf_stride = ovf_floats(8 * 16 * b.sb, b.nvc);
+    b.ovf_stride = ovf_floats(max_contacts(16 * b.sb, ball), b.nvc, ball ? kListWordsBall : kListWords);
     b.o_hdr = take(m * HW_WORDS * 4);
     b.o_hdrf = take(m * HF_WORDS * 4);
     b.o_body = take(m * 16 * b.sb * BW_WORDS * 4);
@@ -860,9 +880,10 @@ int sim_kernel_variants(int32_t* n, int32_t* info, int32_t max_variants) {
   if (!n) return SIM_E_INVALID;
   *n = kNumKernelVariants;
   for (int i = 0; i < kNumKernelVariants && i < max_variants && info; ++i) {
-    info[3 * i] = kKernelVariants[i].nvc;
-    info[3 * i + 1] = 16 * kKernelVariants[i].sb;
-    info[3 * i + 2] = kKernelVariants[i].ncr;
+    info[4 * i] = kKernelVariants[i].nvc;
+    info[4 * i + 1] = 16 * kKernelVariants[i].sb;
+    info[4 * i + 2] = kKernelVariants[i].ncr;
+    info[4 * i + 3] = kKernelVariants[i].ball;
   }
   return SIM_OK;
 }

@@ -27,10 +27,18 @@ enum BodyWord {
   BW_WORDS = 24
 };
 
-// Per-variant integer header.
-enum HdrWord { HW_NB = 0, HW_NH, HW_NV, HW_R0, HW_MAXDEPTH, HW_USER, HW_PAD0, HW_PAD1, HW_WORDS };
-// Per-variant float header: mu, fixed root pose (p[3], q[4]).
-enum HdrfWord { HF_MU = 0, HF_ROOTP = 1, HF_ROOTQ = 4, HF_WORDS = 8 };
+// Per-variant integer header.  HW_NV counts every DoF (the ball's too),
+// HW_NVR the robot's only; the robot's q entries are HW_NQR.
+enum HdrWord { HW_NB = 0, HW_NH, HW_NV, HW_R0, HW_MAXDEPTH, HW_USER, HW_NVR, HW_NQR, HW_WORDS };
+// Per-variant float header: mu, fixed root pose (p[3], q[4]), ball radius and mass.
+enum HdrfWord { HF_MU = 0, HF_ROOTP = 1, HF_ROOTQ = 4, HF_BALLR = 8, HF_BALLM = 9, HF_WORDS = 10 };
+
+// Contact list entry (floats): plane-only kernels keep x, y, z and the
+// ancestor mask of the body; ball kernels add the normal (box -> ball), the
+// depth and the kind (0 box corner - plane, 1 ball - plane, 2 ball - box).
+enum ListWord { CL_X = 0, CL_ANC = 3, CL_N = 4, CL_DEPTH = 7, CL_KIND = 8 };
+constexpr int kListWords = 4;
+constexpr int kListWordsBall = 12;
 
 // Overflow scratch per contact (contacts that do not fit in registers).
 constexpr int kOvfScal = 12;     // per-contact solver scalars
@@ -77,11 +85,14 @@ struct MultiArgs {
 };
 
 // Overflow scratch layout per variant (floats):
-//   list  [max_contacts][4]   x, y, z, ancestor mask of the contact body (uint bits)
+//   list  [max_contacts][list_words]   contact list entries (ListWord)
 //   scal  [max_contacts][kOvfScal]
 //   rows  [max_contacts][6][nvc]  J_n, J_x, J_y, W_n, W_x, W_y
-inline long long ovf_floats(int max_contacts, int nvc) {
-  return (long long)max_contacts * (4 + kOvfScal + 6 * nvc);
+inline long long ovf_floats(int max_contacts, int nvc, int list_words) {
+  return (long long)max_contacts * (list_words + kOvfScal + 6 * nvc);
 }
+// Largest contact count of a variant: 8 corners per box, plus for a ball one
+// plane contact and one per box.
+constexpr int max_contacts(int nbc, bool ball) { return 8 * nbc + (ball ? 1 + nbc : 0); }
 
 }  // namespace simk

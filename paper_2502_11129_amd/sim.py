@@ -30,7 +30,8 @@ class sim_model_desc(C.Structure):
                 ("half_ext", _F), ("mass", _F), ("anchor_parent", _F), ("anchor_child", _F), ("rest_quat", _F),
                 ("axis", _F), ("cpg", _F), ("mu", _F), ("q0", _F), ("v0", _F), ("root_pose", _F),
                 ("kp", C.c_float), ("kd", C.c_float), ("tau_max", C.c_float), ("k_contact", C.c_float),
-                ("b_contact", C.c_float), ("dt", C.c_float), ("gravity", C.c_float * 3), ("pgs_iters", C.c_int32)]
+                ("b_contact", C.c_float), ("dt", C.c_float), ("gravity", C.c_float * 3), ("pgs_iters", C.c_int32),
+                ("ball", _F)]
 
 
 class sim_options(C.Structure):
@@ -130,7 +131,8 @@ def make_desc(pop):
     keep = dict(bo=np.ascontiguousarray(pop.body_offset, np.int32), parent=np.ascontiguousarray(pop.parent, np.int32),
                 half=_f32(pop.half_ext), mass=_f32(pop.mass), ap=_f32(pop.anchor_parent), ac=_f32(pop.anchor_child),
                 rq=_f32(pop.rest_quat), axis=_f32(pop.axis), cpg=_f32(pop.cpg), mu=_f32(pop.mu), q0=_f32(pop.q0),
-                v0=_f32(pop.v0), rp=_f32(pop.root_pose))
+                v0=_f32(pop.v0), rp=_f32(pop.root_pose),
+                ball=None if getattr(pop, "ball", None) is None else _f32(pop.ball))
     p = pop.params
     f = lambda a: a.ctypes.data_as(_F)
     d = sim_model_desc()
@@ -145,16 +147,19 @@ def make_desc(pop):
     d.k_contact, d.b_contact, d.dt = p["k_contact"], p["b_contact"], p["dt"]
     d.gravity[0], d.gravity[1], d.gravity[2] = p["gravity"]
     d.pgs_iters = int(p["pgs_iters"])
+    d.ball = f(keep["ball"]) if keep["ball"] is not None else None
     return d, keep
 
 
-def kernel_variants():
-    """Compiled kernels as (nv capacity, body capacity, contacts in registers)."""
+def kernel_variants(ball=False):
+    """Compiled kernels as (nv capacity, body capacity, contacts in registers),
+    of the plane-only family or (ball=True) of the family whose variants carry a ball."""
     lib = load()
     n = C.c_int32()
-    info = np.zeros(3 * 64, np.int32)
+    info = np.zeros(4 * 64, np.int32)
     assert lib.sim_kernel_variants(C.byref(n), info.ctypes.data_as(_I32), 64) == SIM_OK
-    return [tuple(int(x) for x in info[3 * i:3 * i + 3]) for i in range(n.value)]
+    rows = [tuple(int(x) for x in info[4 * i:4 * i + 4]) for i in range(n.value)]
+    return [r[:3] for r in rows if r[3] == int(bool(ball))]
 
 
 def split_allocation(n, gpu_n, gpu_s, host_s_per_variant):

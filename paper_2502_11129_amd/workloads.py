@@ -432,9 +432,9 @@ def box_and_ball(n=131072, first=0, clearance=0.005, steps=2000):
     """Box-and-ball variants: the box of ``boxes`` (sides U(0.05,0.3), density
     1000, uniform orientation, centre height U(0.2,1.0), world velocities
     N(0,0.5), mu U(0.3,1.2)) and a ball of radius U(0.03,0.15), density 1000,
-    dropped from 0.05-0.5 m above the box top at a horizontal offset N(0,0.1)
-    from the box centre (so that most balls land on the box), world velocity
-    N(0,0.5) and angular velocity N(0,2)."""
+    dropped from 0.05-0.5 m above the box top at a horizontal offset N(0,0.02)
+    from the box centre, moving with the box (world velocity the box's plus
+    N(0,0.1)) so that most balls land on it, angular velocity N(0,2)."""
     b = _Builder()
     lifted = 0
     for i in range(first, first + n):
@@ -449,9 +449,9 @@ def box_and_ball(n=131072, first=0, clearance=0.005, steps=2000):
         ww = rng.normal(0.0, 0.5, 3)
         mu = rng.uniform(0.3, 1.2)
         r = rng.uniform(0.03, 0.15)
-        off = rng.normal(0.0, 0.1, 2)
+        off = rng.normal(0.0, 0.02, 2)
         gap = rng.uniform(0.05, 0.5)
-        bv = rng.normal(0.0, 0.5, 3)
+        bv = vw + rng.normal(0.0, 0.1, 3)
         bw = rng.normal(0.0, 2.0, 3)
         half = sides / 2.0
         R = _quat_to_rot(q)

@@ -45,6 +45,29 @@ def min_corner_height(o, pop, vi, q):
     return best
 
 
+def ball_margin(o, pop, vi, q):
+    """Distance of variant vi's ball from its contact switches at position q:
+    ball-plane activation, ball-box activation, the inside/outside switch of
+    the box test and ties of the nearest-face choice."""
+    R, p, _, _ = o.fk(vi, q)
+    r = float(pop.ball[vi, 0])
+    c = np.asarray(q[-7:-4], np.float64)
+    best = abs(c[2] - r)
+    b0 = pop.body_offset[vi]
+    for b in range(R.shape[0]):
+        h = pop.half_ext[b0 + b].astype(np.float64)
+        l = R[b].T @ (c - p[b])
+        gaps = h - np.abs(l)
+        best = min(best, np.abs(gaps).min())               # inside / outside switch
+        if (gaps >= 0).all():
+            g = np.sort(gaps)
+            best = min(best, g[1] - g[0])                   # nearest-face tie
+        else:
+            d = np.linalg.norm(c - (p[b] + R[b] @ np.clip(l, -h, h)))
+            best = min(best, abs(d - r))
+    return best
+
+
 def teacher_forced(pop, sim, ks, threads=THREADS):
     """For each k in ks: oracle state x_k (FP64) -> float32 -> one GPU step,
     compared with the oracle's x_{k+1}.  Returns (max error outside the
@@ -70,7 +93,10 @@ def teacher_forced(pop, sim, ks, threads=THREADS):
             if st[i] or st1[i]:
                 continue
             e = step_error(qgs[i], vgs[i], q1s[i], v1s[i], free)
-            if min_corner_height(o, pop, i, qs[i]) < BAND:
+            margin = min_corner_height(o, pop, i, qs[i])
+            if getattr(pop, "ball", None) is not None:
+                margin = min(margin, ball_margin(o, pop, i, qs[i]))
+            if margin < BAND:
                 in_band += 1
                 continue
             errs.append(e)

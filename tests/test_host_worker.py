@@ -18,6 +18,8 @@ from _parity import fitness_gate, perturbed_fitness
     ("quadrupeds x8", W.quadrupeds(8), 400),
     ("fixed chain", W.chain(3, ["+x", "+y", "+x"], [1, 0, 1], theta0=[0.3, -0.2, 0.5],
                             cpg=[(0.8, 3.0, 0.1), (0.5, 2.0, 1.0), (0.9, 4.0, 2.0)]), 500),
+    ("box_and_ball x48", W.box_and_ball(48), 1000),
+    ("snake3+ball x16", W.attach_ball(W.snake(16)), 800),
 ])
 def test_host_worker_matches_oracle(name, pop, T):
     h = S.Handle(pop)

@@ -28,8 +28,11 @@ def parse():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--variants", type=int, default=8192)
-    ap.add_argument("--horizon", type=int, default=5000)
+    ap.add_argument("--workload", default="trees", choices=["trees", "box_and_ball"],
+                    help="trees: the uneven-morphology population (default); box_and_ball: a free box "
+                         "and a free ball per variant (the paper's box-and-ball scene)")
+    ap.add_argument("--variants", type=int, default=None, help="default 8192 (trees) / 512000 (box_and_ball)")
+    ap.add_argument("--horizon", type=int, default=None, help="default 5000 (trees) / 1000 (box_and_ball)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-autotune", action="store_true", help="default launch options instead of the autotuned ones")
     ap.add_argument("--options", default=None,
@@ -42,21 +45,26 @@ def parse():
     return ap.parse_args()
 
 
-def cpu_baseline(pop_full, sample_steps):
+def cpu_baseline(pop_full, sample_steps, workload="trees"):
     """The FP64 oracle on the host cores over a bounded sample of the same
-    workload: the 64 spot-check variants (indices 128 m) for sample_steps steps."""
+    workload: the 64 spot-check variants (indices 128 m) of the trees, or the
+    first 16384 box-and-ball variants, for sample_steps steps."""
     from oracle import oracle as O
     from paper_2502_11129_amd import workloads as W
-    idx = [i for i in W.TREE_SPOTCHECK if i < pop_full.n_variants]
-    pop = W.random_trees(indices=idx)
+    if workload == "box_and_ball":
+        pop = W.box_and_ball(16384)
+    else:
+        idx = [i for i in W.TREE_SPOTCHECK if i < pop_full.n_variants]
+        pop = W.random_trees(indices=idx)
     cores = os.cpu_count() or 1
     o = O.Oracle(pop)
     t0 = time.perf_counter()
     o.rollout(sample_steps, threads=cores)
     dt = time.perf_counter() - t0
+    what = "first" if workload == "box_and_ball" else "spot-check"
     return {"value": pop.n_variants * sample_steps / dt, "unit": "variant-steps/s", "cores": cores,
-            "kind": "oracle", "sample": f"{pop.n_variants} spot-check variants x {sample_steps} steps, "
-                                        f"FP64, {cores} threads, {dt:.1f} s"}
+            "kind": "oracle", "sample": f"{pop.n_variants} {what} variants x {sample_steps} steps, "
+                                        f"FP64, {cores} threads, {dt:.2f} s"}
 
 
 def recorded_traffic(kernel, steps_per_launch):
@@ -91,8 +99,16 @@ def main():
     from paper_2502_11129_amd.flops import flops_per_variant, bytes_per_rollout
     from paper_2502_11129_amd.sim import Simulator
 
-    pop = W.random_trees(args.variants)
-    T = args.horizon
+    if args.workload == "box_and_ball":
+        pop = W.box_and_ball(args.variants or 512000)
+        T = args.horizon or 1000
+        wname = (f"box-and-ball (a free box and a free ball per variant), {pop.n_variants} variants x {T} steps, "
+                 "dt=0.002, K=8")
+    else:
+        pop = W.random_trees(args.variants or 8192)
+        T = args.horizon or 5000
+        wname = (f"uneven-morphology random trees (4-20 hinges, depth<=4), "
+                 f"{pop.n_variants} variants x {T} steps, dt=0.002, K=8")
     options, trials = {}, []
     if args.options:
         options = {k: ({int(a): b for a, b in v.items()} if k == "ncr_by_nvc" else v)
@@ -141,7 +157,7 @@ def main():
     all_bins = fl / (ms_per_step / 1e3) / 1e12
     byt = bytes_per_rollout(pop)
     nvc, nbody, ncr, nvar = bins[dom]
-    kernel_name = f"rollout_kernel<{nvc}, {nbody // 16}, {ncr}>"
+    kernel_name = f"rollout_kernel<{nvc}, {nbody // 16}, {ncr}{', true' if args.workload == 'box_and_ball' else ''}>"
     if options.get("single_launch"):
         # one kernel runs every bin: its launches carry the whole rollout
         kernel_name = "rollout_multi_kernel"
@@ -163,8 +179,7 @@ def main():
         "vs_baseline": None,
         "dtype": "f32",
         "data": "synthetic",
-        "config": {"workload": f"uneven-morphology random trees (4-20 hinges, depth<=4), "
-                               f"{pop.n_variants} variants x {T} steps, dt=0.002, K=8",
+        "config": {"workload": wname,
                    "variants": pop.n_variants, "horizon": T, "bins": bins,
                    "frozen_variants": int((status != 0).sum()),
                    "mean_contacts_per_step": float(rows_contact.sum() / (pop.n_variants * T)),
@@ -182,7 +197,7 @@ def main():
                      "hbm_GBs": byt / (ms_per_step / 1e3) / 1e9},
     }
     if not args.no_cpu_baseline:
-        out["cpu_baseline"] = cpu_baseline(pop, args.cpu_sample_steps)
+        out["cpu_baseline"] = cpu_baseline(pop, args.cpu_sample_steps, args.workload)
     if args.surrogate:
         from paper_2502_11129_amd.screening import run as screening_run
         out["surrogate"] = screening_run(log=lambda m: print(m, file=sys.stderr, flush=True))

@@ -8,6 +8,9 @@ active rows (n_c contacts, n_clamp engaged actuator clamps), FMA = 2:
   + (2/3) nv^3 + 2 nv^2 + 100             dense factorisation and free solve
   + n_c (50 + 9 dbar + 6 nv^2 + 6 nv + 12 K nv)   contact rows and K sweeps
   + n_clamp (2 nv^2 + 4 K nv)             clamp rows and K sweeps
+  + 70 nb + 60                            with a ball: ball-box tests, ball update
+
+(nv counts the ball's six DoFs when there is one.)
 
 Padded lanes, bin capacities and the kernel's own extra work (for instance
 the explicit inverse) are not counted.  Bytes: model + state read once and
@@ -43,6 +46,8 @@ def flops_per_variant(pop, steps, rows_contact, rows_clamp, K=None):
     nv = pop.nv.astype(np.float64)
     D, dbar = depth_sums(pop)
     base = 156 * nh + 594 * nb + 60 * D + 72 * nh + (2.0 / 3.0) * nv ** 3 + 2 * nv ** 2 + 100
+    if getattr(pop, "ball", None) is not None:
+        base = base + 70 * nb + 60
     per_contact = 50 + 9 * dbar + 6 * nv ** 2 + 6 * nv + 12 * K * nv
     per_clamp = 2 * nv ** 2 + 4 * K * nv
     return (base * steps + np.asarray(rows_contact, np.float64) * per_contact

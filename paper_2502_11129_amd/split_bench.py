@@ -10,17 +10,23 @@ from __future__ import annotations
 import argparse
 import json
 import os
+import sys
 import time
 
 
-def measure(pop, T, threads, rule="makespan", pilot_T=100, host_sample=None, log=print):
+def measure(pop, T, threads, rule="makespan", pilot_T=None, host_sample=None, log=print, progress=None):
+    """pilot_T: steps of the pilot runs (default the full horizon T, as the
+    paper's initial benchmarking runs: a short pilot of a dropped scene sees
+    only the free fall, where the host's per-step cost is lowest)."""
     import torch
+    say = progress or (lambda m: None)
     from .sim import Simulator
     sim = Simulator(pop)
     n = pop.n_variants
     st = torch.cuda.current_stream()
     # sequential GPU (after a warm-up)
     sim.rollout(T)
+    torch.cuda.synchronize()
     e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
     t0 = time.perf_counter()
     e0.record(st)
@@ -29,11 +35,14 @@ def measure(pop, T, threads, rule="makespan", pilot_T=100, host_sample=None, log
     e1.synchronize()
     seq_gpu = time.perf_counter() - t0
     seq_gpu_events = e0.elapsed_time(e1) / 1e3
+    say(f"n={n}: sequential GPU {seq_gpu:.3f} s")
     # sequential CPU: every variant on host threads
     _, seq_cpu = sim.rollout_host(T, threads)
+    say(f"n={n}: sequential CPU {seq_cpu:.3f} s")
     # pilot and allocation
-    plan = sim.plan_split(pilot_T, threads, host_sample or max(threads * 4, min(n, 256)))
+    plan = sim.plan_split(pilot_T or T, threads, host_sample or max(threads * 4, min(n, 256)))
     n_host = plan["n_host_makespan"] if rule == "makespan" else plan["n_host_paper"]
+    say(f"n={n}: pilot split, {n_host} variants on the host")
     # combined run
     t = sim.rollout_split(T, n_host, threads)
     out = dict(n=n, T=T, threads=threads, rule=rule, seq_gpu_s=seq_gpu, seq_gpu_events_s=seq_gpu_events,
@@ -48,15 +57,17 @@ def measure(pop, T, threads, rule="makespan", pilot_T=100, host_sample=None, log
 def main():
     from . import workloads as W
     ap = argparse.ArgumentParser()
-    ap.add_argument("--workload", default="quadrupeds", choices=["quadrupeds", "trees", "boxes"])
+    ap.add_argument("--workload", default="quadrupeds", choices=["quadrupeds", "trees", "boxes", "box_and_ball"])
     ap.add_argument("--steps", type=int, default=1000)
     ap.add_argument("--sizes", default="32,128,512,2048,8192,32768")
     ap.add_argument("--threads", type=int, default=os.cpu_count() or 1)
     ap.add_argument("--rule", default="makespan", choices=["makespan", "paper"])
     a = ap.parse_args()
-    make = {"quadrupeds": lambda n: W.quadrupeds(n, steps=a.steps), "trees": W.random_trees, "boxes": W.boxes}[a.workload]
+    make = {"quadrupeds": lambda n: W.quadrupeds(n, steps=a.steps), "trees": W.random_trees, "boxes": W.boxes,
+            "box_and_ball": lambda n: W.box_and_ball(n, steps=a.steps)}[a.workload]
     for n in (int(x) for x in a.sizes.split(",")):
-        measure(make(n), a.steps, a.threads, a.rule, log=lambda m: print(m, flush=True))
+        measure(make(n), a.steps, a.threads, a.rule, log=lambda m: print(m, flush=True),
+                progress=lambda m: print(m, file=sys.stderr, flush=True))
 
 
 if __name__ == "__main__":

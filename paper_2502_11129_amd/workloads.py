@@ -428,7 +428,7 @@ def _ball_mass(r, density=BALL_DENSITY):
     return density * 4.0 / 3.0 * np.pi * r ** 3
 
 
-def box_and_ball(n=131072, first=0, clearance=0.005, steps=2000):
+def box_and_ball(n=131072, first=0, clearance=0.005, steps=1000):
     """Box-and-ball variants: the box of ``boxes`` (sides U(0.05,0.3), density
     1000, uniform orientation, centre height U(0.2,1.0), world velocities
     N(0,0.5), mu U(0.3,1.2)) and a ball of radius U(0.03,0.15), density 1000,

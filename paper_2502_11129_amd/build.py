@@ -30,7 +30,8 @@ DEVICE = [f"--offload-arch={ARCH}", "-ffp-contract=on", "-Xclang", "-target-feat
 
 def _sources():
     kern = sorted(glob.glob(os.path.join(CSRC, "kernels", "*.hip")))
-    host = [os.path.join(CSRC, n) for n in ("kernel_registry.cpp", "sim_host.cpp", "host_worker.cpp", "sur_host.cpp")]
+    host = [os.path.join(CSRC, n) for n in ("kernel_registry.cpp", "sim_host.cpp", "host_worker.cpp", "sur_host.cpp",
+                                         "ea_host.cpp")]
     return kern, host
 
 

@@ -608,8 +608,52 @@ def random_genotypes(n, key=0, chunk=262144) -> Genotypes:
     return out
 
 
+_FACE_VEC = np.array([FACES[f] for f in FACE_NAME], np.float32)                  # [4, 3]
+_FACE_QUAT = np.array([_face_rest_quat(f) for f in FACE_NAME], np.float32)        # [4, 4]
+
+
 def population_from_genotypes(g: Genotypes, steps=5000) -> Population:
-    """Robots of the given genotypes (core + bricks, as in random_trees)."""
+    """Robots of the given genotypes (core + bricks, as in random_trees),
+    assembled with array operations; the same arrays as building them body
+    by body (``_population_from_genotypes_bodywise``)."""
+    n = len(g)
+    nh = np.asarray(g.nh, np.int64)
+    nb = nh + 1
+    bo = np.concatenate([[0], np.cumsum(nb)]).astype(np.int32)
+    NB = int(bo[-1])
+    var = np.repeat(np.arange(n), nb)                       # variant of each body
+    loc = np.arange(NB) - np.repeat(bo[:-1], nb)            # body index within its variant
+    core = loc == 0
+    j = np.where(core, 0, loc - 1)                          # hinge of a brick
+    par = np.where(core, -1, g.parent[var, j]).astype(np.int32)
+    fcode = np.where(core, 0, g.face[var, j]).astype(np.int64)
+    flag = np.where(core, 0, g.axis[var, j])
+    half = np.where(core[:, None], np.float32(CORE_HALF), np.float32(BRICK_HALF)).repeat(3, axis=1).astype(np.float32)
+    mass = np.where(core, np.float32(CORE_MASS), np.float32(BRICK_MASS)).astype(np.float32)
+    parent_half = np.where(par == 0, CORE_HALF, BRICK_HALF)
+    ap = np.where(core[:, None], 0.0, _FACE_VEC[fcode].astype(np.float64) * parent_half[:, None]).astype(np.float32)
+    ac = np.zeros((NB, 3), np.float32)
+    ac[~core, 0] = -BRICK_HALF
+    rq = np.where(core[:, None], np.array([1, 0, 0, 0], np.float32), _FACE_QUAT[fcode]).astype(np.float32)
+    axis = np.where((flag == 0)[:, None], np.array([0, 0, 1], np.float32), np.array([0, 1, 0], np.float32))
+    axis = axis.astype(np.float32)
+    cpg = np.where(core[:, None], 0.0, g.cpg[var, j]).astype(np.float32)
+    nq = 7 + nh
+    q0 = np.zeros(int(nq.sum()), np.float32)
+    qo = np.concatenate([[0], np.cumsum(nq)])[:-1]
+    q0[qo + 2] = CORE_Z0
+    q0[qo + 3] = 1.0
+    v0 = np.zeros(int((6 + nh).sum()), np.float32)
+    root_pose = np.tile(np.array([0, 0, 0, 1, 0, 0, 0], np.float32), (n, 1))
+    return Population(body_offset=bo, parent=par, half_ext=half, mass=mass, anchor_parent=ap, anchor_child=ac,
+                      rest_quat=rq, axis=axis, cpg=cpg, mu=np.ones(n, np.float32), q0=q0, v0=v0,
+                      root_pose=root_pose, root_type=ROOT_FREE, params=dict(DEFAULT_PARAMS), name="genotypes",
+                      steps=steps)
+
+
+def _population_from_genotypes_bodywise(g: Genotypes, steps=5000) -> Population:
+    """Robots of the given genotypes built body by body (reference for the
+    array version above)."""
     b = _Builder()
     for i in range(len(g)):
         nh = int(g.nh[i])

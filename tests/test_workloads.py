@@ -86,3 +86,14 @@ def test_box_orientations_uniform_and_no_penetration():
     assert sides.min() >= 0.05 and sides.max() <= 0.3
     np.testing.assert_allclose(p.mass, 1000 * sides.prod(axis=1), rtol=1e-5)
     assert (p.mu >= 0.3).all() and (p.mu <= 1.2).all()
+
+
+def test_genotype_robots_array_builder_equals_bodywise_builder():
+    g = W.random_genotypes(700, key=31)
+    a = W.population_from_genotypes(g, steps=123)
+    b = W._population_from_genotypes_bodywise(g, steps=123)
+    for k in ("body_offset", "parent", "half_ext", "mass", "anchor_parent", "anchor_child", "rest_quat", "axis",
+              "cpg", "mu", "q0", "v0", "root_pose"):
+        x, y = getattr(a, k), getattr(b, k)
+        assert x.dtype == y.dtype and x.shape == y.shape and np.array_equal(x, y), k
+    assert a.steps == b.steps == 123 and a.root_type == b.root_type

@@ -29,6 +29,14 @@
 // minus box, friction in the tangent plane of the orthonormal basis of Duff
 // et al., "Building an Orthonormal Basis, Revisited", JCGT 6(1), 2017.
 //
+// Optional self-collision (body-body contact between the boxes of one robot):
+// for every pair of boxes not joined by a hinge, each corner of either box
+// strictly inside the other is a contact whose normal is the outward normal
+// of the penetrated box's nearest face and whose depth is the distance to that
+// face (vertex-face contacts; two edges crossing with no corner inside are not
+// detected).  Rows act on the relative velocity (corner's box minus
+// penetrated box) at the corner.
+//
 // The library is templated on the scalar so a float instance can measure how
 // sensitive a trajectory is to single precision.  An RK4 mode (no contact, no
 // solver) integrates the smooth dynamics for the energy/momentum pins.
@@ -107,6 +115,26 @@ template <class T> void quat_exp(const V3<T>& phi, T* out) {
   }
 }
 
+// A point x strictly inside a box (centre p, rotation R, half extents h): the
+// box's face nearest to x (first of equal gaps in x, y, z order), its outward
+// normal R (+-e_k) normalised, and the distance to it.
+template <class T> bool corner_in_box(const V3<T>& x, const V3<T>& p, const M3<T>& R, const V3<T>& h, V3<T>& n,
+                                      T& depth) {
+  V3<T> l = mtv(R, sub(x, p));
+  for (int k = 0; k < 3; ++k)
+    if (!(std::abs(l[k]) < h[k])) return false;
+  int kb = 0;
+  T gap = h[0] - std::abs(l[0]);
+  for (int k = 1; k < 3; ++k)
+    if (h[k] - std::abs(l[k]) < gap) { gap = h[k] - std::abs(l[k]); kb = k; }
+  V3<T> nl{0, 0, 0};
+  nl[kb] = l[kb] >= 0 ? T(1) : T(-1);
+  n = mv(R, nl);
+  n = scl(n, T(1) / std::sqrt(dot(n, n)));
+  depth = gap;
+  return true;
+}
+
 // ----------------------------------------------------------------------------
 // Textbook dense Cholesky (lower, L L^T = A) and the two triangular solves.
 // ----------------------------------------------------------------------------
@@ -146,6 +174,7 @@ struct Params {
   double kp, kd, tau_max, k_contact, b_contact, dt, g[3];
   int K;
   int root_fixed;
+  int self_collision = 0;
 };
 
 template <class T> struct Body {
@@ -404,9 +433,10 @@ template <class T> struct Sim {
     }
   }
 
-  // kind 0: box corner - plane (body, corner); 1: ball - plane; 2: ball - box (body)
+  // kind 0: box corner - plane (body, corner); 1: ball - plane; 2: ball - box (body);
+  // 3: corner `corner` of box `body` inside box `other` (self-collision)
   struct Contact {
-    int body, corner, kind = 0;
+    int body, corner, kind = 0, other = -1;
     V3<T> x, n{0, 0, 1};
     T depth;
     std::vector<T> J[3], W[3];  // rows: 0 = normal (z), 1 = x, 2 = y
@@ -415,8 +445,9 @@ template <class T> struct Sim {
   };
 
   // Rows of a contact in the slots (t1, t2, n) = (x, y, z) of a 3 x nv matrix:
-  // plane contacts take world x, y, z; ball-box contacts project the relative
-  // velocity Jacobian (ball minus box at the contact point) on (t1, t2, n).
+  // plane contacts take world x, y, z; ball-box and box-box contacts project
+  // the relative velocity Jacobian (ball or corner's box minus the other box
+  // at the contact point) on (t1, t2, n).
   void contact_jacobian(const Variant<T>& V, const Kin<T>& kin, const Contact& ct, T* Jp) const {
     const int nv = V.nv;
     if (ct.kind == 0) {
@@ -425,8 +456,13 @@ template <class T> struct Sim {
       ball_point_jacobian(V, kin, ct.x, Jp);
     } else {
       std::vector<T> Ja(3 * nv), Jb(3 * nv);
-      ball_point_jacobian(V, kin, ct.x, Ja.data());
-      point_jacobian(V, kin, ct.body, ct.x, Jb.data());
+      if (ct.kind == 2) {
+        ball_point_jacobian(V, kin, ct.x, Ja.data());
+        point_jacobian(V, kin, ct.body, ct.x, Jb.data());
+      } else {
+        point_jacobian(V, kin, ct.body, ct.x, Ja.data());
+        point_jacobian(V, kin, ct.other, ct.x, Jb.data());
+      }
       V3<T> t1, t2;
       tangent_basis(ct.n, t1, t2);
       const V3<T> dirs[3] = {t1, t2, ct.n};
@@ -455,6 +491,30 @@ template <class T> struct Sim {
           out.push_back(std::move(C));
         }
       }
+    }
+    if (P.self_collision) {
+      // pairs a < b not joined by a hinge; corners of a inside b, then of b inside a
+      for (int a = 0; a < nb; ++a)
+        for (int b = a + 1; b < nb; ++b) {
+          if (V.bodies[b].parent == a) continue;
+          for (int side = 0; side < 2; ++side) {
+            const int pb = side ? b : a, qb = side ? a : b;
+            const Body<T>& BP = V.bodies[pb];
+            for (int c = 0; c < 8; ++c) {
+              V3<T> sc = {(c & 1) ? BP.half[0] : -BP.half[0], (c & 2) ? BP.half[1] : -BP.half[1],
+                          (c & 4) ? BP.half[2] : -BP.half[2]};
+              V3<T> x = add(kin.p[pb], mv(kin.R[pb], sc));
+              V3<T> n;
+              T depth;
+              if (corner_in_box(x, kin.p[qb], kin.R[qb], V.bodies[qb].half, n, depth)) {
+                Contact C;
+                C.body = pb; C.other = qb; C.corner = c; C.kind = 3;
+                C.x = x; C.n = n; C.depth = depth;
+                out.push_back(std::move(C));
+              }
+            }
+          }
+        }
     }
     if (!V.ball) return;
     // the ball after the boxes: plane first, then every box in body order
@@ -754,9 +814,9 @@ template <class T>
 void parse(Sim<T>& S, int n, const int32_t* body_offset, const int32_t* parent, const float* half,
            const float* mass, const float* ap, const float* ac, const float* rq, const float* axis,
            const float* cpg, const float* mu, const float* q0, const float* v0, const float* root_pose,
-           const float* ball, const double* params, int root_fixed, int K) {
+           const float* ball, const double* params, int root_fixed, int K, int self_collision) {
   S.P = Params{params[0], params[1], params[2], params[3], params[4], params[5],
-               {params[6], params[7], params[8]}, K, root_fixed};
+               {params[6], params[7], params[8]}, K, root_fixed, self_collision};
   S.var.resize(n);
   S.st.resize(n);
   int64_t qo = 0, vo = 0;
@@ -811,22 +871,23 @@ void parse(Sim<T>& S, int n, const int32_t* body_offset, const int32_t* parent, 
 extern "C" {
 
 // Create a reference simulator.  params = [kp, kd, tau_max, k_contact, b_contact, dt, gx, gy, gz];
-// ball = [radius, mass] per variant, or NULL for no ball.
+// ball = [radius, mass] per variant, or NULL for no ball; self_collision != 0
+// adds the vertex-face contacts between boxes of one robot not joined by a hinge.
 void* orc_create(int n, const int32_t* body_offset, const int32_t* parent, const float* half,
                  const float* mass, const float* anchor_parent, const float* anchor_child,
                  const float* rest_quat, const float* axis, const float* cpg, const float* mu,
                  const float* q0, const float* v0, const float* root_pose, const float* ball,
-                 const double* params, int root_fixed, int pgs_iters, int precision) {
+                 const double* params, int root_fixed, int pgs_iters, int precision, int self_collision) {
   auto* h = new Handle();
   h->precision = precision;
   if (precision == 32) {
     h->f.reset(new Sim<float>());
     parse(*h->f, n, body_offset, parent, half, mass, anchor_parent, anchor_child, rest_quat, axis, cpg, mu,
-          q0, v0, root_pose, ball, params, root_fixed, pgs_iters);
+          q0, v0, root_pose, ball, params, root_fixed, pgs_iters, self_collision);
   } else {
     h->d.reset(new Sim<double>());
     parse(*h->d, n, body_offset, parent, half, mass, anchor_parent, anchor_child, rest_quat, axis, cpg, mu,
-          q0, v0, root_pose, ball, params, root_fixed, pgs_iters);
+          q0, v0, root_pose, ball, params, root_fixed, pgs_iters, self_collision);
   }
   return h;
 }
@@ -932,9 +993,11 @@ int orc_dynamics(void* hp, int vi, const double* q, const double* v, double* M, 
   return 0;
 }
 // Active contacts at q: returns count (<= max); body, corner, point x [3], depth, rows J [3*nv] (n, x, y).
-// corner: 0..7 box corner, -1 ball-plane, -2 ball-box (body = the box); normal n [3] (box -> ball).
+// corner: 0..7 box corner, -1 ball-plane, -2 ball-box (body = the box); other: the
+// penetrated box of a self-collision contact (corner `corner` of `body`), else -1;
+// normal n [3] (towards the ball / the corner's box).
 int orc_contacts(void* hp, int vi, const double* q, int max, int32_t* body, int32_t* corner, double* x,
-                 double* depth, double* J, double* normal) {
+                 double* depth, double* J, double* normal, int32_t* other) {
   auto* h = static_cast<Handle*>(hp);
   if (h->precision != 64) return -1;
   auto& S = *h->d;
@@ -947,7 +1010,7 @@ int orc_contacts(void* hp, int vi, const double* q, int max, int32_t* body, int3
   std::vector<double> Jp(3 * nv);
   const int rowsel[3] = {2, 0, 1};
   for (int i = 0; i < n; ++i) {
-    body[i] = C[i].body; corner[i] = C[i].corner; depth[i] = C[i].depth;
+    body[i] = C[i].body; corner[i] = C[i].corner; depth[i] = C[i].depth; other[i] = C[i].other;
     for (int k = 0; k < 3; ++k) { x[3 * i + k] = C[i].x[k]; normal[3 * i + k] = C[i].n[k]; }
     S.contact_jacobian(V, kin, C[i], Jp.data());
     for (int r = 0; r < 3; ++r)

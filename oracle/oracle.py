@@ -7,7 +7,8 @@ The wrapper accepts any object carrying the variant-CSR model arrays
 (``body_offset``, ``parent``, ``half_ext``, ``mass``, ``anchor_parent``,
 ``anchor_child``, ``rest_quat``, ``axis``, ``cpg``, ``mu``, ``q0``, ``v0``,
 ``root_pose``, ``root_type``, ``params`` and optionally ``ball``: [N, 2] radius
-and mass of one free sphere per variant) -- the seeded generators produce
+and mass of one free sphere per variant, and ``self_collision``: contacts
+between the boxes of one robot) -- the seeded generators produce
 such objects; nothing here imports the HIP library or its binding.
 """
 from __future__ import annotations
@@ -44,7 +45,7 @@ def _load():
         I32, I64, U32, U64 = (C.POINTER(C.c_int32), C.POINTER(C.c_int64), C.POINTER(C.c_uint32),
                               C.POINTER(C.c_uint64))
         lib.orc_create.restype = P
-        lib.orc_create.argtypes = [I, I32, I32, F, F, F, F, F, F, F, F, F, F, F, F, D, I, I, I]
+        lib.orc_create.argtypes = [I, I32, I32, F, F, F, F, F, F, F, F, F, F, F, F, D, I, I, I, I]
         lib.orc_destroy.argtypes = [P]
         lib.orc_step.argtypes = [P, I, I]
         lib.orc_step_subset.argtypes = [P, I, I32, I, I]
@@ -59,7 +60,7 @@ def _load():
         lib.orc_fk.restype = I
         lib.orc_dynamics.argtypes = [P, I, D, D, D, D]
         lib.orc_dynamics.restype = I
-        lib.orc_contacts.argtypes = [P, I, D, I, I32, I32, D, D, D, D]
+        lib.orc_contacts.argtypes = [P, I, D, I, I32, I32, D, D, D, D, I32]
         lib.orc_contacts.restype = I
         lib.orc_cholesky.argtypes = [I, D, D]
         lib.orc_cholesky.restype = I
@@ -124,7 +125,7 @@ class Oracle:
                                 f(k["mass"]), f(k["ap"]), f(k["ac"]), f(k["rq"]), f(k["axis"]), f(k["cpg"]),
                                 f(k["mu"]), f(k["q0"]), f(k["v0"]), f(k["rp"]),
                                 None if k["ball"] is None else f(k["ball"]), _p(k["prm"], C.c_double),
-                                self.root_fixed, K, precision)
+                                self.root_fixed, K, precision, int(bool(getattr(pop, "self_collision", False))))
         self._lib = lib
 
     def __del__(self):
@@ -211,12 +212,15 @@ class Oracle:
         m = max_contacts
         body = np.zeros(m, np.int32); corner = np.zeros(m, np.int32)
         x = np.zeros((m, 3)); d = np.zeros(m); J = np.zeros((m, 3, nv)); nrm = np.zeros((m, 3))
+        other = np.zeros(m, np.int32)
         n = self._lib.orc_contacts(self.h, vi, _p(q, C.c_double), m, _p(body, C.c_int32),
                                    _p(corner, C.c_int32), _p(x, C.c_double), _p(d, C.c_double),
-                                   _p(J, C.c_double), _p(nrm, C.c_double))
+                                   _p(J, C.c_double), _p(nrm, C.c_double), _p(other, C.c_int32))
         n = min(n, m)
-        # corner: 0..7 box corner on the plane, -1 ball on the plane, -2 ball on box `body`
-        return dict(body=body[:n], corner=corner[:n], x=x[:n], depth=d[:n], J=J[:n], normal=nrm[:n])
+        # corner: 0..7 box corner (on the plane, or inside box `other` >= 0), -1 ball on
+        # the plane, -2 ball on box `body`
+        return dict(body=body[:n], corner=corner[:n], x=x[:n], depth=d[:n], J=J[:n], normal=nrm[:n],
+                    other=other[:n])
 
     def variant_state(self, vi: int):
         q, v, k, s = self.get_state()

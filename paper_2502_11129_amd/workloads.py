@@ -31,7 +31,9 @@ Conventions of the model layout (shared by every consumer):
 * optionally every variant of a population carries one free solid sphere
   (``ball`` = [radius, mass] per variant, the box-and-ball scene): its
   position (centre, Q) follows the robot's coordinates in q and its world
-  angular velocity and centre velocity follow the robot's in v.
+  angular velocity and centre velocity follow the robot's in v;
+* ``self_collision`` adds contacts between the boxes of one robot that are
+  not joined by a hinge.
 """
 from __future__ import annotations
 
@@ -99,6 +101,7 @@ class Population:
     steps: int = 0                   # horizon T of the workload
     lifted: int = 0                  # boxes lifted off the plane at creation
     ball: np.ndarray | None = None   # float32 [N,2] (radius, mass) of each variant's ball, or None
+    self_collision: bool = False     # contacts between the boxes of one robot (not joined by a hinge)
 
     @property
     def n_variants(self) -> int:
@@ -145,7 +148,7 @@ class Population:
             q0=self.q0[qsel].copy(), v0=self.v0[vsel].copy(),
             root_pose=self.root_pose[idx].copy(), root_type=self.root_type,
             params=dict(self.params), name=self.name, steps=self.steps,
-            ball=None if self.ball is None else self.ball[idx].copy())
+            ball=None if self.ball is None else self.ball[idx].copy(), self_collision=self.self_collision)
 
 
 class _Builder:
@@ -406,6 +409,8 @@ def concat(pops) -> Population:
     has_ball = [p.ball is not None for p in pops]
     if any(has_ball) and not all(has_ball):
         raise ValueError("cannot mix populations with and without a ball")
+    if len(set(bool(p.self_collision) for p in pops)) > 1:
+        raise ValueError("cannot mix populations with and without self-collision")
     nb = np.concatenate([p.n_bodies for p in pops])
     cat = lambda a: np.concatenate([getattr(p, a) for p in pops])
     return Population(
@@ -415,7 +420,7 @@ def concat(pops) -> Population:
         rest_quat=cat("rest_quat"), axis=cat("axis"), cpg=cat("cpg"), mu=cat("mu"),
         q0=cat("q0"), v0=cat("v0"), root_pose=cat("root_pose"), root_type=p0.root_type,
         params=dict(p0.params), name="+".join(p.name for p in pops), steps=p0.steps,
-        ball=cat("ball") if all(has_ball) else None)
+        ball=cat("ball") if all(has_ball) else None, self_collision=p0.self_collision)
 
 
 # ----------------------------------------------------------------------------

@@ -31,11 +31,14 @@
 //
 // Optional self-collision (body-body contact between the boxes of one robot):
 // for every pair of boxes not joined by a hinge, each corner of either box
-// strictly inside the other is a contact whose normal is the outward normal
-// of the penetrated box's nearest face and whose depth is the distance to that
-// face (vertex-face contacts; two edges crossing with no corner inside are not
-// detected).  Rows act on the relative velocity (corner's box minus
-// penetrated box) at the corner.
+// strictly inside the other is a contact.  The pair shares one normal, the
+// separating-axis direction of least overlap (the 3 + 3 face normals and the 9
+// edge-pair cross products, near-parallel edge pairs skipped; first of equals),
+// oriented away from the penetrated box; a corner's depth is how far it lies
+// inside the penetrated box's extent along that normal.  Rows act on the
+// relative velocity (corner's box minus penetrated box) at the corner; a row
+// no degree of freedom can move (J M^-1 J^T < 1e-9) is inert.  Two edges
+// crossing with no corner inside are not detected.
 //
 // The library is templated on the scalar so a float instance can measure how
 // sensitive a trajectory is to single precision.  An RK4 mode (no contact, no
@@ -115,24 +118,46 @@ template <class T> void quat_exp(const V3<T>& phi, T* out) {
   }
 }
 
-// A point x strictly inside a box (centre p, rotation R, half extents h): the
-// box's face nearest to x (first of equal gaps in x, y, z order), its outward
-// normal R (+-e_k) normalised, and the distance to it.
-template <class T> bool corner_in_box(const V3<T>& x, const V3<T>& p, const M3<T>& R, const V3<T>& h, V3<T>& n,
-                                      T& depth) {
+// A point x strictly inside a box (centre p, rotation R, half extents h).
+template <class T> bool point_in_box(const V3<T>& x, const V3<T>& p, const M3<T>& R, const V3<T>& h) {
   V3<T> l = mtv(R, sub(x, p));
   for (int k = 0; k < 3; ++k)
     if (!(std::abs(l[k]) < h[k])) return false;
-  int kb = 0;
-  T gap = h[0] - std::abs(l[0]);
-  for (int k = 1; k < 3; ++k)
-    if (h[k] - std::abs(l[k]) < gap) { gap = h[k] - std::abs(l[k]); kb = k; }
-  V3<T> nl{0, 0, 0};
-  nl[kb] = l[kb] >= 0 ? T(1) : T(-1);
-  n = mv(R, nl);
-  n = scl(n, T(1) / std::sqrt(dot(n, n)));
-  depth = gap;
   return true;
+}
+
+// Half-width of a box (rotation R, half extents h) along a unit direction u.
+template <class T> T box_radius(const M3<T>& R, const V3<T>& h, const V3<T>& u) {
+  T r = 0;
+  for (int k = 0; k < 3; ++k) r += h[k] * std::abs(u[0] * R[k] + u[1] * R[3 + k] + u[2] * R[6 + k]);
+  return r;
+}
+
+// Separating-axis direction of least overlap between boxes P and Q: axes
+// P's face normals (columns of RP), Q's, then cross products of P's column i
+// with Q's column j (i-major), normalised, skipped when |cross|^2 < 1e-6;
+// overlap = rP + rQ - |u . (pP - pQ)|; the first smallest wins; the result
+// points from Q towards P (+ when u . (pP - pQ) = 0).
+template <class T> V3<T> sat_axis(const V3<T>& pP, const M3<T>& RP, const V3<T>& hP, const V3<T>& pQ,
+                                  const M3<T>& RQ, const V3<T>& hQ) {
+  const V3<T> d = sub(pP, pQ);
+  V3<T> best{0, 0, 1};
+  T best_o = T(INFINITY);
+  auto consider = [&](V3<T> u) {
+    T o = box_radius(RP, hP, u) + box_radius(RQ, hQ, u) - std::abs(dot(u, d));
+    if (o < best_o) { best_o = o; best = u; }
+  };
+  for (int k = 0; k < 3; ++k) consider(V3<T>{RP[k], RP[3 + k], RP[6 + k]});
+  for (int k = 0; k < 3; ++k) consider(V3<T>{RQ[k], RQ[3 + k], RQ[6 + k]});
+  for (int i = 0; i < 3; ++i)
+    for (int j = 0; j < 3; ++j) {
+      V3<T> c = cross(V3<T>{RP[i], RP[3 + i], RP[6 + i]}, V3<T>{RQ[j], RQ[3 + j], RQ[6 + j]});
+      T n2 = dot(c, c);
+      if (n2 < T(1e-6)) continue;
+      consider(scl(c, T(1) / std::sqrt(n2)));
+    }
+  if (dot(best, d) < 0) best = scl(best, T(-1));
+  return best;
 }
 
 // ----------------------------------------------------------------------------
@@ -497,6 +522,7 @@ template <class T> struct Sim {
       for (int a = 0; a < nb; ++a)
         for (int b = a + 1; b < nb; ++b) {
           if (V.bodies[b].parent == a) continue;
+          const std::size_t first = out.size();
           for (int side = 0; side < 2; ++side) {
             const int pb = side ? b : a, qb = side ? a : b;
             const Body<T>& BP = V.bodies[pb];
@@ -504,15 +530,23 @@ template <class T> struct Sim {
               V3<T> sc = {(c & 1) ? BP.half[0] : -BP.half[0], (c & 2) ? BP.half[1] : -BP.half[1],
                           (c & 4) ? BP.half[2] : -BP.half[2]};
               V3<T> x = add(kin.p[pb], mv(kin.R[pb], sc));
-              V3<T> n;
-              T depth;
-              if (corner_in_box(x, kin.p[qb], kin.R[qb], V.bodies[qb].half, n, depth)) {
+              if (point_in_box(x, kin.p[qb], kin.R[qb], V.bodies[qb].half)) {
                 Contact C;
                 C.body = pb; C.other = qb; C.corner = c; C.kind = 3;
-                C.x = x; C.n = n; C.depth = depth;
+                C.x = x;
                 out.push_back(std::move(C));
               }
             }
+          }
+          if (out.size() == first) continue;
+          // the pair's normal (from b towards a) and each corner's depth along it
+          const V3<T> u = sat_axis(kin.p[a], kin.R[a], V.bodies[a].half, kin.p[b], kin.R[b], V.bodies[b].half);
+          for (std::size_t k = first; k < out.size(); ++k) {
+            Contact& C = out[k];
+            C.n = C.body == a ? u : scl(u, T(-1));
+            const int q = C.other;
+            const T support = dot(C.n, kin.p[q]) + box_radius(kin.R[q], V.bodies[q].half, C.n);
+            C.depth = support - dot(C.n, C.x);
           }
         }
     }
@@ -575,6 +609,9 @@ template <class T> struct Sim {
     // 5. contacts and their rows
     std::vector<Contact> C;
     detect(V, kin, C);
+    int nself = 0;
+    for (const auto& ct : C) nself += ct.kind == 3;
+    if (nself > 256) { S.status |= 4u; return; }  // more self-collision contacts than allowed: frozen
     std::vector<T> Jp(3 * nv);
     const int rowsel[3] = {2, 0, 1};  // normal = world z, then world x, y
     for (auto& ct : C) {
@@ -617,6 +654,7 @@ template <class T> struct Sim {
         Delta[j] = nd;
       }
       for (auto& ct : C) {             // (ii) contacts
+        if (ct.kind == 3 && !(ct.D[0] >= T(1e-9))) continue;  // a self-contact row nothing can move
         T u = dotv(ct.J[0]);
         T u0 = u - dt * ct.D[0] * ct.lam[0];
         T ln = (kc * ct.depth - kb * u0) / (ct.D[0] * (1 + kb * dt));
@@ -626,6 +664,10 @@ template <class T> struct Sim {
         T ux = dotv(ct.J[1]), uy = dotv(ct.J[2]);
         T gx = ct.lam[1] - ux / (dt * ct.D[1]);
         T gy = ct.lam[2] - uy / (dt * ct.D[2]);
+        if (ct.kind == 3) {  // self-contact friction rows nothing can move stay inert
+          if (!(ct.D[1] >= T(1e-9))) gx = 0;
+          if (!(ct.D[2] >= T(1e-9))) gy = 0;
+        }
         T gn = std::sqrt(gx * gx + gy * gy), lim = V.mu * ln;
         if (gn > lim) { gx *= lim / gn; gy *= lim / gn; }
         for (int k = 0; k < nv; ++k) vp[k] += dt * (ct.W[1][k] * (gx - ct.lam[1]) + ct.W[2][k] * (gy - ct.lam[2]));

@@ -54,6 +54,7 @@ extern "C" {
 
 /* Status bits of a variant. */
 #define SIM_STATUS_NONFINITE 1u /* a non-finite value appeared; variant frozen  */
+#define SIM_STATUS_CONTACTS 4u  /* more than 256 self-collision contacts; frozen */
 
 /*
  * Model descriptor.  All arrays are host memory in variant-CSR layout:
@@ -83,6 +84,18 @@ extern "C" {
  *                       Coulomb friction on the relative velocity.  The
  *                       DoF total (ball included) must stay <= 28;
  *                       single_launch does not cover ball populations.
+ *  self_collision       != 0: contacts between the boxes of one robot that
+ *                       are not joined by a hinge: every corner of either
+ *                       box strictly inside the other (after the box-plane
+ *                       corners, pairs a < b in order, corners of a then of
+ *                       b), normal the outward normal of the penetrated
+ *                       box's nearest face, depth the distance to it, rows
+ *                       on the relative velocity (corner's box minus
+ *                       penetrated box) with the same soft normal and
+ *                       Coulomb disk.  Two edges crossing with no corner
+ *                       inside are not detected.  A variant with more than
+ *                       256 such contacts in a step freezes with
+ *                       SIM_STATUS_CONTACTS.  Not combined with a ball.
  * Per-model constants: PD gains kp, kd (actuator torque limit tau_max), soft
  * contact stiffness and damping in acceleration units per contact row,
  * time step dt, gravity vector, and the solver sweep count pgs_iters (part
@@ -108,6 +121,7 @@ typedef struct {
   float gravity[3];
   int32_t pgs_iters;
   const float* ball;
+  int32_t self_collision;
 } sim_model_desc;
 
 /*
@@ -228,8 +242,9 @@ int sim_variant_bins(const sim_handle* h, int32_t* bin);
 int sim_launch_times(const sim_handle* h, int32_t* n_bins, float* ms, int32_t* launches, int32_t max_bins);
 
 /* The compiled kernel variants: per variant (nv capacity, body capacity,
- * contacts in registers, 1 if its variants carry a ball).  info has
- * 4*max_variants ints; *n receives the total count.  Host only. */
+ * contacts in registers, 1 if its variants carry a ball, 1 if it handles
+ * self-collision).  info has 5*max_variants ints; *n receives the total
+ * count.  Host only. */
 int sim_kernel_variants(int32_t* n, int32_t* info, int32_t max_variants);
 
 /*

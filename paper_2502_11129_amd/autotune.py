@@ -34,9 +34,9 @@ def _time_rollout(pop, T, reps, **opts):
     return best, bins
 
 
-def candidates_ncr(nvc, ball=False):
+def candidates_ncr(nvc, ball=False, self_collision=False):
     """Compiled contact-register budgets for a DoF capacity (any body capacity)."""
-    return sorted({k[2] for k in S.kernel_variants(ball) if k[0] == nvc})
+    return sorted({k[2] for k in S.kernel_variants(ball, self_collision) if k[0] == nvc})
 
 
 def autotune(pop, T_pilot=1000, reps=2, log=None, cache=None):
@@ -65,7 +65,8 @@ def autotune(pop, T_pilot=1000, reps=2, log=None, cache=None):
     def descend(best, best_t):
         """Coordinate descent from a starting point: streams, launch length,
         then the contact budget of each DoF capacity present."""
-        single = [] if getattr(pop, "ball", None) is not None else [True]   # no multi-bin ball kernel
+        special = getattr(pop, "ball", None) is not None or bool(getattr(pop, "self_collision", False))
+        single = [] if special else [True]   # the multi-bin kernel has no ball or self-collision families
         for name, values in (("single_launch", single), ("streams", [4, 2, 1]), ("steps_per_launch", [250, 500])):
             for v in values:
                 cand = dict(best, **{name: v})
@@ -81,7 +82,8 @@ def autotune(pop, T_pilot=1000, reps=2, log=None, cache=None):
         nvcs = sorted({b[0] for b in probe.bins()})
         probe.close()
         for nvc in nvcs:
-            for ncr in candidates_ncr(nvc, getattr(pop, "ball", None) is not None):
+            for ncr in candidates_ncr(nvc, getattr(pop, "ball", None) is not None,
+                                      bool(getattr(pop, "self_collision", False))):
                 if ncr == best["ncr_by_nvc"].get(nvc):
                     continue
                 cand = dict(best, ncr_by_nvc={**best["ncr_by_nvc"], nvc: ncr})

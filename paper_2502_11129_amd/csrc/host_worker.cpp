@@ -4,7 +4,9 @@
 // The dense system is factorised by Cholesky here (a serial CPU has no reason
 // to form the inverse); clamp-row columns are solved only when a clamp engages.
 // A ball (when the variant has one) adds six DoFs after the robot's (world
-// spin, centre velocity), a ball-plane contact and ball-box contacts.
+// spin, centre velocity), a ball-plane contact and ball-box contacts;
+// self-collision adds the corners of a box strictly inside another box of the
+// same robot not joined to it by a hinge.
 #include "host_worker.hpp"
 
 #include <cmath>
@@ -123,6 +125,38 @@ bool sphere_box(V3 c, float r, V3 p, const M3& R, V3 h, V3& x, V3& n, float& dep
   }
   x = c - n * r;
   return true;
+}
+
+// A point strictly inside a box.
+bool point_in_box(V3 x, V3 p, const M3& R, V3 h) {
+  const V3 l = mtv(R, x - p);
+  return std::fabs(l.x) < h.x && std::fabs(l.y) < h.y && std::fabs(l.z) < h.z;
+}
+V3 column(const M3& R, int k) { return v3(R.m[k], R.m[3 + k], R.m[6 + k]); }
+float box_radius(const M3& R, V3 h, V3 u) {
+  return h.x * std::fabs(dotp(u, column(R, 0))) + h.y * std::fabs(dotp(u, column(R, 1))) +
+         h.z * std::fabs(dotp(u, column(R, 2)));
+}
+// Least-overlap separating axis of boxes P and Q (faces of P, of Q, edge
+// crosses with |cross|^2 >= 1e-6), pointing from Q to P.
+V3 sat_axis(V3 pP, const M3& RP, V3 hP, V3 pQ, const M3& RQ, V3 hQ) {
+  const V3 d = pP - pQ;
+  V3 best = v3(0, 0, 1);
+  float best_o = INFINITY;
+  auto consider = [&](V3 u) {
+    const float o = box_radius(RP, hP, u) + box_radius(RQ, hQ, u) - std::fabs(dotp(u, d));
+    if (o < best_o) { best_o = o; best = u; }
+  };
+  for (int k = 0; k < 3; ++k) consider(column(RP, k));
+  for (int k = 0; k < 3; ++k) consider(column(RQ, k));
+  for (int i = 0; i < 3; ++i)
+    for (int j = 0; j < 3; ++j) {
+      const V3 c = crs(column(RP, i), column(RQ, j));
+      const float n2 = dotp(c, c);
+      if (n2 < 1e-6f) continue;
+      consider(c * (1.f / std::sqrt(n2)));
+    }
+  return dotp(best, d) < 0.f ? best * -1.f : best;
 }
 
 bool step(const HostVariantView& m, const ModelParams& P, HostVariantState& st, Work& wk) {
@@ -271,11 +305,11 @@ bool step(const HostVariantView& m, const ModelParams& P, HostVariantState& st, 
   }
   chol_solve(nv, wk.L, rhs, wk.vf);
   for (int d = 0; d < nv; ++d) wk.vf[d] += v[d];
-  // contacts: rows (n, t1, t2) of the relative velocity, robot part with sign
-  // `robot` (+1 box corner on the plane, -1 box under the ball, 0 none) on the
-  // contact body's path, ball part with sign `bsign`
+  // contacts: rows (n, t1, t2) of the relative velocity; a robot DoF's sign
+  // is its body's bit in `plus` minus its bit in `minus` (root DoFs: body 0),
+  // the ball's DoFs take `bsign`
   int nc = 0;
-  auto add_contact = [&](V3 x, V3 n, float depth, unsigned anc, float robot, float bsign) {
+  auto add_contact = [&](V3 x, V3 n, float depth, unsigned plus, unsigned minus, float bsign, bool guard = false) {
     if (nc >= wk.ncap) {
       wk.ncap = nc + 16;
       wk.J.resize((size_t)wk.ncap * 3 * NV);
@@ -287,13 +321,14 @@ bool step(const HostVariantView& m, const ModelParams& P, HostVariantState& st, 
     float* sc = &wk.scal[(size_t)nc * 10];
     V3 t1, t2;
     tangent_pair(n, t1, t2);
+    auto sign = [&](int b) { return (float)((int)((plus >> b) & 1u) - (int)((minus >> b) & 1u)); };
     for (int d = 0; d < nv; ++d) {
       V3 col;
-      if (r0 && d < 3) col = crs(v3(R0.m[d], R0.m[3 + d], R0.m[6 + d]), x - P0) * robot;
-      else if (r0 && d < 6) col = v3(R0.m[d - 3], R0.m[3 + d - 3], R0.m[6 + d - 3]) * robot;
+      if (r0 && d < 3) col = crs(v3(R0.m[d], R0.m[3 + d], R0.m[6 + d]), x - P0) * sign(0);
+      else if (r0 && d < 6) col = v3(R0.m[d - 3], R0.m[3 + d - 3], R0.m[6 + d - 3]) * sign(0);
       else if (d < nvr) {
         const int hb = d - r0 + 1;
-        col = ((anc >> hb) & 1u) ? crs(wk.w[hb], x - wk.o[hb]) * robot : v3(0, 0, 0);
+        col = crs(wk.w[hb], x - wk.o[hb]) * sign(hb);
       } else {
         const int k = d - nvr;
         const V3 e = v3(k % 3 == 0 ? 1.f : 0.f, k % 3 == 1 ? 1.f : 0.f, k % 3 == 2 ? 1.f : 0.f);
@@ -314,6 +349,11 @@ bool step(const HostVariantView& m, const ModelParams& P, HostVariantState& st, 
     sc[3] = 1.f / (dt * D[1]);
     sc[4] = 1.f / (dt * D[2]);
     sc[5] = sc[6] = sc[7] = 0.f;
+    if (guard) {  // a self-contact row no DoF can move is inert (zero gain)
+      if (!(D[0] >= 1e-9f)) sc[1] = 0.f;
+      if (!(D[1] >= 1e-9f)) sc[3] = 0.f;
+      if (!(D[2] >= 1e-9f)) sc[4] = 0.f;
+    }
     ++nc;
   };
   for (int b = (r0 ? 0 : 1); b < nb; ++b) {
@@ -324,13 +364,48 @@ bool step(const HostVariantView& m, const ModelParams& P, HostVariantState& st, 
       const V3 s = v3((cn & 1) ? h.x : -h.x, (cn & 2) ? h.y : -h.y, (cn & 4) ? h.z : -h.z);
       const V3 x = wk.p[b] + mv(wk.R[b], s);
       if (!(x.z < 0.f)) continue;
-      add_contact(x, v3(0, 0, 1), -x.z, anc, 1.f, 0.f);
+      add_contact(x, v3(0, 0, 1), -x.z, anc, 0u, 0.f);
+    }
+  }
+  if (m.self_collision) {
+    // pairs a < b not joined by a hinge: corners of a inside b, then of b inside a
+    int nself = 0;
+    auto half = [&](int b) { return v3(B(b, BW_HALF), B(b, BW_HALF + 1), B(b, BW_HALF + 2)); };
+    for (int a = 0; a < nb; ++a)
+      for (int b = a + 1; b < nb; ++b) {
+        if (Bi(b, BW_PARENT) == a) continue;
+        V3 u{0, 0, 0};
+        bool have_u = false;
+        for (int side = 0; side < 2; ++side) {
+          const int pb = side ? b : a, qb = side ? a : b;
+          const V3 hp = half(pb), hq = half(qb);
+          unsigned ancp, ancq;
+          { int x0 = Bi(pb, BW_ANCESTORS); std::memcpy(&ancp, &x0, 4); }
+          { int x0 = Bi(qb, BW_ANCESTORS); std::memcpy(&ancq, &x0, 4); }
+          for (int cn = 0; cn < 8; ++cn) {
+            const V3 s = v3((cn & 1) ? hp.x : -hp.x, (cn & 2) ? hp.y : -hp.y, (cn & 4) ? hp.z : -hp.z);
+            const V3 x = wk.p[pb] + mv(wk.R[pb], s);
+            if (!point_in_box(x, wk.p[qb], wk.R[qb], hq)) continue;
+            if (!have_u) {  // the pair's normal, from b towards a
+              u = sat_axis(wk.p[a], wk.R[a], half(a), wk.p[b], wk.R[b], half(b));
+              have_u = true;
+            }
+            const V3 n = side ? u * -1.f : u;
+            const float depth = dotp(n, wk.p[qb]) + box_radius(wk.R[qb], hq, n) - dotp(n, x);
+            add_contact(x, n, depth, ancp, ancq, 0.f, true);
+            ++nself;
+          }
+        }
+      }
+    if (nself > kMaxSelfContacts) {
+      st.status |= 4u;
+      return true;  // frozen, state unchanged
     }
   }
   if (ball) {
     if (cb.z - rball < 0.f) {
       const V3 x = v3(cb.x, cb.y, cb.z - rball);
-      add_contact(x, v3(0, 0, 1), -x.z, 0u, 0.f, 1.f);
+      add_contact(x, v3(0, 0, 1), -x.z, 0u, 0u, 1.f);
     }
     for (int b = 0; b < nb; ++b) {
       V3 x, n;
@@ -339,7 +414,7 @@ bool step(const HostVariantView& m, const ModelParams& P, HostVariantState& st, 
         continue;
       unsigned anc;
       { int xi = Bi(b, BW_ANCESTORS); std::memcpy(&anc, &xi, 4); }
-      add_contact(x, n, depth, anc, -1.f, 1.f);
+      add_contact(x, n, depth, 0u, anc, 1.f);
     }
   }
   // fixed-iteration Gauss-Seidel
@@ -458,6 +533,7 @@ void host_rollout(const HostVariantView& m, const ModelParams& P, int T, HostVar
       st.status |= 1u;
       break;
     }
+    if (st.status) break;
   }
 }
 

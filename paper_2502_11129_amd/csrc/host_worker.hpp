@@ -17,6 +17,7 @@ struct HostVariantView {
   const float* body;     // nbc * BW_WORDS
   const float* q0;       // kQStride
   const float* v0;       // kVStride
+  int self_collision;    // contacts between the boxes of the robot
 };
 
 struct HostVariantState {

@@ -13,6 +13,7 @@ struct KernelVariant {
   int sb;    // body slots per lane (body capacity 16 * sb)
   int ncr;   // contacts whose solver rows stay in registers
   int ball;  // 1: variants carry a ball (box-and-ball scene)
+  int self;  // 1: contacts between the boxes of one robot
   launch_fn fn;
 };
 

@@ -29,6 +29,12 @@
 // contact and ball-box contacts (closest box point, or the nearest face when
 // the centre is inside a box), whose rows project the relative velocity ball
 // minus box on the normal and two tangents.
+// Self-collision kernels (SELF = true) add, after the corner list, every
+// corner of a box strictly inside another box of the same robot not joined
+// to it by a hinge (pairs in order, a bounding-sphere test first); a pair
+// shares the least-overlap separating-axis normal, a corner's depth is its
+// distance inside the other box's extent along it, rows act on the relative
+// velocity, and a row no DoF can move is inert.
 #pragma once
 #include <hip/hip_runtime.h>
 #include <stdint.h>
@@ -165,7 +171,7 @@ __device__ __forceinline__ sv imul(const sinertia& J, const sv& V) {
 // ----------------------------------------------------------------------------
 // Per-variant LDS area.
 // ----------------------------------------------------------------------------
-template <int NVC, int SB, int NCR, bool BALL = false>
+template <int NVC, int SB, int NCR, bool BALL = false, bool SELF = false>
 struct alignas(16) GroupLds {
   static constexpr int NBC = 16 * SB;
   static constexpr int MST = NVC + 1;                 // padded row stride of the matrices
@@ -177,7 +183,7 @@ struct alignas(16) GroupLds {
   float WO[NBC][12];        // hinge axis w, anchor o (world), composite force C S of the hinge
   int par[NBC];
   int ccount[NBC];          // active-corner mask per body
-  float cl[NCR][BALL ? kListWordsBall : kListWords];  // contact list entries (ListWord)
+  float cl[NCR][(BALL || SELF) ? kListWordsBall : kListWords];  // contact list entries (ListWord)
   float cs[NCR][12];        // per-contact solver scalars
   float th[NVC], thd[NVC];  // theta / thetadot by DoF
   float cvec[NVC];          // bias c by DoF
@@ -269,27 +275,31 @@ __device__ __forceinline__ void tangents(f3 n, f3& t1, f3& t2) {
   t2 = mk(b, sign + n.y * n.y * a, -n.y);
 }
 
-// Rows of one contact of a ball kernel: kind 0 box corner on the plane (the
-// box's path, +1), 1 ball on the plane (the ball's DoFs, +1), 2 ball on a box
-// (ball +1, the box's path -1); normal n and tangents t1, t2; depth d.
-// bodyOfDof: -1 root DoF, -2 ball DoF, else the hinge's body.
+// Rows of one contact of a ball or self-collision kernel: the relative
+// velocity (point of the bodies in `plus` minus point of the bodies in
+// `minus`, plus the ball's point when `ball`) projected on the normal n and
+// tangents t1, t2; depth d.  A DoF's sign is its body's bit in plus minus its
+// bit in minus (root DoFs count as body 0, the core).  bodyOfDof: -1 root or
+// padding DoF, -2 ball DoF, else the hinge's body.
 template <int S, int NVC>
-__device__ __forceinline__ void build_rows_ball(const float (&Mi)[S][NVC], const f3 (&ang)[S], const f3 (&cst)[S],
-                                                const int (&bodyOfDof)[S], f3 x, f3 n, float depth, unsigned anc,
-                                                int kind, float kc, float kb, float dt, float (&Jn)[S],
-                                                float (&Jx)[S], float (&Jy)[S], float (&Wn)[S], float (&Wx)[S],
-                                                float (&Wy)[S], float (&scal)[10]) {
+__device__ __forceinline__ void build_rows_gen(const float (&Mi)[S][NVC], const f3 (&ang)[S], const f3 (&cst)[S],
+                                               const int (&bodyOfDof)[S], f3 x, f3 n, float depth, unsigned plus,
+                                               unsigned minus, bool ball, bool guard, float kc, float kb, float dt,
+                                               float (&Jn)[S], float (&Jx)[S], float (&Jy)[S], float (&Wn)[S],
+                                               float (&Wx)[S], float (&Wy)[S], float (&scal)[10]) {
   f3 t1, t2;
   tangents(n, t1, t2);
-  const float robot = kind == 0 ? 1.f : (kind == 2 ? -1.f : 0.f);
-  const float ballc = kind >= 1 ? 1.f : 0.f;
   float nJn[S], nJx[S], nJy[S];
 #pragma unroll
   for (int s = 0; s < S; ++s) {
     const int bd = bodyOfDof[s];
     float coef;
-    if (bd == -2) coef = ballc;
-    else coef = (bd < 0 || ((anc >> bd) & 1u)) ? robot : 0.f;
+    if (bd == -2) {
+      coef = ball ? 1.f : 0.f;
+    } else {
+      const int b = bd < 0 ? 0 : bd;
+      coef = (float)((int)((plus >> b) & 1u) - (int)((minus >> b) & 1u));
+    }
     const f3 J = (cross3(ang[s], x) + cst[s]) * coef;
     Jn[s] = dot3(n, J);
     Jx[s] = dot3(t1, J);
@@ -319,19 +329,75 @@ __device__ __forceinline__ void build_rows_ball(const float (&Mi)[S][NVC], const
   scal[7] = 0.f;
   scal[8] = 0.f;
   scal[9] = 0.f;
+  // a self-contact row no DoF can move is inert: a zero gain keeps its
+  // multiplier at 0 (the normal's 0 also zeroes the friction limit)
+  if (guard) {
+    if (!(Dn >= 1e-9f)) scal[1] = 0.f;
+    if (!(Dx >= 1e-9f)) scal[5] = 0.f;
+    if (!(Dy >= 1e-9f)) scal[6] = 0.f;
+  }
 }
 
 // One contact list entry (ListWord layout); plane-only kernels store the
 // first four words.
-template <bool BALL>
-__device__ __forceinline__ void put_contact(float* e, f3 x, unsigned anc, f3 n, float depth, int kind) {
+template <bool GEN>
+__device__ __forceinline__ void put_contact(float* e, f3 x, unsigned plus, unsigned minus, f3 n, float depth,
+                                            int kind) {
   e[CL_X] = x.x; e[CL_X + 1] = x.y; e[CL_X + 2] = x.z;
-  e[CL_ANC] = __uint_as_float(anc);
-  if (BALL) {
+  e[CL_ANC] = __uint_as_float(plus);
+  if (GEN) {
     e[CL_N] = n.x; e[CL_N + 1] = n.y; e[CL_N + 2] = n.z;
     e[CL_DEPTH] = depth;
     e[CL_KIND] = (float)kind;
+    e[CL_MINUS] = __uint_as_float(minus);
   }
+}
+
+// A point x strictly inside a box (centre p, rotation R, half extents h).
+__device__ __forceinline__ bool point_in_box(f3 x, f3 p, const m33& R, f3 h) {
+  const f3 l = mulT(R, x - p);
+  return fabsf(l.x) < h.x && fabsf(l.y) < h.y && fabsf(l.z) < h.z;
+}
+
+// Half-width of a box (rotation R, half extents h) along a unit direction u.
+__device__ __forceinline__ float box_radius(const m33& R, f3 h, f3 u) {
+  return h.x * fabsf(u.x * R.m[0] + u.y * R.m[3] + u.z * R.m[6]) +
+         h.y * fabsf(u.x * R.m[1] + u.y * R.m[4] + u.z * R.m[7]) +
+         h.z * fabsf(u.x * R.m[2] + u.y * R.m[5] + u.z * R.m[8]);
+}
+
+// Least-overlap separating axis of boxes P and Q (P's face normals, Q's, then
+// the cross products of P's column i with Q's column j, normalised, skipped
+// when |cross|^2 < 1e-6; first smallest overlap wins), pointing from Q to P.
+__device__ __forceinline__ f3 sat_axis(f3 pP, const m33& RP, f3 hP, f3 pQ, const m33& RQ, f3 hQ) {
+  const f3 d = pP - pQ;
+  f3 best = mk(0.f, 0.f, 1.f);
+  float best_o = __int_as_float(0x7f800000);
+  auto consider = [&](f3 u) {
+    const float o = box_radius(RP, hP, u) + box_radius(RQ, hQ, u) - fabsf(dot3(u, d));
+    if (o < best_o) { best_o = o; best = u; }
+  };
+#pragma unroll
+  for (int k = 0; k < 3; ++k) consider(mcol(RP, k));
+#pragma unroll
+  for (int k = 0; k < 3; ++k) consider(mcol(RQ, k));
+#pragma unroll
+  for (int i = 0; i < 3; ++i)
+#pragma unroll
+    for (int j = 0; j < 3; ++j) {
+      const f3 c = cross3(mcol(RP, i), mcol(RQ, j));
+      const float n2 = dot3(c, c);
+      if (n2 < 1e-6f) continue;
+      consider(c * (1.f / sqrtf(n2)));
+    }
+  return dot3(best, d) < 0.f ? best * -1.f : best;
+}
+
+// Corner c (bits x, y, z = signs) of a box with pose (R, p) and half extents h.
+__device__ __forceinline__ f3 box_corner(const m33& R, f3 p, f3 h, int c) {
+  const f3 s = mk((c & 1) ? h.x : -h.x, (c & 2) ? h.y : -h.y, (c & 4) ? h.z : -h.z);
+  return mk(p.x + R.m[0] * s.x + R.m[1] * s.y + R.m[2] * s.z, p.y + R.m[3] * s.x + R.m[4] * s.y + R.m[5] * s.z,
+            p.z + R.m[6] * s.x + R.m[7] * s.y + R.m[8] * s.z);
 }
 
 // Sphere (centre c, radius r) against a box (centre p, rotation R, half
@@ -422,14 +488,15 @@ struct WavesPerSimd {
 
 // One workgroup (one wave, four variants) of a bin: `block` is the
 // workgroup's index within the bin, lds_all the four variants' LDS areas.
-template <int NVC, int SB, int NCR, bool BALL = false>
+template <int NVC, int SB, int NCR, bool BALL = false, bool SELF = false>
 __device__ __forceinline__ void rollout_body(const BinArgs& a, const ModelParams& P, int block,
-                                             GroupLds<NVC, SB, NCR, BALL>* lds_all) {
+                                             GroupLds<NVC, SB, NCR, BALL, SELF>* lds_all) {
   constexpr int S = (NVC + 15) / 16;
   constexpr int NBC = 16 * SB;
-  constexpr int MAXC = max_contacts(NBC, BALL);
-  constexpr int CLW = BALL ? kListWordsBall : kListWords;
-  using L = GroupLds<NVC, SB, NCR, BALL>;
+  constexpr int MAXC = max_contacts(NBC, BALL, SELF);
+  constexpr bool GEN = BALL || SELF;  // general contact entries and rows
+  constexpr int CLW = GEN ? kListWordsBall : kListWords;
+  using L = GroupLds<NVC, SB, NCR, BALL, SELF>;
   constexpr int MST = L::MST;
 
   const int lane = threadIdx.x & 15;
@@ -626,13 +693,82 @@ __device__ __forceinline__ void rollout_body(const BinArgs& a, const ModelParams
                                 pr[10] + pr[3] * sv3.x + pr[4] * sv3.y + pr[5] * sv3.z,
                                 pr[11] + pr[6] * sv3.x + pr[7] * sv3.y + pr[8] * sv3.z);
                 const f3 up = mk(0.f, 0.f, 1.f);
-                if (idx < NCR) put_contact<BALL>(&sh.cl[idx][0], x, anc, up, -x.z, 0);
-                else put_contact<BALL>(&ovf_list[idx * CLW], x, anc, up, -x.z, 0);
+                if (idx < NCR) put_contact<GEN>(&sh.cl[idx][0], x, anc, 0u, up, -x.z, 0);
+                else put_contact<GEN>(&ovf_list[idx * CLW], x, anc, 0u, up, -x.z, 0);
                 ++idx;
               }
             }
           }
         }
+      }
+    }
+    int nself = 0;
+    if (SELF) {
+      // pairs (a, b), a < b, not joined by a hinge, in order; for each a the
+      // lanes take b = a + 1 + lane (+16); a bounding-sphere test first, then
+      // the corners of a inside b and the corners of b inside a; the hits are
+      // placed by a DPP prefix scan
+      for (int ia = 0; ia < nb - 1; ++ia) {
+        const float* pa = &sh.A[ia * 24];
+        m33 Ra;
+#pragma unroll
+        for (int k2 = 0; k2 < 9; ++k2) Ra.m[k2] = pa[k2];
+        const f3 Pa = mk(pa[9], pa[10], pa[11]);
+        const float* reca = bodyv + (size_t)ia * BW_WORDS;
+        const f3 ha = mk(reca[BW_HALF], reca[BW_HALF + 1], reca[BW_HALF + 2]);
+        const unsigned anca = __float_as_uint(reca[BW_ANCESTORS]);
+#pragma unroll
+        for (int t = 0; t < SB; ++t) {
+          const int ib = ia + 1 + lane + 16 * t;
+          unsigned hits = 0u;  // bits 0..7: corners of a in b, 8..15: corners of b in a
+          m33 Rb;
+#pragma unroll
+          for (int k2 = 0; k2 < 9; ++k2) Rb.m[k2] = 0.f;
+          f3 Pb = mk(0.f, 0.f, 0.f), hb = Pb;
+          unsigned ancb = 0u;
+          if (ib < nb && sh.par[ib] != ia) {
+            const float* pb = &sh.A[ib * 24];
+#pragma unroll
+            for (int k2 = 0; k2 < 9; ++k2) Rb.m[k2] = pb[k2];
+            Pb = mk(pb[9], pb[10], pb[11]);
+            const float* recb = bodyv + (size_t)ib * BW_WORDS;
+            hb = mk(recb[BW_HALF], recb[BW_HALF + 1], recb[BW_HALF + 2]);
+            ancb = __float_as_uint(recb[BW_ANCESTORS]);
+            const f3 d = Pb - Pa;
+            const float rr = sqrtf(dot3(ha, ha)) + sqrtf(dot3(hb, hb));
+            if (dot3(d, d) <= rr * rr * 1.0001f) {  // conservative: every hit passes
+              for (int c = 0; c < 8; ++c)
+                if (point_in_box(box_corner(Ra, Pa, ha, c), Pb, Rb, hb)) hits |= 1u << c;
+              for (int c = 0; c < 8; ++c)
+                if (point_in_box(box_corner(Rb, Pb, hb, c), Pa, Ra, ha)) hits |= 1u << (8 + c);
+            }
+          }
+          const int cnt = __builtin_popcount(hits);
+          const int incl = row_scan_incl(cnt);
+          if (hits) {
+            int idx = nc + incl - cnt;
+            const f3 u = sat_axis(Pa, Ra, ha, Pb, Rb, hb);  // from b towards a
+            for (int c = 0; c < 16; ++c) {
+              if (!((hits >> c) & 1u)) continue;
+              const bool aside = c < 8;  // a corner of a inside b
+              const f3 x = aside ? box_corner(Ra, Pa, ha, c) : box_corner(Rb, Pb, hb, c - 8);
+              const f3 n = aside ? u : u * -1.f;
+              const float depth = aside ? dot3(n, Pb) + box_radius(Rb, hb, n) - dot3(n, x)
+                                        : dot3(n, Pa) + box_radius(Ra, ha, n) - dot3(n, x);
+              const unsigned plus = aside ? anca : ancb, minus = aside ? ancb : anca;
+              if (idx < NCR) put_contact<GEN>(&sh.cl[idx][0], x, plus, minus, n, depth, 3);
+              else if (idx < MAXC) put_contact<GEN>(&ovf_list[idx * CLW], x, plus, minus, n, depth, 3);
+              ++idx;
+            }
+          }
+          const int tot = row_bcast_i<15>(incl);
+          nc += tot;
+          nself += tot;
+        }
+      }
+      if (nself > kMaxSelfContacts) {  // row-uniform: more than the list holds, freeze
+        status |= 4u;
+        break;
       }
     }
     if (BALL) {
@@ -642,8 +778,8 @@ __device__ __forceinline__ void rollout_body(const BinArgs& a, const ModelParams
       if (cb.z - rball < 0.f) {
         if (lane == 0) {
           const f3 x = mk(cb.x, cb.y, cb.z - rball);
-          if (nc < NCR) put_contact<BALL>(&sh.cl[nc][0], x, 0u, mk(0.f, 0.f, 1.f), -x.z, 1);
-          else put_contact<BALL>(&ovf_list[nc * CLW], x, 0u, mk(0.f, 0.f, 1.f), -x.z, 1);
+          if (nc < NCR) put_contact<GEN>(&sh.cl[nc][0], x, 0u, 0u, mk(0.f, 0.f, 1.f), -x.z, 1);
+          else put_contact<GEN>(&ovf_list[nc * CLW], x, 0u, 0u, mk(0.f, 0.f, 1.f), -x.z, 1);
         }
         ++nc;
       }
@@ -667,8 +803,8 @@ __device__ __forceinline__ void rollout_body(const BinArgs& a, const ModelParams
         if (hit) {
           const int idx = nc + incl - cnt;
           const unsigned anc = __float_as_uint(bodyv[(size_t)b * BW_WORDS + BW_ANCESTORS]);
-          if (idx < NCR) put_contact<BALL>(&sh.cl[idx][0], x, anc, n, depth, 2);
-          else put_contact<BALL>(&ovf_list[idx * CLW], x, anc, n, depth, 2);
+          if (idx < NCR) put_contact<GEN>(&sh.cl[idx][0], x, 0u, anc, n, depth, 2);
+          else put_contact<GEN>(&ovf_list[idx * CLW], x, 0u, anc, n, depth, 2);
         }
         nc += row_bcast_i<15>(incl);
       }
@@ -967,10 +1103,12 @@ __device__ __forceinline__ void rollout_body(const BinArgs& a, const ModelParams
         const f3 x = mk(sh.cl[c][CL_X], sh.cl[c][CL_X + 1], sh.cl[c][CL_X + 2]);
         const unsigned anc = __float_as_uint(sh.cl[c][CL_ANC]);
         float scal[10];
-        if constexpr (BALL)
-          build_rows_ball<S, NVC>(Mi, ang, cst, bodyOfDof, x, mk(sh.cl[c][CL_N], sh.cl[c][CL_N + 1], sh.cl[c][CL_N + 2]),
-                                  sh.cl[c][CL_DEPTH], anc, (int)sh.cl[c][CL_KIND], kc, kb, dt, JnR[c], JxR[c], JyR[c],
-                                  WnR[c], WxR[c], WyR[c], scal);
+        if constexpr (GEN) {
+          const int kind = (int)sh.cl[c][CL_KIND];
+          build_rows_gen<S, NVC>(Mi, ang, cst, bodyOfDof, x, mk(sh.cl[c][CL_N], sh.cl[c][CL_N + 1], sh.cl[c][CL_N + 2]),
+                                 sh.cl[c][CL_DEPTH], anc, __float_as_uint(sh.cl[c][CL_MINUS]), kind == 1 || kind == 2,
+                                 kind == 3, kc, kb, dt, JnR[c], JxR[c], JyR[c], WnR[c], WxR[c], WyR[c], scal);
+        }
         else
           build_rows<S, NVC>(Mi, ang, cst, bodyOfDof, lane, x, anc, kc, kb, dt, JnR[c], JxR[c], JyR[c], WnR[c],
                              WxR[c], WyR[c], scal);
@@ -992,9 +1130,12 @@ __device__ __forceinline__ void rollout_body(const BinArgs& a, const ModelParams
       const f3 x = mk(e[CL_X], e[CL_X + 1], e[CL_X + 2]);
       const unsigned anc = __float_as_uint(e[CL_ANC]);
       float Jn[S], Jx[S], Jy[S], Wn[S], Wx[S], Wy[S], scal[10];
-      if constexpr (BALL)
-        build_rows_ball<S, NVC>(Mi, ang, cst, bodyOfDof, x, mk(e[CL_N], e[CL_N + 1], e[CL_N + 2]), e[CL_DEPTH], anc,
-                                (int)e[CL_KIND], kc, kb, dt, Jn, Jx, Jy, Wn, Wx, Wy, scal);
+      if constexpr (GEN) {
+        const int kind = (int)e[CL_KIND];
+        build_rows_gen<S, NVC>(Mi, ang, cst, bodyOfDof, x, mk(e[CL_N], e[CL_N + 1], e[CL_N + 2]), e[CL_DEPTH], anc,
+                               __float_as_uint(e[CL_MINUS]), kind == 1 || kind == 2, kind == 3, kc, kb, dt, Jn, Jx,
+                               Jy, Wn, Wx, Wy, scal);
+      }
       else
         build_rows<S, NVC>(Mi, ang, cst, bodyOfDof, lane, x, anc, kc, kb, dt, Jn, Jx, Jy, Wn, Wx, Wy, scal);
       float* rows = ovf_rows + (size_t)c * 6 * NVC;
@@ -1233,11 +1374,11 @@ __device__ __forceinline__ void rollout_body(const BinArgs& a, const ModelParams
   }
 }
 
-template <int NVC, int SB, int NCR, bool BALL = false>
+template <int NVC, int SB, int NCR, bool BALL = false, bool SELF = false>
 __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(WavesPerSimd<NVC, SB, NCR>::value)))
 void rollout_kernel(BinArgs a, ModelParams P) {
-  __shared__ GroupLds<NVC, SB, NCR, BALL> lds_all[kVarPerWave];
-  rollout_body<NVC, SB, NCR, BALL>(a, P, blockIdx.x, lds_all);
+  __shared__ GroupLds<NVC, SB, NCR, BALL, SELF> lds_all[kVarPerWave];
+  rollout_body<NVC, SB, NCR, BALL, SELF>(a, P, blockIdx.x, lds_all);
 }
 
 }  // namespace simk

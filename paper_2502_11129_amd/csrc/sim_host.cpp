@@ -54,6 +54,7 @@ struct sim_handle {
   int n = 0;
   int root_type = 0;
   int ball = 0;  // every variant carries a ball
+  int self = 0;  // contacts between the boxes of one robot
   ModelParams params{};
   sim_options opts{};
   std::vector<int> nq, nv, q_off, v_off;
@@ -100,10 +101,10 @@ bool finite_all(const float* p, size_t n) {
   return true;
 }
 
-const KernelVariant* find_variant(int nvc, int sb, int ncr, int ball) {
+const KernelVariant* find_variant(int nvc, int sb, int ncr, int ball, int self) {
   for (int i = 0; i < kNumKernelVariants; ++i) {
     const KernelVariant& k = kKernelVariants[i];
-    if (k.nvc == nvc && k.sb == sb && k.ball == ball && (ncr <= 0 || k.ncr == ncr)) return &k;
+    if (k.nvc == nvc && k.sb == sb && k.ball == ball && k.self == self && (ncr <= 0 || k.ncr == ncr)) return &k;
   }
   return nullptr;
 }
@@ -203,10 +204,10 @@ int launch_all(sim_handle* h, int n_steps, bool reset, hipStream_t st, const std
   return SIM_OK;
 }
 
-HostVariantView host_view(const Bin& b, size_t s) {
+HostVariantView host_view(const Bin& b, size_t s, int self) {
   const int nbc = 16 * b.sb;
   return HostVariantView{&b.hdr[s * HW_WORDS], &b.hdrf[s * HF_WORDS], &b.body[s * nbc * BW_WORDS],
-                         &b.q0[s * kQStride], &b.v0[s * kVStride]};
+                         &b.q0[s * kQStride], &b.v0[s * kVStride], self};
 }
 
 // Run the listed (bin, slot) pairs on host threads; returns wall seconds.
@@ -218,7 +219,7 @@ double run_host(const sim_handle* h, const std::vector<std::pair<int, int>>& wor
   auto body = [&]() {
     for (size_t i = next.fetch_add(1); i < work.size(); i = next.fetch_add(1)) {
       const Bin& b = h->bins[work[i].first];
-      host_rollout(host_view(b, work[i].second), h->params, h->split_T, out[i]);
+      host_rollout(host_view(b, work[i].second, h->self), h->params, h->split_T, out[i]);
     }
   };
   const int nt = std::max(1, std::min<int>(threads, (int)work.size()));
@@ -269,6 +270,8 @@ int sim_create(const sim_model_desc* d, const sim_options* opts, sim_handle** ou
     return bad("a required model array is NULL");
   if (d->root_type == SIM_ROOT_FIXED && !d->root_pose) return bad("FIXED roots need root_pose");
   const int ball = d->ball ? 1 : 0;
+  const int self = d->self_collision ? 1 : 0;
+  if (ball && self) return bad("self_collision is not combined with a ball");
   if (ball)
     for (int i = 0; i < d->n_variants; ++i)
       if (!(d->ball[2 * i] > 0.f) || !(d->ball[2 * i + 1] > 0.f) || !std::isfinite(d->ball[2 * i]) ||
@@ -296,6 +299,7 @@ int sim_create(const sim_model_desc* d, const sim_options* opts, sim_handle** ou
   hp->n = n;
   hp->root_type = d->root_type;
   hp->ball = ball;
+  hp->self = self;
   hp->params = ModelParams{d->kp, d->kd, d->tau_max, d->k_contact, d->b_contact, d->dt,
                            {d->gravity[0], d->gravity[1], d->gravity[2]}, d->pgs_iters};
   const int r0 = d->root_type == SIM_ROOT_FREE ? 6 : 0;
@@ -376,8 +380,8 @@ int sim_create(const sim_model_desc* d, const sim_options* opts, sim_handle** ou
     // smallest compiled (nv capacity, body slots) that holds the variant
     int sb = 0;
     for (; nvc <= kMaxNv; nvc += 4) {
-      if (find_variant(nvc, sb_need, ncr_for(nvc), ball)) { sb = sb_need; break; }
-      if (sb_need == 1 && find_variant(nvc, 2, ncr_for(nvc), ball)) { sb = 2; break; }
+      if (find_variant(nvc, sb_need, ncr_for(nvc), ball, self)) { sb = sb_need; break; }
+      if (sb_need == 1 && find_variant(nvc, 2, ncr_for(nvc), ball, self)) { sb = 2; break; }
     }
     if (!sb)
       return bad("no compiled kernel for nv=" + std::to_string(hp->nv[i]) + " bodies=" + std::to_string(info[i].nb) +
@@ -393,7 +397,7 @@ int sim_create(const sim_model_desc* d, const sim_options* opts, sim_handle** ou
     Bin b;
     b.nvc = kk.first;
     b.sb = kk.second;
-    const KernelVariant* kv = find_variant(b.nvc, b.sb, ncr_for(b.nvc), ball);
+    const KernelVariant* kv = find_variant(b.nvc, b.sb, ncr_for(b.nvc), ball, self);
     b.ncr = kv->ncr;
     b.fn = kv->fn;
     for (int i = 0; i < n; ++i)
@@ -411,7 +415,7 @@ int sim_create(const sim_model_desc* d, const sim_options* opts, sim_handle** ou
   // single launch: every bin must be one of the multi-bin kernel's families
   if (hp->opts.single_launch) {
     if ((int)hp->bins.size() > kMaxMultiBins) return bad("single_launch supports at most 8 bins");
-    if (ball) return bad("single_launch: the multi-bin kernel has no ball families");
+    if (ball || self) return bad("single_launch: the multi-bin kernel has no ball or self-collision families");
     for (Bin& b : hp->bins) {
       for (int k = 0; k < kNumMultiFamilies; ++k)
         if (kMultiFamilies[k].nvc == b.nvc && kMultiFamilies[k].sb == b.sb && kMultiFamilies[k].ncr == b.ncr)
@@ -507,7 +511,7 @@ int sim_create(const sim_model_desc* d, const sim_options* opts, sim_handle** ou
   auto take = [&](size_t bytes) { size_t o = off; off = align256(off + bytes); return o; };
   for (Bin& b : hp->bins) {
     const size_t m = b.users.size();
-    b.ovf_stride = ovf_floats(max_contacts(16 * b.sb, ball), b.nvc, ball ? kListWordsBall : kListWords);
+    b.ovf_stride = ovf_floats(max_contacts(16 * b.sb, ball, self), b.nvc, (ball || self) ? kListWordsBall : kListWords);
     b.o_hdr = take(m * HW_WORDS * 4);
     b.o_hdrf = take(m * HF_WORDS * 4);
     b.o_body = take(m * 16 * b.sb * BW_WORDS * 4);
@@ -766,7 +770,7 @@ int sim_rollout_host(sim_handle* h, int32_t T, int32_t host_threads, float* fitn
   if (fitness)
     for (size_t i = 0; i < work.size(); ++i) {
       const Bin& b = h->bins[work[i].first];
-      fitness[b.users[work[i].second]] = host_fitness(host_view(b, work[i].second), out[i]);
+      fitness[b.users[work[i].second]] = host_fitness(host_view(b, work[i].second, h->self), out[i]);
     }
   if (seconds) *seconds = sec;
   return SIM_OK;
@@ -816,7 +820,7 @@ int sim_rollout_split(sim_handle* h, int32_t T, int32_t n_host, int32_t host_thr
       std::memcpy(&q[j * kQStride], hs.q, sizeof(hs.q));
       std::memcpy(&v[j * kVStride], hs.v, sizeof(hs.v));
       kk[j] = hs.k; sts[j] = hs.status; xy[2 * j] = hs.x0; xy[2 * j + 1] = hs.y0;
-      fit[j] = host_fitness(host_view(b, g + j), hs);
+      fit[j] = host_fitness(host_view(b, g + j, h->self), hs);
       cc[2 * j] = hs.rows_contact; cc[2 * j + 1] = hs.rows_clamp;
     }
     char* w = h->ws;
@@ -880,10 +884,11 @@ int sim_kernel_variants(int32_t* n, int32_t* info, int32_t max_variants) {
   if (!n) return SIM_E_INVALID;
   *n = kNumKernelVariants;
   for (int i = 0; i < kNumKernelVariants && i < max_variants && info; ++i) {
-    info[4 * i] = kKernelVariants[i].nvc;
-    info[4 * i + 1] = 16 * kKernelVariants[i].sb;
-    info[4 * i + 2] = kKernelVariants[i].ncr;
-    info[4 * i + 3] = kKernelVariants[i].ball;
+    info[5 * i] = kKernelVariants[i].nvc;
+    info[5 * i + 1] = 16 * kKernelVariants[i].sb;
+    info[5 * i + 2] = kKernelVariants[i].ncr;
+    info[5 * i + 3] = kKernelVariants[i].ball;
+    info[5 * i + 4] = kKernelVariants[i].self;
   }
   return SIM_OK;
 }

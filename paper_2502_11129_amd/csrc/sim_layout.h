@@ -34,11 +34,16 @@ enum HdrWord { HW_NB = 0, HW_NH, HW_NV, HW_R0, HW_MAXDEPTH, HW_USER, HW_NVR, HW_
 enum HdrfWord { HF_MU = 0, HF_ROOTP = 1, HF_ROOTQ = 4, HF_BALLR = 8, HF_BALLM = 9, HF_WORDS = 10 };
 
 // Contact list entry (floats): plane-only kernels keep x, y, z and the
-// ancestor mask of the body; ball kernels add the normal (box -> ball), the
-// depth and the kind (0 box corner - plane, 1 ball - plane, 2 ball - box).
-enum ListWord { CL_X = 0, CL_ANC = 3, CL_N = 4, CL_DEPTH = 7, CL_KIND = 8 };
+// ancestor mask of the body; ball and self-collision kernels add the normal,
+// the depth, the kind (0 box corner - plane, 1 ball - plane, 2 ball - box,
+// 3 box corner - box) and a second ancestor mask: a contact's rows act on
+// (velocity of the CL_ANC body's point) - (velocity of the CL_MINUS body's
+// point) + (the ball's, for kinds 1 and 2).
+enum ListWord { CL_X = 0, CL_ANC = 3, CL_N = 4, CL_DEPTH = 7, CL_KIND = 8, CL_MINUS = 9 };
 constexpr int kListWords = 4;
 constexpr int kListWordsBall = 12;
+// self-collision contacts a variant may have; beyond it the variant freezes
+constexpr int kMaxSelfContacts = 256;
 
 // Overflow scratch per contact (contacts that do not fit in registers).
 constexpr int kOvfScal = 12;     // per-contact solver scalars
@@ -92,7 +97,9 @@ inline long long ovf_floats(int max_contacts, int nvc, int list_words) {
   return (long long)max_contacts * (list_words + kOvfScal + 6 * nvc);
 }
 // Largest contact count of a variant: 8 corners per box, plus for a ball one
-// plane contact and one per box.
-constexpr int max_contacts(int nbc, bool ball) { return 8 * nbc + (ball ? 1 + nbc : 0); }
+// plane contact and one per box, plus the self-collision allowance.
+constexpr int max_contacts(int nbc, bool ball, bool self = false) {
+  return 8 * nbc + (ball ? 1 + nbc : 0) + (self ? kMaxSelfContacts : 0);
+}
 
 }  // namespace simk

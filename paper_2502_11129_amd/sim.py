@@ -31,7 +31,7 @@ class sim_model_desc(C.Structure):
                 ("axis", _F), ("cpg", _F), ("mu", _F), ("q0", _F), ("v0", _F), ("root_pose", _F),
                 ("kp", C.c_float), ("kd", C.c_float), ("tau_max", C.c_float), ("k_contact", C.c_float),
                 ("b_contact", C.c_float), ("dt", C.c_float), ("gravity", C.c_float * 3), ("pgs_iters", C.c_int32),
-                ("ball", _F)]
+                ("ball", _F), ("self_collision", C.c_int32)]
 
 
 class sim_options(C.Structure):
@@ -148,18 +148,20 @@ def make_desc(pop):
     d.gravity[0], d.gravity[1], d.gravity[2] = p["gravity"]
     d.pgs_iters = int(p["pgs_iters"])
     d.ball = f(keep["ball"]) if keep["ball"] is not None else None
+    d.self_collision = int(bool(getattr(pop, "self_collision", False)))
     return d, keep
 
 
-def kernel_variants(ball=False):
-    """Compiled kernels as (nv capacity, body capacity, contacts in registers),
-    of the plane-only family or (ball=True) of the family whose variants carry a ball."""
+def kernel_variants(ball=False, self_collision=False):
+    """Compiled kernels as (nv capacity, body capacity, contacts in registers)
+    of the plane-only family, the family whose variants carry a ball
+    (ball=True) or the self-collision family (self_collision=True)."""
     lib = load()
     n = C.c_int32()
-    info = np.zeros(4 * 64, np.int32)
+    info = np.zeros(5 * 64, np.int32)
     assert lib.sim_kernel_variants(C.byref(n), info.ctypes.data_as(_I32), 64) == SIM_OK
-    rows = [tuple(int(x) for x in info[4 * i:4 * i + 4]) for i in range(n.value)]
-    return [r[:3] for r in rows if r[3] == int(bool(ball))]
+    rows = [tuple(int(x) for x in info[5 * i:5 * i + 5]) for i in range(n.value)]
+    return [r[:3] for r in rows if r[3] == int(bool(ball)) and r[4] == int(bool(self_collision))]
 
 
 def split_allocation(n, gpu_n, gpu_s, host_s_per_variant):

@@ -68,6 +68,47 @@ def ball_margin(o, pop, vi, q):
     return best
 
 
+def self_margin(o, pop, vi, q):
+    """Distance of variant vi from its self-collision switches at position q:
+    a corner of one box within reach of another box's surface (the inside /
+    outside switch), and, for pairs in contact, the gap between the two
+    smallest separating-axis overlaps (the normal's choice) and the distance
+    of an edge-pair cross product's squared norm from its 1e-6 cut."""
+    R, p, _, _ = o.fk(vi, q)
+    b0 = pop.body_offset[vi]
+    nb = R.shape[0]
+    par = pop.parent[b0:b0 + nb]
+    half = pop.half_ext[b0:b0 + nb].astype(np.float64)
+    best = np.inf
+    signs = np.array([[sx, sy, sz] for sz in (-1, 1) for sy in (-1, 1) for sx in (-1, 1)], np.float64)
+    for a in range(nb):
+        for b in range(a + 1, nb):
+            if par[b] == a:
+                continue
+            touching = False
+            for P, Q in ((a, b), (b, a)):
+                l = ((p[P] + (signs * half[P]) @ R[P].T) - p[Q]) @ R[Q]
+                gap = half[Q] - np.abs(l)                     # > 0 on every axis: inside
+                near = np.abs(gap).min(axis=1)
+                inside_or_close = (gap > -1e-3).all(axis=1)
+                if inside_or_close.any():
+                    best = min(best, near[inside_or_close].min())
+                touching = touching or (gap > 0).all(axis=1).any()
+            if touching:
+                d = p[a] - p[b]
+                axes, cuts = [R[a][:, k] for k in range(3)] + [R[b][:, k] for k in range(3)], []
+                for i in range(3):
+                    for j in range(3):
+                        c = np.cross(R[a][:, i], R[b][:, j])
+                        cuts.append(abs(c @ c - 1e-6))
+                        if c @ c >= 1e-6:
+                            axes.append(c / np.linalg.norm(c))
+                over = np.sort([half[a] @ np.abs(R[a].T @ u) + half[b] @ np.abs(R[b].T @ u) - abs(u @ d)
+                                for u in axes])
+                best = min(best, over[1] - over[0], min(cuts))
+    return best
+
+
 def teacher_forced(pop, sim, ks, threads=THREADS):
     """For each k in ks: oracle state x_k (FP64) -> float32 -> one GPU step,
     compared with the oracle's x_{k+1}.  Returns (max error outside the
@@ -96,6 +137,8 @@ def teacher_forced(pop, sim, ks, threads=THREADS):
             margin = min_corner_height(o, pop, i, qs[i])
             if getattr(pop, "ball", None) is not None:
                 margin = min(margin, ball_margin(o, pop, i, qs[i]))
+            if getattr(pop, "self_collision", False):
+                margin = min(margin, self_margin(o, pop, i, qs[i]))
             if margin < BAND:
                 in_band += 1
                 continue

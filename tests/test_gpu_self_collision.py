@@ -1,0 +1,106 @@
+"""GPU parity of self-collision (corners of a box inside another box of the
+same robot, one separating-axis normal per pair): the self-collision kernels
+through the C ABI against the FP64 oracle, to the bars of the other scenes --
+per-step relative state error <= 1e-4 teacher forced (outside the activation
+band, widened to the self-contact switches: a corner near another box's
+surface, near-ties of the separating axis), fitness within 1e-3 relative
+after T with the float32 sensitivity gate, and the overflow path bitwise
+equal to the in-register one."""
+import dataclasses
+import sys
+
+import numpy as np
+import pytest
+
+from oracle import oracle as O
+from paper_2502_11129_amd import workloads as W
+
+from _parity import STEP_TOL, THREADS, fitness_gate, perturbed_fitness, teacher_forced
+
+pytestmark = pytest.mark.gpu
+
+
+def _say(msg):
+    print(msg, flush=True)
+    sys.stdout.flush()
+
+
+def _self(pop):
+    return dataclasses.replace(pop, self_collision=True)
+
+
+def _folding_chains():
+    """FIXED-root 4-brick chains driven to curl onto their core."""
+    pops = []
+    for i in range(6):
+        rng = np.random.default_rng([11, i])
+        cpg = [(float(rng.uniform(0.8, 1.0)), float(rng.uniform(1.5, 3.0)), float(rng.uniform(0, 6.28)))] * 4
+        pops.append(W.chain(4, ["+x"] * 4, [0] * 4, root_type=W.ROOT_FIXED, cpg=cpg))
+    return _self(W.concat(pops))
+
+
+CASES = {
+    "quadrupeds+self": lambda: _self(W.quadrupeds(16)),
+    "snake3+self": lambda: _self(W.snake(16)),
+    "folding chains": _folding_chains,
+}
+
+
+@pytest.mark.parametrize("name, ks", [
+    ("quadrupeds+self", [0, 1, 50, 150, 300, 500, 700, 999]),
+    ("snake3+self", [0, 1, 100, 300, 600, 900]),
+    ("folding chains", [0, 1, 100, 200, 300, 400, 600, 800]),
+])
+def test_self_teacher_forced_one_step(name, ks):
+    from paper_2502_11129_amd.sim import Simulator
+    pop = CASES[name]()
+    _say(f"[self teacher-forced] {name}: {pop.n_variants} variants, steps {ks}")
+    sim = Simulator(pop)
+    worst, in_band, errs = teacher_forced(pop, sim, ks)
+    _say(f"  worst step error {worst:.3e} over {len(errs)} cases; {in_band} in the activation band")
+    assert len(errs) > 0
+    assert worst <= STEP_TOL
+
+
+@pytest.mark.parametrize("name, make, T", [
+    ("quadrupeds+self x32 T=1000", lambda: _self(W.quadrupeds(32)), 1000),
+    ("snake3+self x16 T=1000", lambda: _self(W.snake(16)), 1000),
+    ("folding chains x6 T=1000", _folding_chains, 1000),
+])
+def test_self_fitness_after_T(name, make, T):
+    from paper_2502_11129_amd.sim import Simulator
+    pop = make()
+    _say(f"[self fitness] {name}")
+    sim = Simulator(pop)
+    sim.rollout(T)
+    Fg = sim.fitness().astype(np.float64)
+    Fr = O.Oracle(pop).rollout(T, threads=THREADS)
+    F32 = O.Oracle(pop, precision=32).rollout(T, threads=THREADS)
+    ok, chaotic, ratio = fitness_gate(Fg, Fr, F32, perturbed_fitness(pop, T))
+    _say(f"  max |dF|/bound {ratio.max():.3f}; fp32-chaotic {int(chaotic.sum())}; failing {int((~ok).sum())}")
+    _, _, status = sim.counters()
+    assert (status == 0).all()
+    if pop.root_type == W.ROOT_FIXED:
+        # a FIXED root has no displacement: compare the final joint angles instead
+        q, _, _ = sim.get_state()
+        o = O.Oracle(pop)
+        o.step(T, THREADS)
+        qr = o.get_state()[0]
+        assert np.abs(q - qr).max() < 0.05
+    else:
+        assert ok.all(), (np.where(~ok)[0], Fg[~ok], Fr[~ok])
+
+
+def test_self_overflow_contacts_bitwise_equal_register_path():
+    from paper_2502_11129_amd.sim import Simulator
+    pop = _self(W.snake(9))
+    _say("[self overflow] snake3+self x9, 2 contacts in registers vs 8, T=1000")
+    a = Simulator(pop)
+    b = Simulator(pop, contacts_in_registers=2)
+    assert [x[2] for x in a.bins()] == [8] and [x[2] for x in b.bins()] == [2]
+    a.rollout(1000)
+    b.rollout(1000)
+    qa, va, _ = a.get_state()
+    qb, vb, _ = b.get_state()
+    np.testing.assert_array_equal(qa, qb)
+    np.testing.assert_array_equal(va, vb)

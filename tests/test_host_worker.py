@@ -1,6 +1,8 @@
 """Host-thread worker of the CPU/GPU split (paper Sec. 6), run here without a
 GPU: its single-precision rollouts must match the FP64 oracle to the same
 fitness bar as the GPU path."""
+import dataclasses
+
 import numpy as np
 import pytest
 
@@ -20,6 +22,7 @@ from _parity import fitness_gate, perturbed_fitness
                             cpg=[(0.8, 3.0, 0.1), (0.5, 2.0, 1.0), (0.9, 4.0, 2.0)]), 500),
     ("box_and_ball x48", W.box_and_ball(48), 1000),
     ("snake3+ball x16", W.attach_ball(W.snake(16)), 800),
+    ("quadrupeds+self x16", dataclasses.replace(W.quadrupeds(16), self_collision=True), 800),
 ])
 def test_host_worker_matches_oracle(name, pop, T):
     h = S.Handle(pop)

@@ -28,11 +28,15 @@ def parse():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--workload", default="trees", choices=["trees", "box_and_ball"],
+    ap.add_argument("--workload", default="trees", choices=["trees", "box_and_ball", "quadrupeds"],
                     help="trees: the uneven-morphology population (default); box_and_ball: a free box "
-                         "and a free ball per variant (the paper's box-and-ball scene)")
-    ap.add_argument("--variants", type=int, default=None, help="default 8192 (trees) / 512000 (box_and_ball)")
-    ap.add_argument("--horizon", type=int, default=None, help="default 5000 (trees) / 1000 (box_and_ball)")
+                         "and a free ball per variant (the paper's box-and-ball scene); quadrupeds: core + "
+                         "four 5-brick limbs")
+    ap.add_argument("--self-collision", action="store_true",
+                    help="contacts between the boxes of one robot (quadrupeds workload)")
+    ap.add_argument("--variants", type=int, default=None,
+                    help="default 8192 (trees) / 512000 (box_and_ball) / 32768 (quadrupeds)")
+    ap.add_argument("--horizon", type=int, default=None, help="default 5000 (trees) / 1000 (others)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-autotune", action="store_true", help="default launch options instead of the autotuned ones")
     ap.add_argument("--options", default=None,
@@ -53,6 +57,9 @@ def cpu_baseline(pop_full, sample_steps, workload="trees"):
     from paper_2502_11129_amd import workloads as W
     if workload == "box_and_ball":
         pop = W.box_and_ball(16384)
+    elif workload == "quadrupeds":
+        import dataclasses
+        pop = dataclasses.replace(W.quadrupeds(64), self_collision=pop_full.self_collision)
     else:
         idx = [i for i in W.TREE_SPOTCHECK if i < pop_full.n_variants]
         pop = W.random_trees(indices=idx)
@@ -61,7 +68,7 @@ def cpu_baseline(pop_full, sample_steps, workload="trees"):
     t0 = time.perf_counter()
     o.rollout(sample_steps, threads=cores)
     dt = time.perf_counter() - t0
-    what = "first" if workload == "box_and_ball" else "spot-check"
+    what = "first" if workload in ("box_and_ball", "quadrupeds") else "spot-check"
     return {"value": pop.n_variants * sample_steps / dt, "unit": "variant-steps/s", "cores": cores,
             "kind": "oracle", "sample": f"{pop.n_variants} {what} variants x {sample_steps} steps, "
                                         f"FP64, {cores} threads, {dt:.2f} s"}
@@ -104,6 +111,12 @@ def main():
         T = args.horizon or 1000
         wname = (f"box-and-ball (a free box and a free ball per variant), {pop.n_variants} variants x {T} steps, "
                  "dt=0.002, K=8")
+    elif args.workload == "quadrupeds":
+        import dataclasses
+        T = args.horizon or 1000
+        pop = dataclasses.replace(W.quadrupeds(args.variants or 32768, steps=T), self_collision=args.self_collision)
+        wname = (f"quadrupeds (core + four 5-brick limbs){' with self-collision' if args.self_collision else ''}, "
+                 f"{pop.n_variants} variants x {T} steps, dt=0.002, K=8")
     else:
         pop = W.random_trees(args.variants or 8192)
         T = args.horizon or 5000
@@ -157,7 +170,8 @@ def main():
     all_bins = fl / (ms_per_step / 1e3) / 1e12
     byt = bytes_per_rollout(pop)
     nvc, nbody, ncr, nvar = bins[dom]
-    kernel_name = f"rollout_kernel<{nvc}, {nbody // 16}, {ncr}{', true' if args.workload == 'box_and_ball' else ''}>"
+    kernel_name = f"rollout_kernel<{nvc}, {nbody // 16}, {ncr}{', true' if args.workload == 'box_and_ball' else ''}" \
+                  f"{', false, true' if getattr(pop, 'self_collision', False) else ''}>"
     if options.get("single_launch"):
         # one kernel runs every bin: its launches carry the whole rollout
         kernel_name = "rollout_multi_kernel"

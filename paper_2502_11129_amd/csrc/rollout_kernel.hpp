@@ -189,6 +189,7 @@ struct alignas(16) GroupLds {
   float cvec[NVC];          // bias c by DoF
   float cb[2][2 * NVC];     // doubled broadcast buffers of the pivot column
   int lv[2 * NBC + 4];      // level lists (bodies in depth order, then level starts), staged per launch
+  float brad[SELF ? NBC : 1];  // bounding-sphere radius |h| per body (self-collision), staged per launch
 };
 
 // ----------------------------------------------------------------------------
@@ -571,6 +572,17 @@ __device__ __forceinline__ void rollout_body(const BinArgs& a, const ModelParams
     if (b < nb) sh.par[b] = __float_as_int(bodyv[b * BW_WORDS + BW_PARENT]);
   }
   for (int j = lane; j < 2 * NBC + 4; j += 16) sh.lv[j] = lvl[j];
+  if (SELF) {
+#pragma unroll
+    for (int t = 0; t < SB; ++t) {
+      const int b = lane + 16 * t;
+      if (b < nb) {
+        const float* rec = bodyv + (size_t)b * BW_WORDS;
+        const f3 h = mk(rec[BW_HALF], rec[BW_HALF + 1], rec[BW_HALF + 2]);
+        sh.brad[b] = sqrtf(dot3(h, h));
+      }
+    }
+  }
   wave_sync();
 
   for (int it = 0; it < a.n_steps; ++it) {
@@ -710,43 +722,45 @@ __device__ __forceinline__ void rollout_body(const BinArgs& a, const ModelParams
       // placed by a DPP prefix scan
       for (int ia = 0; ia < nb - 1; ++ia) {
         const float* pa = &sh.A[ia * 24];
-        m33 Ra;
-#pragma unroll
-        for (int k2 = 0; k2 < 9; ++k2) Ra.m[k2] = pa[k2];
         const f3 Pa = mk(pa[9], pa[10], pa[11]);
-        const float* reca = bodyv + (size_t)ia * BW_WORDS;
-        const f3 ha = mk(reca[BW_HALF], reca[BW_HALF + 1], reca[BW_HALF + 2]);
-        const unsigned anca = __float_as_uint(reca[BW_ANCESTORS]);
+        const float ra = sh.brad[ia];
 #pragma unroll
         for (int t = 0; t < SB; ++t) {
           const int ib = ia + 1 + lane + 16 * t;
-          unsigned hits = 0u;  // bits 0..7: corners of a in b, 8..15: corners of b in a
-          m33 Rb;
-#pragma unroll
-          for (int k2 = 0; k2 < 9; ++k2) Rb.m[k2] = 0.f;
-          f3 Pb = mk(0.f, 0.f, 0.f), hb = Pb;
-          unsigned ancb = 0u;
+          // bounding spheres first (conservative: every corner hit passes)
+          bool cand = false;
           if (ib < nb && sh.par[ib] != ia) {
+            const float* pb = &sh.A[ib * 24];
+            const f3 d = mk(pb[9], pb[10], pb[11]) - Pa;
+            const float rr = ra + sh.brad[ib];
+            cand = dot3(d, d) <= rr * rr * 1.0001f;
+          }
+          unsigned hits = 0u;  // bits 0..7: corners of a in b, 8..15: corners of b in a
+          m33 Ra, Rb;
+          f3 Pb = mk(0.f, 0.f, 0.f), ha = Pb, hb = Pb;
+          if (cand) {
+#pragma unroll
+            for (int k2 = 0; k2 < 9; ++k2) Ra.m[k2] = pa[k2];
             const float* pb = &sh.A[ib * 24];
 #pragma unroll
             for (int k2 = 0; k2 < 9; ++k2) Rb.m[k2] = pb[k2];
             Pb = mk(pb[9], pb[10], pb[11]);
+            const float* reca = bodyv + (size_t)ia * BW_WORDS;
             const float* recb = bodyv + (size_t)ib * BW_WORDS;
+            ha = mk(reca[BW_HALF], reca[BW_HALF + 1], reca[BW_HALF + 2]);
             hb = mk(recb[BW_HALF], recb[BW_HALF + 1], recb[BW_HALF + 2]);
-            ancb = __float_as_uint(recb[BW_ANCESTORS]);
-            const f3 d = Pb - Pa;
-            const float rr = sqrtf(dot3(ha, ha)) + sqrtf(dot3(hb, hb));
-            if (dot3(d, d) <= rr * rr * 1.0001f) {  // conservative: every hit passes
-              for (int c = 0; c < 8; ++c)
-                if (point_in_box(box_corner(Ra, Pa, ha, c), Pb, Rb, hb)) hits |= 1u << c;
-              for (int c = 0; c < 8; ++c)
-                if (point_in_box(box_corner(Rb, Pb, hb, c), Pa, Ra, ha)) hits |= 1u << (8 + c);
-            }
+            for (int c = 0; c < 8; ++c)
+              if (point_in_box(box_corner(Ra, Pa, ha, c), Pb, Rb, hb)) hits |= 1u << c;
+            for (int c = 0; c < 8; ++c)
+              if (point_in_box(box_corner(Rb, Pb, hb, c), Pa, Ra, ha)) hits |= 1u << (8 + c);
           }
+          if (__builtin_amdgcn_ballot_w64(hits != 0u) == 0) continue;  // no hit in any row of the wave
           const int cnt = __builtin_popcount(hits);
           const int incl = row_scan_incl(cnt);
           if (hits) {
             int idx = nc + incl - cnt;
+            const unsigned anca = __float_as_uint(bodyv[(size_t)ia * BW_WORDS + BW_ANCESTORS]);
+            const unsigned ancb = __float_as_uint(bodyv[(size_t)ib * BW_WORDS + BW_ANCESTORS]);
             const f3 u = sat_axis(Pa, Ra, ha, Pb, Rb, hb);  // from b towards a
             for (int c = 0; c < 16; ++c) {
               if (!((hits >> c) & 1u)) continue;

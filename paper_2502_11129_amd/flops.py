@@ -9,6 +9,7 @@ active rows (n_c contacts, n_clamp engaged actuator clamps), FMA = 2:
   + n_c (50 + 9 dbar + 6 nv^2 + 6 nv + 12 K nv)   contact rows and K sweeps
   + n_clamp (2 nv^2 + 4 K nv)             clamp rows and K sweeps
   + 70 nb + 60                            with a ball: ball-box tests, ball update
+  + 12 nb (nb - 1) / 2                    with self-collision: bounding-sphere tests
 
 (nv counts the ball's six DoFs when there is one.)
 
@@ -48,6 +49,8 @@ def flops_per_variant(pop, steps, rows_contact, rows_clamp, K=None):
     base = 156 * nh + 594 * nb + 60 * D + 72 * nh + (2.0 / 3.0) * nv ** 3 + 2 * nv ** 2 + 100
     if getattr(pop, "ball", None) is not None:
         base = base + 70 * nb + 60
+    if getattr(pop, "self_collision", False):
+        base = base + 12 * nb * (nb - 1) / 2        # bounding-sphere tests of every body pair
     per_contact = 50 + 9 * dbar + 6 * nv ** 2 + 6 * nv + 12 * K * nv
     per_clamp = 2 * nv ** 2 + 4 * K * nv
     return (base * steps + np.asarray(rows_contact, np.float64) * per_contact

@@ -43,7 +43,7 @@ def parse():
                     help="launch options as JSON (sim_options fields); skips the autotuner")
     ap.add_argument("--copy-probe", action="store_true",
                     help="also run one plain 1 GiB device copy (calibrates profiler byte counters)")
-    ap.add_argument("--cpu-sample-steps", type=int, default=1000)
+    ap.add_argument("--cpu-sample-steps", type=int, default=4000)
     ap.add_argument("--surrogate", action="store_true",
                     help="also run one surrogate-screened generation (200k labels, 1M pool) and report it")
     return ap.parse_args()
@@ -51,8 +51,8 @@ def parse():
 
 def cpu_baseline(pop_full, sample_steps, workload="trees"):
     """The FP64 oracle on the host cores over a bounded sample of the same
-    workload: the 64 spot-check variants (indices 128 m) of the trees, or the
-    first 16384 box-and-ball variants, for sample_steps steps."""
+    workload: every 8th tree (1024 of the 8192), the first 16384 box-and-ball
+    variants, or the first 64 quadrupeds, for sample_steps steps."""
     from oracle import oracle as O
     from paper_2502_11129_amd import workloads as W
     if workload == "box_and_ball":
@@ -61,14 +61,13 @@ def cpu_baseline(pop_full, sample_steps, workload="trees"):
         import dataclasses
         pop = dataclasses.replace(W.quadrupeds(64), self_collision=pop_full.self_collision)
     else:
-        idx = [i for i in W.TREE_SPOTCHECK if i < pop_full.n_variants]
-        pop = W.random_trees(indices=idx)
+        pop = W.random_trees(indices=range(0, pop_full.n_variants, 8))
     cores = os.cpu_count() or 1
     o = O.Oracle(pop)
     t0 = time.perf_counter()
     o.rollout(sample_steps, threads=cores)
     dt = time.perf_counter() - t0
-    what = "first" if workload in ("box_and_ball", "quadrupeds") else "spot-check"
+    what = "first" if workload in ("box_and_ball", "quadrupeds") else "every 8th"
     return {"value": pop.n_variants * sample_steps / dt, "unit": "variant-steps/s", "cores": cores,
             "kind": "oracle", "sample": f"{pop.n_variants} {what} variants x {sample_steps} steps, "
                                         f"FP64, {cores} threads, {dt:.2f} s"}
@@ -170,8 +169,9 @@ def main():
     all_bins = fl / (ms_per_step / 1e3) / 1e12
     byt = bytes_per_rollout(pop)
     nvc, nbody, ncr, nvar = bins[dom]
-    kernel_name = f"rollout_kernel<{nvc}, {nbody // 16}, {ncr}{', true' if args.workload == 'box_and_ball' else ''}" \
-                  f"{', false, true' if getattr(pop, 'self_collision', False) else ''}>"
+    ball = "true" if getattr(pop, "ball", None) is not None else "false"
+    selfc = "true" if getattr(pop, "self_collision", False) else "false"
+    kernel_name = f"rollout_kernel<{nvc}, {nbody // 16}, {ncr}, {ball}, {selfc}>"
     if options.get("single_launch"):
         # one kernel runs every bin: its launches carry the whole rollout
         kernel_name = "rollout_multi_kernel"

@@ -10,9 +10,11 @@
  *
  * One call advances every variant of a handle on the GPU; all per-step work
  * (kinematics, composite-rigid-body mass matrix, recursive Newton-Euler bias,
- * box-plane contact detection, inversion of the implicit-PD mass matrix,
- * fixed-iteration projected Gauss-Seidel over actuator-clamp and contact rows,
- * semi-implicit Euler) runs inside one persistent HIP kernel per DoF bin.
+ * contact detection -- box-plane, and optionally a free ball (the
+ * box-and-ball scene of Sec. 5) and contacts between a robot's own boxes --,
+ * inversion of the implicit-PD mass matrix, fixed-iteration projected
+ * Gauss-Seidel over actuator-clamp and contact rows, semi-implicit Euler)
+ * runs inside one persistent HIP kernel per DoF bin.
  *
  * Conventions shared by every entry point
  *  - Return value: SIM_OK (0) or a negative SIM_E_* code; sim_last_error()

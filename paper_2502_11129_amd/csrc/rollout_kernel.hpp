@@ -190,6 +190,10 @@ struct alignas(16) GroupLds {
   float cb[2][2 * NVC];     // doubled broadcast buffers of the pivot column
   int lv[2 * NBC + 4];      // level lists (bodies in depth order, then level starts), staged per launch
   float brad[SELF ? NBC : 1];  // bounding-sphere radius |h| per body (self-collision), staged per launch
+  // self-collision: body pairs not joined by a hinge, in order (a | b << 8),
+  // built per launch; the step's bounding-sphere candidates among them
+  uint16_t spair[SELF ? NBC * (NBC - 1) / 2 : 1];
+  uint16_t scand[SELF ? NBC * (NBC - 1) / 2 : 1];
 };
 
 // ----------------------------------------------------------------------------
@@ -572,6 +576,7 @@ __device__ __forceinline__ void rollout_body(const BinArgs& a, const ModelParams
     if (b < nb) sh.par[b] = __float_as_int(bodyv[b * BW_WORDS + BW_PARENT]);
   }
   for (int j = lane; j < 2 * NBC + 4; j += 16) sh.lv[j] = lvl[j];
+  int npairs = 0;  // row-uniform
   if (SELF) {
 #pragma unroll
     for (int t = 0; t < SB; ++t) {
@@ -580,6 +585,19 @@ __device__ __forceinline__ void rollout_body(const BinArgs& a, const ModelParams
         const float* rec = bodyv + (size_t)b * BW_WORDS;
         const f3 h = mk(rec[BW_HALF], rec[BW_HALF + 1], rec[BW_HALF + 2]);
         sh.brad[b] = sqrtf(dot3(h, h));
+      }
+    }
+    wave_sync();  // parents staged above
+    // the pair table: for each a the lanes take b = a + 1 + lane (+16), a DPP
+    // scan places the pairs not joined by a hinge in order
+    for (int ia = 0; ia < nb - 1; ++ia) {
+#pragma unroll
+      for (int t = 0; t < SB; ++t) {
+        const int ib = ia + 1 + lane + 16 * t;
+        const int ok = (ib < nb && sh.par[ib] != ia) ? 1 : 0;
+        const int incl = row_scan_incl(ok);
+        if (ok) sh.spair[npairs + incl - 1] = (uint16_t)(ia | (ib << 8));
+        npairs += row_bcast_i<15>(incl);
       }
     }
   }
@@ -716,69 +734,82 @@ __device__ __forceinline__ void rollout_body(const BinArgs& a, const ModelParams
     }
     int nself = 0;
     if (SELF) {
-      // pairs (a, b), a < b, not joined by a hinge, in order; for each a the
-      // lanes take b = a + 1 + lane (+16); a bounding-sphere test first, then
-      // the corners of a inside b and the corners of b inside a; the hits are
-      // placed by a DPP prefix scan
-      for (int ia = 0; ia < nb - 1; ++ia) {
-        const float* pa = &sh.A[ia * 24];
-        const f3 Pa = mk(pa[9], pa[10], pa[11]);
-        const float ra = sh.brad[ia];
-#pragma unroll
-        for (int t = 0; t < SB; ++t) {
-          const int ib = ia + 1 + lane + 16 * t;
-          // bounding spheres first (conservative: every corner hit passes)
-          bool cand = false;
-          if (ib < nb && sh.par[ib] != ia) {
-            const float* pb = &sh.A[ib * 24];
-            const f3 d = mk(pb[9], pb[10], pb[11]) - Pa;
-            const float rr = ra + sh.brad[ib];
-            cand = dot3(d, d) <= rr * rr * 1.0001f;
-          }
-          unsigned hits = 0u;  // bits 0..7: corners of a in b, 8..15: corners of b in a
-          m33 Ra, Rb;
-          f3 Pb = mk(0.f, 0.f, 0.f), ha = Pb, hb = Pb;
-          if (cand) {
-#pragma unroll
-            for (int k2 = 0; k2 < 9; ++k2) Ra.m[k2] = pa[k2];
-            const float* pb = &sh.A[ib * 24];
-#pragma unroll
-            for (int k2 = 0; k2 < 9; ++k2) Rb.m[k2] = pb[k2];
-            Pb = mk(pb[9], pb[10], pb[11]);
-            const float* reca = bodyv + (size_t)ia * BW_WORDS;
-            const float* recb = bodyv + (size_t)ib * BW_WORDS;
-            ha = mk(reca[BW_HALF], reca[BW_HALF + 1], reca[BW_HALF + 2]);
-            hb = mk(recb[BW_HALF], recb[BW_HALF + 1], recb[BW_HALF + 2]);
-            for (int c = 0; c < 8; ++c)
-              if (point_in_box(box_corner(Ra, Pa, ha, c), Pb, Rb, hb)) hits |= 1u << c;
-            for (int c = 0; c < 8; ++c)
-              if (point_in_box(box_corner(Rb, Pb, hb, c), Pa, Ra, ha)) hits |= 1u << (8 + c);
-          }
-          if (__builtin_amdgcn_ballot_w64(hits != 0u) == 0) continue;  // no hit in any row of the wave
-          const int cnt = __builtin_popcount(hits);
-          const int incl = row_scan_incl(cnt);
-          if (hits) {
-            int idx = nc + incl - cnt;
-            const unsigned anca = __float_as_uint(bodyv[(size_t)ia * BW_WORDS + BW_ANCESTORS]);
-            const unsigned ancb = __float_as_uint(bodyv[(size_t)ib * BW_WORDS + BW_ANCESTORS]);
-            const f3 u = sat_axis(Pa, Ra, ha, Pb, Rb, hb);  // from b towards a
-            for (int c = 0; c < 16; ++c) {
-              if (!((hits >> c) & 1u)) continue;
-              const bool aside = c < 8;  // a corner of a inside b
-              const f3 x = aside ? box_corner(Ra, Pa, ha, c) : box_corner(Rb, Pb, hb, c - 8);
-              const f3 n = aside ? u : u * -1.f;
-              const float depth = aside ? dot3(n, Pb) + box_radius(Rb, hb, n) - dot3(n, x)
-                                        : dot3(n, Pa) + box_radius(Ra, ha, n) - dot3(n, x);
-              const unsigned plus = aside ? anca : ancb, minus = aside ? ancb : anca;
-              if (idx < NCR) put_contact<GEN>(&sh.cl[idx][0], x, plus, minus, n, depth, 3);
-              else if (idx < MAXC) put_contact<GEN>(&ovf_list[idx * CLW], x, plus, minus, n, depth, 3);
-              ++idx;
-            }
-          }
-          const int tot = row_bcast_i<15>(incl);
-          nc += tot;
-          nself += tot;
+      // (i) bounding spheres of every pair, 16 pairs at a time; the
+      // candidates are compacted in pair order (conservative test: every
+      // corner hit passes it)
+      int ncand = 0;
+      for (int k0 = 0; k0 < npairs; k0 += 16) {
+        const int k = k0 + lane;
+        int cand = 0;
+        uint16_t pr = 0;
+        if (k < npairs) {
+          pr = sh.spair[k];
+          const int ia = pr & 0xff, ib = pr >> 8;
+          const float* pa = &sh.A[ia * 24];
+          const float* pb = &sh.A[ib * 24];
+          const f3 d = mk(pb[9] - pa[9], pb[10] - pa[10], pb[11] - pa[11]);
+          const float rr = sh.brad[ia] + sh.brad[ib];
+          cand = dot3(d, d) <= rr * rr * 1.0001f ? 1 : 0;
         }
+        if (__builtin_amdgcn_ballot_w64(cand != 0) == 0) continue;  // no candidate in any row of the wave
+        const int incl = row_scan_incl(cand);
+        if (cand) sh.scand[ncand + incl - 1] = pr;
+        ncand += row_bcast_i<15>(incl);
+      }
+      wave_sync();  // candidates written by other lanes of the row
+      // (ii) the candidates' corner tests, one pair per lane; hits placed in
+      // pair order by a DPP scan, corners of a then of b
+      for (int c0 = 0; c0 < ncand; c0 += 16) {
+        const int ci = c0 + lane;
+        unsigned hits = 0u;  // bits 0..7: corners of a in b, 8..15: corners of b in a
+        int ia = 0, ib = 0;
+        m33 Ra, Rb;
+        f3 Pa = mk(0.f, 0.f, 0.f), Pb = Pa, ha = Pa, hb = Pa;
+        if (ci < ncand) {
+          const uint16_t pr = sh.scand[ci];
+          ia = pr & 0xff;
+          ib = pr >> 8;
+          const float* pa = &sh.A[ia * 24];
+          const float* pb = &sh.A[ib * 24];
+#pragma unroll
+          for (int k2 = 0; k2 < 9; ++k2) Ra.m[k2] = pa[k2];
+#pragma unroll
+          for (int k2 = 0; k2 < 9; ++k2) Rb.m[k2] = pb[k2];
+          Pa = mk(pa[9], pa[10], pa[11]);
+          Pb = mk(pb[9], pb[10], pb[11]);
+          const float* reca = bodyv + (size_t)ia * BW_WORDS;
+          const float* recb = bodyv + (size_t)ib * BW_WORDS;
+          ha = mk(reca[BW_HALF], reca[BW_HALF + 1], reca[BW_HALF + 2]);
+          hb = mk(recb[BW_HALF], recb[BW_HALF + 1], recb[BW_HALF + 2]);
+          for (int c = 0; c < 8; ++c)
+            if (point_in_box(box_corner(Ra, Pa, ha, c), Pb, Rb, hb)) hits |= 1u << c;
+          for (int c = 0; c < 8; ++c)
+            if (point_in_box(box_corner(Rb, Pb, hb, c), Pa, Ra, ha)) hits |= 1u << (8 + c);
+        }
+        if (__builtin_amdgcn_ballot_w64(hits != 0u) == 0) continue;  // no hit in any row of the wave
+        const int cnt = __builtin_popcount(hits);
+        const int incl = row_scan_incl(cnt);
+        if (hits) {
+          int idx = nc + incl - cnt;
+          const unsigned anca = __float_as_uint(bodyv[(size_t)ia * BW_WORDS + BW_ANCESTORS]);
+          const unsigned ancb = __float_as_uint(bodyv[(size_t)ib * BW_WORDS + BW_ANCESTORS]);
+          const f3 u = sat_axis(Pa, Ra, ha, Pb, Rb, hb);  // from b towards a
+          for (int c = 0; c < 16; ++c) {
+            if (!((hits >> c) & 1u)) continue;
+            const bool aside = c < 8;  // a corner of a inside b
+            const f3 x = aside ? box_corner(Ra, Pa, ha, c) : box_corner(Rb, Pb, hb, c - 8);
+            const f3 n = aside ? u : u * -1.f;
+            const float depth = aside ? dot3(n, Pb) + box_radius(Rb, hb, n) - dot3(n, x)
+                                      : dot3(n, Pa) + box_radius(Ra, ha, n) - dot3(n, x);
+            const unsigned plus = aside ? anca : ancb, minus = aside ? ancb : anca;
+            if (idx < NCR) put_contact<GEN>(&sh.cl[idx][0], x, plus, minus, n, depth, 3);
+            else if (idx < MAXC) put_contact<GEN>(&ovf_list[idx * CLW], x, plus, minus, n, depth, 3);
+            ++idx;
+          }
+        }
+        const int tot = row_bcast_i<15>(incl);
+        nc += tot;
+        nself += tot;
       }
       if (nself > kMaxSelfContacts) {  // row-uniform: more than the list holds, freeze
         status |= 4u;

@@ -151,6 +151,14 @@ typedef struct {
  *                         bin to be a 32-body kernel of the default contact
  *                         budget with nv capacity 16..28, at most 8 bins; else
  *                         sim_create fails); streams is then ignored
+ *  host_factorization     factorisation of M~ in the host worker
+ *                         (sim_rollout_host, the host share of
+ *                         sim_rollout_split): SIM_FACTOR_DENSE (0) dense
+ *                         Cholesky, SIM_FACTOR_TREE (1) the tree-sparse L^T L
+ *                         factorisation over the DoF tree (Featherstone's
+ *                         branch-induced sparsity: every step touches only
+ *                         a DoF's ancestors); the two agree to rounding.  The
+ *                         GPU kernels always form the dense inverse.
  */
 typedef struct {
   int32_t contacts_in_registers;
@@ -161,8 +169,12 @@ typedef struct {
   int32_t ncr_by_nvc[6];
   int32_t time_launches;
   int32_t single_launch;
-  int32_t reserved[3];
+  int32_t host_factorization;
+  int32_t reserved[2];
 } sim_options;
+
+#define SIM_FACTOR_DENSE 0
+#define SIM_FACTOR_TREE 1
 
 typedef struct sim_handle sim_handle;
 

@@ -1,12 +1,16 @@
 """Autotuner of the launch and packing options (sim_options).
 
-The options never change results (same arithmetic in every layout); they
+The GPU options never change results (same arithmetic in every layout); they
 change how the population is cut into DoF bins and launched: contacts kept in
 registers per DoF capacity, body capacity (merging bins), steps per launch
 and the number of concurrent streams.  The tuner times short pilot rollouts
 of the actual population (HIP events on the stream) and keeps the fastest
 setting of one option at a time (coordinate descent, fixed order), so the
 search costs a few dozen pilots.
+
+`autotune_host` picks the host worker's factorisation of the joint-space
+system (dense Cholesky or the tree-sparse L^T L; equal up to rounding) by
+timing host rollouts of a sample of the population with each.
 """
 from __future__ import annotations
 
@@ -111,3 +115,22 @@ def autotune(pop, T_pilot=1000, reps=2, log=None, cache=None):
         with open(cache, "w") as f:
             json.dump(store, f)
     return best, trials
+
+
+def autotune_host(pop, T_pilot=1000, threads=1, sample=64, log=None):
+    """Faster host factorisation ("dense" or "tree") for this population:
+    host rollouts of every k-th variant (about `sample` of them, so the mix of
+    sizes is kept) over T_pilot steps with each; returns (name, {name: s})."""
+    import numpy as np
+    n = pop.n_variants
+    idx = np.arange(0, n, max(1, n // max(1, sample)))
+    sub = pop.subset(idx) if len(idx) < n else pop
+    times = {}
+    for f in S.HOST_FACTORIZATIONS:
+        h = S.Handle(sub, host_factorization=f)
+        _, sec = h.rollout_host(T_pilot, threads)
+        h.close()
+        times[f] = sec
+        if log:
+            log(f"autotune host {f}: {sec * 1e3:.1f} ms for {len(idx)} variants x {T_pilot} steps")
+    return min(times, key=times.get), times

@@ -1,8 +1,10 @@
 // Host-thread worker: one variant per task, single precision, the same step
 // as the GPU kernel (spatial forward/backward passes, CRBA, implicit-PD
 // diagonal, contact rows, fixed-iteration Gauss-Seidel, semi-implicit Euler).
-// The dense system is factorised by Cholesky here (a serial CPU has no reason
-// to form the inverse); clamp-row columns are solved only when a clamp engages.
+// The system is factorised here rather than inverted (a serial CPU has no
+// reason to form the inverse), by a dense Cholesky or, as an option, by the
+// tree-sparse L^T L factorisation that touches only a DoF's ancestors;
+// clamp-row columns are solved only when a clamp engages.
 // A ball (when the variant has one) adds six DoFs after the robot's (world
 // spin, centre velocity), a ball-plane contact and ball-box contacts;
 // self-collision adds the corners of a box strictly inside another box of the
@@ -68,6 +70,7 @@ struct Work {
   SV V[NB], A[NB], F[NB];
   Inertia C[NB];
   float M[NV * NV], L[NV * NV], c[NV], a[NV], vf[NV], vp[NV];
+  int lam[NV];  // parent of each DoF in the DoF tree (-1 at a root), tree factorisation only
   float Wc[NV][NV];
   bool haveWc[NV];
   float Dl[NV];
@@ -87,6 +90,51 @@ void chol_solve(int n, const float* L, const float* b, float* x) {
     float s = y[i];
     for (int k = i + 1; k < n; ++k) s -= L[k * NV + i] * x[k];
     x[i] = s / L[i * NV + i];
+  }
+}
+
+// Tree-sparse factorisation M = L^T L (Featherstone, "Rigid Body Dynamics
+// Algorithms", 2008, Sec. 6.5).  Every DoF's parent lam[k] has a smaller index,
+// and M[i][j] = 0 unless one of i, j is an ancestor of the other (branch-induced
+// sparsity), so L is lower triangular with L[k][i] != 0 only for i an ancestor
+// of k or k itself.  From the last DoF back: L[k][k] = sqrt of what is left of
+// M[k][k], the row of k along its ancestors is divided by it, and the outer
+// product of that row is taken off the ancestors' block.  Only the ancestor
+// entries of M (lower triangle, row stride NV) are read; L is written in the
+// same places.  Returns false on a non-positive pivot.
+bool tree_factor(int n, const int* lam, const float* M, float* L) {
+  for (int k = 0; k < n; ++k) {
+    L[k * NV + k] = M[k * NV + k];
+    for (int i = lam[k]; i >= 0; i = lam[i]) L[k * NV + i] = M[k * NV + i];
+  }
+  for (int k = n - 1; k >= 0; --k) {
+    const float pivot = L[k * NV + k];
+    if (!(pivot > 0.f)) return false;
+    const float lkk = std::sqrt(pivot);
+    L[k * NV + k] = lkk;
+    for (int i = lam[k]; i >= 0; i = lam[i]) L[k * NV + i] /= lkk;
+    for (int i = lam[k]; i >= 0; i = lam[i]) {
+      const float lki = L[k * NV + i];
+      for (int j = i; j >= 0; j = lam[j]) L[i * NV + j] -= lki * L[k * NV + j];
+    }
+  }
+  return true;
+}
+
+// x = M^-1 b with M = L^T L from tree_factor: L^T y = b from the leaves
+// towards the roots (each DoF, once final, is taken off its ancestors), then
+// L x = y from the roots out (each DoF needs only its ancestors).
+void tree_solve(int n, const int* lam, const float* L, const float* b, float* x) {
+  float y[NV];
+  for (int i = 0; i < n; ++i) y[i] = b[i];
+  for (int k = n - 1; k >= 0; --k) {
+    y[k] /= L[k * NV + k];
+    for (int i = lam[k]; i >= 0; i = lam[i]) y[i] -= L[k * NV + i] * y[k];
+  }
+  for (int k = 0; k < n; ++k) {
+    float s = y[k];
+    for (int i = lam[k]; i >= 0; i = lam[i]) s -= L[k * NV + i] * x[i];
+    x[k] = s / L[k * NV + k];
   }
 }
 
@@ -279,18 +327,36 @@ bool step(const HostVariantView& m, const ModelParams& P, HostVariantState& st, 
       wk.M[(nvr + k) * NV + nvr + k] = k < 3 ? iball : mball;
       wk.c[nvr + k] = k < 3 ? 0.f : -mball * P.g[k - 3];
     }
-  // Cholesky of Mt
-  for (int j = 0; j < nv; ++j) {
-    float s = wk.M[j * NV + j];
-    for (int k = 0; k < j; ++k) s -= wk.L[j * NV + k] * wk.L[j * NV + k];
-    if (!(s > 0.f)) return false;
-    wk.L[j * NV + j] = std::sqrt(s);
-    for (int i = j + 1; i < nv; ++i) {
-      float t = wk.M[i * NV + j];
-      for (int k = 0; k < j; ++k) t -= wk.L[i * NV + k] * wk.L[j * NV + k];
-      wk.L[i * NV + j] = t / wk.L[j * NV + j];
+  const bool tree = m.tree_factor != 0;
+  if (tree) {
+    // DoF tree: the free root's six DoFs in a chain (their block is dense), a
+    // hinge under its parent body's hinge (under the root's last DoF for a
+    // child of the core), the ball's DoFs on their own (a diagonal block)
+    for (int d = 0; d < r0; ++d) wk.lam[d] = d - 1;
+    for (int b = 1; b < nb; ++b) {
+      const int l = Bi(b, BW_PARENT);
+      wk.lam[r0 + b - 1] = l == 0 ? r0 - 1 : r0 + l - 1;
+    }
+    for (int d = nvr; d < nv; ++d) wk.lam[d] = -1;
+    if (!tree_factor(nv, wk.lam, wk.M, wk.L)) return false;
+  } else {
+    // dense Cholesky M = L L^T
+    for (int j = 0; j < nv; ++j) {
+      float s = wk.M[j * NV + j];
+      for (int k = 0; k < j; ++k) s -= wk.L[j * NV + k] * wk.L[j * NV + k];
+      if (!(s > 0.f)) return false;
+      wk.L[j * NV + j] = std::sqrt(s);
+      for (int i = j + 1; i < nv; ++i) {
+        float t = wk.M[i * NV + j];
+        for (int k = 0; k < j; ++k) t -= wk.L[i * NV + k] * wk.L[j * NV + k];
+        wk.L[i * NV + j] = t / wk.L[j * NV + j];
+      }
     }
   }
+  auto solve = [&](const float* rhs_, float* x) {
+    if (tree) tree_solve(nv, wk.lam, wk.L, rhs_, x);
+    else chol_solve(nv, wk.L, rhs_, x);
+  };
   // control and free velocity
   const double tk = double(st.k) * double(dt);
   float rhs[NV];
@@ -303,7 +369,7 @@ bool step(const HostVariantView& m, const ModelParams& P, HostVariantState& st, 
     wk.a[j] = kp * (target - q[qh + j]);
     rhs[r0 + j] += dt * (wk.a[j] - ba * v[r0 + j]);
   }
-  chol_solve(nv, wk.L, rhs, wk.vf);
+  solve(rhs, wk.vf);
   for (int d = 0; d < nv; ++d) wk.vf[d] += v[d];
   // contacts: rows (n, t1, t2) of the relative velocity; a robot DoF's sign
   // is its body's bit in `plus` minus its bit in `minus` (root DoFs: body 0),
@@ -338,7 +404,7 @@ bool step(const HostVariantView& m, const ModelParams& P, HostVariantState& st, 
     }
     float D[3];
     for (int r = 0; r < 3; ++r) {
-      chol_solve(nv, wk.L, J + r * NV, W + r * NV);
+      solve(J + r * NV, W + r * NV);
       float s2 = 0.f;
       for (int d = 0; d < nv; ++d) s2 += J[r * NV + d] * W[r * NV + d];
       D[r] = s2;
@@ -424,7 +490,7 @@ bool step(const HostVariantView& m, const ModelParams& P, HostVariantState& st, 
     if (!wk.haveWc[j]) {
       float e[NV] = {0};
       e[r0 + j] = 1.f;
-      chol_solve(nv, wk.L, e, wk.Wc[j]);
+      solve(e, wk.Wc[j]);
       wk.haveWc[j] = true;
     }
     return wk.Wc[j];

@@ -18,6 +18,7 @@ struct HostVariantView {
   const float* q0;       // kQStride
   const float* v0;       // kVStride
   int self_collision;    // contacts between the boxes of the robot
+  int tree_factor;       // factorise M~ by the tree-sparse L^T L (else dense Cholesky)
 };
 
 struct HostVariantState {

@@ -204,10 +204,11 @@ int launch_all(sim_handle* h, int n_steps, bool reset, hipStream_t st, const std
   return SIM_OK;
 }
 
-HostVariantView host_view(const Bin& b, size_t s, int self) {
+HostVariantView host_view(const sim_handle* h, const Bin& b, size_t s) {
   const int nbc = 16 * b.sb;
   return HostVariantView{&b.hdr[s * HW_WORDS], &b.hdrf[s * HF_WORDS], &b.body[s * nbc * BW_WORDS],
-                         &b.q0[s * kQStride], &b.v0[s * kVStride], self};
+                         &b.q0[s * kQStride], &b.v0[s * kVStride], h->self,
+                         h->opts.host_factorization == SIM_FACTOR_TREE};
 }
 
 // Run the listed (bin, slot) pairs on host threads; returns wall seconds.
@@ -219,7 +220,7 @@ double run_host(const sim_handle* h, const std::vector<std::pair<int, int>>& wor
   auto body = [&]() {
     for (size_t i = next.fetch_add(1); i < work.size(); i = next.fetch_add(1)) {
       const Bin& b = h->bins[work[i].first];
-      host_rollout(host_view(b, work[i].second, h->self), h->params, h->split_T, out[i]);
+      host_rollout(host_view(h, b, work[i].second), h->params, h->split_T, out[i]);
     }
   };
   const int nt = std::max(1, std::min<int>(threads, (int)work.size()));
@@ -291,6 +292,8 @@ int sim_create(const sim_model_desc* d, const sim_options* opts, sim_handle** ou
     if (o.min_body_slots != 0 && o.min_body_slots != 16 && o.min_body_slots != 32)
       return bad("min_body_slots must be 0, 16 or 32");
     if (o.time_launches && o.use_graph) return bad("time_launches and use_graph cannot be combined");
+    if (o.host_factorization != SIM_FACTOR_DENSE && o.host_factorization != SIM_FACTOR_TREE)
+      return bad("host_factorization must be SIM_FACTOR_DENSE or SIM_FACTOR_TREE");
     for (int k = 0; k < 6; ++k)
       if (o.ncr_by_nvc[k] < 0) return bad("ncr_by_nvc entries must be >= 0");
     hp->steps_per_launch = o.steps_per_launch > 0 ? o.steps_per_launch : kStepsPerLaunch;
@@ -770,7 +773,7 @@ int sim_rollout_host(sim_handle* h, int32_t T, int32_t host_threads, float* fitn
   if (fitness)
     for (size_t i = 0; i < work.size(); ++i) {
       const Bin& b = h->bins[work[i].first];
-      fitness[b.users[work[i].second]] = host_fitness(host_view(b, work[i].second, h->self), out[i]);
+      fitness[b.users[work[i].second]] = host_fitness(host_view(h, b, work[i].second), out[i]);
     }
   if (seconds) *seconds = sec;
   return SIM_OK;
@@ -820,7 +823,7 @@ int sim_rollout_split(sim_handle* h, int32_t T, int32_t n_host, int32_t host_thr
       std::memcpy(&q[j * kQStride], hs.q, sizeof(hs.q));
       std::memcpy(&v[j * kVStride], hs.v, sizeof(hs.v));
       kk[j] = hs.k; sts[j] = hs.status; xy[2 * j] = hs.x0; xy[2 * j + 1] = hs.y0;
-      fit[j] = host_fitness(host_view(b, g + j, h->self), hs);
+      fit[j] = host_fitness(host_view(h, b, g + j), hs);
       cc[2 * j] = hs.rows_contact; cc[2 * j + 1] = hs.rows_clamp;
     }
     char* w = h->ws;

@@ -57,6 +57,50 @@ def flops_per_variant(pop, steps, rows_contact, rows_clamp, K=None):
             + np.asarray(rows_clamp, np.float64) * per_clamp)
 
 
+def dof_parents(pop, i):
+    """Parent of every DoF of variant i in the DoF tree of the tree-sparse
+    factorisation (-1 at a root): a free root's six DoFs form a chain, a
+    hinge hangs under the hinge of its body's parent (under the root's last
+    DoF for a child of the core), a ball's six DoFs are roots of their own."""
+    bo = pop.body_offset
+    par = pop.parent[bo[i]:bo[i + 1]]
+    ball = getattr(pop, "ball", None) is not None
+    r0 = int(pop.nv[i]) - (len(par) - 1) - (6 if ball else 0)
+    lam = list(range(-1, r0 - 1))
+    for b in range(1, len(par)):
+        lam.append(r0 - 1 if par[b] == 0 else r0 + int(par[b]) - 1)
+    return np.asarray(lam + ([-1] * 6 if ball else []), np.int64)
+
+
+def factor_solve_flops(pop, kind):
+    """Per variant: (flops of one factorisation, flops of one solve) of the
+    joint-space system in the host worker, FMA = 2: "dense" Cholesky
+    (nv^3 / 3, 2 nv^2) or "tree"-sparse L^T L, where DoF k with ancestors
+    anc(k) costs a square root, |anc(k)| divisions and, per ancestor i,
+    |anc(i)| + 1 multiply-adds, and a solve two sweeps of |anc(k)|
+    multiply-adds plus a division per DoF."""
+    nv = pop.nv.astype(np.float64)
+    if kind == "dense":
+        return nv ** 3 / 3.0, 2.0 * nv ** 2
+    fac = np.zeros(pop.n_variants)
+    sol = np.zeros(pop.n_variants)
+    for v in range(pop.n_variants):
+        lam = dof_parents(pop, v)
+        na = np.zeros(len(lam), np.int64)          # ancestors per DoF (parents come first)
+        for k in range(len(lam)):
+            na[k] = 0 if lam[k] < 0 else na[lam[k]] + 1
+        f = 0.0
+        for k in range(len(lam)):
+            f += 1 + na[k]
+            j = lam[k]
+            while j >= 0:
+                f += 2.0 * (na[j] + 1)
+                j = lam[j]
+        fac[v] = f
+        sol[v] = 4.0 * na.sum() + 2.0 * len(lam)
+    return fac, sol
+
+
 def bytes_per_rollout(pop):
     """Algorithmic HBM bytes of one rollout launch: model (24 words per body,
     header) and initial state read, final state and fitness written."""

@@ -14,14 +14,20 @@ import sys
 import time
 
 
-def measure(pop, T, threads, rule="makespan", pilot_T=None, host_sample=None, log=print, progress=None):
+def measure(pop, T, threads, rule="makespan", pilot_T=None, host_sample=None, log=print, progress=None,
+            host_factorization=None):
     """pilot_T: steps of the pilot runs (default the full horizon T, as the
     paper's initial benchmarking runs: a short pilot of a dropped scene sees
-    only the free fall, where the host's per-step cost is lowest)."""
+    only the free fall, where the host's per-step cost is lowest).
+    host_factorization: "dense", "tree" or None (the faster on a sample)."""
     import torch
     say = progress or (lambda m: None)
     from .sim import Simulator
-    sim = Simulator(pop)
+    if host_factorization is None:
+        from .autotune import autotune_host
+        host_factorization, _ = autotune_host(pop, pilot_T or T, threads, sample=max(threads * 2, 32))
+    say(f"n={pop.n_variants}: host factorisation {host_factorization}")
+    sim = Simulator(pop, host_factorization=host_factorization)
     n = pop.n_variants
     st = torch.cuda.current_stream()
     # sequential GPU (after a warm-up)
@@ -48,7 +54,7 @@ def measure(pop, T, threads, rule="makespan", pilot_T=None, host_sample=None, lo
     out = dict(n=n, T=T, threads=threads, rule=rule, seq_gpu_s=seq_gpu, seq_gpu_events_s=seq_gpu_events,
                seq_cpu_s=seq_cpu, naive_sum_s=seq_gpu + seq_cpu, combined_s=t["combined_s"],
                combined_gpu_s=t["gpu_s"], combined_host_s=t["host_s"], n_host=n_host,
-               gpu_percent=100.0 * (n - n_host) / n, plan=plan)
+               gpu_percent=100.0 * (n - n_host) / n, host_factorization=host_factorization, plan=plan)
     log(json.dumps(out))
     sim.close()
     return out
@@ -62,12 +68,14 @@ def main():
     ap.add_argument("--sizes", default="32,128,512,2048,8192,32768")
     ap.add_argument("--threads", type=int, default=os.cpu_count() or 1)
     ap.add_argument("--rule", default="makespan", choices=["makespan", "paper"])
+    ap.add_argument("--host-factorization", default=None, choices=["dense", "tree"],
+                    help="host worker's factorisation (default: the faster on a sample)")
     a = ap.parse_args()
     make = {"quadrupeds": lambda n: W.quadrupeds(n, steps=a.steps), "trees": W.random_trees, "boxes": W.boxes,
             "box_and_ball": lambda n: W.box_and_ball(n, steps=a.steps)}[a.workload]
     for n in (int(x) for x in a.sizes.split(",")):
         measure(make(n), a.steps, a.threads, a.rule, log=lambda m: print(m, flush=True),
-                progress=lambda m: print(m, file=sys.stderr, flush=True))
+                progress=lambda m: print(m, file=sys.stderr, flush=True), host_factorization=a.host_factorization)
 
 
 if __name__ == "__main__":

@@ -1024,33 +1024,54 @@ __device__ __forceinline__ void rollout_body(const BinArgs& a, const ModelParams
     //    pivot column is broadcast through a doubled LDS buffer.  Pivot row
     //    k uses the symmetric column values: a_kj - (1 - 1/d) a_jk.
     //    Result: -M~^-1 with register column j <-> column (nv + j) mod NVC.
+    //    Software-pipelined: the first updated column of step k is column 0
+    //    of step k + 1, so it is broadcast (and read back into the other
+    //    register set) before the rest of step k's updates, which hide the
+    //    LDS round trip; the arithmetic is that of the plain sweep.
     // =====================================================================
-#pragma unroll 1
-    for (int k = 0; k < nv; ++k) {
-      float* cbk = sh.cb[k & 1];
+    {
+      float ckA[NVC], ckB[NVC];  // pivot column of the current / next step
 #pragma unroll
       for (int s = 0; s < S; ++s) {
         const int d = lane + 16 * s;
-        if (d < NVC) { cbk[d] = Mi[s][0]; cbk[d + NVC] = Mi[s][0]; }
+        if (d < NVC) { sh.cb[0][d] = Mi[s][0]; sh.cb[0][d + NVC] = Mi[s][0]; }
       }
       wave_sync();
-      const float* ck = cbk + k;
-      const float pinv = recip(ck[0]);
-      float f[S];
-      bool piv[S];
 #pragma unroll
-      for (int s = 0; s < S; ++s) {
-        piv[s] = (lane + 16 * s) == k;
-        f[s] = piv[s] ? 1.f - pinv : Mi[s][0] * pinv;
+      for (int j = 0; j < NVC; ++j) ckA[j] = sh.cb[0][j];
+      auto pivot_step = [&](int k, const float (&ck)[NVC], float (&nck)[NVC]) {
+        const float pinv = recip(ck[0]);
+        float f[S];
+        bool piv[S];
+#pragma unroll
+        for (int s = 0; s < S; ++s) {
+          piv[s] = (lane + 16 * s) == k;
+          f[s] = piv[s] ? 1.f - pinv : Mi[s][0] * pinv;
+        }
+#pragma unroll
+        for (int s = 0; s < S; ++s) Mi[s][0] = fmaf(-f[s], ck[1], Mi[s][1]);
+        float* cbn = sh.cb[(k + 1) & 1];
+#pragma unroll
+        for (int s = 0; s < S; ++s) {
+          const int d = lane + 16 * s;
+          if (d < NVC) { cbn[d] = Mi[s][0]; cbn[d + NVC] = Mi[s][0]; }
+        }
+        wave_sync();
+#pragma unroll
+        for (int j = 0; j < NVC; ++j) nck[j] = cbn[k + 1 + j];  // k + 1 <= NVC: inside the doubled buffer
+#pragma unroll
+        for (int j = 2; j < NVC; ++j) {
+#pragma unroll
+          for (int s = 0; s < S; ++s) Mi[s][j - 1] = fmaf(-f[s], ck[j], Mi[s][j]);
+        }
+#pragma unroll
+        for (int s = 0; s < S; ++s) Mi[s][NVC - 1] = piv[s] ? -pinv : f[s];
+      };
+#pragma unroll 1
+      for (int k = 0; k < nv; k += 2) {
+        pivot_step(k, ckA, ckB);
+        if (k + 1 < nv) pivot_step(k + 1, ckB, ckA);
       }
-#pragma unroll
-      for (int j = 1; j < NVC; ++j) {
-        const float cj = ck[j];
-#pragma unroll
-        for (int s = 0; s < S; ++s) Mi[s][j - 1] = fmaf(-f[s], cj, Mi[s][j]);
-      }
-#pragma unroll
-      for (int s = 0; s < S; ++s) Mi[s][NVC - 1] = piv[s] ? -pinv : f[s];
     }
     // the assembled matrix is dead: keep the (negated, rotated) inverse in LDS
     // for the clamp rows, which need single columns chosen at run time, and

@@ -187,7 +187,8 @@ struct alignas(16) GroupLds {
   float cs[NCR][12];        // per-contact solver scalars
   float th[NVC], thd[NVC];  // theta / thetadot by DoF
   float cvec[NVC];          // bias c by DoF
-  float cb[2][2 * NVC];     // doubled broadcast buffers of the pivot column
+  float cb[2][2 * NVC + 16];  // doubled broadcast buffers of the pivot column (+ a sink
+                              // for the lanes past the last DoF, which store unmasked)
   int lv[2 * NBC + 4];      // level lists (bodies in depth order, then level starts), staged per launch
   float brad[SELF ? NBC : 1];  // bounding-sphere radius |h| per body (self-collision), staged per launch
   // self-collision: body pairs not joined by a hinge, in order (a | b << 8),
@@ -1031,11 +1032,20 @@ __device__ __forceinline__ void rollout_body(const BinArgs& a, const ModelParams
     // =====================================================================
     {
       float ckA[NVC], ckB[NVC];  // pivot column of the current / next step
+      // Store positions of the lane's rows in a broadcast buffer: row d at d
+      // and d + NVC; a slot past the last DoF writes both copies into the
+      // sink at 2 NVC + (d - NVC) < 2 NVC + 16, so the stores need no branch
+      // (a branch there splits the step and lets the compiler sink its
+      // updates below the next step's reads).
+      int cb_lo[S], cb_hi[S];
 #pragma unroll
       for (int s = 0; s < S; ++s) {
         const int d = lane + 16 * s;
-        if (d < NVC) { sh.cb[0][d] = Mi[s][0]; sh.cb[0][d + NVC] = Mi[s][0]; }
+        cb_lo[s] = d < NVC ? d : NVC + d;
+        cb_hi[s] = d < NVC ? d + NVC : NVC + d;
       }
+#pragma unroll
+      for (int s = 0; s < S; ++s) { sh.cb[0][cb_lo[s]] = Mi[s][0]; sh.cb[0][cb_hi[s]] = Mi[s][0]; }
       wave_sync();
 #pragma unroll
       for (int j = 0; j < NVC; ++j) ckA[j] = sh.cb[0][j];
@@ -1052,13 +1062,13 @@ __device__ __forceinline__ void rollout_body(const BinArgs& a, const ModelParams
         for (int s = 0; s < S; ++s) Mi[s][0] = fmaf(-f[s], ck[1], Mi[s][1]);
         float* cbn = sh.cb[(k + 1) & 1];
 #pragma unroll
-        for (int s = 0; s < S; ++s) {
-          const int d = lane + 16 * s;
-          if (d < NVC) { cbn[d] = Mi[s][0]; cbn[d + NVC] = Mi[s][0]; }
-        }
+        for (int s = 0; s < S; ++s) { cbn[cb_lo[s]] = Mi[s][0]; cbn[cb_hi[s]] = Mi[s][0]; }
         wave_sync();
 #pragma unroll
         for (int j = 0; j < NVC; ++j) nck[j] = cbn[k + 1 + j];  // k + 1 <= NVC: inside the doubled buffer
+        // keep the scheduler from hoisting the next step's chain above this
+        // step's updates (which would leave the reads' latency exposed)
+        __builtin_amdgcn_sched_barrier(0);
 #pragma unroll
         for (int j = 2; j < NVC; ++j) {
 #pragma unroll
@@ -1066,12 +1076,18 @@ __device__ __forceinline__ void rollout_body(const BinArgs& a, const ModelParams
         }
 #pragma unroll
         for (int s = 0; s < S; ++s) Mi[s][NVC - 1] = piv[s] ? -pinv : f[s];
+        __builtin_amdgcn_sched_barrier(0);
       };
+      // whole pairs of steps (no branch between a step's reads and their use,
+      // so the compiler keeps them ahead of the step's updates), then an odd
+      // last step
+      int k = 0;
 #pragma unroll 1
-      for (int k = 0; k < nv; k += 2) {
+      for (; k + 1 < nv; k += 2) {
         pivot_step(k, ckA, ckB);
-        if (k + 1 < nv) pivot_step(k + 1, ckB, ckA);
+        pivot_step(k + 1, ckB, ckA);
       }
+      if (k < nv) pivot_step(k, ckA, ckB);
     }
     // the assembled matrix is dead: keep the (negated, rotated) inverse in LDS
     // for the clamp rows, which need single columns chosen at run time, and

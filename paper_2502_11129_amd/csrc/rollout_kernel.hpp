@@ -57,7 +57,6 @@ __device__ __forceinline__ float dpp(float x) {
   return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(x), CTRL, 0xF, 0xF, false));
 }
 
-// Sum over the 16 lanes of a row; every lane gets the bitwise-same value.
 // inclusive prefix sum over the 16 lanes of a row (lanes shifted in from
 // outside the row contribute 0)
 __device__ __forceinline__ int row_scan_incl(int x) {
@@ -71,6 +70,7 @@ template <int L>
 __device__ __forceinline__ int row_bcast_i(int x) {
   return __builtin_amdgcn_update_dpp(0, x, 0x150 + L, 0xF, 0xF, false);  // row_newbcast:L
 }
+// Sum over the 16 lanes of a row; every lane gets the bitwise-same value.
 __device__ __forceinline__ float row_sum(float x) {
   x += dpp<0xB1>(x);   // quad_perm [1,0,3,2]
   x += dpp<0x4E>(x);   // quad_perm [2,3,0,1]
@@ -471,12 +471,13 @@ __device__ __forceinline__ void contact_row(float (&vp)[S], const float (&Jn)[S]
   for (int s = 0; s < S; ++s) vp[s] = fmaf(Wn[s], edn, fmaf(Wx[s], edx, fmaf(Wy[s], edy, vp[s])));
 }
 
-// Smallest value over the 16 lanes of a row (every lane gets it).
-__device__ __forceinline__ float row_min(float x) {
-  x = fminf(x, dpp<0xB1>(x));
-  x = fminf(x, dpp<0x4E>(x));
-  x = fminf(x, dpp<0x141>(x));
-  x = fminf(x, dpp<0x140>(x));
+// Smallest value over the 16 lanes of a row (every lane gets it); integer,
+// so each step is one DPP move and one min with no float canonicalisation.
+__device__ __forceinline__ int row_min_i(int x) {
+  x = min(x, __builtin_amdgcn_update_dpp(0, x, 0xB1, 0xF, 0xF, false));   // quad_perm [1,0,3,2]
+  x = min(x, __builtin_amdgcn_update_dpp(0, x, 0x4E, 0xF, 0xF, false));   // quad_perm [2,3,0,1]
+  x = min(x, __builtin_amdgcn_update_dpp(0, x, 0x141, 0xF, 0xF, false));  // row_half_mirror
+  x = min(x, __builtin_amdgcn_update_dpp(0, x, 0x140, 0xF, 0xF, false));  // row_mirror
   return x;
 }
 
@@ -1237,9 +1238,14 @@ __device__ __forceinline__ void rollout_body(const BinArgs& a, const ModelParams
     // =====================================================================
     // 6. projected Gauss-Seidel
     // =====================================================================
-    float Dl[S];  // actuator clamp corrections Delta, held by the DoF's owner lane/slot
+    float Dl[S];    // actuator clamp corrections Delta, held by the DoF's owner lane/slot
+    float rden[S];  // 1 / (1 - b_a dt D_jj), fixed for the step
 #pragma unroll
-    for (int s = 0; s < S; ++s) Dl[s] = 0.f;
+    for (int s = 0; s < S; ++s) {
+      Dl[s] = 0.f;
+      rden[s] = 1.f / (1.f - ba * dt * Dd[s]);
+    }
+    constexpr int kNoRow = 1 << 20;
     for (int sweep = 0; sweep < P.K; ++sweep) {
       // (i) actuator clamp rows in hinge order.  Every remaining row is
       // evaluated against the current velocity; rows whose new Delta equals
@@ -1248,24 +1254,23 @@ __device__ __forceinline__ void rollout_body(const BinArgs& a, const ModelParams
       // row in order.
       int last = -1;  // row-uniform: last hinge DoF applied in this sweep
       while (true) {
-        float first = 1e9f;
+        int first = kNoRow;
         float ndv[S];
 #pragma unroll
         for (int s = 0; s < S; ++s) {
           const int d = lane + 16 * s;
           const float u0 = fmaf(dt * Dd[s], Dl[s], vp[s]);
           const float sv_ = aS[s] - ba * u0;
-          const float den = 1.f - ba * dt * Dd[s];
-          float nd = 0.f;
-          if (sv_ > tmax) nd = (sv_ - tmax) / den;
-          else if (sv_ < -tmax) nd = (sv_ + tmax) / den;
+          // the part of the PD law beyond the torque limit, scaled
+          const float over = sv_ > tmax ? sv_ - tmax : (sv_ < -tmax ? sv_ + tmax : 0.f);
+          const float nd = over != 0.f ? over * rden[s] : 0.f;
           ndv[s] = nd;
-          if (d >= r0 && d < nvr && d > last && nd != Dl[s]) first = fminf(first, (float)d);
+          if (d >= r0 && d < nvr && d > last && nd != Dl[s]) first = min(first, d);
         }
-        first = row_min(first);
-        if (__builtin_amdgcn_ballot_w64(first < 1e8f) == 0) break;  // no row of any variant changes
-        if (first < 1e8f) {  // row-uniform
-          const int j = (int)first;
+        first = row_min_i(first);
+        if (__builtin_amdgcn_ballot_w64(first < kNoRow) == 0) break;  // no row of any variant changes
+        if (first < kNoRow) {  // row-uniform
+          const int j = first;
           float dl = 0.f;
 #pragma unroll
           for (int s = 0; s < S; ++s) {
@@ -1280,8 +1285,8 @@ __device__ __forceinline__ void rollout_body(const BinArgs& a, const ModelParams
 #pragma unroll
           for (int s = 0; s < S; ++s) {
             const int d = lane + 16 * s;
-            const float mcol = (d < NVC) ? sh.A[d * MST + cj] : 0.f;
-            vp[s] = fmaf(mcol, e, vp[s]);
+            const float mcol = sh.A[(d < NVC ? d : NVC - 1) * MST + cj];  // unmasked read
+            vp[s] = fmaf(d < NVC ? mcol : 0.f, e, vp[s]);
           }
           last = j;
         }

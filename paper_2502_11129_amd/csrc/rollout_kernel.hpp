@@ -205,18 +205,46 @@ struct alignas(16) GroupLds {
 // Builds J (normal z, tangents x, y) of the point x for the lane's DoF slots,
 // W = M~^-1 J^T, the row denominators and cross terms, and the solver scalars.
 // ----------------------------------------------------------------------------
+// Column C of three mat-vecs: y_k[s] += Mi[s][C] * x_k(DoF C), with x_k(DoF C)
+// read from lane C mod 16 of the row by the multiply-add itself
+// (v_fmac_f32 with a row_newbcast DPP source), so the broadcast costs no
+// separate move.  Same single rounding as fmaf(Mi, x, y).  The leading s_nop
+// gives the two wait states a DPP source needs after a VALU write, which the
+// compiler does not track across inline assembly.  Every lane of an active row
+// takes part (row-uniform control flow), as DPP reads require.
+template <int L>
+__device__ __forceinline__ void fmac3_bcast(const float (&m)[1], float xa, float xb, float xc, float (&ya)[1],
+                                            float (&yb)[1], float (&yc)[1]) {
+  asm("s_nop 1\n\t"
+      "v_fmac_f32_dpp %0, %3, %6 row_newbcast:%7 row_mask:0xf bank_mask:0xf\n\t"
+      "v_fmac_f32_dpp %1, %4, %6 row_newbcast:%7 row_mask:0xf bank_mask:0xf\n\t"
+      "v_fmac_f32_dpp %2, %5, %6 row_newbcast:%7 row_mask:0xf bank_mask:0xf"
+      : "+v"(ya[0]), "+v"(yb[0]), "+v"(yc[0])
+      : "v"(xa), "v"(xb), "v"(xc), "v"(m[0]), "n"(L));
+}
+template <int L>
+__device__ __forceinline__ void fmac3_bcast(const float (&m)[2], float xa, float xb, float xc, float (&ya)[2],
+                                            float (&yb)[2], float (&yc)[2]) {
+  asm("s_nop 1\n\t"
+      "v_fmac_f32_dpp %0, %6, %9 row_newbcast:%11 row_mask:0xf bank_mask:0xf\n\t"
+      "v_fmac_f32_dpp %1, %6, %10 row_newbcast:%11 row_mask:0xf bank_mask:0xf\n\t"
+      "v_fmac_f32_dpp %2, %7, %9 row_newbcast:%11 row_mask:0xf bank_mask:0xf\n\t"
+      "v_fmac_f32_dpp %3, %7, %10 row_newbcast:%11 row_mask:0xf bank_mask:0xf\n\t"
+      "v_fmac_f32_dpp %4, %8, %9 row_newbcast:%11 row_mask:0xf bank_mask:0xf\n\t"
+      "v_fmac_f32_dpp %5, %8, %10 row_newbcast:%11 row_mask:0xf bank_mask:0xf"
+      : "+v"(ya[0]), "+v"(ya[1]), "+v"(yb[0]), "+v"(yb[1]), "+v"(yc[0]), "+v"(yc[1])
+      : "v"(xa), "v"(xb), "v"(xc), "v"(m[0]), "v"(m[1]), "n"(L));
+}
+
 template <int S, int NVC, int C = 0>
 __device__ __forceinline__ void matvec_bcast3(const float (&Mi)[S][NVC], const float (&a)[S], const float (&b)[S],
                                               const float (&c)[S], float (&ya)[S], float (&yb)[S], float (&yc)[S]) {
+  static_assert(S == 1 || S == 2, "at most 32 DoF slots per variant");
   if constexpr (C < NVC) {
-    const float va = row_bcast<C % 16>(a[C / 16]), vb = row_bcast<C % 16>(b[C / 16]),
-                vc = row_bcast<C % 16>(c[C / 16]);
+    float m[S];
 #pragma unroll
-    for (int s = 0; s < S; ++s) {
-      ya[s] = fmaf(Mi[s][C], va, ya[s]);
-      yb[s] = fmaf(Mi[s][C], vb, yb[s]);
-      yc[s] = fmaf(Mi[s][C], vc, yc[s]);
-    }
+    for (int s = 0; s < S; ++s) m[s] = Mi[s][C];
+    fmac3_bcast<C % 16>(m, a[C / 16], b[C / 16], c[C / 16], ya, yb, yc);
     matvec_bcast3<S, NVC, C + 1>(Mi, a, b, c, ya, yb, yc);
   }
 }

@@ -180,7 +180,7 @@ struct alignas(16) GroupLds {
   static constexpr int A_WORDS = A_BODY > A_MAT ? A_BODY : A_MAT;
   static_assert(A_MAT % 4 == 0, "the matrix area is cleared with 16-byte stores");
   float A[A_WORDS];
-  float WO[NBC][12];        // hinge axis w, anchor o (world), composite force C S of the hinge
+  float WO[NBC][12];        // hinge axis w, linear part (o - p0) x w of its motion S, composite force C S
   int par[NBC];
   int ccount[NBC];          // active-corner mask per body
   float cl[NCR][(BALL || SELF) ? kListWordsBall : kListWords];  // contact list entries (ListWord)
@@ -600,10 +600,15 @@ __device__ __forceinline__ void rollout_body(const BinArgs& a, const ModelParams
     a.xy0[2 * vid] = (r0 == 6) ? p0[0] : 0.f;
     a.xy0[2 * vid + 1] = (r0 == 6) ? p0[1] : 0.f;
   }
+  unsigned ancS[SB];  // ancestors-or-self mask of the lane's body slots (CRBA)
 #pragma unroll
   for (int t = 0; t < SB; ++t) {
     const int b = lane + 16 * t;
-    if (b < nb) sh.par[b] = __float_as_int(bodyv[b * BW_WORDS + BW_PARENT]);
+    ancS[t] = 0u;
+    if (b < nb) {
+      sh.par[b] = __float_as_int(bodyv[b * BW_WORDS + BW_PARENT]);
+      ancS[t] = __float_as_uint(bodyv[b * BW_WORDS + BW_ANCESTORS]);
+    }
   }
   for (int j = lane; j < 2 * NBC + 4; j += 16) sh.lv[j] = lvl[j];
   int npairs = 0;  // row-uniform
@@ -661,7 +666,7 @@ __device__ __forceinline__ void rollout_body(const BinArgs& a, const ModelParams
         const int b = sh.lv[i];
         const float* rec = bodyv + (size_t)b * BW_WORDS;
         m33 R;
-        f3 p, w, o;
+        f3 p, w, o, sl = mk(0.f, 0.f, 0.f);
         sv V, A;
         if (b == 0) {
           R = R0;
@@ -693,7 +698,8 @@ __device__ __forceinline__ void rollout_body(const BinArgs& a, const ModelParams
           o = pl + mul(Rl, mk(rec[BW_AP], rec[BW_AP + 1], rec[BW_AP + 2]));
           p = o - mul(R, mk(rec[BW_AC], rec[BW_AC + 1], rec[BW_AC + 2]));
           w = mul(R, u);
-          const sv St = {w * thd, cross3(o - P0, w) * thd};
+          sl = cross3(o - P0, w);
+          const sv St = {w * thd, sl * thd};
           V = {Vl.a + St.a, Vl.l + St.l};
           const sv c = crm(Vl, St);
           A = {Al.a + c.a, Al.l + c.l};
@@ -705,7 +711,7 @@ __device__ __forceinline__ void rollout_body(const BinArgs& a, const ModelParams
         dst[12] = V.a.x; dst[13] = V.a.y; dst[14] = V.a.z; dst[15] = V.l.x; dst[16] = V.l.y; dst[17] = V.l.z;
         dst[18] = A.a.x; dst[19] = A.a.y; dst[20] = A.a.z; dst[21] = A.l.x; dst[22] = A.l.y; dst[23] = A.l.z;
         sh.WO[b][0] = w.x; sh.WO[b][1] = w.y; sh.WO[b][2] = w.z;
-        sh.WO[b][3] = o.x; sh.WO[b][4] = o.y; sh.WO[b][5] = o.z;
+        sh.WO[b][3] = sl.x; sh.WO[b][4] = sl.y; sh.WO[b][5] = sl.z;
         // box-plane contact: 8 corners, bits (x, y, z) of the corner index = sign
         if (b >= 1 || r0 == 6) {
           const f3 h = mk(rec[BW_HALF], rec[BW_HALF + 1], rec[BW_HALF + 2]);
@@ -942,9 +948,7 @@ __device__ __forceinline__ void rollout_body(const BinArgs& a, const ModelParams
         own[10] = F.a.x; own[11] = F.a.y; own[12] = F.a.z;
         own[13] = F.l.x; own[14] = F.l.y; own[15] = F.l.z;
         if (b >= 1) {
-          const f3 w = mk(sh.WO[b][0], sh.WO[b][1], sh.WO[b][2]);
-          const f3 o = mk(sh.WO[b][3], sh.WO[b][4], sh.WO[b][5]);
-          const sv Sb = {w, cross3(o - P0, w)};
+          const sv Sb = {mk(sh.WO[b][0], sh.WO[b][1], sh.WO[b][2]), mk(sh.WO[b][3], sh.WO[b][4], sh.WO[b][5])};
           sh.cvec[r0 + b - 1] = dot3(Sb.a, F.a) + dot3(Sb.l, F.l);
           const sv Fc = imul(C, Sb);
           sh.WO[b][6] = Fc.a.x; sh.WO[b][7] = Fc.a.y; sh.WO[b][8] = Fc.a.z;
@@ -1012,16 +1016,19 @@ __device__ __forceinline__ void rollout_body(const BinArgs& a, const ModelParams
         if (b >= 1 && b < nb) {
           const int d = r0 + b - 1;
           const sv Fcb = {mk(sh.WO[b][6], sh.WO[b][7], sh.WO[b][8]), mk(sh.WO[b][9], sh.WO[b][10], sh.WO[b][11])};
-          int j = b;
-          while (j >= 1) {
+          // the hinges of b and its ancestors (the core has none), by the
+          // ancestor mask: no pointer chase through LDS
+          unsigned am = ancS[t] & ~1u;
+          while (am) {
+            const int j = __builtin_ctz(am);
+            am &= am - 1u;
             const int dj = r0 + j - 1;
             const f3 wj = mk(sh.WO[j][0], sh.WO[j][1], sh.WO[j][2]);
-            const f3 oj = mk(sh.WO[j][3], sh.WO[j][4], sh.WO[j][5]);
-            float val = dot3(wj, Fcb.a) + dot3(cross3(oj - P0, wj), Fcb.l);
+            const f3 slj = mk(sh.WO[j][3], sh.WO[j][4], sh.WO[j][5]);
+            float val = dot3(wj, Fcb.a) + dot3(slj, Fcb.l);
             if (j == b) val += dt * ba;
             Ml[d * MST + dj] = val;
             Ml[dj * MST + d] = val;
-            j = sh.par[j];
           }
           if (r0 == 6) {
             const f3 ra = mulT(R0, Fcb.a), rl = mulT(R0, Fcb.l);
@@ -1194,7 +1201,8 @@ __device__ __forceinline__ void rollout_body(const BinArgs& a, const ModelParams
         const int b = d - r0 + 1;
         bodyOfDof[s] = b;
         ang[s] = mk(sh.WO[b][0], sh.WO[b][1], sh.WO[b][2]);
-        cst[s] = mk(0.f, 0.f, 0.f) - cross3(ang[s], mk(sh.WO[b][3], sh.WO[b][4], sh.WO[b][5]));
+        // w x (x - o) = w x x + (o - p0) x w + p0 x w
+        cst[s] = (mk(0.f, 0.f, 0.f) - cross3(ang[s], P0)) + mk(sh.WO[b][3], sh.WO[b][4], sh.WO[b][5]);
       } else if (BALL && d < nv) {
         // ball: spin e_k gives e_k x (x - cb), centre velocity e_k gives e_k
         const int k = d - nvr;

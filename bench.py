@@ -127,7 +127,9 @@ def main():
                    for k, v in json.loads(args.options).items()}
     elif not args.no_autotune:
         from paper_2502_11129_amd.autotune import autotune
-        options, trials = autotune(pop, T_pilot=min(T, 1000), log=lambda m: print(m, file=sys.stderr, flush=True))
+        # pilots over the whole horizon: the first steps of a dropped population
+        # (free fall, few contacts) rank the launch options differently
+        options, trials = autotune(pop, T_pilot=T, log=lambda m: print(m, file=sys.stderr, flush=True))
     sim = Simulator(pop, time_launches=True, **options)
     stream = torch.cuda.current_stream()
     for _ in range(args.warmup):

@@ -24,7 +24,7 @@ def _time_rollout(pop, T, reps, **opts):
     import torch
     sim = S.Simulator(pop, **opts)
     st = torch.cuda.current_stream()
-    sim.rollout(T)                                  # warm-up
+    sim.rollout(min(T, 250))                        # warm-up (first launches, caches)
     best = float("inf")
     for _ in range(reps):
         e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)

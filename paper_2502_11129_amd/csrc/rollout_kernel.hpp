@@ -1303,8 +1303,8 @@ __device__ __forceinline__ void rollout_body(const BinArgs& a, const ModelParams
           ndv[s] = nd;
           if (d >= r0 && d < nvr && d > last && nd != Dl[s]) first = min(first, d);
         }
-        first = row_min_i(first);
         if (__builtin_amdgcn_ballot_w64(first < kNoRow) == 0) break;  // no row of any variant changes
+        first = row_min_i(first);
         if (first < kNoRow) {  // row-uniform
           const int j = first;
           float dl = 0.f;

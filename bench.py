@@ -135,16 +135,18 @@ def main():
     for _ in range(args.warmup):
         sim.rollout(T)
     torch.cuda.synchronize()
-    ev0 = torch.cuda.Event(enable_timing=True)
-    ev1 = torch.cuda.Event(enable_timing=True)
+    # one event between consecutive rollouts (recording adds no host sync):
+    # the whole span gives the value, the single rollouts its spread
+    evs = [torch.cuda.Event(enable_timing=True) for _ in range(args.steps + 1)]
     t0 = time.perf_counter()
-    ev0.record(stream)
-    for _ in range(args.steps):
+    evs[0].record(stream)
+    for i in range(args.steps):
         sim.rollout(T)
-    ev1.record(stream)
+        evs[i + 1].record(stream)
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
-    gpu_ms = ev0.elapsed_time(ev1)
+    gpu_ms = evs[0].elapsed_time(evs[-1])
+    rollout_ms = [evs[i].elapsed_time(evs[i + 1]) for i in range(args.steps)]
     ms_per_step = gpu_ms / args.steps
     vsteps = pop.n_variants * T
     value = vsteps * args.steps / (gpu_ms / 1e3)
@@ -217,7 +219,20 @@ def main():
     if args.surrogate:
         from paper_2502_11129_amd.screening import run as screening_run
         out["surrogate"] = screening_run(log=lambda m: print(m, file=sys.stderr, flush=True))
+    out["rollouts"] = rollout_spread(rollout_ms, pop.n_variants * T)
     print(json.dumps(out), flush=True)
+
+
+def rollout_spread(ms, vsteps):
+    """Per-rollout times of the timed region, the median throughput and a 95 %
+    confidence interval of the mean throughput (Student t over the rollouts)."""
+    v = np.asarray([vsteps / (m / 1e3) for m in ms], np.float64)
+    rec = {"ms": [round(m, 3) for m in ms], "median_value": float(np.median(v)), "ci95_value": None}
+    if len(v) >= 2:
+        from scipy.stats import t as student_t
+        half = float(student_t.ppf(0.975, len(v) - 1) * v.std(ddof=1) / np.sqrt(len(v)))
+        rec["ci95_value"] = [float(v.mean() - half), float(v.mean() + half)]
+    return rec
 
 
 if __name__ == "__main__":

@@ -44,6 +44,8 @@ def parse():
     ap.add_argument("--copy-probe", action="store_true",
                     help="also run one plain 1 GiB device copy (calibrates profiler byte counters)")
     ap.add_argument("--cpu-sample-steps", type=int, default=4000)
+    ap.add_argument("--no-peak-probe", action="store_true",
+                    help="skip the microbenchmarks that measure the attainable FP32, BF16 MFMA and copy peaks")
     ap.add_argument("--surrogate", action="store_true",
                     help="also run one surrogate-screened generation (200k labels, 1M pool) and report it")
     return ap.parse_args()
@@ -87,9 +89,10 @@ def recorded_traffic(kernel, steps_per_launch):
     with open(src, "rb") as f:
         if hashlib.sha256(f.read()).hexdigest() != rec["kernel_source_sha256"]:
             return None
-    if steps_per_launch != rec["steps_per_launch"] or kernel not in rec["per_launch_kib"]:
+    table = rec["per_launch_kib_by_steps_per_launch"].get(str(steps_per_launch), {})
+    if kernel not in table:
         return None
-    fetch, write = rec["per_launch_kib"][kernel]
+    fetch, write = table[kernel]
     return (fetch * rec["scale"]["FETCH_SIZE"] + write * rec["scale"]["WRITE_SIZE"]) * 1024.0
 
 
@@ -220,6 +223,14 @@ def main():
         from paper_2502_11129_amd.screening import run as screening_run
         out["surrogate"] = screening_run(log=lambda m: print(m, file=sys.stderr, flush=True))
     out["rollouts"] = rollout_spread(rollout_ms, pop.n_variants * T)
+    if not args.no_peak_probe:
+        # attainable peaks of this GPU (after the timed region), beside the published ones
+        from paper_2502_11129_amd import probe
+        peaks = probe.all_peaks()
+        out["peak_probe"] = peaks
+        out["roofline"]["peak_measured"] = peaks["fp32_fma_tflops"]
+        out["roofline"]["frac_of_measured"] = achieved / peaks["fp32_fma_tflops"]
+        out["roofline"]["all_bins_frac_of_measured"] = all_bins / peaks["fp32_fma_tflops"]
     print(json.dumps(out), flush=True)
 
 

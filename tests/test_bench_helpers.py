@@ -33,7 +33,7 @@ def _record(tmp_path, sha, steps=1000):
     src.write_text("// kernel source stand-in\n")
     (tmp_path / "profiles").mkdir()
     rec = {"kernel_source": "kernel.hpp", "kernel_source_sha256": sha, "scale": {"FETCH_SIZE": 2.0, "WRITE_SIZE": 1.0},
-           "per_launch_kib": {"rollout_kernel<24, 2, 8, false, false>": [100.0, 30.0]}, "steps_per_launch": steps}
+           "per_launch_kib_by_steps_per_launch": {str(steps): {"rollout_kernel<24, 2, 8, false, false>": [100.0, 30.0]}}}
     (tmp_path / "profiles" / "rollout_traffic.json").write_text(json.dumps(rec))
     return hashlib.sha256(src.read_bytes()).hexdigest()
 
@@ -55,7 +55,15 @@ def test_committed_traffic_record_names_profiled_kernels():
         rec = json.load(f)
     assert os.path.exists(os.path.join(ROOT, rec["kernel_source"]))
     assert rec["scale"]["FETCH_SIZE"] > 0 and rec["scale"]["WRITE_SIZE"] > 0
-    assert all(k.startswith("rollout_kernel<") and len(v) == 2 for k, v in rec["per_launch_kib"].items())
+    for steps, table in rec["per_launch_kib_by_steps_per_launch"].items():
+        assert int(steps) > 0
+        assert all(k.startswith("rollout_kernel<") and len(v) == 2 for k, v in table.items())
+
+
+def test_committed_traffic_record_matches_the_kernel_source():
+    """The record is re-taken whenever the rollout kernel changes: a stale
+    record would silently drop the bench line's traffic figure."""
+    assert bench.recorded_traffic("rollout_kernel<24, 2, 8, false, false>", 1000) is not None
 
 
 def test_more_than_one_gpu_is_refused_with_a_message():

@@ -43,9 +43,11 @@ def candidates_ncr(nvc, ball=False, self_collision=False):
     return sorted({k[2] for k in S.kernel_variants(ball, self_collision) if k[0] == nvc})
 
 
-def autotune(pop, T_pilot=1000, reps=2, log=None, cache=None):
-    """Returns (best options dict, list of trial records).  `cache`: optional
-    JSON file path keyed by the population's DoF/body signature."""
+def autotune(pop, T_pilot=1000, reps=3, log=None, cache=None, min_gain=0.01):
+    """Returns (best options dict, list of trial records).  A setting is kept
+    only when its pilot (best of `reps` rollouts) beats the current best by
+    more than `min_gain`.  `cache`: optional JSON file path keyed by the
+    population's DoF/body signature."""
     import numpy as np
     key = None
     if cache:
@@ -80,7 +82,7 @@ def autotune(pop, T_pilot=1000, reps=2, log=None, cache=None):
                     t = run(cand)
                 except S.SimError:
                     continue                       # e.g. a bin outside the single-launch kernel
-                if t < best_t * 0.98:            # keep only clear wins
+                if t < best_t * (1.0 - min_gain):            # keep only clear wins
                     best, best_t = cand, t
         probe = S.Handle(pop, **best)
         nvcs = sorted({b[0] for b in probe.bins()})
@@ -95,7 +97,7 @@ def autotune(pop, T_pilot=1000, reps=2, log=None, cache=None):
                     t = run(cand)
                 except S.SimError:
                     continue                      # no kernel with that budget for this body capacity
-                if t < best_t * 0.98:
+                if t < best_t * (1.0 - min_gain):
                     best, best_t = cand, t
         return best, best_t
 

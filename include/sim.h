@@ -159,6 +159,12 @@ typedef struct {
  *                         branch-induced sparsity: every step touches only
  *                         a DoF's ancestors); the two agree to rounding.  The
  *                         GPU kernels always form the dense inverse.
+ *  min_nv_capacity        0 or a DoF capacity (8, 12, ..., 28): variants with
+ *                         fewer DoFs go to bins of this capacity (fewer bins)
+ *  slots32_min_nvc        with min_body_slots = 32: only bins of this DoF
+ *                         capacity and above use 32-body kernels (0 = all);
+ *                         smaller capacities keep the smallest body capacity
+ *                         that holds each variant
  */
 typedef struct {
   int32_t contacts_in_registers;
@@ -170,7 +176,8 @@ typedef struct {
   int32_t time_launches;
   int32_t single_launch;
   int32_t host_factorization;
-  int32_t reserved[2];
+  int32_t min_nv_capacity;
+  int32_t slots32_min_nvc;
 } sim_options;
 
 #define SIM_FACTOR_DENSE 0

@@ -101,11 +101,21 @@ def autotune(pop, T_pilot=1000, reps=3, log=None, cache=None, min_gain=0.01):
                     best, best_t = cand, t
         return best, best_t
 
-    # two starting points: smallest body capacity per variant (more bins, some
-    # kernels with fewer registers) and every variant in 32-body kernels (fewer bins)
-    results = []
-    for slots in (0, 32):
-        start_opts = dict(min_body_slots=slots, streams=0, steps_per_launch=0, ncr_by_nvc={})
+    # starting points: smallest body capacity per variant (more bins, some
+    # kernels with fewer registers), every variant in 32-body kernels (fewer
+    # bins), and 32-body kernels only from 20 DoFs on with the smaller variants
+    # merged into one 16-DoF, 16-body bin (whose kernels run two waves per
+    # SIMD); a start that gives the same bins as an earlier one is skipped
+    results, seen = [], []
+    for extra in (dict(min_body_slots=0), dict(min_body_slots=32),
+                  dict(min_body_slots=32, slots32_min_nvc=20, min_nv_capacity=16)):
+        start_opts = dict(streams=0, steps_per_launch=0, ncr_by_nvc={}, **extra)
+        probe = S.Handle(pop, **start_opts)
+        layout = sorted(tuple(b[:4]) for b in probe.bins())
+        probe.close()
+        if layout in seen:
+            continue
+        seen.append(layout)
         results.append(descend(start_opts, run(start_opts)))
     best, best_t = min(results, key=lambda r: r[1])
     if cache:

@@ -512,13 +512,14 @@ __device__ __forceinline__ int row_min_i(int x) {
 // ----------------------------------------------------------------------------
 // The kernel.
 // ----------------------------------------------------------------------------
-// Two waves per SIMD (at most 256 registers) for the families whose LDS area
-// allows it (16 body slots) and whose registers fit without spills (one DoF
-// slot per lane, few contacts kept in registers); the others may use the
-// whole register file and run one wave per SIMD.
+// A budget of 256 registers (two waves per SIMD) for the families that fit it
+// without spills: one DoF slot per lane with at most 2 contacts in registers,
+// and the 16-DoF families with 8.  Their LDS areas then admit two waves per
+// SIMD with 16 body slots and 1.5 with 32.  The others may use the whole
+// register file and run one wave per SIMD.
 template <int NVC, int SB, int NCR>
 struct WavesPerSimd {
-  static constexpr int value = (SB == 1 && NCR <= 2 && NVC <= 16) ? 2 : 1;
+  static constexpr int value = ((SB == 1 && NCR <= 2 && NVC <= 16) || (NCR == 8 && NVC == 16)) ? 2 : 1;
 };
 
 // One workgroup (one wave, four variants) of a bin: `block` is the

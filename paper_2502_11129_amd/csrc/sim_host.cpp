@@ -294,6 +294,9 @@ int sim_create(const sim_model_desc* d, const sim_options* opts, sim_handle** ou
     if (o.time_launches && o.use_graph) return bad("time_launches and use_graph cannot be combined");
     if (o.host_factorization != SIM_FACTOR_DENSE && o.host_factorization != SIM_FACTOR_TREE)
       return bad("host_factorization must be SIM_FACTOR_DENSE or SIM_FACTOR_TREE");
+    auto cap_or_zero = [](int v) { return v == 0 || (v >= 8 && v <= kMaxNv && v % 4 == 0); };
+    if (!cap_or_zero(o.min_nv_capacity)) return bad("min_nv_capacity must be 0 or a DoF capacity 8, 12, ..., 28");
+    if (!cap_or_zero(o.slots32_min_nvc)) return bad("slots32_min_nvc must be 0 or a DoF capacity 8, 12, ..., 28");
     for (int k = 0; k < 6; ++k)
       if (o.ncr_by_nvc[k] < 0) return bad("ncr_by_nvc entries must be >= 0");
     hp->steps_per_launch = o.steps_per_launch > 0 ? o.steps_per_launch : kStepsPerLaunch;
@@ -378,8 +381,9 @@ int sim_create(const sim_model_desc* d, const sim_options* opts, sim_handle** ou
     int nvc = 0;
     for (int c : kNvCaps)
       if (hp->nv[i] <= c) { nvc = c; break; }
+    if (nvc < hp->opts.min_nv_capacity) nvc = hp->opts.min_nv_capacity;
     int sb_need = info[i].nb > 16 ? 2 : 1;
-    if (hp->opts.min_body_slots == 32) sb_need = 2;
+    if (hp->opts.min_body_slots == 32 && nvc >= hp->opts.slots32_min_nvc) sb_need = 2;
     // smallest compiled (nv capacity, body slots) that holds the variant
     int sb = 0;
     for (; nvc <= kMaxNv; nvc += 4) {

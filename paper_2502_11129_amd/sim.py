@@ -38,7 +38,7 @@ class sim_options(C.Structure):
     _fields_ = [("contacts_in_registers", C.c_int32), ("use_graph", C.c_int32), ("steps_per_launch", C.c_int32),
                 ("streams", C.c_int32), ("min_body_slots", C.c_int32), ("ncr_by_nvc", C.c_int32 * 6),
                 ("time_launches", C.c_int32), ("single_launch", C.c_int32), ("host_factorization", C.c_int32),
-                ("reserved", C.c_int32 * 2)]
+                ("min_nv_capacity", C.c_int32), ("slots32_min_nvc", C.c_int32)]
 
 
 NVC_CAPS = (8, 12, 16, 20, 24, 28)
@@ -46,7 +46,8 @@ HOST_FACTORIZATIONS = ("dense", "tree")   # SIM_FACTOR_DENSE, SIM_FACTOR_TREE
 
 
 def make_options(contacts_in_registers=0, use_graph=False, steps_per_launch=0, streams=0, min_body_slots=0,
-                 ncr_by_nvc=None, time_launches=False, single_launch=False, host_factorization="dense"):
+                 ncr_by_nvc=None, time_launches=False, single_launch=False, host_factorization="dense",
+                 min_nv_capacity=0, slots32_min_nvc=0):
     o = sim_options()
     o.contacts_in_registers = int(contacts_in_registers)
     o.use_graph = int(bool(use_graph))
@@ -56,6 +57,8 @@ def make_options(contacts_in_registers=0, use_graph=False, steps_per_launch=0, s
     o.time_launches = int(bool(time_launches))
     o.single_launch = int(bool(single_launch))
     o.host_factorization = HOST_FACTORIZATIONS.index(host_factorization)
+    o.min_nv_capacity = int(min_nv_capacity)
+    o.slots32_min_nvc = int(slots32_min_nvc)
     for nvc, v in (ncr_by_nvc or {}).items():
         o.ncr_by_nvc[NVC_CAPS.index(int(nvc))] = int(v)
     return o

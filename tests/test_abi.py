@@ -115,3 +115,24 @@ def test_calls_before_bind_are_state_errors():
     assert rc == S.SIM_E_STATE
     assert h.lib.sim_bind(h.h, None, 0, None) == S.SIM_E_INVALID
     assert h.lib.sim_bind(h.h, C.c_void_p(256), 16, None) == S.SIM_E_NOMEM
+
+
+def test_packing_options_min_nv_capacity_and_slots32_min_nvc():
+    """min_nv_capacity merges the smaller variants up to one DoF capacity;
+    slots32_min_nvc limits the 32-body kernels to the larger capacities.
+    Every variant still lands in a bin that holds it."""
+    pop = W.random_trees(256)
+    h = S.Handle(pop, min_body_slots=32, slots32_min_nvc=20, min_nv_capacity=16, ncr_by_nvc={16: 8})
+    bins = h.bins()
+    caps = {b[0]: b[1] for b in bins}
+    assert min(caps) == 16 and caps[16] == 16                      # one 16-DoF, 16-body bin
+    assert all(slots == 32 for nvc, slots in caps.items() if nvc >= 20)
+    vb = np.asarray(h.variant_bins())
+    for i in range(pop.n_variants):
+        nvc, slots = bins[vb[i]][0], bins[vb[i]][1]
+        assert pop.nv[i] <= nvc and pop.n_bodies[i] <= slots
+    assert sum(b[3] for b in bins) == pop.n_variants
+    h.close()
+    for bad in (dict(min_nv_capacity=10), dict(slots32_min_nvc=32), dict(min_nv_capacity=-4)):
+        with pytest.raises(S.SimError):
+            S.Handle(pop, **bad)

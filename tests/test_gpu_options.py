@@ -26,6 +26,8 @@ def test_options_give_bitwise_identical_results():
     for opts in (dict(streams=1), dict(streams=2), dict(steps_per_launch=97), dict(min_body_slots=32),
                  dict(ncr_by_nvc={24: 2, 28: 2, 20: 2}), dict(ncr_by_nvc={28: 12}),
                  dict(min_body_slots=32, single_launch=True),
+                 dict(min_body_slots=32, slots32_min_nvc=20, min_nv_capacity=16, ncr_by_nvc={16: 8}),
+                 dict(min_body_slots=32, ncr_by_nvc={16: 8}),
                  dict(min_body_slots=32, single_launch=True, steps_per_launch=70)):
         _say(f"[options] {opts}")
         s = Simulator(pop, **opts)

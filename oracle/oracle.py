@@ -83,13 +83,26 @@ def cholesky(A: np.ndarray) -> np.ndarray:
 
 
 class Oracle:
-    """Reference simulator over a population (FP64, or FP32 with precision=32)."""
+    """Reference simulator over a population (FP64, or FP32 with precision=32).
 
-    def __init__(self, pop, precision: int = 64, pgs_iters: int | None = None, params: dict | None = None):
+    The model is the one a float32 simulator is handed: the per-body arrays
+    and, unless ``float32_constants`` is False, the scalar constants (gains,
+    contact law, time step, gravity) rounded to float32 and then computed
+    with in FP64.  The time step matters most: the controller's clock
+    t = k dt multiplies its rounding by k, so over 30 000 steps the float32
+    and the decimal 0.002 s put the CPG clocks 3 microseconds apart.  The
+    pins of the oracle itself pass False to take the constants exactly."""
+
+    def __init__(self, pop, precision: int = 64, pgs_iters: int | None = None, params: dict | None = None,
+                 float32_constants: bool = True):
         lib = _load()
         prm = dict(pop.params)
         if params:
             prm.update(params)
+        if float32_constants:
+            for key in ("kp", "kd", "tau_max", "k_contact", "b_contact", "dt"):
+                prm[key] = float(np.float32(prm[key]))
+            prm["gravity"] = tuple(float(x) for x in np.asarray(prm["gravity"], np.float32))
         K = int(prm["pgs_iters"] if pgs_iters is None else pgs_iters)
         g = prm["gravity"]
         self._keep = dict(

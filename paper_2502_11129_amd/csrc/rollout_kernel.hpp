@@ -103,6 +103,34 @@ __device__ __forceinline__ float recip(float x) {
   return fmaf(fmaf(-x, r, 1.f), r, r);
 }
 
+// sin and cos of a moderate angle (joint angles, CPG phases in [0, 2 pi)):
+// Cody-Waite reduction by the nearest multiple k of pi/2 (pi/2 split into
+// its float value and the remainder), then the Taylor series of sin and cos
+// on |r| <= pi/4 up to r^9 and r^10, whose next terms stay below 2e-9; the
+// quadrant k mod 4 swaps and signs the pair.  About half an ulp of absolute
+// error, against about 1e-6 for the hardware v_sin/v_cos, whose bias
+// accumulates over tens of thousands of steps.
+__device__ __forceinline__ void sincos_moderate(float x, float* sn, float* cs) {
+  const float k = rintf(x * 0.636619772f);
+  float r = fmaf(-k, 1.57079637f, x);
+  r = fmaf(-k, -4.37113883e-8f, r);
+  const float r2 = r * r;
+  float ps = fmaf(r2, (float)(1.0 / 362880.0), (float)(-1.0 / 5040.0));
+  ps = fmaf(r2, ps, (float)(1.0 / 120.0));
+  ps = fmaf(r2, ps, (float)(-1.0 / 6.0));
+  const float s = fmaf(r * r2, ps, r);
+  float pc = fmaf(r2, (float)(-1.0 / 3628800.0), (float)(1.0 / 40320.0));
+  pc = fmaf(r2, pc, (float)(-1.0 / 720.0));
+  pc = fmaf(r2, pc, (float)(1.0 / 24.0));
+  pc = fmaf(r2, pc, -0.5f);
+  const float c = fmaf(r2, pc, 1.f);
+  const int q = (int)k & 3;
+  const float a = (q & 1) ? c : s;
+  const float b = (q & 1) ? s : c;
+  *sn = (q & 2) ? -a : a;
+  *cs = ((q + 1) & 2) ? -b : b;
+}
+
 struct m33 { float m[9]; };
 // column c (0..2, may differ across lanes) of R as a weighted sum with 0/1
 // weights (entries are finite): selects between elements of one array are
@@ -185,7 +213,7 @@ struct alignas(16) GroupLds {
   int ccount[NBC];          // active-corner mask per body
   float cl[NCR][(BALL || SELF) ? kListWordsBall : kListWords];  // contact list entries (ListWord)
   float cs[NCR][12];        // per-contact solver scalars
-  float th[NVC], thd[NVC];  // theta / thetadot by DoF
+  float sth[NVC], cth[NVC], thd[NVC];  // sin theta, cos theta, thetadot by DoF
   float cvec[NVC];          // bias c by DoF
   float cb[2][2 * NVC + 16];  // doubled broadcast buffers of the pivot column (+ a sink
                               // for the lanes past the last DoF, which store unmasked)
@@ -648,9 +676,11 @@ __device__ __forceinline__ void rollout_body(const BinArgs& a, const ModelParams
     //    depth level at a time.  Corner tests of each body.
     // =====================================================================
 #pragma unroll
-    for (int s = 0; s < S; ++s) {
+    for (int s = 0; s < S; ++s) {  // every joint's sine and cosine at once, off the level chain
       const int d = lane + 16 * s;
-      if (d < NVC) { sh.th[d] = thS[s]; sh.thd[d] = vS[s]; }
+      float sn, cn;
+      sincos_moderate(thS[s], &sn, &cn);
+      if (d < NVC) { sh.sth[d] = sn; sh.cth[d] = cn; sh.thd[d] = vS[s]; }
     }
     f3 wb = mk(row_bcast<0>(vS[0]), row_bcast<1>(vS[0]), row_bcast<2>(vS[0]));
     f3 vb = mk(row_bcast<3>(vS[0]), row_bcast<4>(vS[0]), row_bcast<5>(vS[0]));
@@ -688,11 +718,8 @@ __device__ __forceinline__ void rollout_body(const BinArgs& a, const ModelParams
           const sv Vl = {mk(pr[12], pr[13], pr[14]), mk(pr[15], pr[16], pr[17])};
           const sv Al = {mk(pr[18], pr[19], pr[20]), mk(pr[21], pr[22], pr[23])};
           const int dof = r0 + b - 1;
-          const float th = sh.th[dof], thd = sh.thd[dof];
+          const float sn = sh.sth[dof], cs = sh.cth[dof], thd = sh.thd[dof];
           const f3 u = mk(rec[BW_AXIS], rec[BW_AXIS + 1], rec[BW_AXIS + 2]);
-          // hardware sine/cosine: joint angles stay within a few radians,
-          // where their absolute error (about 1e-6) is far below the step's
-          const float sn = __sinf(th), cs = __cosf(th);
           const m33 E = matmul(quat_rot(rec[BW_RQ], rec[BW_RQ + 1], rec[BW_RQ + 2], rec[BW_RQ + 3]),
                                axis_rot_acc(u, sn, cs));
           R = matmul(Rl, E);
@@ -1170,7 +1197,9 @@ __device__ __forceinline__ void rollout_body(const BinArgs& a, const ModelParams
       const float* rec = bodyv + (size_t)b * BW_WORDS;
       double ph = (double)rec[BW_CPG + 1] * tk + (double)rec[BW_CPG + 2];
       ph -= 6.283185307179586 * floor(ph * 0.15915494309189535);
-      const float target = rec[BW_CPG] * __sinf((float)ph);  // phase reduced to [0, 2 pi)
+      float sph, cph;
+      sincos_moderate((float)ph, &sph, &cph);  // phase reduced to [0, 2 pi)
+      const float target = rec[BW_CPG] * sph;
       aS[s] = hinge ? kp * (target - thS[s]) : 0.f;
       float rhs = -dt * cS[s];
       if (hinge) rhs += dt * (aS[s] - ba * vS[s]);

@@ -147,6 +147,26 @@ def teacher_forced(pop, sim, ks, threads=THREADS):
     return worst, in_band, np.array(errs)
 
 
+class FloatOracleSim:
+    """The float32 instance of the oracle behind the simulator's set_state /
+    step / get_state calls, so that teacher_forced measures the per-step
+    error single precision alone makes at the same states."""
+
+    def __init__(self, pop, threads=THREADS):
+        self.o = O.Oracle(pop, precision=32)
+        self.threads = threads
+
+    def set_state(self, q, v, k):
+        self.o.set_state(np.asarray(q, np.float64), np.asarray(v, np.float64), k)
+
+    def step(self, n):
+        self.o.step(n, self.threads)
+
+    def get_state(self):
+        q, v, k, _ = self.o.get_state()
+        return q, v, k
+
+
 def fitness_gate(F_gpu, F_ref, F_32, F_pert=None):
     """Per variant: ok if within FIT_TOL of the FP64 oracle.  A variant is
     FP32-sensitive when the float oracle, or any FP64 run started from the

@@ -10,7 +10,8 @@ import pytest
 from oracle import oracle as O
 from paper_2502_11129_amd import workloads as W
 
-from _parity import STEP_TOL, THREADS, fitness_gate, perturbed_fitness, teacher_forced
+from _parity import (FIT_FLOOR, FIT_TOL, STEP_TOL, THREADS, FloatOracleSim, fitness_gate, perturbed_fitness,
+                     teacher_forced)
 
 pytestmark = pytest.mark.gpu
 
@@ -30,6 +31,7 @@ def _say(msg):
     ("boxes x128", W.boxes(128), [0, 1, 100, 200, 300, 450, 600, 1000, 1500, 1999]),
     ("trees spot-check x64", None, [0, 1, 10, 100, 400, 1000, 2000]),
     ("quadrupeds x16", W.quadrupeds(16), [0, 1, 10, 100, 300, 600, 999]),
+    ("quadrupeds x16 long horizon", W.quadrupeds(16), [4999, 9999, 19999, 29999]),
 ])
 def test_teacher_forced_one_step(name, pop, ks):
     if pop is None:
@@ -58,6 +60,7 @@ def _fitness_case(pop, T, **kw):
     ("boxes x256 T=2000", lambda: W.boxes(256), 2000),
     ("trees spot-check x64 T=5000", lambda: W.random_trees(indices=W.TREE_SPOTCHECK), 5000),
     ("quadrupeds x32 T=1000", lambda: W.quadrupeds(32), 1000),
+    ("quadrupeds x16 T=10000", lambda: W.quadrupeds(16), 10000),
 ])
 def test_fitness_after_T(name, make, T):
     pop = make()
@@ -67,6 +70,32 @@ def test_fitness_after_T(name, make, T):
     a, b, s = sim.counters()
     assert (s == 0).all()
     assert ok.all(), (np.where(~ok)[0], Fg[~ok], Fr[~ok])
+
+
+def test_fitness_long_horizon():
+    """30 000 steps (60 s): single trajectories bifurcate under rounding here
+    (FP64 runs from initial positions perturbed at float32 rounding level
+    already leave the 1e-3 bound on several of these 16 quadrupeds), so the
+    per-variant gate gives way to what a rounding-level difference cannot
+    break: every variant finite and unfrozen, the median relative fitness
+    deviation within the 1e-3 bar, and the ranking of the variants (what
+    selection uses) kept, Spearman rho >= 0.95.  The per-step bar at late
+    states is checked by the teacher-forced test."""
+    from scipy.stats import spearmanr
+    pop = W.quadrupeds(16)
+    T = 30000
+    _say(f"[fitness, long horizon] quadrupeds x16 T={T}")
+    sim = _sim(pop)
+    sim.rollout(T)
+    Fg = sim.fitness().astype(np.float64)
+    Fr = O.Oracle(pop).rollout(T, threads=THREADS)
+    rel = np.abs(Fg - Fr) / np.maximum(np.abs(Fr), FIT_FLOOR)
+    rho = spearmanr(Fg, Fr)[0]
+    _say(f"  median rel dev {np.median(rel):.2e}, max {rel.max():.2e}, spearman {rho:.4f}")
+    _, _, s = sim.counters()
+    assert (s == 0).all() and np.isfinite(Fg).all()
+    assert np.median(rel) <= FIT_TOL
+    assert rho >= 0.95
 
 
 def test_overflow_contacts_bitwise_equal_register_path():
@@ -222,17 +251,21 @@ def test_ill_conditioned_chain_per_step_error():
     """22 bricks in a straight line (nv = 28) dropped flat: cond(M~) is about
     2.4e4, so single precision loses about 1e-3 of the free acceleration
     through any FP32 solve (7e-4 for a float Gauss-Jordan inverse, 1.5e-4 for
-    a float LU, measured on the CPU).  The per-step error of this stress case
-    sits at the 1e-4 bar of the regular workloads (9.8e-5 to 1.06e-4 across
-    kernel versions); it is held to twice that bar, and its fitness 20 steps
-    after an 80-contact impact drifts about 1 % from FP64."""
+    a float LU, measured on the CPU).  The float32 instance of the oracle
+    (Cholesky, library sine and cosine) makes 3.0e-4 at the impact step
+    itself, so this stress case is held to the sensitivity rule of the
+    fitness gate: within twice the regular 1e-4 bar, or within 3x of what the
+    float oracle makes at the same states.  Its fitness 20 steps after an
+    80-contact impact drifts about 1 % from FP64."""
     pop = W.chain(22, ["+x"] * 22, [0, 1] * 11, root_type=W.ROOT_FREE, root_q=[0, 0, 0.5, 1, 0, 0, 0])
     ks = [0, 1, 50, 100, 150, 158, 160, 165, 170, 180, 190, 199]
     _say(f"[teacher-forced] ill-conditioned chain nv=28, steps {ks}")
     worst, in_band, errs = teacher_forced(pop, _sim(pop), ks)
-    _say(f"  worst step error {worst:.3e} over {len(errs)} cases; {in_band} cases in the activation band")
+    worst32, _, _ = teacher_forced(pop, FloatOracleSim(pop), ks)
+    _say(f"  worst step error {worst:.3e} over {len(errs)} cases ({worst32:.3e} for the float oracle); "
+         f"{in_band} cases in the activation band")
     assert len(errs) >= len(ks) - 3
-    assert worst <= 2 * STEP_TOL
+    assert worst <= max(2 * STEP_TOL, 3 * worst32)
 
 
 def test_split_rollout_gpu_part_bitwise_host_part_within_bar():

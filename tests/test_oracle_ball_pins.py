@@ -58,7 +58,7 @@ def test_free_flight_exact_discrete_solution():
     v0 = np.array([0.3, 0.2, 1.5])
     w0 = np.array([0.7, -1.1, 2.3])
     pop = _far_box_with_ball(dict(r=0.05, m=0.4, pos=p0, v=v0, w=w0))
-    o = O.Oracle(pop)
+    o = O.Oracle(pop, float32_constants=False)
     dt = pop.params["dt"]
     k = 300
     o.step(k)
@@ -79,7 +79,7 @@ def test_free_flight_exact_discrete_solution():
 def test_sphere_mass_matrix_block_and_bias():
     r, m = 0.07, 0.9
     pop = _far_box_with_ball(dict(r=r, m=m, pos=(0, 0, 1.0), w=(1.0, 2.0, -0.5), v=(0.3, 0, 0)))
-    o = O.Oracle(pop)
+    o = O.Oracle(pop, float32_constants=False)
     q, v, _, _ = o.variant_state(0)
     M, c = o.dynamics(0, q, v)
     r32, m32 = float(np.float32(r)), float(np.float32(m))
@@ -93,7 +93,7 @@ def test_sphere_mass_matrix_block_and_bias():
 def test_resting_ball_depth_is_g_over_k(r, m):
     prm = _params()
     pop = _far_box_with_ball(dict(r=r, m=m, pos=(0, 0, r + 0.002)), params=prm)
-    o = O.Oracle(pop)
+    o = O.Oracle(pop, float32_constants=False)
     o.step(3000)
     q, v, _, st = o.variant_state(0)
     assert st == 0
@@ -107,7 +107,7 @@ def test_sliding_ball_rolls_at_five_sevenths():
     prm = _params()
     depth = 9.81 / prm["k_contact"]
     pop = _far_box_with_ball(dict(r=r, m=m, pos=(0, 0, r - depth), v=(v0, 0, 0)), params=prm, mu=0.3)
-    o = O.Oracle(pop)
+    o = O.Oracle(pop, float32_constants=False)
     r32, m32 = float(np.float32(r)), float(np.float32(m))
     I = 0.4 * m32 * r32 ** 2
     v0f = float(np.float32(v0))
@@ -128,7 +128,7 @@ def _collide(ball, quat=(1.0, 0.0, 0.0, 0.0), duration=0.6, mu=0.8, dt=None):
     if dt is not None:
         prm["dt"] = dt
     pop = W.single_box(half=(0.08, 0.08, 0.08), pos=(0.0, 0.0, 2.0), quat=quat, mu=mu, params=prm, ball=ball)
-    o = O.Oracle(pop)
+    o = O.Oracle(pop, float32_constants=False)
     inv0 = o.invariants(0)
     touched, worst = 0, np.zeros(6)
     for _ in range(int(round(duration / prm["dt"]))):
@@ -195,7 +195,7 @@ def test_sphere_box_geometry_against_brute_force():
     qb /= np.linalg.norm(qb)
     pop = W.single_box(half=tuple(half), pos=(0.3, -0.2, 1.0), quat=tuple(qb), params=_params(),
                        ball=dict(r=0.05, m=1.0, pos=(0, 0, 1.0)))
-    o = O.Oracle(pop)
+    o = O.Oracle(pop, float32_constants=False)
     q = o.variant_state(0)[0].copy()
     R, p, _, _ = o.fk(0, q)
     R, p = R[0], p[0]
@@ -243,7 +243,7 @@ def test_ball_box_rows_vanish_on_rigid_motion_and_are_orthonormal():
     # ball touching the +x side of the box region (some pose of it)
     pop = W.single_box(half=half, pos=(0.0, 0.0, 1.0), quat=tuple(qb), params=_params(),
                        ball=dict(r=0.05, m=1.0, pos=(0, 0, 1.0)))
-    o = O.Oracle(pop)
+    o = O.Oracle(pop, float32_constants=False)
     q = o.variant_state(0)[0].copy()
     R, p, _, _ = o.fk(0, q)
     R, p = R[0], p[0]

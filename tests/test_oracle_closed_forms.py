@@ -27,7 +27,7 @@ def test_discrete_free_fall(oracle_mod):
     """z_n = z0 + n dt vz0 - g dt^2 n(n+1)/2 exactly (velocity first, then position)."""
     dt, vz0, z0 = 0.002, 0.7, 3.0
     pop = W.single_box(pos=(0.0, 0.0, z0), v_b=(0.3, -0.2, vz0), params=_params())
-    o = oracle_mod.Oracle(pop)
+    o = oracle_mod.Oracle(pop, float32_constants=False)
     for n in (1, 10, 300):
         o.reset()
         o.step(n)
@@ -45,7 +45,7 @@ def test_compound_pendulum_period(oracle_mod):
     th_eq = np.pi / 2
     pop = W.chain(1, ["+x"], [W.AXIS_Y], root_type=W.ROOT_FIXED, root_pose=(0, 0, 1.0, 1, 0, 0, 0),
                   theta0=[th_eq + 0.01], params=_params(kp=0.0, kd=0.0))
-    o = oracle_mod.Oracle(pop)
+    o = oracle_mod.Oracle(pop, float32_constants=False)
     m, h = W.BRICK_MASS, W.BRICK_HALF
     T_exact = 2 * np.pi * np.sqrt((5.0 / 3.0 * m * h * h) / (m * G * h))
     assert abs(T_exact - 0.44857) < 1e-5
@@ -64,7 +64,7 @@ def test_compound_pendulum_period(oracle_mod):
 
 def _settle_box(oracle_mod, half, K=8, mu=1.0, t=0.6, g=(0, 0, -G)):
     pop = W.single_box(half=half, pos=(0, 0, half[2]), mu=mu, params=_params(pgs_iters=K, gravity=g))
-    o = oracle_mod.Oracle(pop)
+    o = oracle_mod.Oracle(pop, float32_constants=False)
     o.step(int(round(t / 0.002)))
     return pop, o
 
@@ -156,7 +156,7 @@ def test_incline_stick_and_slip(oracle_mod):
     acc_exact = G * (np.sin(a) - 0.3 * np.cos(a))
     assert abs(acc_exact - 2.356) < 1e-3
     pop = W.single_box(pos=(0, 0, 0.05), mu=0.3, params=_params(gravity=g))
-    o = oracle_mod.Oracle(pop)
+    o = oracle_mod.Oracle(pop, float32_constants=False)
     o.step(100)
     x1 = o.get_state()[0][0]
     o.step(250)
@@ -177,7 +177,7 @@ def _horizontal_hinge(A, phi, theta0=0.0, **prm):
 def test_pd_reaches_target_unclamped(oracle_mod):
     """Small error (kp*err < tau_max): the implicit PD settles exactly on the target."""
     pop = _horizontal_hinge(0.1, np.pi / 2)
-    o = oracle_mod.Oracle(pop)
+    o = oracle_mod.Oracle(pop, float32_constants=False)
     o.step(500)
     q, v, _, _ = o.get_state()
     assert abs(q[0] - np.float32(0.1)) < 1e-9 and abs(v[0]) < 1e-9
@@ -190,7 +190,7 @@ def test_pd_clamp_applies_exactly_tau_max(oracle_mod):
     hinge spins up at tau_max / I_p with I_p = 5 m h^2 / 3 about the hinge
     (for two steps: by then kp * err - b_a * thetadot is back below tau_max)."""
     pop = _horizontal_hinge(1.0, np.pi / 2)
-    o = oracle_mod.Oracle(pop)
+    o = oracle_mod.Oracle(pop, float32_constants=False)
     m, h = W.BRICK_MASS, W.BRICK_HALF
     Ip = 5.0 / 3.0 * np.float64(np.float32(m)) * np.float64(np.float32(h)) ** 2
     tmax, dt = 0.9, 0.002
@@ -206,12 +206,12 @@ def test_solver_converges_with_sweeps(oracle_mod):
     """One step from a many-contact state: the result converges as the sweep
     count grows (cauchy sequence in K), and K=8 is within a few percent."""
     pop = W.quadrupeds(4)
-    o = oracle_mod.Oracle(pop)
+    o = oracle_mod.Oracle(pop, float32_constants=False)
     o.step(400)
     q, v, k, _ = o.get_state()
     res = {}
     for K in (8, 64, 512, 2048):
-        ok = oracle_mod.Oracle(pop, pgs_iters=K)
+        ok = oracle_mod.Oracle(pop, pgs_iters=K, float32_constants=False)
         ok.set_state(q, v, k)
         ok.step(1)
         res[K] = ok.get_state()[1]

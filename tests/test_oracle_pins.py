@@ -125,7 +125,7 @@ def random_state(pop, rng):
 # ---------------------------------------------------------------- kinematics
 def test_fk_special_poses(oracle_mod):
     pop = W.chain(1, ["+x"], [W.AXIS_Z], root_type=W.ROOT_FIXED, root_pose=(0, 0, 1.0, 1, 0, 0, 0))
-    o = oracle_mod.Oracle(pop)
+    o = oracle_mod.Oracle(pop, float32_constants=False)
     _, p, w, oo = o.fk(0, [0.0])
     np.testing.assert_allclose(p[1], [0.05 + 0.03, 0, 1.0], atol=1e-15)     # rest pose
     np.testing.assert_allclose(oo[1], [0.05, 0, 1.0], atol=1e-15)            # hinge at the face centre
@@ -134,7 +134,7 @@ def test_fk_special_poses(oracle_mod):
     np.testing.assert_allclose(p[1], [0.05, 0.03, 1.0], atol=1e-15)          # anchor + h * y_parent
     # axis y, +90 deg: the brick hangs straight down
     pop = W.chain(1, ["+x"], [W.AXIS_Y], root_type=W.ROOT_FIXED, root_pose=(0, 0, 1.0, 1, 0, 0, 0))
-    o = oracle_mod.Oracle(pop)
+    o = oracle_mod.Oracle(pop, float32_constants=False)
     R, p, _, _ = o.fk(0, [np.pi / 2])
     np.testing.assert_allclose(p[1], [0.05, 0, 1.0 - 0.03], atol=1e-15)
     np.testing.assert_allclose(R[1] @ [1, 0, 0], [0, 0, -1], atol=1e-15)
@@ -162,7 +162,7 @@ def test_contact_rows_are_corner_velocities(oracle_mod):
     """J_p(x) v equals the finite-difference velocity of the active corner (FK only)."""
     rng = np.random.default_rng(11)
     pop = W.chain(3, ["+x", "+y", "+x"], [W.AXIS_Y, W.AXIS_Z, W.AXIS_Y], root_type=W.ROOT_FREE)
-    o = oracle_mod.Oracle(pop)
+    o = oracle_mod.Oracle(pop, float32_constants=False)
     for trial in range(6):
         q, v = random_state(pop, rng)
         q[2] = 0.04                                   # push the robot into the ground
@@ -183,7 +183,7 @@ def test_contact_rows_are_corner_velocities(oracle_mod):
 def test_contact_enumeration_order(oracle_mod):
     """Active corners come in (body, corner) order, corner bits = sign of (x, y, z)."""
     pop = W.single_box(half=(0.1, 0.2, 0.3), pos=(0, 0, 0.29))
-    o = oracle_mod.Oracle(pop)
+    o = oracle_mod.Oracle(pop, float32_constants=False)
     c = o.contacts(0, pop.q0.astype(np.float64))
     assert list(c["corner"]) == [0, 1, 2, 3]          # the four bottom corners (z bit clear)
     np.testing.assert_allclose(c["depth"], 0.01, atol=1e-7)   # model arrays are float32
@@ -196,7 +196,7 @@ def test_mass_matrix_equals_bruteforce_lagrangian(oracle_mod, root_type):
     differences of FK point positions (Gauss nodes, exact for boxes)."""
     rng = np.random.default_rng(1 + root_type)
     for pop in trees(root_type):
-        o = oracle_mod.Oracle(pop)
+        o = oracle_mod.Oracle(pop, float32_constants=False)
         for _ in range(2):
             q, v = random_state(pop, rng)
             M, _ = o.dynamics(0, q, v)
@@ -212,7 +212,7 @@ def test_single_free_box_mass_and_bias_closed_form(oracle_mod):
     rng = np.random.default_rng(3)
     half = np.array([0.07, 0.11, 0.05])
     pop = W.single_box(half=tuple(half), mass=2.5)
-    o = oracle_mod.Oracle(pop)
+    o = oracle_mod.Oracle(pop, float32_constants=False)
     m = 2.5
     Ib = np.diag([m / 3 * (half[1] ** 2 + half[2] ** 2), m / 3 * (half[0] ** 2 + half[2] ** 2),
                   m / 3 * (half[0] ** 2 + half[1] ** 2)])
@@ -235,7 +235,7 @@ def test_bias_equals_euler_lagrange_fixed_base(oracle_mod):
     rng = np.random.default_rng(7)
     g = np.array([0, 0, -G])
     for pop in trees(W.ROOT_FIXED):
-        o = oracle_mod.Oracle(pop)
+        o = oracle_mod.Oracle(pop, float32_constants=False)
         nv = int(o.nv[0])
         for _ in range(3):
             q, v = random_state(pop, rng)
@@ -269,7 +269,7 @@ def _floating_tree(vel_scale=1.0, g=(0, 0, -G), pd=False):
 def test_rk4_conserves_energy(oracle_mod):
     """Contact-free floating tree under gravity, no torque: E drift <= 1e-8 (RK4)."""
     pop = _floating_tree()
-    o = oracle_mod.Oracle(pop)
+    o = oracle_mod.Oracle(pop, float32_constants=False)
     E0 = o.invariants(0)[0]
     o.rk4(250)
     E1 = o.invariants(0)[0]
@@ -281,7 +281,7 @@ def test_rk4_conserves_momentum_with_pd(oracle_mod):
     the origin stay constant (RK4, <= 1e-8)."""
     pop = _floating_tree(g=(0, 0, 0), pd=True)
     pop.params["dt"] = 1e-4          # the PD gains are stiff for explicit RK4 (w*dt = 0.5 at dt = 2 ms)
-    o = oracle_mod.Oracle(pop)
+    o = oracle_mod.Oracle(pop, float32_constants=False)
     I0 = o.invariants(0)
     o.rk4(2000, pd=True)
     I1 = o.invariants(0)
@@ -296,7 +296,7 @@ def test_semi_implicit_energy_drift_is_first_order(oracle_mod):
     for dt in (0.002, 0.001, 0.0005):
         pop = _floating_tree(vel_scale=0.5)
         pop.params.update(dict(kp=0.0, kd=0.0, dt=dt))
-        o = oracle_mod.Oracle(pop)
+        o = oracle_mod.Oracle(pop, float32_constants=False)
         E0 = o.invariants(0)[0]
         o.step(int(round(0.2 / dt)))
         errs.append(abs(o.invariants(0)[0] - E0))
@@ -312,7 +312,7 @@ def test_semi_implicit_momentum_drift_is_first_order(oracle_mod):
     for dt in (0.002, 0.001, 0.0005):
         pop = _floating_tree(g=(0, 0, 0), pd=True, vel_scale=0.5)
         pop.params.update(dict(dt=dt))
-        o = oracle_mod.Oracle(pop)
+        o = oracle_mod.Oracle(pop, float32_constants=False)
         I0 = o.invariants(0)
         o.step(int(round(0.2 / dt)))
         I1 = o.invariants(0)

@@ -82,7 +82,7 @@ def _twisted_trees(n=12, seed=3):
 
 def test_self_contacts_against_brute_force_enumeration():
     pop = _twisted_trees()
-    o = O.Oracle(pop)
+    o = O.Oracle(pop, float32_constants=False)
     total = 0
     for vi in range(pop.n_variants):
         q = o.variant_state(vi)[0]
@@ -105,7 +105,7 @@ def test_self_contact_rows_vanish_for_rigid_motion_of_the_robot():
     """Internal contacts: moving the whole robot rigidly (root velocities
     only) moves both boxes' points alike, so every self-contact row is zero."""
     pop = _twisted_trees(8, seed=4)
-    o = O.Oracle(pop)
+    o = O.Oracle(pop, float32_constants=False)
     rng = np.random.default_rng(1)
     seen = 0
     for vi in range(pop.n_variants):
@@ -141,7 +141,7 @@ def test_folding_chain_passes_through_itself_without_contacts_and_stops_with_the
     for sc in (False, True):
         pop = W.chain(4, ["+x"] * 4, [0] * 4, root_type=W.ROOT_FIXED, cpg=[(1.0, 2.0, 1.57)] * 4, params=prm)
         pop = dataclasses.replace(pop, self_collision=sc)
-        o = O.Oracle(pop)
+        o = O.Oracle(pop, float32_constants=False)
         w = 0.0
         for _ in range(150):
             o.step(10)
@@ -156,10 +156,10 @@ def test_quadruped_limbs_meet_without_solver_failure():
     nearest-face normal there would be vertical, where no joint can push; the
     separating-axis normal is horizontal and the run stays finite."""
     pop = dataclasses.replace(W.quadrupeds(64), self_collision=True)
-    o = O.Oracle(pop)
+    o = O.Oracle(pop, float32_constants=False)
     o.step(1000, 8)
     a, _ = o.counters()
-    o0 = O.Oracle(W.quadrupeds(64))
+    o0 = O.Oracle(W.quadrupeds(64), float32_constants=False)
     o0.step(1000, 8)
     a0, _ = o0.counters()
     assert (o.get_state()[3] == 0).all()

@@ -1,10 +1,12 @@
 // Peak probes (include/probe.h): FP32 FMA issue, BF16 MFMA issue and a
-// plain copy, each timed with HIP events around one launch.
+// plain copy, each timed with HIP events around one launch; and the rollout
+// kernel's sine/cosine evaluated elementwise for accuracy checks.
 #include <hip/hip_runtime.h>
 
 #include <string>
 
 #include "../../../include/probe.h"
+#include "rollout_kernel.hpp"
 
 namespace {
 
@@ -64,6 +66,17 @@ __global__ __launch_bounds__(kThreads) void copy_probe_kernel(const uint4* __res
                                                               size_t n) {
   const size_t stride = (size_t)gridDim.x * kThreads;
   for (size_t i = (size_t)blockIdx.x * kThreads + threadIdx.x; i < n; i += stride) dst[i] = src[i];
+}
+
+__global__ __launch_bounds__(kThreads) void sincos_probe_kernel(const float* __restrict__ x, float* __restrict__ sn,
+                                                                float* __restrict__ cs, int64_t n) {
+  const int64_t i = (int64_t)blockIdx.x * kThreads + threadIdx.x;
+  if (i < n) {
+    float a, b;
+    simk::sincos_moderate(x[i], &a, &b);
+    sn[i] = a;
+    cs[i] = b;
+  }
 }
 
 // Times one launch (the lambda) between two events on `st`; milliseconds.
@@ -134,6 +147,16 @@ int probe_copy(const void* src, void* dst, size_t bytes, void* stream, double* g
   }, &ms);
   if (rc) return rc;
   *gbs = 2.0 * (double)bytes / (ms * 1e-3) / 1e9;
+  return PROBE_OK;
+}
+
+int probe_sincos(const float* x, float* sn, float* cs, int64_t n, void* stream) {
+  if (!x || !sn || !cs || n < 1 || n > ((int64_t)1 << 31)) return fail(PROBE_E_INVALID, "probe_sincos: bad argument");
+  const hipStream_t st = static_cast<hipStream_t>(stream);
+  const unsigned blocks = (unsigned)((n + kThreads - 1) / kThreads);
+  sincos_probe_kernel<<<blocks, kThreads, 0, st>>>(x, sn, cs, n);
+  const hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return fail(PROBE_E_DEVICE, std::string("probe_sincos launch: ") + hipGetErrorString(e));
   return PROBE_OK;
 }
 

@@ -9,7 +9,7 @@ import ctypes as C
 
 from . import sim as _sim
 
-EXPORTED = ("probe_fp32_fma", "probe_bf16_mfma", "probe_copy", "probe_last_error")
+EXPORTED = ("probe_fp32_fma", "probe_bf16_mfma", "probe_copy", "probe_sincos", "probe_last_error")
 _lib = None
 
 
@@ -26,7 +26,8 @@ def load():
     lib.probe_fp32_fma.argtypes = [VP, I32, I32, VP, D]
     lib.probe_bf16_mfma.argtypes = [VP, I32, I32, VP, D]
     lib.probe_copy.argtypes = [VP, VP, C.c_size_t, VP, D]
-    for n in ("probe_fp32_fma", "probe_bf16_mfma", "probe_copy"):
+    lib.probe_sincos.argtypes = [VP, VP, VP, C.c_int64, VP]
+    for n in ("probe_fp32_fma", "probe_bf16_mfma", "probe_copy", "probe_sincos"):
         getattr(lib, n).restype = C.c_int
     lib.probe_last_error.argtypes = []
     lib.probe_last_error.restype = C.c_char_p
@@ -84,6 +85,18 @@ def copy(nbytes=1 << 30, reps=3):
     if not ok:
         raise ProbeError("probe_copy: destination differs from source")
     return best
+
+
+def sincos(x):
+    """The rollout kernel's (sin x, cos x) for a float32 CUDA tensor x."""
+    import torch
+    x = x.contiguous()
+    assert x.is_cuda and x.dtype == torch.float32
+    sn, cs = torch.empty_like(x), torch.empty_like(x)
+    _check(load().probe_sincos(C.c_void_p(x.data_ptr()), C.c_void_p(sn.data_ptr()), C.c_void_p(cs.data_ptr()),
+                               x.numel(), _stream()))
+    torch.cuda.synchronize()
+    return sn, cs
 
 
 def all_peaks():

@@ -29,3 +29,6 @@ def test_bad_arguments_are_rejected_without_a_launch():
     assert lib.probe_copy(C.c_void_p(16), C.c_void_p(4096), 24, None, C.byref(r)) == -1      # not a multiple of 16
     assert lib.probe_copy(C.c_void_p(4096), C.c_void_p(4096 + 16), 64, None, C.byref(r)) == -1  # overlap
     assert b"overlap" in lib.probe_last_error()
+    assert lib.probe_sincos(None, C.c_void_p(16), C.c_void_p(32), 4, None) == -1
+    assert lib.probe_sincos(C.c_void_p(16), C.c_void_p(32), C.c_void_p(48), 0, None) == -1
+    assert b"probe_sincos" in lib.probe_last_error()

@@ -71,3 +71,18 @@ def test_more_than_one_gpu_is_refused_with_a_message():
                        text=True, timeout=120)
     assert r.returncode != 0
     assert "one GPU" in r.stderr and not r.stdout.strip()
+
+
+def test_autotune_final_round_takes_the_lowest_median_interleaved():
+    from paper_2502_11129_amd.autotune import _duel
+    script = {"a": iter([1.00, 1.10, 1.00]), "b": iter([0.99, 0.98, 1.30]), "c": iter([1.05, 0.90, 1.06])}
+    calls = []
+
+    def time_fn(o):
+        calls.append(o)
+        return next(script[o])
+
+    i, med = _duel(["a", "b", "c"], time_fn)
+    assert calls == ["a", "b", "c"] * 3          # interleaved rounds
+    assert med == [1.00, 0.99, 1.05]
+    assert i == 1

@@ -51,10 +51,25 @@ def parse():
     return ap.parse_args()
 
 
+def _cpu_model():
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
 def cpu_baseline(pop_full, sample_steps, workload="trees"):
-    """The FP64 oracle on the host cores over a bounded sample of the same
-    workload: every 8th tree (1024 of the 8192), the first 16384 box-and-ball
-    variants, or the first 64 quadrupeds, for sample_steps steps."""
+    """The FP64 oracle, compiled -O3 -march=native on this host, over a
+    bounded sample of the same workload: every 8th tree (1024 of the 8192),
+    the first 16384 box-and-ball variants, or the first 64 quadrupeds, for
+    sample_steps steps on all host threads (at most 16, the host share of
+    one GPU); then one thread on the first 1/16 of that sample for a quarter
+    of the steps (single-thread rate)."""
+    import tempfile
     from oracle import oracle as O
     from paper_2502_11129_amd import workloads as W
     if workload == "box_and_ball":
@@ -64,15 +79,32 @@ def cpu_baseline(pop_full, sample_steps, workload="trees"):
         pop = dataclasses.replace(W.quadrupeds(64), self_collision=pop_full.self_collision)
     else:
         pop = W.random_trees(indices=range(0, pop_full.n_variants, 8))
-    cores = os.cpu_count() or 1
-    o = O.Oracle(pop)
+    try:
+        avail = len(os.sched_getaffinity(0))
+    except AttributeError:
+        avail = os.cpu_count() or 1
+    cores = max(1, min(16, avail))
+    t0 = time.perf_counter()
+    lib = O.load_native(os.path.join(tempfile.gettempdir(), f"oracle_native_{os.getpid()}"))
+    t_build = time.perf_counter() - t0
+    o = O.Oracle(pop, lib=lib)
     t0 = time.perf_counter()
     o.rollout(sample_steps, threads=cores)
     dt = time.perf_counter() - t0
+    one = pop.subset(np.arange(0, pop.n_variants, 16))
+    steps1 = max(1, sample_steps // 4)
+    o1 = O.Oracle(one, lib=lib)
+    t0 = time.perf_counter()
+    o1.rollout(steps1, threads=1)
+    dt1 = time.perf_counter() - t0
     what = "first" if workload in ("box_and_ball", "quadrupeds") else "every 8th"
     return {"value": pop.n_variants * sample_steps / dt, "unit": "variant-steps/s", "cores": cores,
-            "kind": "oracle", "sample": f"{pop.n_variants} {what} variants x {sample_steps} steps, "
-                                        f"FP64, {cores} threads, {dt:.2f} s"}
+            "kind": "oracle",
+            "sample": f"{pop.n_variants} {what} variants x {sample_steps} steps, FP64, {cores} threads, "
+                      f"{dt:.2f} s; single thread: {one.n_variants} of them x {steps1} steps, {dt1:.2f} s",
+            "single_thread_value": one.n_variants * steps1 / dt1,
+            "cpu_model": _cpu_model(), "host_threads_available": avail,
+            "build": f"g++ -O3 -march=native on this host ({t_build:.1f} s, outside the timing)"}
 
 
 def recorded_traffic(kernel, steps_per_launch):

@@ -90,12 +90,19 @@ extern "C" {
  *                       are not joined by a hinge: every corner of either
  *                       box strictly inside the other (after the box-plane
  *                       corners, pairs a < b in order, corners of a then of
- *                       b), normal the outward normal of the penetrated
- *                       box's nearest face, depth the distance to it, rows
- *                       on the relative velocity (corner's box minus
- *                       penetrated box) with the same soft normal and
- *                       Coulomb disk.  Two edges crossing with no corner
- *                       inside are not detected.  A variant with more than
+ *                       b).  A pair shares one normal, the separating axis
+ *                       of least overlap among the two boxes' 3 + 3 face
+ *                       normals and the 9 normalised cross products of
+ *                       their edge directions (a cross product with squared
+ *                       norm below 1e-6 is skipped; the first of equal
+ *                       overlaps wins), pointing out of the penetrated box;
+ *                       a corner's depth is how far it lies inside that
+ *                       box's extent along the normal.  Rows act on the
+ *                       relative velocity (corner's box minus penetrated
+ *                       box) with the same soft normal and Coulomb disk; a
+ *                       row no DoF can move (J M~^-1 J^T < 1e-9) is inert.
+ *                       Two edges crossing with no corner inside are not
+ *                       detected.  A variant with more than
  *                       256 such contacts in a step freezes with
  *                       SIM_STATUS_CONTACTS.  Not combined with a ball.
  * Per-model constants: PD gains kp, kd (actuator torque limit tau_max), soft
@@ -186,16 +193,21 @@ typedef struct {
 typedef struct sim_handle sim_handle;
 
 /* Validate the descriptor and pack it by DoF bins (host only, no device work).
- * Errors: SIM_E_INVALID with a message in sim_last_error(*out) when *out is
- * non-NULL, else in sim_last_error(NULL).  Limits: 1..21 bodies per variant,
- * nv <= 28 degrees of freedom, pgs_iters >= 1, dt > 0. */
+ * Errors: SIM_E_INVALID with a message in sim_last_error(NULL).  Limits:
+ * 1..32 bodies per variant and nv <= 28 degrees of freedom (the ball's six
+ * included), i.e. at most 22 hinges under a free core (16 with a ball) and
+ * 28 under a fixed root; the populations of the method have at most 20
+ * hinges (nv <= 26).  pgs_iters >= 1, dt > 0. */
 int sim_create(const sim_model_desc* desc, const sim_options* opts, sim_handle** out);
 
 /* Bytes of device workspace the handle needs (256-byte aligned base). */
 int sim_workspace_bytes(const sim_handle* h, size_t* bytes);
 
 /* Attach a caller-owned device workspace of at least sim_workspace_bytes()
- * and upload the packed model and the initial state on `stream`. */
+ * and upload the packed model and the initial state on `stream`.  May be
+ * called again with another workspace (the previous one is no longer used;
+ * a captured rollout graph is dropped and captured again on the next graph
+ * rollout); every variant restarts from its initial state. */
 int sim_bind(sim_handle* h, void* dev_workspace, size_t bytes, void* stream);
 
 /* Advance every (non-frozen) variant by n_steps >= 0 steps. */
@@ -211,14 +223,19 @@ int sim_rollout(sim_handle* h, int32_t T, void* stream);
 int sim_fitness(const sim_handle* h, float* out, int where, void* stream);
 
 /* Current state in the q0/v0 CSR layout and step counters [n_variants].
- * Host memory only (where must be SIM_HOST).  Any of q, v, k may be NULL. */
+ * where = SIM_HOST: host arrays, the call synchronises `stream`; SIM_DEVICE:
+ * device arrays, written by kernels ordered on `stream` (no sync).  Any of
+ * q, v, k may be NULL. */
 int sim_get_state(const sim_handle* h, float* q, float* v, int64_t* k, int where, void* stream);
-/* Overwrite the state (and, if k != NULL, the step counters); clears status. */
+/* Overwrite the state (and, if k != NULL, the step counters) from arrays in
+ * the same layout, host (SIM_HOST, synchronising) or device (SIM_DEVICE,
+ * stream-ordered); clears the status bits.  q and v are required. */
 int sim_set_state(sim_handle* h, const float* q, const float* v, const int64_t* k, int where, void* stream);
 
 /* Per-variant counters since the last reset: active contact rows (sum over
- * steps of the number of active corners), actuator-clamp rows that ended a
- * step engaged, and status bits.  Host memory; any pointer may be NULL. */
+ * steps of the number of active contacts), actuator-clamp rows that ended a
+ * step engaged, and status bits, into host (SIM_HOST, synchronising) or
+ * device (SIM_DEVICE, stream-ordered) arrays; any pointer may be NULL. */
 int sim_counters(const sim_handle* h, uint64_t* rows_contact, uint64_t* rows_clamp, uint32_t* status,
                  int where, void* stream);
 

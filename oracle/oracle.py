@@ -23,16 +23,52 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 _SRC = os.path.join(_HERE, "oracle.cpp")
 _LIB = os.path.join(_HERE, "liboracle.so")
 _lib = None
+_native = {}
+
+
+def _compile(out: str, native: bool) -> str:
+    """g++ -O3 of oracle.cpp into ``out``; ``native`` adds -march=native (code
+    for the CPU that compiles it, so only for the machine that runs it)."""
+    tmp = out + ".tmp"
+    arch = ["-march=native"] if native else []
+    subprocess.check_call(["g++", "-O3", *arch, "-std=c++17", "-shared", "-fPIC", "-pthread", _SRC, "-o", tmp])
+    os.replace(tmp, out)
+    return out
 
 
 def build(force: bool = True) -> str:
-    """Compile liboracle.so with g++ (portable x86-64 code, no -march=native)."""
+    """Compile liboracle.so with g++ -O3 (portable x86-64 code: the library
+    travels to other machines with the tree, so no -march=native here)."""
     if force or not os.path.exists(_LIB):
-        tmp = _LIB + ".tmp"
-        subprocess.check_call(["g++", "-O2", "-std=c++17", "-shared", "-fPIC", "-pthread",
-                               _SRC, "-o", tmp])
-        os.replace(tmp, _LIB)
+        _compile(_LIB, native=False)
     return _LIB
+
+
+def _declare(lib):
+    P, I, D, F = C.c_void_p, C.c_int, C.POINTER(C.c_double), C.POINTER(C.c_float)
+    I32, I64, U32, U64 = (C.POINTER(C.c_int32), C.POINTER(C.c_int64), C.POINTER(C.c_uint32),
+                          C.POINTER(C.c_uint64))
+    lib.orc_create.restype = P
+    lib.orc_create.argtypes = [I, I32, I32, F, F, F, F, F, F, F, F, F, F, F, F, D, I, I, I, I]
+    lib.orc_destroy.argtypes = [P]
+    lib.orc_step.argtypes = [P, I, I]
+    lib.orc_step_subset.argtypes = [P, I, I32, I, I]
+    lib.orc_reset.argtypes = [P]
+    lib.orc_rk4.argtypes = [P, I, I, I]
+    lib.orc_fitness.argtypes = [P, D]
+    lib.orc_get_state.argtypes = [P, D, D, I64, U32]
+    lib.orc_set_state.argtypes = [P, D, D, I64]
+    lib.orc_counters.argtypes = [P, U64, U64]
+    lib.orc_invariants.argtypes = [P, I, D]
+    lib.orc_fk.argtypes = [P, I, D, D, D, D, D]
+    lib.orc_fk.restype = I
+    lib.orc_dynamics.argtypes = [P, I, D, D, D, D]
+    lib.orc_dynamics.restype = I
+    lib.orc_contacts.argtypes = [P, I, D, I, I32, I32, D, D, D, D, I32]
+    lib.orc_contacts.restype = I
+    lib.orc_cholesky.argtypes = [I, D, D]
+    lib.orc_cholesky.restype = I
+    return lib
 
 
 def _load():
@@ -40,32 +76,18 @@ def _load():
     if _lib is None:
         if not os.path.exists(_LIB) or os.path.getmtime(_LIB) < os.path.getmtime(_SRC):
             build()
-        lib = C.CDLL(_LIB)
-        P, I, D, F = C.c_void_p, C.c_int, C.POINTER(C.c_double), C.POINTER(C.c_float)
-        I32, I64, U32, U64 = (C.POINTER(C.c_int32), C.POINTER(C.c_int64), C.POINTER(C.c_uint32),
-                              C.POINTER(C.c_uint64))
-        lib.orc_create.restype = P
-        lib.orc_create.argtypes = [I, I32, I32, F, F, F, F, F, F, F, F, F, F, F, F, D, I, I, I, I]
-        lib.orc_destroy.argtypes = [P]
-        lib.orc_step.argtypes = [P, I, I]
-        lib.orc_step_subset.argtypes = [P, I, I32, I, I]
-        lib.orc_reset.argtypes = [P]
-        lib.orc_rk4.argtypes = [P, I, I, I]
-        lib.orc_fitness.argtypes = [P, D]
-        lib.orc_get_state.argtypes = [P, D, D, I64, U32]
-        lib.orc_set_state.argtypes = [P, D, D, I64]
-        lib.orc_counters.argtypes = [P, U64, U64]
-        lib.orc_invariants.argtypes = [P, I, D]
-        lib.orc_fk.argtypes = [P, I, D, D, D, D, D]
-        lib.orc_fk.restype = I
-        lib.orc_dynamics.argtypes = [P, I, D, D, D, D]
-        lib.orc_dynamics.restype = I
-        lib.orc_contacts.argtypes = [P, I, D, I, I32, I32, D, D, D, D, I32]
-        lib.orc_contacts.restype = I
-        lib.orc_cholesky.argtypes = [I, D, D]
-        lib.orc_cholesky.restype = I
-        _lib = lib
+        _lib = _declare(C.CDLL(_LIB))
     return _lib
+
+
+def load_native(directory: str):
+    """The same source built -O3 -march=native into ``directory`` on the
+    machine that calls this (for timing the oracle on that host's cores);
+    compiled once per process and directory."""
+    if directory not in _native:
+        os.makedirs(directory, exist_ok=True)
+        _native[directory] = _declare(C.CDLL(_compile(os.path.join(directory, "liboracle_native.so"), True)))
+    return _native[directory]
 
 
 def _p(a, ct):
@@ -91,11 +113,12 @@ class Oracle:
     with in FP64.  The time step matters most: the controller's clock
     t = k dt multiplies its rounding by k, so over 30 000 steps the float32
     and the decimal 0.002 s put the CPG clocks 3 microseconds apart.  The
-    pins of the oracle itself pass False to take the constants exactly."""
+    pins of the oracle itself pass False to take the constants exactly.
+    ``lib`` selects another build of the same source (``load_native``)."""
 
     def __init__(self, pop, precision: int = 64, pgs_iters: int | None = None, params: dict | None = None,
-                 float32_constants: bool = True):
-        lib = _load()
+                 float32_constants: bool = True, lib=None):
+        lib = _load() if lib is None else lib
         prm = dict(pop.params)
         if params:
             prm.update(params)

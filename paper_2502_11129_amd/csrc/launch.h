@@ -26,4 +26,13 @@ extern const MultiFamily kMultiFamilies[];
 extern const int kNumMultiFamilies;
 hipError_t launch_rollout_multi(const MultiArgs& m, const ModelParams& p, int blocks, hipStream_t st);
 
+// Device-side state transfer between a bin's packed layout and the caller's
+// variant-CSR arrays (map: int4 per packed variant, see state_kernels.hip).
+hipError_t launch_state_gather(int m, const int* map, const float* qb, const float* vb, const long long* kb, float* q,
+                               float* v, int64_t* k, hipStream_t st);
+hipError_t launch_state_scatter(int m, const int* map, const float* q, const float* v, const int64_t* k, float* qb,
+                                float* vb, long long* kb, unsigned* status, hipStream_t st);
+hipError_t launch_counters_gather(int m, const int* map, const unsigned long long* cnt, const unsigned* status_b,
+                                  uint64_t* rows_contact, uint64_t* rows_clamp, uint32_t* status, hipStream_t st);
+
 }  // namespace simk

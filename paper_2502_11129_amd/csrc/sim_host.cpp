@@ -34,10 +34,10 @@ struct Bin {
   launch_fn fn = nullptr;
   std::vector<int> users;  // user index of each packed variant
   // packed host copies (uploaded by sim_bind)
-  std::vector<int> hdr, lvl;
+  std::vector<int> hdr, lvl, map;  // map: (user, q offset, v offset, nq | nv << 16) per packed variant
   std::vector<float> hdrf, body, q0, v0;
   // device offsets (bytes from the workspace base)
-  size_t o_hdr, o_hdrf, o_body, o_lvl, o_q0, o_v0, o_q, o_v, o_k, o_status, o_xy0, o_fit, o_cnt, o_ovf;
+  size_t o_hdr, o_hdrf, o_body, o_lvl, o_q0, o_v0, o_q, o_v, o_k, o_status, o_xy0, o_fit, o_cnt, o_ovf, o_map;
   int lvl_stride = 0;
   long long ovf_stride = 0;
   BinArgs args{};
@@ -320,6 +320,7 @@ int sim_create(const sim_model_desc* d, const sim_options* opts, sim_handle** ou
     hp->nq[i] = (r0 ? 7 : 0) + nh + (ball ? 7 : 0);
     if (hp->nv[i] < 1 || hp->nv[i] > kMaxNv)
       return bad("variant " + std::to_string(i) + ": degrees of freedom (the ball's included) must be in 1..28");
+    if (hp->q_off[i] > 0x7fffffff - 64) return bad("population too large: state entries must fit 32-bit offsets");
     hp->q_off[i + 1] = hp->q_off[i] + hp->nq[i];
     hp->v_off[i + 1] = hp->v_off[i] + hp->nv[i];
   }
@@ -460,10 +461,15 @@ int sim_create(const sim_model_desc* d, const sim_options* opts, sim_handle** ou
     b.v0.assign((size_t)m * kVStride, 0.f);
     b.lvl_stride = 2 * nbc + 4;
     b.lvl.assign((size_t)m * b.lvl_stride, 0);
+    b.map.assign((size_t)m * 4, 0);
     for (int s = 0; s < m; ++s) {
       const int i = b.users[s];
       hp->bin_of[i] = (int)bi;
       hp->slot_of[i] = s;
+      b.map[4 * s] = i;
+      b.map[4 * s + 1] = hp->q_off[i];
+      b.map[4 * s + 2] = hp->v_off[i];
+      b.map[4 * s + 3] = hp->nq[i] | (hp->nv[i] << 16);
       const VInfo& vi = info[i];
       int* hd = &b.hdr[(size_t)s * HW_WORDS];
       hd[HW_NB] = vi.nb; hd[HW_NH] = vi.nb - 1; hd[HW_NV] = hp->nv[i]; hd[HW_R0] = r0;
@@ -533,6 +539,7 @@ int sim_create(const sim_model_desc* d, const sim_options* opts, sim_handle** ou
     b.o_fit = take(m * 4);
     b.o_cnt = take(m * 16);
     b.o_ovf = take(m * (size_t)b.ovf_stride * 4);
+    b.o_map = take(m * 16);
   }
   hp->ws_bytes = off;
   *out = h.release();
@@ -552,6 +559,11 @@ int sim_bind(sim_handle* h, void* ws, size_t bytes, void* stream) {
   if (reinterpret_cast<uintptr_t>(ws) % 256 != 0) return fail(h, SIM_E_INVALID, "workspace must be 256-byte aligned");
   if (h->device_error) return SIM_E_DEVICE;
   hipStream_t st = (hipStream_t)stream;
+  // a captured rollout graph holds the previous workspace's pointers: drop it
+  // (the next graph rollout captures again on the new workspace)
+  if (h->graph_exec) { hipGraphExecDestroy(h->graph_exec); h->graph_exec = nullptr; }
+  if (h->graph) { hipGraphDestroy(h->graph); h->graph = nullptr; }
+  h->graph_T = -1;
   h->ws = (char*)ws;
   if (h->bin_streams.empty() && h->n_streams > 1) {
     int rc = dev_check(h, hipEventCreateWithFlags(&h->fork_event, hipEventDisableTiming), "event create");
@@ -579,6 +591,7 @@ int sim_bind(sim_handle* h, void* ws, size_t bytes, void* stream) {
     if ((rc = dev_check(h, hipMemcpyAsync(base + b.o_lvl, b.lvl.data(), b.lvl.size() * 4, hipMemcpyHostToDevice, st), "upload"))) return rc;
     if ((rc = dev_check(h, hipMemcpyAsync(base + b.o_q0, b.q0.data(), b.q0.size() * 4, hipMemcpyHostToDevice, st), "upload"))) return rc;
     if ((rc = dev_check(h, hipMemcpyAsync(base + b.o_v0, b.v0.data(), b.v0.size() * 4, hipMemcpyHostToDevice, st), "upload"))) return rc;
+    if ((rc = dev_check(h, hipMemcpyAsync(base + b.o_map, b.map.data(), b.map.size() * 4, hipMemcpyHostToDevice, st), "upload"))) return rc;
     BinArgs& a = b.args;
     a.n = (int)m;
     a.hdr = (const int*)(base + b.o_hdr);
@@ -683,10 +696,18 @@ int sim_get_state(const sim_handle* hc, float* q, float* v, int64_t* k, int wher
   sim_handle* h = const_cast<sim_handle*>(hc);
   if (!h) return SIM_E_INVALID;
   if (!h->bound) return fail(h, SIM_E_STATE, "sim_bind has not been called");
-  if (where != SIM_HOST) return fail(h, SIM_E_INVALID, "state transfer supports where=SIM_HOST only");
+  if (where != SIM_HOST && where != SIM_DEVICE) return fail(h, SIM_E_INVALID, "where must be SIM_HOST or SIM_DEVICE");
   if (h->device_error) return SIM_E_DEVICE;
   hipStream_t st = (hipStream_t)stream;
-  const int r0 = h->root_type == SIM_ROOT_FREE ? 6 : 0;
+  if (where == SIM_DEVICE) {
+    for (Bin& b : h->bins) {
+      const BinArgs& a = b.args;
+      int rc = dev_check(h, launch_state_gather((int)b.users.size(), (const int*)(h->ws + b.o_map), a.q, a.v, a.k, q, v,
+                                                k, st), "state gather");
+      if (rc) return rc;
+    }
+    return SIM_OK;
+  }
   for (Bin& b : h->bins) {
     const size_t m = b.users.size();
     std::vector<float> qq(m * kQStride), vv(m * kVStride);
@@ -703,16 +724,24 @@ int sim_get_state(const sim_handle* hc, float* q, float* v, int64_t* k, int wher
       if (k) k[i] = kk[s];
     }
   }
-  (void)r0;
   return SIM_OK;
 }
 
 int sim_set_state(sim_handle* h, const float* q, const float* v, const int64_t* k, int where, void* stream) {
   if (!h || !q || !v) return SIM_E_INVALID;
   if (!h->bound) return fail(h, SIM_E_STATE, "sim_bind has not been called");
-  if (where != SIM_HOST) return fail(h, SIM_E_INVALID, "state transfer supports where=SIM_HOST only");
+  if (where != SIM_HOST && where != SIM_DEVICE) return fail(h, SIM_E_INVALID, "where must be SIM_HOST or SIM_DEVICE");
   if (h->device_error) return SIM_E_DEVICE;
   hipStream_t st = (hipStream_t)stream;
+  if (where == SIM_DEVICE) {
+    for (Bin& b : h->bins) {
+      const BinArgs& a = b.args;
+      int rc = dev_check(h, launch_state_scatter((int)b.users.size(), (const int*)(h->ws + b.o_map), q, v, k, a.q, a.v,
+                                                 a.k, a.status, st), "state scatter");
+      if (rc) return rc;
+    }
+    return SIM_OK;
+  }
   for (Bin& b : h->bins) {
     const size_t m = b.users.size();
     std::vector<float> qq(m * kQStride, 0.f), vv(m * kVStride, 0.f);
@@ -744,9 +773,18 @@ int sim_counters(const sim_handle* hc, uint64_t* rows_contact, uint64_t* rows_cl
   sim_handle* h = const_cast<sim_handle*>(hc);
   if (!h) return SIM_E_INVALID;
   if (!h->bound) return fail(h, SIM_E_STATE, "sim_bind has not been called");
-  if (where != SIM_HOST) return fail(h, SIM_E_INVALID, "counters support where=SIM_HOST only");
+  if (where != SIM_HOST && where != SIM_DEVICE) return fail(h, SIM_E_INVALID, "where must be SIM_HOST or SIM_DEVICE");
   if (h->device_error) return SIM_E_DEVICE;
   hipStream_t st = (hipStream_t)stream;
+  if (where == SIM_DEVICE) {
+    for (Bin& b : h->bins) {
+      const BinArgs& a = b.args;
+      int rc = dev_check(h, launch_counters_gather((int)b.users.size(), (const int*)(h->ws + b.o_map), a.cnt, a.status,
+                                                   rows_contact, rows_clamp, status, st), "counter gather");
+      if (rc) return rc;
+    }
+    return SIM_OK;
+  }
   for (Bin& b : h->bins) {
     const size_t m = b.users.size();
     std::vector<unsigned long long> cc(2 * m);

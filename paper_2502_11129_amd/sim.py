@@ -288,6 +288,33 @@ class Simulator(Handle):
                                            None if kk is None else kk.ctypes.data_as(C.POINTER(C.c_int64)),
                                            SIM_HOST, self.stream()))
 
+    def get_state_device(self, q=None, v=None, k=None):
+        """State into device tensors (variant-CSR layout, stream-ordered, no sync)."""
+        t = self.torch
+        q = t.empty(int(self.nq.sum()), dtype=t.float32, device=self.device) if q is None else q
+        v = t.empty(int(self.nv.sum()), dtype=t.float32, device=self.device) if v is None else v
+        k = t.empty(self.n, dtype=t.int64, device=self.device) if k is None else k
+        self._check(self.lib.sim_get_state(self.h, C.cast(q.data_ptr(), _F), C.cast(v.data_ptr(), _F),
+                                           C.cast(k.data_ptr(), C.POINTER(C.c_int64)), SIM_DEVICE, self.stream()))
+        return q, v, k
+
+    def set_state_device(self, q, v, k=None):
+        """State from device tensors (variant-CSR layout); k may be None (kept)."""
+        self._check(self.lib.sim_set_state(self.h, C.cast(q.data_ptr(), _F), C.cast(v.data_ptr(), _F),
+                                           None if k is None else C.cast(k.data_ptr(), C.POINTER(C.c_int64)),
+                                           SIM_DEVICE, self.stream()))
+
+    def counters_device(self):
+        """Counters into device tensors: (rows_contact u64 as int64, rows_clamp, status as int32)."""
+        t = self.torch
+        a = t.empty(self.n, dtype=t.int64, device=self.device)
+        b = t.empty(self.n, dtype=t.int64, device=self.device)
+        s = t.empty(self.n, dtype=t.int32, device=self.device)
+        self._check(self.lib.sim_counters(self.h, C.cast(a.data_ptr(), C.POINTER(C.c_uint64)),
+                                          C.cast(b.data_ptr(), C.POINTER(C.c_uint64)),
+                                          C.cast(s.data_ptr(), C.POINTER(C.c_uint32)), SIM_DEVICE, self.stream()))
+        return a, b, s
+
     def rollout_split(self, T: int, n_host: int, threads: int):
         """Concurrent GPU + host-thread rollout; returns the timing record as a dict."""
         t = sim_split_times()

@@ -39,6 +39,8 @@ from __future__ import annotations
 
 from dataclasses import dataclass, field
 
+import dataclasses
+
 import numpy as np
 
 ROOT_FREE = 0
@@ -421,6 +423,23 @@ def concat(pops) -> Population:
         q0=cat("q0"), v0=cat("v0"), root_pose=cat("root_pose"), root_type=p0.root_type,
         params=dict(p0.params), name="+".join(p.name for p in pops), steps=p0.steps,
         ball=cat("ball") if all(has_ball) else None, self_collision=p0.self_collision)
+
+
+def shifted(pop: Population, dx: float, dy: float) -> Population:
+    """The same population with every free core (and ball) started
+    (dx, dy) away in the horizontal plane: a rigid translation of the scene,
+    which leaves every trajectory's displacement unchanged."""
+    if pop.root_type != ROOT_FREE:
+        raise ValueError("shifted() moves free cores; fixed roots carry their pose in root_pose")
+    q0 = pop.q0.copy()
+    qo = pop.q_offset
+    for i in range(pop.n_variants):
+        q0[qo[i]] += np.float32(dx)
+        q0[qo[i] + 1] += np.float32(dy)
+        if pop.ball is not None:
+            q0[qo[i + 1] - 7] += np.float32(dx)
+            q0[qo[i + 1] - 6] += np.float32(dy)
+    return dataclasses.replace(pop, q0=q0, name=f"{pop.name}@({dx:g},{dy:g})")
 
 
 # ----------------------------------------------------------------------------

@@ -109,14 +109,15 @@ def self_margin(o, pop, vi, q):
     return best
 
 
-def teacher_forced(pop, sim, ks, threads=THREADS):
+def teacher_forced(pop, sim, ks, threads=THREADS, keys=False):
     """For each k in ks: oracle state x_k (FP64) -> float32 -> one GPU step,
     compared with the oracle's x_{k+1}.  Returns (max error outside the
-    activation band, number of (variant, k) cases in the band, all errors)."""
+    activation band, number of (variant, k) cases in the band, all errors);
+    with keys=True also the (k, variant) of every error."""
     o = O.Oracle(pop)
     free = pop.root_type == 0
     cur = 0
-    worst, in_band, errs = 0.0, 0, []
+    worst, in_band, errs, where = 0.0, 0, [], []
     for k in sorted(ks):
         o.step(k - cur, threads)
         q, v, kk, st = o.get_state()
@@ -143,8 +144,48 @@ def teacher_forced(pop, sim, ks, threads=THREADS):
                 in_band += 1
                 continue
             errs.append(e)
+            where.append((k, i))
             worst = max(worst, e)
+    if keys:
+        return worst, in_band, np.array(errs), where
     return worst, in_band, np.array(errs)
+
+
+def teacher_forced_counters(pop, sim, ks, threads=THREADS):
+    """Per-step counter increments (active contact rows, clamp rows engaged
+    at the end of the step) of one GPU step from the oracle's state, against
+    the FP64 oracle's for the same step.  Asserted equal for every (variant,
+    step) case where the oracle's float instance counts the same as its FP64
+    instance; a case where even those two differ sits on a contact or clamp
+    switch.  Returns (cases compared, cases on a switch, compared cases with
+    any contact or clamp row)."""
+    o64 = O.Oracle(pop)
+    o32 = O.Oracle(pop, precision=32)
+    cur, compared, skipped, nz = 0, 0, 0, 0
+    for k in sorted(ks):
+        o64.step(k - cur, threads)
+        q, v, kk, st = o64.get_state()
+        c0, l0 = o64.counters()
+        o64.step(1, threads)
+        cur = k + 1
+        c1, l1 = o64.counters()
+        o32.set_state(q, v, kk)
+        f0, g0 = o32.counters()
+        o32.step(1, threads)
+        f1, g1 = o32.counters()
+        sim.set_state(q.astype(np.float32), v.astype(np.float32), kk)
+        a0, b0, _ = sim.counters()
+        sim.step(1)
+        a1, b1, _ = sim.counters()
+        d64 = np.stack([(c1 - c0).astype(np.int64), (l1 - l0).astype(np.int64)])
+        d32 = np.stack([(f1 - f0).astype(np.int64), (g1 - g0).astype(np.int64)])
+        dg = np.stack([(a1 - a0).astype(np.int64), (b1 - b0).astype(np.int64)])
+        agree = (d32 == d64).all(axis=0) & (st == 0)
+        compared += int(agree.sum())
+        skipped += int((~agree).sum())
+        nz += int((d64[:, agree] > 0).any(axis=0).sum())
+        np.testing.assert_array_equal(dg[:, agree], d64[:, agree], err_msg=f"step {k}")
+    return compared, skipped, nz
 
 
 class FloatOracleSim:
@@ -167,20 +208,65 @@ class FloatOracleSim:
         return q, v, k
 
 
+# Largest share of a population that may pass the fitness gate only through
+# the perturbed-start extension (class "fp64" below), a deviation from the
+# float-oracle-only rule; fixed before any GPU result was compared with it.
+PERTURBED_RELAX_CAP = 0.25
+
+
 def fitness_gate(F_gpu, F_ref, F_32, F_pert=None):
-    """Per variant: ok if within FIT_TOL of the FP64 oracle.  A variant is
-    FP32-sensitive when the float oracle, or any FP64 run started from the
-    same state perturbed at float32 rounding level (F_pert rows), lands
-    outside the bound; such a variant must be within 3x of the largest of
-    those deviations."""
+    """Per variant, with bound = FIT_TOL * max(|F_ref|, FIT_FLOOR):
+      * every variant passes when |F_gpu - F_ref| <= bound;
+      * FP32-sensitive (the float instance of the oracle is itself outside the
+        bound): passes within 3x of |F_32 - F_ref| (the spec's rule);
+      * otherwise, when FP64 runs from initial positions perturbed at float32
+        rounding level (F_pert rows) leave the bound (FP64-chaotic), it passes
+        within 3x of the largest of their deviations (the relaxation;
+        gate_counts() counts the variants that need it).
+    Returns (ok, chaotic, dev / bound)."""
     bound = FIT_TOL * np.maximum(np.abs(F_ref), FIT_FLOOR)
     dev = np.abs(F_gpu - F_ref)
-    spread = np.abs(F_32 - F_ref)
+    s32 = np.abs(F_32 - F_ref)
+    sp = np.zeros_like(s32)
     if F_pert is not None and len(F_pert):
-        spread = np.maximum(spread, np.abs(np.asarray(F_pert) - F_ref).max(axis=0))
-    chaotic = spread > bound
-    ok = (dev <= bound) | (chaotic & (dev <= 3.0 * spread))
-    return ok, chaotic, dev / bound
+        sp = np.abs(np.asarray(F_pert) - F_ref).max(axis=0)
+    fp32 = s32 > bound
+    fp64 = ~fp32 & (sp > bound)
+    ok = (dev <= bound) | (fp32 & (dev <= 3.0 * s32)) | (fp64 & (dev <= 3.0 * sp))
+    return ok, fp32 | fp64, dev / bound
+
+
+def gate_counts(F_gpu, F_ref, F_32, F_pert=None):
+    """How each variant met the gate: within the bound outright; FP32-sensitive
+    and within 3x of the float oracle's deviation; or only through the
+    perturbed-start relaxation.  Also the population's classes (stable /
+    FP32-sensitive / FP64-chaotic), which depend on the oracle alone."""
+    bound = FIT_TOL * np.maximum(np.abs(F_ref), FIT_FLOOR)
+    dev = np.abs(F_gpu - F_ref)
+    s32 = np.abs(F_32 - F_ref)
+    sp = np.zeros_like(s32)
+    if F_pert is not None and len(F_pert):
+        sp = np.abs(np.asarray(F_pert) - F_ref).max(axis=0)
+    fp32 = s32 > bound
+    fp64 = ~fp32 & (sp > bound)
+    direct = dev <= bound
+    ok, _, _ = fitness_gate(F_gpu, F_ref, F_32, F_pert)
+    return dict(n=int(len(dev)), within_bound=int(direct.sum()),
+                via_fp32_rule=int((~direct & fp32 & ok).sum()),
+                via_perturbed_relaxation=int((~direct & fp64 & ok).sum()),
+                failing=int((~ok).sum()),
+                class_stable=int((~fp32 & ~fp64).sum()), class_fp32=int(fp32.sum()), class_fp64=int(fp64.sum()))
+
+
+def assert_gate(F_gpu, F_ref, F_32, F_pert, say=print, label=""):
+    """fitness_gate on every variant, the counts printed, and at most
+    PERTURBED_RELAX_CAP of the variants passing only through the relaxation."""
+    ok, chaotic, ratio = fitness_gate(F_gpu, F_ref, F_32, F_pert)
+    c = gate_counts(F_gpu, F_ref, F_32, F_pert)
+    say(f"  {label}gate: {c}; max |dF|/bound {ratio.max():.3f}")
+    assert ok.all(), (np.where(~ok)[0], F_gpu[~ok], F_ref[~ok])
+    assert c["via_perturbed_relaxation"] <= PERTURBED_RELAX_CAP * c["n"], c
+    return ok, chaotic, ratio, c
 
 
 def perturbed_fitness(pop, T, seeds=(1, 2, 3), rel=6e-8, threads=THREADS):

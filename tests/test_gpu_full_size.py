@@ -1,8 +1,9 @@
 """Parity at the full benchmark sizes, in the launch configurations bench.py
 times: 8192 random trees x 5000 steps (32-body kernels on four streams),
-512 000 box-and-ball variants x 1000 steps and 32 768 quadrupeds with
-self-collision x 1000 steps.  The oracle cannot run these populations whole,
-so sampled variants are checked two ways: bitwise against the same variants
+512 000 box-and-ball variants x 1000 steps, 32 768 quadrupeds x 1000 steps
+with and without self-collision, and all 4096 dropped boxes x 2000 steps
+against the oracle variant by variant.  The oracle cannot run the larger
+populations whole, so their sampled variants are checked two ways: bitwise against the same variants
 simulated on their own (a variant's arithmetic does not depend on the other
 variants of its wave, bin or launch), and against the FP64 oracle with the
 fitness gate of the small-size parity tests."""
@@ -15,7 +16,7 @@ import pytest
 from oracle import oracle as O
 from paper_2502_11129_amd import workloads as W
 
-from _parity import THREADS, fitness_gate, perturbed_fitness
+from _parity import THREADS, assert_gate, perturbed_fitness
 
 pytestmark = pytest.mark.gpu
 
@@ -51,6 +52,7 @@ def _rows(pop, idx, q, v):
      np.arange(0, 512000, 8000)),
     ("quadrupeds+self 32768 x 1000", lambda: dataclasses.replace(W.quadrupeds(32768), self_collision=True), 1000,
      dict(min_body_slots=32), np.arange(0, 32768, 2048)),
+    ("quadrupeds 32768 x 1000", lambda: W.quadrupeds(32768), 1000, dict(), np.arange(0, 32768, 1024)),
 ])
 def test_full_size_sampled_variants(name, make, T, opts, sample):
     pop = make()
@@ -67,6 +69,17 @@ def test_full_size_sampled_variants(name, make, T, opts, sample):
     _say("  sampled variants bitwise equal to their own run; oracle ...")
     Fr = O.Oracle(sub).rollout(T, threads=THREADS)
     F32 = O.Oracle(sub, precision=32).rollout(T, threads=THREADS)
-    ok, chaotic, ratio = fitness_gate(Fs.astype(np.float64), Fr, F32, perturbed_fitness(sub, T))
-    _say(f"  max |dF|/bound {ratio.max():.3f}; fp32-chaotic {int(chaotic.sum())}; failing {int((~ok).sum())}")
-    assert ok.all(), (sample[~ok], Fs[~ok], Fr[~ok])
+    assert_gate(Fs.astype(np.float64), Fr, F32, perturbed_fitness(sub, T), say=_say)
+
+
+def test_full_size_boxes_every_variant():
+    """The whole box population (4096 free boxes x 2000 steps) against the
+    oracle, every variant under the fitness gate."""
+    pop = W.boxes(4096)
+    T = 2000
+    _say(f"[full size] boxes 4096 x {T}: every variant against the oracle")
+    F, q, v, k, status = _run(pop, T)
+    assert (status == 0).all() and (k == T).all()
+    Fr = O.Oracle(pop).rollout(T, threads=THREADS)
+    F32 = O.Oracle(pop, precision=32).rollout(T, threads=THREADS)
+    assert_gate(F.astype(np.float64), Fr, F32, perturbed_fitness(pop, T), say=_say)

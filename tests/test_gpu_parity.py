@@ -10,8 +10,8 @@ import pytest
 from oracle import oracle as O
 from paper_2502_11129_amd import workloads as W
 
-from _parity import (FIT_FLOOR, FIT_TOL, STEP_TOL, THREADS, FloatOracleSim, fitness_gate, perturbed_fitness,
-                     teacher_forced)
+from _parity import (FIT_FLOOR, FIT_TOL, STEP_TOL, THREADS, FloatOracleSim, assert_gate, perturbed_fitness,
+                     teacher_forced, teacher_forced_counters)
 
 pytestmark = pytest.mark.gpu
 
@@ -29,9 +29,10 @@ def _say(msg):
 @pytest.mark.parametrize("name, pop, ks", [
     ("snake3 x16", W.snake(16), [0, 1, 5, 20, 60, 150, 300, 500, 750, 999]),
     ("boxes x128", W.boxes(128), [0, 1, 100, 200, 300, 450, 600, 1000, 1500, 1999]),
-    ("trees spot-check x64", None, [0, 1, 10, 100, 400, 1000, 2000]),
+    ("trees spot-check x64", None, [0, 1, 10, 100, 400, 1000, 2000, 3000, 4999]),
     ("quadrupeds x16", W.quadrupeds(16), [0, 1, 10, 100, 300, 600, 999]),
     ("quadrupeds x16 long horizon", W.quadrupeds(16), [4999, 9999, 19999, 29999]),
+    ("snake3 x16 started at (0.3, -0.2)", W.shifted(W.snake(16), 0.3, -0.2), [0, 1, 100, 500, 999]),
 ])
 def test_teacher_forced_one_step(name, pop, ks):
     if pop is None:
@@ -51,51 +52,88 @@ def _fitness_case(pop, T, **kw):
     Fr = O.Oracle(pop).rollout(T, threads=THREADS)
     F32 = O.Oracle(pop, precision=32).rollout(T, threads=THREADS)
     Fp = perturbed_fitness(pop, T)
-    ok, chaotic, ratio = fitness_gate(Fg, Fr, F32, Fp)
-    return sim, Fg, Fr, ok, chaotic, ratio
+    return sim, Fg, Fr, F32, Fp
 
 
 @pytest.mark.parametrize("name, make, T", [
     ("snake3 x16 T=1000", lambda: W.snake(16), 1000),
+    ("snake3 x16 started at (0.3, -0.2) T=1000", lambda: W.shifted(W.snake(16), 0.3, -0.2), 1000),
     ("boxes x256 T=2000", lambda: W.boxes(256), 2000),
     ("trees spot-check x64 T=5000", lambda: W.random_trees(indices=W.TREE_SPOTCHECK), 5000),
+    ("trees x24 started at (-1.5, 2.0) T=2000", lambda: W.shifted(W.random_trees(24), -1.5, 2.0), 2000),
     ("quadrupeds x32 T=1000", lambda: W.quadrupeds(32), 1000),
     ("quadrupeds x16 T=10000", lambda: W.quadrupeds(16), 10000),
 ])
 def test_fitness_after_T(name, make, T):
     pop = make()
     _say(f"[fitness] {name}")
-    sim, Fg, Fr, ok, chaotic, ratio = _fitness_case(pop, T)
-    _say(f"  max |dF|/bound {ratio.max():.3f}; fp32-chaotic variants {int(chaotic.sum())}; failing {int((~ok).sum())}")
+    sim, Fg, Fr, F32, Fp = _fitness_case(pop, T)
     a, b, s = sim.counters()
     assert (s == 0).all()
-    assert ok.all(), (np.where(~ok)[0], Fg[~ok], Fr[~ok])
+    assert_gate(Fg, Fr, F32, Fp, say=_say)
+
+
+def test_fitness_is_displacement_from_the_start():
+    """A population moved away from the origin: every core's fitness is its
+    displacement from its own start, the same as the unmoved population's up
+    to rounding, and far from its distance to the origin.  A free-flying box
+    started at (0.4, -0.7) has the closed form n dt |v_xy|."""
+    pop = W.snake(16)
+    T = 1000
+    _say("[fitness] snake3 x16 at the origin and moved to (0.3, -0.2)")
+    a = _sim(pop)
+    a.rollout(T)
+    b = _sim(W.shifted(pop, 0.3, -0.2))
+    b.rollout(T)
+    Fa, Fb = a.fitness().astype(np.float64), b.fitness().astype(np.float64)
+    _say(f"  max |F_moved - F| {np.abs(Fb - Fa).max():.2e} m; fitness range {Fa.min():.3f} .. {Fa.max():.3f} m")
+    assert (np.abs(Fb - Fa) <= FIT_TOL * np.maximum(Fa, FIT_FLOOR)).all()
+    qb, _, _ = b.get_state()
+    xy = np.stack([qb[pop.q_offset[:-1]], qb[pop.q_offset[:-1] + 1]], 1).astype(np.float64)
+    assert (np.abs(np.linalg.norm(xy, axis=1) - Fb) > 1e-3).all()
+    box = W.single_box(pos=(0.4, -0.7, 3.0), quat=(np.cos(0.35), 0.0, 0.0, np.sin(0.35)), v_b=(0.3, -0.2, 0.7))
+    s = _sim(box)
+    for n in (1, 37, 400):
+        s.rollout(n)
+        F = float(s.fitness()[0])
+        exact = n * 0.002 * np.hypot(0.3, 0.2)
+        assert abs(F - exact) <= FIT_TOL * max(exact, FIT_FLOOR), (n, F, exact)
 
 
 def test_fitness_long_horizon():
-    """30 000 steps (60 s): single trajectories bifurcate under rounding here
-    (FP64 runs from initial positions perturbed at float32 rounding level
-    already leave the 1e-3 bound on several of these 16 quadrupeds), so the
-    per-variant gate gives way to what a rounding-level difference cannot
-    break: every variant finite and unfrozen, the median relative fitness
-    deviation within the 1e-3 bar, and the ranking of the variants (what
-    selection uses) kept, Spearman rho >= 0.95.  The per-step bar at late
-    states is checked by the teacher-forced test."""
+    """30 000 steps (60 s) on 16 quadrupeds under the per-variant fitness
+    gate, with the counts of variants within the bound, FP32-sensitive and
+    relaxed printed; also the median relative deviation and the ranking of
+    the variants (what selection uses), Spearman rho >= 0.95."""
     from scipy.stats import spearmanr
     pop = W.quadrupeds(16)
     T = 30000
     _say(f"[fitness, long horizon] quadrupeds x16 T={T}")
-    sim = _sim(pop)
-    sim.rollout(T)
-    Fg = sim.fitness().astype(np.float64)
-    Fr = O.Oracle(pop).rollout(T, threads=THREADS)
+    sim, Fg, Fr, F32, Fp = _fitness_case(pop, T)
     rel = np.abs(Fg - Fr) / np.maximum(np.abs(Fr), FIT_FLOOR)
     rho = spearmanr(Fg, Fr)[0]
     _say(f"  median rel dev {np.median(rel):.2e}, max {rel.max():.2e}, spearman {rho:.4f}")
     _, _, s = sim.counters()
     assert (s == 0).all() and np.isfinite(Fg).all()
+    assert_gate(Fg, Fr, F32, Fp, say=_say)
     assert np.median(rel) <= FIT_TOL
     assert rho >= 0.95
+
+
+def test_teacher_forced_counters_exact():
+    """The per-step counters (active contact rows, clamp rows engaged at the
+    end of the step) of one GPU step from the oracle's state equal the
+    oracle's exactly, for every case where the oracle's own float instance
+    agrees with its FP64 counts (a case where even that disagrees sits on a
+    contact or clamp switch, where single precision may flip the decision:
+    counted and printed)."""
+    for name, pop, ks in (("snake3 x16", W.snake(16), [0, 1, 50, 200, 500, 999]),
+                          ("trees spot-check x64", W.random_trees(indices=W.TREE_SPOTCHECK),
+                           [0, 1, 100, 400, 1000, 2500, 4999])):
+        _say(f"[counters] {name}, steps {ks}")
+        compared, skipped, nz = teacher_forced_counters(pop, _sim(pop), ks)
+        _say(f"  {compared} (variant, step) cases equal ({nz} with contacts or clamps), {skipped} on a switch")
+        assert compared > 0.9 * (compared + skipped) and nz > 0
 
 
 def test_overflow_contacts_bitwise_equal_register_path():
@@ -242,30 +280,31 @@ def test_edge_cases_sizes():
         Fg = sim.fitness().astype(np.float64)
         Fr = O.Oracle(pop).rollout(1000)
         F32 = O.Oracle(pop, precision=32).rollout(1000)
-        ok, _, ratio = fitness_gate(Fg, Fr, F32, perturbed_fitness(pop, 1000))
-        _say(f"  {pop.name}: max |dF|/bound {ratio.max():.3f}")
-        assert ok.all(), (Fg, Fr)
+        assert_gate(Fg, Fr, F32, perturbed_fitness(pop, 1000), say=_say, label=f"{pop.name}: ")
 
 
 def test_ill_conditioned_chain_per_step_error():
-    """22 bricks in a straight line (nv = 28) dropped flat: cond(M~) is about
-    2.4e4, so single precision loses about 1e-3 of the free acceleration
-    through any FP32 solve (7e-4 for a float Gauss-Jordan inverse, 1.5e-4 for
-    a float LU, measured on the CPU).  The float32 instance of the oracle
-    (Cholesky, library sine and cosine) makes 3.0e-4 at the impact step
-    itself, so this stress case is held to the sensitivity rule of the
-    fitness gate: within twice the regular 1e-4 bar, or within 3x of what the
-    float oracle makes at the same states.  Its fitness 20 steps after an
-    80-contact impact drifts about 1 % from FP64."""
-    pop = W.chain(22, ["+x"] * 22, [0, 1] * 11, root_type=W.ROOT_FREE, root_q=[0, 0, 0.5, 1, 0, 0, 0])
-    ks = [0, 1, 50, 100, 150, 158, 160, 165, 170, 180, 190, 199]
-    _say(f"[teacher-forced] ill-conditioned chain nv=28, steps {ks}")
-    worst, in_band, errs = teacher_forced(pop, _sim(pop), ks)
-    worst32, _, _ = teacher_forced(pop, FloatOracleSim(pop), ks)
+    """20 bricks in a straight line (nv = 26, the largest tree of the spec)
+    dropped flat: cond(M~) is about 1.9e4.  Every teacher-forced step is held
+    to the 1e-4 bar, except the steps where single precision itself cannot
+    meet it: where the oracle's float instance (textbook Cholesky in float32,
+    same states) makes more than 1e-4, the step is FP32-sensitive and the GPU
+    must be within 3x of that float error (the rule of the fitness gate,
+    applied per step).  Those steps are counted; they are the impact steps."""
+    pop = W.chain(20, ["+x"] * 20, [0, 1] * 10, root_type=W.ROOT_FREE, root_q=[0, 0, 0.5, 1, 0, 0, 0])
+    ks = [0, 1, 50, 100, 150, 151, 152, 153, 154, 155, 156, 158, 160, 165, 170, 180, 190, 199, 250, 300]
+    _say(f"[teacher-forced] ill-conditioned chain nv=26, steps {ks}")
+    worst, in_band, errs, where = teacher_forced(pop, _sim(pop), ks, keys=True)
+    worst32, _, errs32, where32 = teacher_forced(pop, FloatOracleSim(pop), ks, keys=True)
+    assert where == where32
+    sensitive = errs32 > STEP_TOL
+    bar = np.where(sensitive, 3.0 * errs32, STEP_TOL)
     _say(f"  worst step error {worst:.3e} over {len(errs)} cases ({worst32:.3e} for the float oracle); "
-         f"{in_band} cases in the activation band")
+         f"{int(sensitive.sum())} FP32-sensitive steps {[where[i][0] for i in np.where(sensitive)[0]]}; "
+         f"worst error / bar {np.max(errs / bar):.3f}; {in_band} cases in the activation band")
     assert len(errs) >= len(ks) - 3
-    assert worst <= max(2 * STEP_TOL, 3 * worst32)
+    assert (errs <= bar).all(), [(where[i], errs[i], errs32[i]) for i in np.where(errs > bar)[0]]
+    assert (errs[~sensitive] <= STEP_TOL).all()
 
 
 def test_split_rollout_gpu_part_bitwise_host_part_within_bar():
@@ -283,8 +322,7 @@ def test_split_rollout_gpu_part_bitwise_host_part_within_bar():
     assert t["n_host"] == 10 and t["n_gpu"] == 30 and t["combined_s"] > 0
     Fr = O.Oracle(pop).rollout(400, threads=THREADS)
     F32 = O.Oracle(pop, precision=32).rollout(400, threads=THREADS)
-    ok, _, _ = fitness_gate(Fs.astype(np.float64), Fr, F32, perturbed_fitness(pop, 400))
-    assert ok.all()
+    assert_gate(Fs.astype(np.float64), Fr, F32, perturbed_fitness(pop, 400), say=_say)
     same = Fs == Fg
     assert same.sum() >= 30          # the GPU share is bit-identical
     _, _, k = s.get_state()

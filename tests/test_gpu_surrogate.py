@@ -2,9 +2,11 @@
 (BF16-emulating at the same rounding points), through the C ABI.
 
 Bars: features bit-exact; top-k indices exact; forward predictions and
-parameter gradients within 1e-3 relative (norm-wise per tensor; FP32
-accumulation order and occasional one-ulp BF16 rounding differences are the
-only expected deviations); Adam within 1e-6 relative of the FP64 formula."""
+parameter gradients within 1e-3 relative norm-wise per tensor and, element by
+element, |got - ref| <= 1e-2 |ref| + 1e-3 rms(ref) (FP32 accumulation order
+and occasional one-ulp BF16 rounding differences are the only expected
+deviations: a flipped BF16 activation moves an output by about 2^-8 of one
+term of its sum); Adam within 1e-6 relative of the FP64 formula."""
 import sys
 
 import numpy as np
@@ -48,6 +50,17 @@ def _rel(a, b):
     return np.linalg.norm(np.asarray(a, np.float64) - b) / max(np.linalg.norm(b), 1e-30)
 
 
+ELEM_REL, ELEM_RMS = 1e-2, 1e-3
+
+
+def _elem(a, b):
+    """Largest |a - b| / (ELEM_REL |b| + ELEM_RMS rms(b)) over the elements."""
+    a = np.asarray(a, np.float64)
+    b = np.asarray(b, np.float64)
+    rms = np.sqrt(np.mean(b * b))
+    return float(np.max(np.abs(a - b) / (ELEM_REL * np.abs(b) + ELEM_RMS * rms + 1e-30)))
+
+
 def test_features_bit_exact(torch):
     g = W.random_genotypes(3001, key=11)            # ragged: not a multiple of the 64-thread block
     gt = W.tree_genotypes(range(200))
@@ -84,9 +97,9 @@ def test_forward_matches_oracle_and_gathers(torch):
     s = _sur(params=p)
     X = s.features(s.upload_genotypes(g))
     y = s.predict(X).cpu().numpy()
-    e = _rel(y, yref)
-    _say(f"  relative error {e:.2e}, max abs {np.abs(y - yref).max():.2e}")
-    assert e <= REL
+    e, r = _rel(y, yref), _elem(y, yref)
+    _say(f"  relative error {e:.2e}, max abs {np.abs(y - yref).max():.2e}, element ratio {r:.3f}")
+    assert e <= REL and r <= 1.0
     # gathered rows give the same values bit for bit (rows are independent)
     idx = np.random.default_rng(0).permutation(1000)[:333].astype(np.int32)
     yg = s.predict(X, torch.from_numpy(idx).cuda()).cpu().numpy()
@@ -105,9 +118,9 @@ def test_forward_beyond_one_chunk(torch):
     rows = np.concatenate([rng.choice(n, 400, replace=False), [0, 65535, 65536, n - 1]])
     Wl, bl = M.unflatten(p)
     yref, _ = M.forward(Xh[rows], Wl, bl, emulate_bf16=True)
-    e = _rel(y[rows], yref)
-    _say(f"[forward] n={n}: sampled relative error {e:.2e}")
-    assert e <= REL
+    e, r = _rel(y[rows], yref), _elem(y[rows], yref)
+    _say(f"[forward] n={n}: sampled relative error {e:.2e}, element ratio {r:.3f}")
+    assert e <= REL and r <= 1.0
 
 
 def _grads_case(torch, B, seed):
@@ -136,8 +149,10 @@ def test_train_step_gradients_match_oracle(torch, B):
     Wg, bg = M.unflatten(gg)
     for l in range(4):
         ew, eb = _rel(Wg[l], gW[l]), _rel(bg[l], gb[l])
-        _say(f"  layer {l + 1}: grad W rel {ew:.2e}, grad b rel {eb:.2e}")
+        rw, rb = _elem(Wg[l], gW[l]), _elem(bg[l], gb[l])
+        _say(f"  layer {l + 1}: grad W rel {ew:.2e} (element ratio {rw:.3f}), grad b rel {eb:.2e} ({rb:.3f})")
         assert ew <= REL and eb <= REL
+        assert rw <= 1.0 and rb <= 1.0
     # the step that followed used Adam's first update, lr * g / (|g| + eps)
     p1, m1, v1, t = s.get_state()
     assert t == 1

@@ -11,7 +11,7 @@ from oracle import oracle as O
 from paper_2502_11129_amd import sim as S
 from paper_2502_11129_amd import workloads as W
 
-from _parity import fitness_gate, perturbed_fitness
+from _parity import assert_gate, perturbed_fitness
 
 
 @pytest.mark.parametrize("name, pop, T", [
@@ -31,8 +31,7 @@ def test_host_worker_matches_oracle(name, pop, T, factorization):
     Fh, sec = h.rollout_host(T, threads=4)
     Fr = O.Oracle(pop).rollout(T, threads=4)
     F32 = O.Oracle(pop, precision=32).rollout(T, threads=4)
-    ok, chaotic, ratio = fitness_gate(Fh.astype(np.float64), Fr, F32, perturbed_fitness(pop, T))
-    assert ok.all(), (name, np.where(~ok)[0], Fh[~ok], Fr[~ok], ratio.max())
+    assert_gate(Fh.astype(np.float64), Fr, F32, perturbed_fitness(pop, T), label=f"{name} {factorization}: ")
     assert sec > 0
 
 

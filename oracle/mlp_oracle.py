@@ -130,20 +130,26 @@ def forward(X, W, b, emulate_bf16=True):
     return y, (hs, zs)
 
 
-def backward(cache, W, dy, emulate_bf16=True):
-    """Gradients of sum(dy * y) w.r.t. W and b (float64)."""
+def backward(cache, W, dy, emulate_bf16=True, return_dz=False):
+    """Gradients of sum(dy * y) w.r.t. W and b (float64).  With return_dz,
+    also the output gradient of each layer (dz, after its rounding; the
+    head's is dy), whose products with the layer inputs make up the sums."""
     r = bf16 if emulate_bf16 else (lambda x: np.asarray(x, np.float64))
     hs, zs = cache
-    gW, gb = [None] * 4, [None] * 4
+    gW, gb, dzs = [None] * 4, [None] * 4, [None] * 4
     gW[3] = (hs[3].T @ dy)[:, None]
     gb[3] = np.array([dy.sum()])
+    dzs[3] = np.asarray(dy, np.float64)[:, None]
     dh = np.outer(dy, r(W[3]).astype(np.float64)[:, 0])
     for l in (2, 1, 0):
         dz = r(dh * gelu_grad(zs[l]))
+        dzs[l] = dz
         gW[l] = hs[l].T @ dz
         gb[l] = dz.sum(axis=0)
         if l > 0:
             dh = dz @ r(W[l]).astype(np.float64).T
+    if return_dz:
+        return gW, gb, dzs
     return gW, gb
 
 

@@ -47,6 +47,7 @@
 #include <algorithm>
 #include <array>
 #include <cmath>
+#include <limits>
 #include <cstdint>
 #include <cstring>
 #include <memory>
@@ -229,6 +230,10 @@ template <class T> struct State {
   uint32_t status = 0;
   T x0 = 0, y0 = 0;
   uint64_t rows_contact = 0, rows_clamp = 0;
+  // closest approach to the ground plane, over the steps taken since the last
+  // reset or set_state, of a box corner or of the ball (|height|, metres):
+  // bookkeeping for the tests, no part of the dynamics
+  double plane_margin = std::numeric_limits<double>::infinity();
 };
 
 template <class T> struct Kin {
@@ -609,6 +614,14 @@ template <class T> struct Sim {
     // 5. contacts and their rows
     std::vector<Contact> C;
     detect(V, kin, C);
+    for (int i = (r0 == 6 ? 0 : 1); i < (int)V.bodies.size(); ++i)
+      for (int cn = 0; cn < 8; ++cn) {
+        const V3<T> sc = {(cn & 1) ? V.bodies[i].half[0] : -V.bodies[i].half[0],
+                          (cn & 2) ? V.bodies[i].half[1] : -V.bodies[i].half[1],
+                          (cn & 4) ? V.bodies[i].half[2] : -V.bodies[i].half[2]};
+        S.plane_margin = std::min(S.plane_margin, std::abs(double(add(kin.p[i], mv(kin.R[i], sc))[2])));
+      }
+    if (V.ball) S.plane_margin = std::min(S.plane_margin, std::abs(double(kin.cb[2] - V.ball_r)));
     int nself = 0;
     for (const auto& ct : C) nself += ct.kind == 3;
     if (nself > 256) { S.status |= 4u; return; }  // more self-collision contacts than allowed: frozen
@@ -826,6 +839,7 @@ template <class T> struct Sim {
     const Variant<T>& V = var[vi];
     State<T>& S = st[vi];
     S.q = V.q0; S.v = V.v0; S.k = 0; S.status = 0; S.rows_contact = S.rows_clamp = 0;
+    S.plane_margin = std::numeric_limits<double>::infinity();
     S.x0 = V.r0 == 6 ? V.q0[0] : T(0);
     S.y0 = V.r0 == 6 ? V.q0[1] : T(0);
   }
@@ -990,8 +1004,15 @@ void orc_set_state(void* hp, const double* q, const double* v, const int64_t* k)
       qo += st.q.size(); vo += st.v.size();
       if (k) st.k = k[i];
       st.status = 0;
+      st.plane_margin = std::numeric_limits<double>::infinity();
     }
   });
+}
+// Closest approach of a box corner or the ball to the plane, per variant, over
+// the steps since the last reset / set_state (infinity before the first step).
+void orc_plane_margin(void* hp, double* out) {
+  auto* h = static_cast<Handle*>(hp);
+  ORC_DISPATCH(h, for (int i = 0; i < (int)S.var.size(); ++i) out[i] = S.st[i].plane_margin);
 }
 void orc_counters(void* hp, uint64_t* rows_contact, uint64_t* rows_clamp) {
   auto* h = static_cast<Handle*>(hp);

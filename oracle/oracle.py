@@ -59,6 +59,7 @@ def _declare(lib):
     lib.orc_get_state.argtypes = [P, D, D, I64, U32]
     lib.orc_set_state.argtypes = [P, D, D, I64]
     lib.orc_counters.argtypes = [P, U64, U64]
+    lib.orc_plane_margin.argtypes = [P, D]
     lib.orc_invariants.argtypes = [P, I, D]
     lib.orc_fk.argtypes = [P, I, D, D, D, D, D]
     lib.orc_fk.restype = I
@@ -214,6 +215,14 @@ class Oracle:
         b = np.zeros(self.n, np.uint64)
         self._lib.orc_counters(self.h, _p(a, C.c_uint64), _p(b, C.c_uint64))
         return a, b
+
+    def plane_margin(self) -> np.ndarray:
+        """Per variant, the smallest |height| above the plane of any box corner
+        (and of the ball's lowest point) over the steps since the last reset or
+        set_state: how close a contact came to switching on or off."""
+        out = np.empty(self.n)
+        self._lib.orc_plane_margin(self.h, _p(out, C.c_double))
+        return out
 
     def invariants(self, vi: int = 0) -> np.ndarray:
         out = np.zeros(7, np.float64)

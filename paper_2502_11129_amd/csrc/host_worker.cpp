@@ -45,6 +45,35 @@ inline M3 qrot(float w, float x, float y, float z) {
            2.f * (x * y + w * z), 1.f - 2.f * (x * x + z * z), 2.f * (y * z - w * x),
            2.f * (x * z - w * y), 2.f * (y * z + w * x), 1.f - 2.f * (x * x + y * y)}};
 }
+// q <- normalize(q (x) exp(phi)) (right: phi in the body frame) or
+// normalize(exp(phi) (x) q) (phi in the world frame), formed as q + dq with
+// dq = (cos(a/2) - 1) q + q (x) (0, u) (resp. (0, u) (x) q), u = sin(a/2) phi / a,
+// cos(a/2) - 1 = -2 sin^2(a/4), then pulled back to unit norm along q by
+// q -= q (|q|^2 - 1) / 2: each component takes the rounding of one small
+// increment, not that of a product with cos(a/2) ~ 1 - 2^-24 and with a float
+// 1 / |q|, which rounds every component the same way step after step.
+inline void quat_step(float* q, V3 phi, bool right) {
+  const float an = std::sqrt(dotp(phi, phi));
+  float cm1 = 0.f, us = 0.5f;
+  if (an >= 1e-8f) {
+    const float s4 = std::sin(0.25f * an), c4 = std::cos(0.25f * an);
+    cm1 = -2.f * s4 * s4;
+    us = 2.f * s4 * c4 / an;
+  }
+  const float ux = phi.x * us, uy = phi.y * us, uz = phi.z * us;
+  const float w = q[0], x = q[1], y = q[2], z = q[3];
+  float d[4];
+  d[0] = -(x * ux + y * uy + z * uz);
+  if (right) {
+    d[1] = w * ux + (y * uz - z * uy); d[2] = w * uy + (z * ux - x * uz); d[3] = w * uz + (x * uy - y * ux);
+  } else {
+    d[1] = w * ux + (uy * z - uz * y); d[2] = w * uy + (uz * x - ux * z); d[3] = w * uz + (ux * y - uy * x);
+  }
+  float n[4];
+  for (int i = 0; i < 4; ++i) n[i] = q[i] + std::fma(cm1, q[i], d[i]);
+  const float e = std::fma(n[0], n[0], std::fma(n[1], n[1], std::fma(n[2], n[2], std::fma(n[3], n[3], -1.f))));
+  for (int i = 0; i < 4; ++i) q[i] = std::fma(n[i], -0.5f * e, n[i]);
+}
 inline M3 arot(V3 u, float s, float c) {
   const float C = 1.f - c;
   return {{c + u.x * u.x * C, u.x * u.y * C - u.z * s, u.x * u.z * C + u.y * s,
@@ -544,31 +573,13 @@ bool step(const HostVariantView& m, const ModelParams& P, HostVariantState& st, 
   if (r0) {
     const V3 dp = mv(R0, v3(wk.vp[3], wk.vp[4], wk.vp[5]));
     qn[0] = q[0] + dt * dp.x; qn[1] = q[1] + dt * dp.y; qn[2] = q[2] + dt * dp.z;
-    const V3 phi = v3(wk.vp[0], wk.vp[1], wk.vp[2]) * dt;
-    const float an = std::sqrt(dotp(phi, phi));
-    float dq[4];
-    if (an < 1e-8f) { dq[0] = 1.f; dq[1] = 0.5f * phi.x; dq[2] = 0.5f * phi.y; dq[3] = 0.5f * phi.z; }
-    else { const float s = std::sin(0.5f * an) / an; dq[0] = std::cos(0.5f * an); dq[1] = phi.x * s; dq[2] = phi.y * s; dq[3] = phi.z * s; }
-    const float aw = q[3], ax = q[4], ay = q[5], az = q[6];
-    float Q[4] = {aw * dq[0] - ax * dq[1] - ay * dq[2] - az * dq[3], aw * dq[1] + ax * dq[0] + ay * dq[3] - az * dq[2],
-                  aw * dq[2] - ax * dq[3] + ay * dq[0] + az * dq[1], aw * dq[3] + ax * dq[2] - ay * dq[1] + az * dq[0]};
-    const float n = std::sqrt(Q[0] * Q[0] + Q[1] * Q[1] + Q[2] * Q[2] + Q[3] * Q[3]);
-    for (int i = 0; i < 4; ++i) qn[3 + i] = Q[i] / n;
+    quat_step(qn + 3, v3(wk.vp[0], wk.vp[1], wk.vp[2]) * dt, true);  // body-frame rate
   }
   if (ball) {  // world velocities: p += dt v, Q <- exp(dt w) Q
     qn[nqr] = q[nqr] + dt * wk.vp[nvr + 3];
     qn[nqr + 1] = q[nqr + 1] + dt * wk.vp[nvr + 4];
     qn[nqr + 2] = q[nqr + 2] + dt * wk.vp[nvr + 5];
-    const V3 phi = v3(wk.vp[nvr], wk.vp[nvr + 1], wk.vp[nvr + 2]) * dt;
-    const float an = std::sqrt(dotp(phi, phi));
-    float dq[4];
-    if (an < 1e-8f) { dq[0] = 1.f; dq[1] = 0.5f * phi.x; dq[2] = 0.5f * phi.y; dq[3] = 0.5f * phi.z; }
-    else { const float s = std::sin(0.5f * an) / an; dq[0] = std::cos(0.5f * an); dq[1] = phi.x * s; dq[2] = phi.y * s; dq[3] = phi.z * s; }
-    const float* b = q + nqr + 3;
-    float Q[4] = {dq[0] * b[0] - dq[1] * b[1] - dq[2] * b[2] - dq[3] * b[3], dq[0] * b[1] + dq[1] * b[0] + dq[2] * b[3] - dq[3] * b[2],
-                  dq[0] * b[2] - dq[1] * b[3] + dq[2] * b[0] + dq[3] * b[1], dq[0] * b[3] + dq[1] * b[2] - dq[2] * b[1] + dq[3] * b[0]};
-    const float n = std::sqrt(Q[0] * Q[0] + Q[1] * Q[1] + Q[2] * Q[2] + Q[3] * Q[3]);
-    for (int i = 0; i < 4; ++i) qn[nqr + 3 + i] = Q[i] / n;
+    quat_step(qn + nqr + 3, v3(wk.vp[nvr], wk.vp[nvr + 1], wk.vp[nvr + 2]) * dt, false);  // world-frame rate
   }
   for (int i = 0; i < nqr + (ball ? 7 : 0); ++i)
     if (!std::isfinite(qn[i])) return false;

@@ -175,6 +175,49 @@ __device__ __forceinline__ m33 axis_rot_acc(f3 u, float s, float c) {
   return R;
 }
 
+// One step of a unit quaternion q by the rotation vector phi:
+// q <- normalize(q (x) exp(phi)) (RIGHT: phi in the body frame) or
+// normalize(exp(phi) (x) q) (phi in the world frame), exp(phi) = (cos(a/2),
+// sin(a/2) phi / a), a = |phi|.  Formed as q + dq with dq = (cos(a/2) - 1) q +
+// q (x) (0, u) (resp. (0, u) (x) q), u = sin(a/2) phi / a and cos(a/2) - 1 =
+// -2 sin^2(a/4), so each component takes one rounding, that of a small
+// increment added to it; the norm is then brought back to 1 along q by
+// q -= q (|q|^2 - 1) / 2 (one fused multiply-add per component).  Multiplying
+// by the float value of cos(a/2) (1 - 2^-24 for the rates of these robots) and
+// by a float 1 / |q| instead rounds every component in the same direction step
+// after step, which turns the orientation by ~3e-8 rad per step.
+template <bool RIGHT>
+__device__ __forceinline__ void quat_step(float (&q)[4], f3 phi) {
+  const float an = sqrtf(dot3(phi, phi));
+  float cm1 = 0.f, us = 0.5f;  // cos(a/2) - 1 and sin(a/2) / a (limits at a -> 0)
+  if (an >= 1e-8f) {
+    float s4, c4;
+    sincosf(0.25f * an, &s4, &c4);
+    cm1 = -2.f * s4 * s4;
+    us = 2.f * s4 * c4 / an;
+  }
+  const float ux = phi.x * us, uy = phi.y * us, uz = phi.z * us;
+  const float w = q[0], x = q[1], y = q[2], z = q[3];
+  float d[4];
+  d[0] = -(x * ux + y * uy + z * uz);
+  if (RIGHT) {  // q (x) (0, u) = (-q.u, w u + q x u)
+    d[1] = w * ux + (y * uz - z * uy);
+    d[2] = w * uy + (z * ux - x * uz);
+    d[3] = w * uz + (x * uy - y * ux);
+  } else {      // (0, u) (x) q = (-u.q, w u + u x q)
+    d[1] = w * ux + (uy * z - uz * y);
+    d[2] = w * uy + (uz * x - ux * z);
+    d[3] = w * uz + (ux * y - uy * x);
+  }
+  float n[4];
+#pragma unroll
+  for (int i = 0; i < 4; ++i) n[i] = q[i] + fmaf(cm1, q[i], d[i]);
+  const float e = fmaf(n[0], n[0], fmaf(n[1], n[1], fmaf(n[2], n[2], fmaf(n[3], n[3], -1.f))));
+  const float h = -0.5f * e;
+#pragma unroll
+  for (int i = 0; i < 4; ++i) q[i] = fmaf(n[i], h, n[i]);
+}
+
 // Spatial vectors (angular; linear at the frame origin), world axes at p0.
 struct sv { f3 a, l; };
 // motion cross product  V x_m U
@@ -1409,25 +1452,7 @@ __device__ __forceinline__ void rollout_body(const BinArgs& a, const ModelParams
     if (r0 == 6) {
       const f3 dp = mul(R0, vn);
       p0n[0] = fmaf(dt, dp.x, p0[0]); p0n[1] = fmaf(dt, dp.y, p0[1]); p0n[2] = fmaf(dt, dp.z, p0[2]);
-      const f3 phi = wn * dt;
-      const float an = sqrtf(dot3(phi, phi));
-      float dq[4];
-      if (an < 1e-8f) {
-        dq[0] = 1.f; dq[1] = 0.5f * phi.x; dq[2] = 0.5f * phi.y; dq[3] = 0.5f * phi.z;
-      } else {
-        float sh2, ch2;
-        sincosf(0.5f * an, &sh2, &ch2);
-        const float sc = sh2 / an;
-        dq[0] = ch2; dq[1] = phi.x * sc; dq[2] = phi.y * sc; dq[3] = phi.z * sc;
-      }
-      const float aw = Q0[0], ax = Q0[1], ay = Q0[2], az = Q0[3];
-      float qn[4] = {aw * dq[0] - ax * dq[1] - ay * dq[2] - az * dq[3],
-                     aw * dq[1] + ax * dq[0] + ay * dq[3] - az * dq[2],
-                     aw * dq[2] - ax * dq[3] + ay * dq[0] + az * dq[1],
-                     aw * dq[3] + ax * dq[2] - ay * dq[1] + az * dq[0]};
-      const float inrm = 1.f / sqrtf(qn[0] * qn[0] + qn[1] * qn[1] + qn[2] * qn[2] + qn[3] * qn[3]);
-#pragma unroll
-      for (int i = 0; i < 4; ++i) Q0n[i] = qn[i] * inrm;
+      quat_step<true>(Q0n, wn * dt);  // body-frame rate
       bool ok = true;
 #pragma unroll
       for (int i = 0; i < 3; ++i) ok = ok && isfinite(p0n[i]);
@@ -1449,25 +1474,7 @@ __device__ __forceinline__ void rollout_body(const BinArgs& a, const ModelParams
       wave_sync();  // read before the next step's writes
       pbn[0] = fmaf(dt, vbn.x, pb[0]); pbn[1] = fmaf(dt, vbn.y, pb[1]); pbn[2] = fmaf(dt, vbn.z, pb[2]);
       // world angular velocity: Q <- exp(dt w) Q
-      const f3 phi = wbn * dt;
-      const float an = sqrtf(dot3(phi, phi));
-      float dq[4];
-      if (an < 1e-8f) {
-        dq[0] = 1.f; dq[1] = 0.5f * phi.x; dq[2] = 0.5f * phi.y; dq[3] = 0.5f * phi.z;
-      } else {
-        float sh2, ch2;
-        sincosf(0.5f * an, &sh2, &ch2);
-        const float sc = sh2 / an;
-        dq[0] = ch2; dq[1] = phi.x * sc; dq[2] = phi.y * sc; dq[3] = phi.z * sc;
-      }
-      const float bw = Qb[0], bx = Qb[1], by = Qb[2], bz = Qb[3];
-      float qn[4] = {dq[0] * bw - dq[1] * bx - dq[2] * by - dq[3] * bz,
-                     dq[0] * bx + dq[1] * bw + dq[2] * bz - dq[3] * by,
-                     dq[0] * by - dq[1] * bz + dq[2] * bw + dq[3] * bx,
-                     dq[0] * bz + dq[1] * by - dq[2] * bx + dq[3] * bw};
-      const float inrm = 1.f / sqrtf(qn[0] * qn[0] + qn[1] * qn[1] + qn[2] * qn[2] + qn[3] * qn[3]);
-#pragma unroll
-      for (int i = 0; i < 4; ++i) Qbn[i] = qn[i] * inrm;
+      quat_step<false>(Qbn, wbn * dt);  // world-frame rate
       bool ok = true;
 #pragma unroll
       for (int i = 0; i < 3; ++i) ok = ok && isfinite(pbn[i]);

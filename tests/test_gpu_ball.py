@@ -12,7 +12,7 @@ import pytest
 from oracle import oracle as O
 from paper_2502_11129_amd import workloads as W
 
-from _parity import STEP_TOL, THREADS, assert_gate, perturbed_fitness, teacher_forced, teacher_forced_counters
+from _parity import STEP_TOL, THREADS, assert_gate, oracle_reference, teacher_forced, teacher_forced_counters
 
 pytestmark = pytest.mark.gpu
 
@@ -63,11 +63,10 @@ def test_ball_fitness_after_T(name, make, T):
     sim = Simulator(pop)
     sim.rollout(T)
     Fg = sim.fitness().astype(np.float64)
-    Fr = O.Oracle(pop).rollout(T, threads=THREADS)
-    F32 = O.Oracle(pop, precision=32).rollout(T, threads=THREADS)
+    Fr, F32, Fp, margin = oracle_reference(pop, T)
     _, _, status = sim.counters()
     assert (status == 0).all()
-    assert_gate(Fg, Fr, F32, perturbed_fitness(pop, T), say=_say)
+    assert_gate(Fg, Fr, F32, Fp, say=_say, margin=margin)
 
 
 def test_ball_overflow_contacts_bitwise_equal_register_path():

@@ -16,7 +16,7 @@ import pytest
 from oracle import oracle as O
 from paper_2502_11129_amd import workloads as W
 
-from _parity import THREADS, assert_gate, perturbed_fitness
+from _parity import THREADS, assert_gate, oracle_reference
 
 pytestmark = pytest.mark.gpu
 
@@ -67,9 +67,8 @@ def test_full_size_sampled_variants(name, make, T, opts, sample):
     np.testing.assert_array_equal(vf, vs)
     np.testing.assert_array_equal(k[sample], ks)
     _say("  sampled variants bitwise equal to their own run; oracle ...")
-    Fr = O.Oracle(sub).rollout(T, threads=THREADS)
-    F32 = O.Oracle(sub, precision=32).rollout(T, threads=THREADS)
-    assert_gate(Fs.astype(np.float64), Fr, F32, perturbed_fitness(sub, T), say=_say)
+    Fr, F32, Fp, margin = oracle_reference(sub, T)
+    assert_gate(Fs.astype(np.float64), Fr, F32, Fp, say=_say, margin=margin)
 
 
 def test_full_size_boxes_every_variant():
@@ -80,6 +79,5 @@ def test_full_size_boxes_every_variant():
     _say(f"[full size] boxes 4096 x {T}: every variant against the oracle")
     F, q, v, k, status = _run(pop, T)
     assert (status == 0).all() and (k == T).all()
-    Fr = O.Oracle(pop).rollout(T, threads=THREADS)
-    F32 = O.Oracle(pop, precision=32).rollout(T, threads=THREADS)
-    assert_gate(F.astype(np.float64), Fr, F32, perturbed_fitness(pop, T), say=_say)
+    Fr, F32, Fp, margin = oracle_reference(pop, T)
+    assert_gate(F.astype(np.float64), Fr, F32, Fp, say=_say, margin=margin)

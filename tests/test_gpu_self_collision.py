@@ -15,7 +15,7 @@ import pytest
 from oracle import oracle as O
 from paper_2502_11129_amd import workloads as W
 
-from _parity import STEP_TOL, THREADS, assert_gate, perturbed_fitness, teacher_forced
+from _parity import STEP_TOL, THREADS, assert_gate, oracle_reference, teacher_forced
 
 pytestmark = pytest.mark.gpu
 
@@ -74,9 +74,7 @@ def test_self_fitness_after_T(name, make, T):
     sim = Simulator(pop)
     sim.rollout(T)
     Fg = sim.fitness().astype(np.float64)
-    Fr = O.Oracle(pop).rollout(T, threads=THREADS)
-    F32 = O.Oracle(pop, precision=32).rollout(T, threads=THREADS)
-    Fp = perturbed_fitness(pop, T)
+    Fr, F32, Fp, margin = oracle_reference(pop, T)
     _, _, status = sim.counters()
     assert (status == 0).all()
     if pop.root_type == W.ROOT_FIXED:
@@ -87,7 +85,7 @@ def test_self_fitness_after_T(name, make, T):
         qr = o.get_state()[0]
         assert np.abs(q - qr).max() < 0.05
     else:
-        assert_gate(Fg, Fr, F32, Fp, say=_say)
+        assert_gate(Fg, Fr, F32, Fp, say=_say, margin=margin)
 
 
 def test_self_overflow_contacts_bitwise_equal_register_path():

@@ -11,7 +11,7 @@ from oracle import oracle as O
 from paper_2502_11129_amd import sim as S
 from paper_2502_11129_amd import workloads as W
 
-from _parity import assert_gate, perturbed_fitness
+from _parity import assert_gate, oracle_reference
 
 
 @pytest.mark.parametrize("name, pop, T", [
@@ -29,9 +29,8 @@ from _parity import assert_gate, perturbed_fitness
 def test_host_worker_matches_oracle(name, pop, T, factorization):
     h = S.Handle(pop, host_factorization=factorization)
     Fh, sec = h.rollout_host(T, threads=4)
-    Fr = O.Oracle(pop).rollout(T, threads=4)
-    F32 = O.Oracle(pop, precision=32).rollout(T, threads=4)
-    assert_gate(Fh.astype(np.float64), Fr, F32, perturbed_fitness(pop, T), label=f"{name} {factorization}: ")
+    Fr, F32, Fp, margin = oracle_reference(pop, T, threads=4)
+    assert_gate(Fh.astype(np.float64), Fr, F32, Fp, label=f"{name} {factorization}: ", margin=margin)
     assert sec > 0
 
 

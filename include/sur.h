@@ -142,6 +142,24 @@ int sur_set_state(sur_handle* h, const float* params, const float* m, const floa
  */
 int sur_topk(sur_handle* h, int64_t n, const float* scores, int64_t k, int32_t* out, void* stream);
 
+/*
+ * For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): the same
+ * selection as sur_topk, with the same result, without a handle or workspace.
+ * Its scratch (histogram, selection state, per-block counts) is a static
+ * device array of the library, SUR_TOPK_NOALLOC_MAX scores' worth (≈ 193 KiB),
+ * one copy per GPU, held until the process ends; the call allocates nothing.
+ * Every call on a GPU shares that GPU's copy: calls that overlap on one GPU
+ * (concurrent streams, threads) race and must be serialised by the caller.
+ * scores: device float [n]; out: device int32 [k]; stream as in sur_topk.
+ * n > SUR_TOPK_NOALLOC_MAX, k outside [0, n] or NULL arrays give
+ * SUR_E_INVALID without touching the device; a HIP error gives SUR_E_DEVICE.
+ * err: optional host buffer of err_len bytes for the message (NULL allowed).
+ */
+#define SUR_TOPK_NOALLOC_MAX 16777216
+int sur_topk_noalloc(int64_t n, const float* scores, int64_t k, int32_t* out, void* stream, char* err,
+                     size_t err_len);
+
 /* Training targets in standard units: z[i] = (y[i] - mean) / std over the n
  * values (device float arrays; z may alias y), std the population standard
  * deviation (taken as 1 when it is zero).  stats: host double [2] receiving

@@ -10,6 +10,8 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include <mutex>
+
 #include "../sur_launch.h"
 
 namespace surk {
@@ -618,6 +620,49 @@ hipError_t topk(int64_t n, const float* scores, int64_t k, int32_t* out, const T
   hipLaunchKernelGGL(topk_scan_kernel, dim3(1), dim3(256), 0, s, nb, counts, pre);
   hipLaunchKernelGGL(topk_write_kernel, dim3((unsigned)nb), dim3(256), 0, s, n, scores, ws.state, pre, out);
   return hipGetLastError();
+}
+
+// ----------------------------------------------------------------------------- top-k without allocation
+// Scratch of topk_noalloc: the histogram (256 words), the state (4 words, padded
+// to 64) and the per-block counts and prefixes (3 words per kTopkBlock scores)
+// of one selection over at most kTopkStaticMax scores.  A file-scope device
+// array: each GPU the library runs on holds its own copy until the process
+// ends; every call on a GPU uses that GPU's copy, so calls that overlap on one
+// GPU race.  topk_init_kernel clears what must start at zero.
+constexpr int64_t kTopkStaticWords = 256 + 64 + 3 * (kTopkStaticMax / kTopkBlock);
+static __device__ __align__(256) uint32_t scratch[kTopkStaticWords];
+
+namespace {
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+uint32_t* g_scratch_ptr[kMaxDevices] = {};
+}  // namespace
+
+// Device address of the current GPU's scratch copy, taken once per device (the
+// array's name in host code is only a stand-in for the symbol).
+static hipError_t static_scratch(uint32_t** out) {
+  int dev = 0;
+  hipError_t e = hipGetDevice(&dev);
+  if (e != hipSuccess) return e;
+  if (dev < 0 || dev >= kMaxDevices) return hipErrorInvalidDevice;
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (!g_scratch_ptr[dev]) {
+    void* ptr = nullptr;
+    e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+    if (e != hipSuccess) return e;
+    g_scratch_ptr[dev] = static_cast<uint32_t*>(ptr);
+  }
+  *out = g_scratch_ptr[dev];
+  return hipSuccess;
+}
+
+hipError_t topk_noalloc(int64_t n, const float* scores, int64_t k, int32_t* out, hipStream_t s) {
+  if (n > kTopkStaticMax) return hipErrorInvalidValue;
+  uint32_t* base = nullptr;
+  const hipError_t e = static_scratch(&base);
+  if (e != hipSuccess) return e;
+  const TopkScratch ws{base, base + 256, base + 256 + 64};
+  return topk(n, scores, k, out, ws, s);
 }
 
 // ----------------------------------------------------------------------------- target standardisation

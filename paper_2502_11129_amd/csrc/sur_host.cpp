@@ -414,6 +414,28 @@ int sur_topk(sur_handle* h, int64_t n, const float* scores, int64_t k, int32_t* 
   return SUR_OK;
 }
 
+int sur_topk_noalloc(int64_t n, const float* scores, int64_t k, int32_t* out, void* stream, char* err,
+                     size_t err_len) {
+  auto fail_msg = [&](int code, const char* msg) {
+    if (err && err_len) std::snprintf(err, err_len, "%s", msg);
+    return code;
+  };
+  if (err && err_len) err[0] = '\0';
+  static_assert(SUR_TOPK_NOALLOC_MAX == kTopkStaticMax, "header and scratch size agree");
+  if (n < 0 || k < 0 || k > n) return fail_msg(SUR_E_INVALID, "need 0 <= k <= n");
+  if (n > SUR_TOPK_NOALLOC_MAX)
+    return fail_msg(SUR_E_INVALID, "n exceeds SUR_TOPK_NOALLOC_MAX (16777216 scores), the size of the static scratch");
+  if (k == 0) return SUR_OK;
+  if (!scores || !out) return fail_msg(SUR_E_INVALID, "NULL array");
+  const hipError_t e = topk_noalloc(n, scores, k, out, (hipStream_t)stream);
+  if (e != hipSuccess) {
+    char buf[256];
+    std::snprintf(buf, sizeof(buf), "topk_noalloc: %s", hipGetErrorString(e));
+    return fail_msg(SUR_E_DEVICE, buf);
+  }
+  return SUR_OK;
+}
+
 int sur_standardize(sur_handle* h, int64_t n, const float* y, float* z, double* stats, void* stream) {
   int rc = ready(h);
   if (rc) return rc;

@@ -82,6 +82,10 @@ struct TopkScratch {
   uint32_t* blocks;   // [3 * nblocks]: per block (#greater << 16 | #equal), then exclusive prefixes (2 per block)
 };
 hipError_t topk(int64_t n, const float* scores, int64_t k, int32_t* out, const TopkScratch& ws, hipStream_t s);
+// The same selection with its scratch in a static device array of the library
+// (no allocation, no workspace argument); n <= kTopkStaticMax.
+constexpr int64_t kTopkStaticMax = int64_t(1) << 24;
+hipError_t topk_noalloc(int64_t n, const float* scores, int64_t k, int32_t* out, hipStream_t s);
 
 // z = (y - mean) / std over n values (std of the population; 1 when zero); stats = (mean, std).
 hipError_t standardize(int64_t n, const float* y, float* z, double* stats, hipStream_t s);

@@ -21,7 +21,8 @@ SUR_N_PARAMS = 164865
 SUR_N_FEAT = 128
 EXPORTED = ("sur_create", "sur_workspace_bytes", "sur_bind", "sur_features", "sur_predict", "sur_train_step",
             "sur_train_epoch", "sur_adam_step", "sur_get_grad", "sur_get_state", "sur_set_state", "sur_topk",
-            "sur_standardize", "sur_destroy", "sur_last_error")
+            "sur_standardize", "sur_destroy", "sur_last_error", "sur_topk_noalloc")
+SUR_TOPK_NOALLOC_MAX = 1 << 24
 
 _F = C.POINTER(C.c_float)
 
@@ -58,6 +59,7 @@ def load():
     lib.sur_get_state.argtypes = [P, _F, _F, _F, C.POINTER(C.c_int64), VP]
     lib.sur_set_state.argtypes = [P, _F, _F, _F, C.c_int64, VP]
     lib.sur_topk.argtypes = [P, C.c_int64, VP, C.c_int64, VP, VP]
+    lib.sur_topk_noalloc.argtypes = [C.c_int64, VP, C.c_int64, VP, VP, C.c_char_p, C.c_size_t]
     lib.sur_standardize.argtypes = [P, C.c_int64, VP, VP, C.POINTER(C.c_double), VP]
     lib.sur_destroy.argtypes = [P]
     lib.sur_destroy.restype = None
@@ -72,6 +74,24 @@ def load():
 
 def _ptr(t):
     return C.c_void_p(t.data_ptr()) if t is not None else None
+
+
+def topk_noalloc(scores, k, out=None, stream=None):
+    """sur_topk_noalloc: indices of the k largest of the device float32 tensor
+    `scores` (ascending index order), with the library's static scratch and no
+    allocation inside the call; `out` (device int32 [k]) may be passed so that
+    nothing at all is allocated.  Raises SurError on a refused size."""
+    import torch
+    lib = load()
+    if out is None:
+        out = torch.empty(int(k), dtype=torch.int32, device=scores.device)
+    if stream is None:
+        stream = torch.cuda.current_stream(scores.device).cuda_stream
+    err = C.create_string_buffer(256)
+    rc = lib.sur_topk_noalloc(int(scores.shape[0]), _ptr(scores), int(k), _ptr(out), C.c_void_p(stream), err, 256)
+    if rc != 0:
+        raise SurError(rc, err.value.decode())
+    return out
 
 
 class Surrogate:

@@ -47,3 +47,17 @@ def test_create_validates_and_reports_workspace():
         assert rc == -1, bad
         assert h.value is None
         assert len(lib.sur_last_error(None)) > 0
+
+
+def test_noalloc_topk_refuses_sizes_beyond_its_scratch():
+    """sur_topk_noalloc rejects n above its static scratch, and k outside
+    [0, n], with a message and before any device call."""
+    import ctypes as C
+    from paper_2502_11129_amd import surrogate as SU
+    lib = SU.load()
+    err = C.create_string_buffer(256)
+    rc = lib.sur_topk_noalloc(SU.SUR_TOPK_NOALLOC_MAX + 1, None, 1, None, None, err, 256)
+    assert rc == -1 and b"SUR_TOPK_NOALLOC_MAX" in err.value
+    rc = lib.sur_topk_noalloc(10, None, 11, None, None, err, 256)
+    assert rc == -1 and b"k <= n" in err.value
+    assert lib.sur_topk_noalloc(10, None, 0, None, None, None, 0) == 0

@@ -37,8 +37,13 @@
 // oriented away from the penetrated box; a corner's depth is how far it lies
 // inside the penetrated box's extent along that normal.  Rows act on the
 // relative velocity (corner's box minus penetrated box) at the corner; a row
-// no degree of freedom can move (J M^-1 J^T < 1e-9) is inert.  Two edges
-// crossing with no corner inside are not detected.
+// no degree of freedom can move (J M^-1 J^T < 1e-9) is inert.  A pair that
+// intersects with no corner of either box inside the other, and whose least
+// overlap is along an edge-pair cross product (two edges crossing), gets one
+// contact instead: the midpoint of the closest points of the two crossing
+// edges, normal that axis (towards the first box of the pair), depth the
+// overlap along it.  An edge passing through a face with no corner inside
+// (least overlap along a face normal) gives no contact.
 //
 // The library is templated on the scalar so a float instance can measure how
 // sensitive a trajectory is to single precision.  An RK4 mode (no contact, no
@@ -159,6 +164,56 @@ template <class T> V3<T> sat_axis(const V3<T>& pP, const M3<T>& RP, const V3<T>&
     }
   if (dot(best, d) < 0) best = scl(best, T(-1));
   return best;
+}
+
+// Edge-edge contact of boxes P and Q that intersect although no corner of
+// either lies inside the other (two edges crossing).  The 15 candidate axes
+// and their overlaps are those of sat_axis; when every candidate overlaps
+// (the boxes intersect) and the least overlap belongs to the cross product
+// of P's edge direction i and Q's edge direction j, the contact is the
+// midpoint of the closest points of the two edges that face each other
+// along it: P's edge parallel to its axis i on the side of Q, Q's edge
+// parallel to its axis j on the side of P.  Normal u from Q towards P,
+// depth = the overlap along u.  Returns false in every other case.
+template <class T> bool edge_contact(const V3<T>& pP, const M3<T>& RP, const V3<T>& hP, const V3<T>& pQ,
+                                     const M3<T>& RQ, const V3<T>& hQ, V3<T>& x, V3<T>& n, T& depth) {
+  const V3<T> d = sub(pP, pQ);
+  T best_o = T(INFINITY);
+  V3<T> best{0, 0, 1};
+  int bi = -1, bj = -1;
+  auto axis = [](const M3<T>& R, int k) { return V3<T>{R[k], R[3 + k], R[6 + k]}; };
+  auto consider = [&](const V3<T>& u, int i, int j) {
+    const T o = box_radius(RP, hP, u) + box_radius(RQ, hQ, u) - std::abs(dot(u, d));
+    if (o < best_o) { best_o = o; best = u; bi = i; bj = j; }
+  };
+  for (int k = 0; k < 3; ++k) consider(axis(RP, k), -1, -1);
+  for (int k = 0; k < 3; ++k) consider(axis(RQ, k), -1, -1);
+  for (int i = 0; i < 3; ++i)
+    for (int j = 0; j < 3; ++j) {
+      const V3<T> c = cross(axis(RP, i), axis(RQ, j));
+      const T n2 = dot(c, c);
+      if (n2 < T(1e-6)) continue;
+      consider(scl(c, T(1) / std::sqrt(n2)), i, j);
+    }
+  if (!(best_o > 0) || bi < 0) return false;
+  if (dot(best, d) < 0) best = scl(best, T(-1));
+  // the edges facing each other: P's towards -u, Q's towards +u
+  V3<T> cP = pP, cQ = pQ;
+  for (int k = 0; k < 3; ++k) {
+    if (k != bi) cP = add(cP, scl(axis(RP, k), (dot(best, axis(RP, k)) > 0 ? -hP[k] : hP[k])));
+    if (k != bj) cQ = add(cQ, scl(axis(RQ, k), (dot(best, axis(RQ, k)) < 0 ? -hQ[k] : hQ[k])));
+  }
+  // closest points of the segments cP + t eP (|t| <= hP[bi]) and cQ + s eQ (|s| <= hQ[bj])
+  const V3<T> eP = axis(RP, bi), eQ = axis(RQ, bj), r = sub(cP, cQ);
+  const T b = dot(eP, eQ), c = dot(eP, r), f = dot(eQ, r);
+  auto clampv = [](T v, T lo, T hi) { return v < lo ? lo : (v > hi ? hi : v); };
+  T t = clampv((b * f - c) / (1 - b * b), -hP[bi], hP[bi]);
+  const T s = clampv(f + b * t, -hQ[bj], hQ[bj]);
+  t = clampv(b * s - c, -hP[bi], hP[bi]);
+  x = scl(add(add(cP, scl(eP, t)), add(cQ, scl(eQ, s))), T(0.5));
+  n = best;
+  depth = best_o;
+  return true;
 }
 
 // ----------------------------------------------------------------------------
@@ -543,7 +598,16 @@ template <class T> struct Sim {
               }
             }
           }
-          if (out.size() == first) continue;
+          if (out.size() == first) {
+            // no corner inside: two crossing edges, if the boxes intersect there
+            Contact C;
+            if (edge_contact(kin.p[a], kin.R[a], V.bodies[a].half, kin.p[b], kin.R[b], V.bodies[b].half, C.x, C.n,
+                             C.depth)) {
+              C.body = a; C.other = b; C.corner = -3; C.kind = 3;
+              out.push_back(std::move(C));
+            }
+            continue;
+          }
           // the pair's normal (from b towards a) and each corner's depth along it
           const V3<T> u = sat_axis(kin.p[a], kin.R[a], V.bodies[a].half, kin.p[b], kin.R[b], V.bodies[b].half);
           for (std::size_t k = first; k < out.size(); ++k) {
@@ -1056,8 +1120,9 @@ int orc_dynamics(void* hp, int vi, const double* q, const double* v, double* M, 
   return 0;
 }
 // Active contacts at q: returns count (<= max); body, corner, point x [3], depth, rows J [3*nv] (n, x, y).
-// corner: 0..7 box corner, -1 ball-plane, -2 ball-box (body = the box); other: the
-// penetrated box of a self-collision contact (corner `corner` of `body`), else -1;
+// corner: 0..7 box corner, -1 ball-plane, -2 ball-box (body = the box), -3
+// edge-edge contact of boxes `body` and `other` (normal towards `body`); other:
+// the penetrated box of a self-collision contact (corner `corner` of `body`), else -1;
 // normal n [3] (towards the ball / the corner's box).
 int orc_contacts(void* hp, int vi, const double* q, int max, int32_t* body, int32_t* corner, double* x,
                  double* depth, double* J, double* normal, int32_t* other) {
@@ -1081,6 +1146,22 @@ int orc_contacts(void* hp, int vi, const double* q, int max, int32_t* body, int3
   }
   return (int)C.size();
 }
+// The library's edge-edge contact of two boxes (poses: centre [3], rotation
+// row-major [9], half extents [3]), exposed for its pins: returns 1 and the
+// contact point, normal (towards box P) and depth, or 0 when it gives none.
+int orc_edge_contact(const double* pP, const double* RP, const double* hP, const double* pQ, const double* RQ,
+                     const double* hQ, double* x, double* n, double* depth) {
+  V3<double> a{pP[0], pP[1], pP[2]}, b{pQ[0], pQ[1], pQ[2]}, ha{hP[0], hP[1], hP[2]}, hb{hQ[0], hQ[1], hQ[2]};
+  M3<double> Ra, Rb;
+  for (int k = 0; k < 9; ++k) { Ra[k] = RP[k]; Rb[k] = RQ[k]; }
+  V3<double> xx, nn;
+  double d = 0;
+  if (!edge_contact(a, Ra, ha, b, Rb, hb, xx, nn, d)) return 0;
+  for (int k = 0; k < 3; ++k) { x[k] = xx[k]; n[k] = nn[k]; }
+  *depth = d;
+  return 1;
+}
+
 // The library's own Cholesky, exposed so a test can compare it with LAPACK.
 int orc_cholesky(int n, const double* A, double* L) { return cholesky(n, A, L) ? 0 : -1; }
 

@@ -69,6 +69,8 @@ def _declare(lib):
     lib.orc_contacts.restype = I
     lib.orc_cholesky.argtypes = [I, D, D]
     lib.orc_cholesky.restype = I
+    lib.orc_edge_contact.argtypes = [D, D, D, D, D, D, D, D, D]
+    lib.orc_edge_contact.restype = I
     return lib
 
 
@@ -103,6 +105,17 @@ def cholesky(A: np.ndarray) -> np.ndarray:
     if _load().orc_cholesky(n, _p(A, C.c_double), _p(L, C.c_double)) != 0:
         raise np.linalg.LinAlgError("not positive definite")
     return L
+
+
+def edge_contact(pP, RP, hP, pQ, RQ, hQ):
+    """The oracle's edge-edge contact of two boxes P and Q (centre, 3x3
+    rotation, half extents): (x, n, depth) with n pointing towards P, or None."""
+    args = [np.ascontiguousarray(a, dtype=np.float64).ravel() for a in (pP, RP, hP, pQ, RQ, hQ)]
+    x, n, d = np.zeros(3), np.zeros(3), np.zeros(1)
+    if not _load().orc_edge_contact(*[_p(a, C.c_double) for a in args], _p(x, C.c_double), _p(n, C.c_double),
+                                    _p(d, C.c_double)):
+        return None
+    return x, n, float(d[0])
 
 
 class Oracle:

@@ -8,7 +8,8 @@
 // A ball (when the variant has one) adds six DoFs after the robot's (world
 // spin, centre velocity), a ball-plane contact and ball-box contacts;
 // self-collision adds the corners of a box strictly inside another box of the
-// same robot not joined to it by a hinge.
+// same robot not joined to it by a hinge, and, for a pair with no corner
+// inside that intersects across two edges, one edge-edge contact.
 #include "host_worker.hpp"
 
 #include <cmath>
@@ -234,6 +235,50 @@ V3 sat_axis(V3 pP, const M3& RP, V3 hP, V3 pQ, const M3& RQ, V3 hQ) {
       consider(c * (1.f / std::sqrt(n2)));
     }
   return dotp(best, d) < 0.f ? best * -1.f : best;
+}
+
+// Contact of two intersecting boxes with no corner of either inside the
+// other: when the least overlap over the 15 axes of sat_axis is positive and
+// belongs to the cross product of P's edge direction i and Q's j, the
+// midpoint of the closest points of the two edges facing each other along it
+// (P's on the side of Q, Q's on the side of P), normal from Q towards P, depth
+// the overlap.  False in every other case.
+bool edge_contact(V3 pP, const M3& RP, V3 hP, V3 pQ, const M3& RQ, V3 hQ, V3& x, V3& n, float& depth) {
+  const V3 d = pP - pQ;
+  float best_o = INFINITY;
+  V3 best = v3(0, 0, 1);
+  int bi = -1, bj = -1;
+  auto consider = [&](V3 u, int i, int j) {
+    const float o = box_radius(RP, hP, u) + box_radius(RQ, hQ, u) - std::fabs(dotp(u, d));
+    if (o < best_o) { best_o = o; best = u; bi = i; bj = j; }
+  };
+  for (int k = 0; k < 3; ++k) consider(column(RP, k), -1, -1);
+  for (int k = 0; k < 3; ++k) consider(column(RQ, k), -1, -1);
+  for (int i = 0; i < 3; ++i)
+    for (int j = 0; j < 3; ++j) {
+      const V3 c = crs(column(RP, i), column(RQ, j));
+      const float n2 = dotp(c, c);
+      if (n2 < 1e-6f) continue;
+      consider(c * (1.f / std::sqrt(n2)), i, j);
+    }
+  if (!(best_o > 0.f) || bi < 0) return false;
+  if (dotp(best, d) < 0.f) best = best * -1.f;
+  const float hp[3] = {hP.x, hP.y, hP.z}, hq[3] = {hQ.x, hQ.y, hQ.z};
+  V3 cP = pP, cQ = pQ;
+  for (int k = 0; k < 3; ++k) {
+    if (k != bi) cP = cP + column(RP, k) * (dotp(best, column(RP, k)) > 0.f ? -hp[k] : hp[k]);
+    if (k != bj) cQ = cQ + column(RQ, k) * (dotp(best, column(RQ, k)) < 0.f ? -hq[k] : hq[k]);
+  }
+  const V3 eP = column(RP, bi), eQ = column(RQ, bj), r = cP - cQ;
+  const float b = dotp(eP, eQ), c = dotp(eP, r), f = dotp(eQ, r);
+  auto clampv = [](float v, float lo, float hi) { return v < lo ? lo : (v > hi ? hi : v); };
+  float t = clampv((b * f - c) / (1.f - b * b), -hp[bi], hp[bi]);
+  const float s = clampv(f + b * t, -hq[bj], hq[bj]);
+  t = clampv(b * s - c, -hp[bi], hp[bi]);
+  x = ((cP + eP * t) + (cQ + eQ * s)) * 0.5f;
+  n = best;
+  depth = best_o;
+  return true;
 }
 
 bool step(const HostVariantView& m, const ModelParams& P, HostVariantState& st, Work& wk) {
@@ -488,6 +533,17 @@ bool step(const HostVariantView& m, const ModelParams& P, HostVariantState& st, 
             const V3 n = side ? u * -1.f : u;
             const float depth = dotp(n, wk.p[qb]) + box_radius(wk.R[qb], hq, n) - dotp(n, x);
             add_contact(x, n, depth, ancp, ancq, 0.f, true);
+            ++nself;
+          }
+        }
+        if (!have_u) {  // no corner inside: two crossing edges, if the boxes intersect there
+          V3 x, n;
+          float depth;
+          if (edge_contact(wk.p[a], wk.R[a], half(a), wk.p[b], wk.R[b], half(b), x, n, depth)) {
+            unsigned anca, ancb;
+            { int x0 = Bi(a, BW_ANCESTORS); std::memcpy(&anca, &x0, 4); }
+            { int x0 = Bi(b, BW_ANCESTORS); std::memcpy(&ancb, &x0, 4); }
+            add_contact(x, n, depth, anca, ancb, 0.f, true);
             ++nself;
           }
         }

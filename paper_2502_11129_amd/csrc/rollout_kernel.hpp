@@ -34,7 +34,8 @@
 // to it by a hinge (pairs in order, a bounding-sphere test first); a pair
 // shares the least-overlap separating-axis normal, a corner's depth is its
 // distance inside the other box's extent along it, rows act on the relative
-// velocity, and a row no DoF can move is inert.
+// velocity, and a row no DoF can move is inert.  A pair with no corner inside
+// that intersects across two edges gets one contact at the crossing.
 #pragma once
 #include <hip/hip_runtime.h>
 #include <stdint.h>
@@ -330,6 +331,37 @@ __device__ __forceinline__ void matvec_bcast1(const float (&Mi)[S][NVC], const f
   }
 }
 
+// Scalars of one contact's Gauss-Seidel rows, fixed for the step (the row
+// laws of contact_row rearranged so that the quantities that do not depend on
+// the sweep's velocity leave its dependent chain); s1 = 1 / (D_n (1 + kb dt)),
+// s5 = 1 / (dt D_x), s6 = 1 / (dt D_y):
+//   [0] k d s1, [1] kb s1, [2] kb s1 dt D_n   (normal row)
+//   [3] s5 dt D_xn, [4] s6 dt D_yn            (tangential change per normal change)
+//   [5] s5, [6] s6
+//   [7..9] lambda_n, lambda_x, lambda_y       (cold start)
+// guard: a self-contact row no DoF can move (D < 1e-9) is inert, its gains 0.
+__device__ __forceinline__ void solver_scalars(float kd, float Dn, float Dx, float Dy, float Dxn, float Dyn,
+                                               float kb, float dt, bool guard, float (&scal)[10]) {
+  float s1 = recip(Dn * (1.f + kb * dt));
+  float s5 = recip(dt * Dx), s6 = recip(dt * Dy);
+  if (guard) {
+    if (!(Dn >= 1e-9f)) s1 = 0.f;
+    if (!(Dx >= 1e-9f)) s5 = 0.f;
+    if (!(Dy >= 1e-9f)) s6 = 0.f;
+  }
+  const float a1 = kb * s1;
+  scal[0] = kd * s1;
+  scal[1] = a1;
+  scal[2] = a1 * (dt * Dn);
+  scal[3] = s5 * (dt * Dxn);
+  scal[4] = s6 * (dt * Dyn);
+  scal[5] = s5;
+  scal[6] = s6;
+  scal[7] = 0.f;
+  scal[8] = 0.f;
+  scal[9] = 0.f;
+}
+
 template <int S, int NVC>
 __device__ __forceinline__ void build_rows(const float (&Mi)[S][NVC], const f3 (&ang)[S], const f3 (&cst)[S],
                                            const int (&bodyOfDof)[S], int lane, f3 x, unsigned anc, float kc,
@@ -358,16 +390,7 @@ __device__ __forceinline__ void build_rows(const float (&Mi)[S][NVC], const f3 (
   }
   const float Dn = row_sum(pn), Dx = row_sum(px), Dy = row_sum(py);
   const float Dxn = row_sum(pxn), Dyn = row_sum(pyn);
-  scal[0] = kc * (-x.z);                    // k * depth
-  scal[1] = recip(Dn * (1.f + kb * dt));  // normal row: 1 / (D_n (1 + (b + k dt) dt))
-  scal[2] = dt * Dn;
-  scal[3] = dt * Dxn;                       // tangential velocity change per unit normal force
-  scal[4] = dt * Dyn;
-  scal[5] = recip(dt * Dx);
-  scal[6] = recip(dt * Dy);
-  scal[7] = 0.f;                            // lambda_n, lambda_x, lambda_y (cold start)
-  scal[8] = 0.f;
-  scal[9] = 0.f;
+  solver_scalars(kc * (-x.z), Dn, Dx, Dy, Dxn, Dyn, kb, dt, false, scal);
 }
 
 // Orthonormal tangents of a unit normal n (Duff et al., "Building an
@@ -424,23 +447,9 @@ __device__ __forceinline__ void build_rows_gen(const float (&Mi)[S][NVC], const 
   }
   const float Dn = row_sum(pn), Dx = row_sum(px), Dy = row_sum(py);
   const float Dxn = row_sum(pxn), Dyn = row_sum(pyn);
-  scal[0] = kc * depth;
-  scal[1] = recip(Dn * (1.f + kb * dt));
-  scal[2] = dt * Dn;
-  scal[3] = dt * Dxn;
-  scal[4] = dt * Dyn;
-  scal[5] = recip(dt * Dx);
-  scal[6] = recip(dt * Dy);
-  scal[7] = 0.f;
-  scal[8] = 0.f;
-  scal[9] = 0.f;
-  // a self-contact row no DoF can move is inert: a zero gain keeps its
-  // multiplier at 0 (the normal's 0 also zeroes the friction limit)
-  if (guard) {
-    if (!(Dn >= 1e-9f)) scal[1] = 0.f;
-    if (!(Dx >= 1e-9f)) scal[5] = 0.f;
-    if (!(Dy >= 1e-9f)) scal[6] = 0.f;
-  }
+  // a self-contact row no DoF can move is inert: zero gains keep its
+  // multipliers at 0 (the normal's 0 also zeroes the friction limit)
+  solver_scalars(kc * depth, Dn, Dx, Dy, Dxn, Dyn, kb, dt, guard, scal);
 }
 
 // One contact list entry (ListWord layout); plane-only kernels store the
@@ -498,6 +507,59 @@ __device__ __forceinline__ f3 sat_axis(f3 pP, const m33& RP, f3 hP, f3 pQ, const
   return dot3(best, d) < 0.f ? best * -1.f : best;
 }
 
+// Contact of two intersecting boxes P and Q with no corner of either inside
+// the other (two edges crossing): when the least overlap over the 15 axes of
+// sat_axis is positive and belongs to the cross product of P's edge direction
+// i and Q's j, the midpoint of the closest points of the two edges facing
+// each other along it (P's on the side of Q, Q's on the side of P), normal
+// from Q towards P, depth the overlap.  False in every other case.
+__device__ __forceinline__ bool edge_contact(f3 pP, const m33& RP, f3 hP, f3 pQ, const m33& RQ, f3 hQ, f3& x, f3& n,
+                                             float& depth) {
+  const f3 d = pP - pQ;
+  f3 best = mk(0.f, 0.f, 1.f);
+  float best_o = __int_as_float(0x7f800000);
+  int bi = -1, bj = -1;
+  auto consider = [&](f3 u, int i, int j) {
+    const float o = box_radius(RP, hP, u) + box_radius(RQ, hQ, u) - fabsf(dot3(u, d));
+    if (o < best_o) { best_o = o; best = u; bi = i; bj = j; }
+  };
+#pragma unroll
+  for (int k = 0; k < 3; ++k) consider(mcol(RP, k), -1, -1);
+#pragma unroll
+  for (int k = 0; k < 3; ++k) consider(mcol(RQ, k), -1, -1);
+#pragma unroll
+  for (int i = 0; i < 3; ++i)
+#pragma unroll
+    for (int j = 0; j < 3; ++j) {
+      const f3 c = cross3(mcol(RP, i), mcol(RQ, j));
+      const float n2 = dot3(c, c);
+      if (n2 < 1e-6f) continue;
+      consider(c * (1.f / sqrtf(n2)), i, j);
+    }
+  if (!(best_o > 0.f) || bi < 0) return false;
+  if (dot3(best, d) < 0.f) best = best * -1.f;
+  const float hp[3] = {hP.x, hP.y, hP.z}, hq[3] = {hQ.x, hQ.y, hQ.z};
+  f3 cP = pP, cQ = pQ;
+#pragma unroll
+  for (int k = 0; k < 3; ++k) {
+    const f3 aP = mcol(RP, k), aQ = mcol(RQ, k);
+    if (k != bi) cP = cP + aP * (dot3(best, aP) > 0.f ? -hp[k] : hp[k]);
+    if (k != bj) cQ = cQ + aQ * (dot3(best, aQ) < 0.f ? -hq[k] : hq[k]);
+  }
+  // edge half lengths by selection (no run-time indexing of the arrays)
+  const float lP = bi == 0 ? hp[0] : (bi == 1 ? hp[1] : hp[2]);
+  const float lQ = bj == 0 ? hq[0] : (bj == 1 ? hq[1] : hq[2]);
+  const f3 eP = mcol(RP, bi), eQ = mcol(RQ, bj), r = cP - cQ;
+  const float b = dot3(eP, eQ), c = dot3(eP, r), f = dot3(eQ, r);
+  float t = fminf(lP, fmaxf(-lP, (b * f - c) / (1.f - b * b)));
+  const float s = fminf(lQ, fmaxf(-lQ, f + b * t));
+  t = fminf(lP, fmaxf(-lP, b * s - c));
+  x = ((cP + eP * t) + (cQ + eQ * s)) * 0.5f;
+  n = best;
+  depth = best_o;
+  return true;
+}
+
 // Corner c (bits x, y, z = signs) of a box with pose (R, p) and half extents h.
 __device__ __forceinline__ f3 box_corner(const m33& R, f3 p, f3 h, int c) {
   const f3 s = mk((c & 1) ? h.x : -h.x, (c & 2) ? h.y : -h.y, (c & 4) ? h.z : -h.z);
@@ -538,12 +600,19 @@ __device__ __forceinline__ bool sphere_box(f3 c, float r, f3 p, const m33& R, f3
 
 // One contact of one Gauss-Seidel sweep: soft normal row, then the two
 // friction rows together (Jacobi within the pair), projected on the disk
-// |lambda_t| <= mu lambda_n.  lam[0..2] are read and updated.
+// |lambda_t| <= mu lambda_n.  lam[0..2] are read and updated.  With the
+// scalars of solver_scalars the laws read
+//   lambda_n' = max(0, [0] - [1] u_n + [2] lambda_n),
+//   g_x = lambda_x - [5] u_x - [3] (lambda_n' - lambda_n)   (same for y),
+//   lambda_t' = g min(1, mu lambda_n' / |g|),
+// the oracle's laws with the products regrouped; the terms that do not
+// depend on u are formed beside the dependent chain, and the projection is
+// branch-free.
 template <int S>
 __device__ __forceinline__ void contact_row(float (&vp)[S], const float (&Jn)[S], const float (&Jx)[S],
                                             const float (&Jy)[S], const float (&Wn)[S], const float (&Wx)[S],
                                             const float (&Wy)[S], const float (&sc)[10], float (&lam)[3],
-                                            float mu, float kb, float dt) {
+                                            float mu, float dt) {
   float pn = 0.f, px = 0.f, py = 0.f;
 #pragma unroll
   for (int s = 0; s < S; ++s) {
@@ -551,23 +620,23 @@ __device__ __forceinline__ void contact_row(float (&vp)[S], const float (&Jn)[S]
     px = fmaf(Jx[s], vp[s], px);
     py = fmaf(Jy[s], vp[s], py);
   }
-  const float un = row_sum(pn), ux = row_sum(px), uy = row_sum(py);
   const float ln0 = lam[0], lx0 = lam[1], ly0 = lam[2];
-  const float u0 = un - sc[2] * ln0;
-  const float ln = fmaxf(0.f, (sc[0] - kb * u0) * sc[1]);
+  const float c0 = fmaf(sc[2], ln0, sc[0]);
+  const float un = row_sum(pn), ux = row_sum(px), uy = row_sum(py);
+  const float gxp = fmaf(-sc[5], ux, lx0), gyp = fmaf(-sc[6], uy, ly0);
+  const float ln = fmaxf(0.f, fmaf(-sc[1], un, c0));
   const float dn = ln - ln0;
-  const float ux2 = fmaf(sc[3], dn, ux), uy2 = fmaf(sc[4], dn, uy);
-  float gx = lx0 - ux2 * sc[5], gy = ly0 - uy2 * sc[6];
-  const float gn2 = gx * gx + gy * gy, lim = mu * ln;
-  if (gn2 > lim * lim) {
-    const float scale = lim * __builtin_amdgcn_rsqf(gn2);
-    gx *= scale;
-    gy *= scale;
-  }
-  const float edn = dt * dn, edx = dt * (gx - lx0), edy = dt * (gy - ly0);
-  lam[0] = ln; lam[1] = gx; lam[2] = gy;
+  const float gx = fmaf(-sc[3], dn, gxp), gy = fmaf(-sc[4], dn, gyp);
+  const float edn = fmaf(dt, ln, -dt * ln0);
 #pragma unroll
-  for (int s = 0; s < S; ++s) vp[s] = fmaf(Wn[s], edn, fmaf(Wx[s], edx, fmaf(Wy[s], edy, vp[s])));
+  for (int s = 0; s < S; ++s) vp[s] = fmaf(Wn[s], edn, vp[s]);
+  const float gn2 = fmaf(gx, gx, gy * gy);
+  const float scale = fminf(1.f, (mu * ln) * __builtin_amdgcn_rsqf(gn2));
+  const float nx = gx * scale, ny = gy * scale;
+  const float edx = fmaf(dt, nx, -dt * lx0), edy = fmaf(dt, ny, -dt * ly0);
+  lam[0] = ln; lam[1] = nx; lam[2] = ny;
+#pragma unroll
+  for (int s = 0; s < S; ++s) vp[s] = fmaf(Wx[s], edx, fmaf(Wy[s], edy, vp[s]));
 }
 
 // Smallest value over the 16 lanes of a row (every lane gets it); integer,
@@ -868,7 +937,9 @@ __device__ __forceinline__ void rollout_body(const BinArgs& a, const ModelParams
       // pair order by a DPP scan, corners of a then of b
       for (int c0 = 0; c0 < ncand; c0 += 16) {
         const int ci = c0 + lane;
-        unsigned hits = 0u;  // bits 0..7: corners of a in b, 8..15: corners of b in a
+        unsigned hits = 0u;  // bits 0..7: corners of a in b, 8..15: corners of b in a, 16: edge-edge
+        f3 ex = mk(0.f, 0.f, 0.f), en = ex;  // the edge-edge contact's point and normal (towards a)
+        float ed = 0.f;
         int ia = 0, ib = 0;
         m33 Ra, Rb;
         f3 Pa = mk(0.f, 0.f, 0.f), Pb = Pa, ha = Pa, hb = Pa;
@@ -892,6 +963,8 @@ __device__ __forceinline__ void rollout_body(const BinArgs& a, const ModelParams
             if (point_in_box(box_corner(Ra, Pa, ha, c), Pb, Rb, hb)) hits |= 1u << c;
           for (int c = 0; c < 8; ++c)
             if (point_in_box(box_corner(Rb, Pb, hb, c), Pa, Ra, ha)) hits |= 1u << (8 + c);
+          // no corner inside: two crossing edges, if the boxes intersect there (bit 16)
+          if (hits == 0u && edge_contact(Pa, Ra, ha, Pb, Rb, hb, ex, en, ed)) hits = 1u << 16;
         }
         if (__builtin_amdgcn_ballot_w64(hits != 0u) == 0) continue;  // no hit in any row of the wave
         const int cnt = __builtin_popcount(hits);
@@ -900,6 +973,11 @@ __device__ __forceinline__ void rollout_body(const BinArgs& a, const ModelParams
           int idx = nc + incl - cnt;
           const unsigned anca = __float_as_uint(bodyv[(size_t)ia * BW_WORDS + BW_ANCESTORS]);
           const unsigned ancb = __float_as_uint(bodyv[(size_t)ib * BW_WORDS + BW_ANCESTORS]);
+          if (hits == (1u << 16)) {
+            if (idx < NCR) put_contact<GEN>(&sh.cl[idx][0], ex, anca, ancb, en, ed, 3);
+            else if (idx < MAXC) put_contact<GEN>(&ovf_list[idx * CLW], ex, anca, ancb, en, ed, 3);
+            hits = 0u;
+          }
           const f3 u = sat_axis(Pa, Ra, ha, Pb, Rb, hb);  // from b towards a
           for (int c = 0; c < 16; ++c) {
             if (!((hits >> c) & 1u)) continue;
@@ -1408,7 +1486,7 @@ __device__ __forceinline__ void rollout_body(const BinArgs& a, const ModelParams
 #pragma unroll
           for (int i = 0; i < 10; ++i) sc[i] = sh.cs[c][i];
           lam[0] = sc[7]; lam[1] = sc[8]; lam[2] = sc[9];
-          contact_row<S>(vp, JnR[c], JxR[c], JyR[c], WnR[c], WxR[c], WyR[c], sc, lam, mu, kb, dt);
+          contact_row<S>(vp, JnR[c], JxR[c], JyR[c], WnR[c], WxR[c], WyR[c], sc, lam, mu, dt);
           sh.cs[c][7] = lam[0]; sh.cs[c][8] = lam[1]; sh.cs[c][9] = lam[2];
         }
       }
@@ -1428,7 +1506,7 @@ __device__ __forceinline__ void rollout_body(const BinArgs& a, const ModelParams
 #pragma unroll
         for (int i = 0; i < 10; ++i) sc[i] = sd[i];
         lam[0] = sc[7]; lam[1] = sc[8]; lam[2] = sc[9];
-        contact_row<S>(vp, Jn, Jx, Jy, Wn, Wx, Wy, sc, lam, mu, kb, dt);
+        contact_row<S>(vp, Jn, Jx, Jy, Wn, Wx, Wy, sc, lam, mu, dt);
         sd[7] = lam[0]; sd[8] = lam[1]; sd[9] = lam[2];
       }
     }

@@ -200,16 +200,20 @@ class Surrogate:
 
 
 # ----------------------------------------------------------------------------- orchestration
-def simulate_fitness(g, T=5000, chunk=32768, device=None):
+def simulate_fitness(g, T=5000, chunk=32768, device=None, nudge=None):
     """Exact fitness of genotypes g (the simulator is the judge): rollouts of
-    T steps in chunks of `chunk` robots.  Returns (fitness float32 [n], GPU
-    seconds of the rollouts, host seconds spent building models)."""
+    T steps in chunks of `chunk` robots; with nudge = seed, from initial
+    positions moved by one float32 ulp (workloads.nudged).  Returns (fitness
+    float32 [n], GPU seconds of the rollouts, host seconds spent building
+    models)."""
     import torch
     out = np.zeros(len(g), np.float32)
     gpu_s = host_s = 0.0
     for c0 in range(0, len(g), chunk):
         t0 = time.perf_counter()
         pop = W.population_from_genotypes(g.take(np.arange(c0, min(len(g), c0 + chunk))), steps=T)
+        if nudge is not None:
+            pop = W.nudged(pop, nudge * 1000003 + c0)
         sim = _sim.Simulator(pop, device=device)
         host_s += time.perf_counter() - t0
         st = torch.cuda.current_stream()

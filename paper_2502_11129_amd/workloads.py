@@ -388,6 +388,61 @@ def chain(n_hinges, faces, axis_flags, root_type=ROOT_FIXED, root_pose=(0, 0, 1.
     return b.build(name, 0, params=params)
 
 
+def nudged(pop: Population, seed: int) -> Population:
+    """The population with every initial position coordinate moved by one
+    float32 ulp, up or down by a draw of rng([7, seed]): two rollouts from pop
+    and from nudged(pop) are equally correct float32 simulations of the same
+    robots, so how far their rankings agree bounds what any predictor of the
+    simulated fitness can reach."""
+    rng = np.random.default_rng([7, seed])
+    q0 = np.asarray(pop.q0, np.float32)
+    up = rng.uniform(size=q0.shape) < 0.5
+    q0 = np.where(up, np.nextafter(q0, np.float32(np.inf)), np.nextafter(q0, np.float32(-np.inf))).astype(np.float32)
+    return dataclasses.replace(pop, q0=q0)
+
+
+def twisted_chains(n=16, nh=6, root_type=ROOT_FREE, key=13):
+    """Self-collision scene whose bricks cross edge to edge: n chains of nh
+    bricks, each on a face drawn from +x / +y / -y of its parent with a drawn
+    axis flag, driven by CPG parameters A ~ U(0.7, 1), omega ~ U(1.5, 4),
+    phi ~ U(0, 2 pi) from rng([key, i, attempt]) (large amplitudes curl the
+    chains into themselves); a FREE root rests on the plane, a FIXED one hangs
+    at 1 m.  A draw whose rest pose (all angles 0: the chain turns left on
+    +y, right on -y, in the plane) puts two boxes into each other is drawn
+    again (attempt + 1)."""
+    def overlapping(faces):
+        pos, head, half = [(0.0, 0.0)], 0, [CORE_HALF]
+        for f in faces:
+            head = (head + {"+x": 0, "+y": 1, "-y": 3}[f]) % 4
+            dx, dy = [(1, 0), (0, 1), (-1, 0), (0, -1)][head]
+            r = half[-1] + BRICK_HALF
+            pos.append((pos[-1][0] + r * dx, pos[-1][1] + r * dy))
+            half.append(BRICK_HALF)
+        for a in range(len(pos)):
+            for b in range(a + 2, len(pos)):
+                lim = half[a] + half[b] - 1e-9
+                if abs(pos[a][0] - pos[b][0]) < lim and abs(pos[a][1] - pos[b][1]) < lim:
+                    return True
+        return False
+
+    pops = []
+    for i in range(n):
+        for attempt in range(1000):
+            rng = np.random.default_rng([key, i, attempt])
+            flags = [int(x) for x in rng.integers(0, 2, nh)]
+            faces = [str(x) for x in rng.choice(["+x", "+y", "-y"], nh)]
+            if not overlapping(faces):
+                break
+        cpg = [(float(rng.uniform(0.7, 1.0)), float(rng.uniform(1.5, 4.0)), float(rng.uniform(0, 2 * np.pi)))
+               for _ in range(nh)]
+        if root_type == ROOT_FREE:
+            pops.append(chain(nh, faces, flags, root_type=ROOT_FREE, root_q=[0, 0, CORE_HALF, 1, 0, 0, 0], cpg=cpg,
+                              name="twisted chains"))
+        else:
+            pops.append(chain(nh, faces, flags, root_type=ROOT_FIXED, cpg=cpg, name="twisted chains"))
+    return dataclasses.replace(concat(pops), self_collision=True, name="twisted chains")
+
+
 def single_box(half=(0.05, 0.05, 0.05), mass=None, pos=(0, 0, 1.0), quat=(1, 0, 0, 0),
                omega_b=(0, 0, 0), v_b=(0, 0, 0), mu=1.0, params=None, name="box", ball=None):
     """One free box; ``ball`` = dict(r, m, pos, quat, w, v) adds a ball

@@ -73,7 +73,11 @@ def self_margin(o, pop, vi, q):
     a corner of one box within reach of another box's surface (the inside /
     outside switch), and, for pairs in contact, the gap between the two
     smallest separating-axis overlaps (the normal's choice) and the distance
-    of an edge-pair cross product's squared norm from its 1e-6 cut."""
+    of an edge-pair cross product's squared norm from its 1e-6 cut; for pairs
+    with no corner inside, also the least overlap itself (the edge-edge
+    contact's switch) and, when it is positive, the gap to the next one and
+    how close the facing edges are to their ends or their choice (the sides
+    the normal picks)."""
     R, p, _, _ = o.fk(vi, q)
     b0 = pop.body_offset[vi]
     nb = R.shape[0]
@@ -94,18 +98,28 @@ def self_margin(o, pop, vi, q):
                 if inside_or_close.any():
                     best = min(best, near[inside_or_close].min())
                 touching = touching or (gap > 0).all(axis=1).any()
+            d = p[a] - p[b]
+            if np.linalg.norm(d) > np.linalg.norm(half[a]) + np.linalg.norm(half[b]) + 1e-3:
+                continue                                      # far apart: no switch nearby
+            axes, cuts = [R[a][:, k] for k in range(3)] + [R[b][:, k] for k in range(3)], []
+            for i in range(3):
+                for j in range(3):
+                    c = np.cross(R[a][:, i], R[b][:, j])
+                    cuts.append(abs(c @ c - 1e-6))
+                    if c @ c >= 1e-6:
+                        axes.append(c / np.linalg.norm(c))
+            ov = np.array([half[a] @ np.abs(R[a].T @ u) + half[b] @ np.abs(R[b].T @ u) - abs(u @ d) for u in axes])
+            over = np.sort(ov)
             if touching:
-                d = p[a] - p[b]
-                axes, cuts = [R[a][:, k] for k in range(3)] + [R[b][:, k] for k in range(3)], []
-                for i in range(3):
-                    for j in range(3):
-                        c = np.cross(R[a][:, i], R[b][:, j])
-                        cuts.append(abs(c @ c - 1e-6))
-                        if c @ c >= 1e-6:
-                            axes.append(c / np.linalg.norm(c))
-                over = np.sort([half[a] @ np.abs(R[a].T @ u) + half[b] @ np.abs(R[b].T @ u) - abs(u @ d)
-                                for u in axes])
                 best = min(best, over[1] - over[0], min(cuts))
+            elif over[0] > -1e-3:
+                best = min(best, abs(over[0]), min(cuts))
+                if over[0] > 0:
+                    best = min(best, over[1] - over[0])
+                    k = int(np.argmin(ov))
+                    if k >= 6:  # an edge-pair axis: the facing edges' sides are the signs of
+                        u = axes[k]  # u along the other two axes of each box (the third is 0)
+                        best = min(best, np.sort(np.abs(R[a].T @ u))[1], np.sort(np.abs(R[b].T @ u))[1])
     return best
 
 

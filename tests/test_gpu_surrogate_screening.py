@@ -51,6 +51,8 @@ def test_screening_beats_unscreened_sample_at_equal_simulation_budget():
     f_rand, _, _ = simulate_fitness(pool.take(np.arange(1000)), T=T)     # the pool is i.i.d.
     _say(f"  mean fitness screened {f_top.mean():.4f} vs unscreened {f_rand.mean():.4f}; "
          f"stage seconds {t}")
-    assert rho > 0.2
-    assert rec > 0.1                     # chance level is 0.05
-    assert f_top.mean() > 1.2 * f_rand.mean()
+    # regression guards at what this configuration reaches (16k labels: Spearman
+    # 0.55, recall 0.15-0.16; chance is 0.05): the 0.9 recall target is not met
+    assert rho >= 0.45
+    assert rec >= 0.12
+    assert f_top.mean() > 1.5 * f_rand.mean()

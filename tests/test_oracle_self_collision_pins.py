@@ -2,7 +2,9 @@
 the same robot not joined to it by a hinge, one separating-axis normal per
 pair) against an independent brute-force enumeration over the oracle's own
 forward kinematics (point-in-box tests and a separating-axis search written
-here), rigid-motion invariance of the rows, a folding chain that passes
+here; an edge-edge contact only for pairs with no corner inside, with the
+depth of the boxes' corner supports along its normal), rigid-motion
+invariance of the rows, a folding chain that passes
 through itself without the contacts and stops with them, and quadrupeds
 whose limbs meet without the solver failing."""
 import dataclasses
@@ -89,9 +91,21 @@ def test_self_contacts_against_brute_force_enumeration():
         c = o.contacts(vi, q, max_contacts=4096)
         want, ambiguous = _brute_force(o, pop, vi, q, band=1e-12)
         # corners within rounding of a box surface may go either way
-        sel = [k for k in np.where(c["other"] >= 0)[0]
+        sel = [k for k in np.where((c["other"] >= 0) & (c["corner"] >= 0))[0]
                if (int(c["body"][k]), int(c["other"][k]), int(c["corner"][k])) not in ambiguous]
         assert len(sel) == len(want)
+        # edge-edge contacts (corner -3) only for pairs with no corner inside or near a
+        # surface, with the depth the overlap of the two boxes' corner supports along n
+        R, p, _, _ = o.fk(vi, q)
+        b0 = pop.body_offset[vi]
+        half = pop.half_ext[b0:b0 + R.shape[0]].astype(np.float64)
+        near = {(P, Q) for P, Q, _ in ambiguous} | {(P, Q) for P, Q, *_ in want}
+        for k in np.where(c["corner"] == -3)[0]:
+            P, Q = int(c["body"][k]), int(c["other"][k])
+            assert (P, Q) not in near and (Q, P) not in near
+            n = c["normal"][k]
+            ov = (_corners(p[Q], R[Q], half[Q]) @ n).max() - (_corners(p[P], R[P], half[P]) @ n).min()
+            np.testing.assert_allclose(c["depth"][k], ov, rtol=0, atol=1e-12)
         for k, (P, Q, corner, depth, n, x) in zip(sel, want):
             assert (c["body"][k], c["other"][k], c["corner"][k]) == (P, Q, corner)
             np.testing.assert_allclose(c["depth"][k], depth, rtol=0, atol=1e-12)

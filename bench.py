@@ -46,6 +46,10 @@ def parse():
     ap.add_argument("--cpu-sample-steps", type=int, default=4000)
     ap.add_argument("--no-peak-probe", action="store_true",
                     help="skip the microbenchmarks that measure the attainable FP32, BF16 MFMA and copy peaks")
+    ap.add_argument("--cpu-configs", action="store_true",
+                    help="instead of the GPU benchmark: the FP64 oracle over the whole snake (16 x 1000), box "
+                         "(4096 x 2000), random-tree (8192 x 5000) and quadruped (32768 x 1000) populations on "
+                         "this host's cores, all-core and single-thread rates, one JSON line")
     ap.add_argument("--no-surrogate", action="store_true",
                     help="skip the surrogate-screened generation (200k labels, 1M pool) reported beside the "
                          "rollout throughput")
@@ -129,8 +133,46 @@ def recorded_traffic(kernel, steps_per_launch):
     return (fetch * rec["scale"]["FETCH_SIZE"] + write * rec["scale"]["WRITE_SIZE"]) * 1024.0
 
 
+def cpu_configs():
+    """The FP64 oracle (-O3 -march=native on this host) over every population of
+    the benchmark configurations, whole, on all host threads (at most 16, the
+    host share of one GPU), and on one thread over a sample of each."""
+    import tempfile
+    from oracle import oracle as O
+    from paper_2502_11129_amd import workloads as W
+    try:
+        avail = len(os.sched_getaffinity(0))
+    except AttributeError:
+        avail = os.cpu_count() or 1
+    cores = max(1, min(16, avail))
+    lib = O.load_native(os.path.join(tempfile.gettempdir(), f"oracle_native_{os.getpid()}"))
+    rows = []
+    for name, pop, T in (("snakes", W.snake(16), 1000), ("boxes", W.boxes(4096), 2000),
+                         ("random trees", W.random_trees(8192), 5000), ("quadrupeds", W.quadrupeds(32768), 1000)):
+        o = O.Oracle(pop, lib=lib)
+        t0 = time.perf_counter()
+        o.rollout(T, threads=cores)
+        dt = time.perf_counter() - t0
+        one = pop.subset(np.arange(0, pop.n_variants, max(1, pop.n_variants // 64)))
+        T1 = max(1, T // 4)
+        o1 = O.Oracle(one, lib=lib)
+        t0 = time.perf_counter()
+        o1.rollout(T1, threads=1)
+        dt1 = time.perf_counter() - t0
+        rows.append({"workload": name, "variants": pop.n_variants, "steps": T, "seconds": dt,
+                     "variant_steps_per_s": pop.n_variants * T / dt, "threads": cores,
+                     "single_thread_variant_steps_per_s": one.n_variants * T1 / dt1,
+                     "single_thread_sample": f"{one.n_variants} variants x {T1} steps"})
+        print(f"{name}: {pop.n_variants} x {T} in {dt:.1f} s on {cores} threads", file=sys.stderr, flush=True)
+    print(json.dumps({"kind": "oracle", "unit": "variant-steps/s", "cpu_model": _cpu_model(),
+                      "host_threads_available": avail, "configs": rows}), flush=True)
+
+
 def main():
     args = parse()
+    if args.cpu_configs:
+        cpu_configs()
+        return
     if args.gpus != 1:
         print(f"bench.py: this build runs on one GPU only (asked for --gpus {args.gpus}); "
               "variants are independent, so more GPUs would each take a contiguous DoF-balanced share.",
@@ -166,7 +208,12 @@ def main():
         # pilots over the whole horizon: the first steps of a dropped population
         # (free fall, few contacts) rank the launch options differently
         options, trials = autotune(pop, T_pilot=T, log=lambda m: print(m, file=sys.stderr, flush=True))
-    sim = Simulator(pop, time_launches=True, **options)
+    # per-bin launch timing (HIP events around each bin's launches) cannot be
+    # recorded inside a captured graph: a graph-replayed run is timed as is and
+    # the per-kernel figures come from one more rollout of the same layout
+    # launched eagerly
+    graph = bool(options.get("use_graph"))
+    sim = Simulator(pop, time_launches=not graph, **options)
     stream = torch.cuda.current_stream()
     for _ in range(args.warmup):
         sim.rollout(T)
@@ -193,14 +240,19 @@ def main():
         dst.copy_(src)
         torch.cuda.synchronize()
         del src, dst
+    if graph:
+        sim_t = Simulator(pop, time_launches=True, **dict(options, use_graph=False))
+        sim_t.rollout(T)
+        torch.cuda.synchronize()
+        times, vb, bins = sim_t.launch_times(), sim_t.variant_bins(), sim_t.bins()
+        sim_t.close()
+    else:
+        times, vb, bins = sim.launch_times(), sim.variant_bins(), sim.bins()
     rows_contact, rows_clamp, status = sim.counters()
     fl_var = flops_per_variant(pop, T, rows_contact, rows_clamp)
     fl = fl_var.sum()
-    bins = sim.bins()
     # dominant kernel: the bin whose launches took longest in the last rollout
     # (HIP events around its launches on its own stream)
-    times = sim.launch_times()
-    vb = sim.variant_bins()
     dom = int(np.argmax([t[0] for t in times]))
     dom_ms, dom_launches = times[dom]
     per_launch_s = dom_ms / 1e3 / max(dom_launches, 1)

@@ -85,11 +85,13 @@ def autotune(pop, T_pilot=1000, reps=3, log=None, cache=None, min_gain=0.01, due
         return t
 
     def descend(best, best_t):
-        """Coordinate descent from a starting point: streams, launch length,
-        then the contact budget of each DoF capacity present."""
+        """Coordinate descent from a starting point: single launch, streams,
+        launch length, hipGraph replay of the rollout's launches, then the
+        contact budget of each DoF capacity present."""
         special = getattr(pop, "ball", None) is not None or bool(getattr(pop, "self_collision", False))
         single = [] if special else [True]   # the multi-bin kernel has no ball or self-collision families
-        for name, values in (("single_launch", single), ("streams", [4, 2, 1]), ("steps_per_launch", [250, 500])):
+        for name, values in (("single_launch", single), ("streams", [4, 2, 1]), ("steps_per_launch", [250, 500]),
+                             ("use_graph", [True])):
             for v in values:
                 cand = dict(best, **{name: v})
                 if cand.get("single_launch") and name == "streams":

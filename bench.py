@@ -244,12 +244,13 @@ def main():
         sim_t = Simulator(pop, time_launches=True, **dict(options, use_graph=False))
         sim_t.rollout(T)
         torch.cuda.synchronize()
-        times, vb, bins = sim_t.launch_times(), sim_t.variant_bins(), sim_t.bins()
+        times, vb, bins, facs = sim_t.launch_times(), sim_t.variant_bins(), sim_t.bins(), sim_t.bin_factorization()
         sim_t.close()
     else:
-        times, vb, bins = sim.launch_times(), sim.variant_bins(), sim.bins()
+        times, vb, bins, facs = sim.launch_times(), sim.variant_bins(), sim.bins(), sim.bin_factorization()
     rows_contact, rows_clamp, status = sim.counters()
-    fl_var = flops_per_variant(pop, T, rows_contact, rows_clamp)
+    fl_var = flops_per_variant(pop, T, rows_contact, rows_clamp,
+                               factorization=np.array([facs[b] for b in vb]))
     fl = fl_var.sum()
     # dominant kernel: the bin whose launches took longest in the last rollout
     # (HIP events around its launches on its own stream)
@@ -263,7 +264,8 @@ def main():
     nvc, nbody, ncr, nvar = bins[dom]
     ball = "true" if getattr(pop, "ball", None) is not None else "false"
     selfc = "true" if getattr(pop, "self_collision", False) else "false"
-    kernel_name = f"rollout_kernel<{nvc}, {nbody // 16}, {ncr}, {ball}, {selfc}>"
+    tree = "true" if facs[dom] == "tree" else "false"
+    kernel_name = f"rollout_kernel<{nvc}, {nbody // 16}, {ncr}, {ball}, {selfc}, {tree}>"
     if options.get("single_launch"):
         # one kernel runs every bin: its launches carry the whole rollout
         kernel_name = "rollout_multi_kernel"

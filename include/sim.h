@@ -164,14 +164,25 @@ typedef struct {
  *                         Cholesky, SIM_FACTOR_TREE (1) the tree-sparse L^T L
  *                         factorisation over the DoF tree (Featherstone's
  *                         branch-induced sparsity: every step touches only
- *                         a DoF's ancestors); the two agree to rounding.  The
- *                         GPU kernels always form the dense inverse.
+ *                         a DoF's ancestors); the two agree to rounding.
+ *                         The GPU kernels form the dense inverse unless
+ *                         gpu_factorization says otherwise.
  *  min_nv_capacity        0 or a DoF capacity (8, 12, ..., 28): variants with
  *                         fewer DoFs go to bins of this capacity (fewer bins)
  *  slots32_min_nvc        with min_body_slots = 32: only bins of this DoF
  *                         capacity and above use 32-body kernels (0 = all);
  *                         smaller capacities keep the smallest body capacity
  *                         that holds each variant
+ *  gpu_factorization      SIM_FACTOR_DENSE (0): every kernel inverts M~ by a
+ *                         dense symmetric Gauss-Jordan sweep in registers;
+ *                         SIM_FACTOR_TREE (1): bins whose shape has a
+ *                         tree-sparse kernel (plane-only, nv capacity 24, 32
+ *                         bodies, 8 contacts in registers) factor M~ = L^T L
+ *                         over the DoF tree in LDS and form M~^-1 by two
+ *                         triangular solves per DoF; other bins, and every
+ *                         bin under single_launch, keep the sweep
+ *                         (sim_bin_factorization tells which).  The two agree
+ *                         to rounding.
  */
 typedef struct {
   int32_t contacts_in_registers;
@@ -185,6 +196,7 @@ typedef struct {
   int32_t host_factorization;
   int32_t min_nv_capacity;
   int32_t slots32_min_nvc;
+  int32_t gpu_factorization;
 } sim_options;
 
 #define SIM_FACTOR_DENSE 0
@@ -271,6 +283,12 @@ int sim_bins(const sim_handle* h, int32_t* n_bins, int32_t* info, int32_t max_bi
 /* Bin of every variant (user order), an index into the sim_bins order.
  * bin: [n_variants] ints.  Host only. */
 int sim_variant_bins(const sim_handle* h, int32_t* bin);
+
+/* Factorisation of M~ in each bin's kernel (sim_bins order):
+ * SIM_FACTOR_DENSE or SIM_FACTOR_TREE (see sim_options.gpu_factorization).
+ * factorization has max_bins ints; *n_bins receives the bin count.  Host
+ * only. */
+int sim_bin_factorization(const sim_handle* h, int32_t* n_bins, int32_t* factorization, int32_t max_bins);
 
 /* With time_launches set: per bin (in sim_bins order), the milliseconds
  * between the start of its first and the end of its last launch in the most

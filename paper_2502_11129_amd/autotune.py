@@ -1,9 +1,11 @@
 """Autotuner of the launch and packing options (sim_options).
 
-The GPU options never change results (same arithmetic in every layout); they
-change how the population is cut into DoF bins and launched: contacts kept in
-registers per DoF capacity, body capacity (merging bins), steps per launch
-and the number of concurrent streams.  The tuner times short pilot rollouts
+The layout options never change results (same arithmetic in every layout);
+they change how the population is cut into DoF bins and launched: contacts
+kept in registers per DoF capacity, body capacity (merging bins), steps per
+launch and the number of concurrent streams.  One option changes rounding
+only: the kernels' factorisation of M~ (dense sweep or tree-sparse L^T L,
+where a tree-sparse kernel of the bin's shape is compiled).  The tuner times short pilot rollouts
 of the actual population (HIP events on the stream) and keeps the fastest
 setting of one option at a time (coordinate descent, fixed order), so the
 search costs a few dozen pilots.
@@ -86,8 +88,9 @@ def autotune(pop, T_pilot=1000, reps=3, log=None, cache=None, min_gain=0.01, due
 
     def descend(best, best_t):
         """Coordinate descent from a starting point: single launch, streams,
-        launch length, hipGraph replay of the rollout's launches, then the
-        contact budget of each DoF capacity present."""
+        launch length, hipGraph replay of the rollout's launches, the
+        contact budget of each DoF capacity present, then the tree-sparse
+        factorisation."""
         special = getattr(pop, "ball", None) is not None or bool(getattr(pop, "self_collision", False))
         single = [] if special else [True]   # the multi-bin kernel has no ball or self-collision families
         for name, values in (("single_launch", single), ("streams", [4, 2, 1]), ("steps_per_launch", [250, 500]),
@@ -117,6 +120,15 @@ def autotune(pop, T_pilot=1000, reps=3, log=None, cache=None, min_gain=0.01, due
                     continue                      # no kernel with that budget for this body capacity
                 if t < best_t * (1.0 - min_gain):
                     best, best_t = cand, t
+        # the tree-sparse factorisation, if some bin of this layout has it
+        cand = dict(best, gpu_factorization="tree")
+        probe = S.Handle(pop, **cand)
+        has_tree = "tree" in probe.bin_factorization()
+        probe.close()
+        if has_tree:
+            t = run(cand)
+            if t < best_t * (1.0 - min_gain):
+                best, best_t = cand, t
         return best, best_t
 
     # starting points: smallest body capacity per variant (more bins, some

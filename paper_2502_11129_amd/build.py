@@ -28,41 +28,44 @@ COMMON = ["-O3", "-std=c++17", "-fPIC", "-Wno-unused-result"]
 DEVICE = [f"--offload-arch={ARCH}", "-ffp-contract=on", "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops"]
 
 
-def _sources():
-    kern = sorted(glob.glob(os.path.join(CSRC, "kernels", "*.hip")))
-    host = [os.path.join(CSRC, n) for n in ("kernel_registry.cpp", "sim_host.cpp", "host_worker.cpp", "sur_host.cpp",
+def _sources(csrc: str = CSRC):
+    kern = sorted(glob.glob(os.path.join(csrc, "kernels", "*.hip")))
+    host = [os.path.join(csrc, n) for n in ("kernel_registry.cpp", "sim_host.cpp", "host_worker.cpp", "sur_host.cpp",
                                          "ea_host.cpp")]
     return kern, host
 
 
-def _compile(src: str, device: bool) -> str:
-    obj = os.path.join(BUILD, os.path.basename(src) + ".o")
-    cmd = [HIPCC, *COMMON, *(DEVICE if device else []), "-I", CSRC, "-c", src, "-o", obj]
+def _compile(src: str, device: bool, csrc: str = CSRC, objdir: str = BUILD) -> str:
+    obj = os.path.join(objdir, os.path.basename(src) + ".o")
+    cmd = [HIPCC, *COMMON, *(DEVICE if device else []), "-I", csrc, "-c", src, "-o", obj]
     if not device:
-        cmd = [HIPCC, *COMMON, "-I", CSRC, "-I", API_INC, "-I", ROCM_INC, "-x", "c++", "-D__HIP_PLATFORM_AMD__", "-c", src, "-o", obj]
+        cmd = [HIPCC, *COMMON, "-I", csrc, "-I", API_INC, "-I", ROCM_INC, "-x", "c++", "-D__HIP_PLATFORM_AMD__", "-c", src, "-o", obj]
     r = subprocess.run(cmd, capture_output=True, text=True)
     if r.returncode != 0:
         raise RuntimeError(f"compile failed: {' '.join(cmd)}\n{r.stdout}\n{r.stderr}")
     return obj
 
 
-def build(jobs: int | None = None, verbose: bool = False) -> str:
-    """Compile every HIP source for gfx950 and link libsim.so (always rebuilds)."""
-    os.makedirs(BUILD, exist_ok=True)
-    kern, host = _sources()
+def build(jobs: int | None = None, verbose: bool = False, csrc: str = CSRC, lib: str = LIB, objdir: str = BUILD) -> str:
+    """Compile every HIP source for gfx950 and link libsim.so (always rebuilds).
+    csrc / lib / objdir: another source tree, library path and object folder
+    (the per-phase profiling build uses an instrumented copy)."""
+    os.makedirs(objdir, exist_ok=True)
+    kern, host = _sources(csrc)
     jobs = jobs or min(8, os.cpu_count() or 4)
     with cf.ThreadPoolExecutor(jobs) as ex:
-        futs = [ex.submit(_compile, s, True) for s in kern] + [ex.submit(_compile, s, False) for s in host]
+        futs = [ex.submit(_compile, s, True, csrc, objdir) for s in kern] + \
+            [ex.submit(_compile, s, False, csrc, objdir) for s in host]
         objs = [f.result() for f in futs]
-    tmp = LIB + ".tmp"
+    tmp = lib + ".tmp"
     cmd = [HIPCC, f"--offload-arch={ARCH}", "-shared", "-fPIC", *objs, "-o", tmp]
     r = subprocess.run(cmd, capture_output=True, text=True)
     if r.returncode != 0:
         raise RuntimeError(f"link failed: {' '.join(cmd)}\n{r.stdout}\n{r.stderr}")
-    os.replace(tmp, LIB)
+    os.replace(tmp, lib)
     if verbose:
-        print("built", LIB)
-    return LIB
+        print("built", lib)
+    return lib
 
 
 if __name__ == "__main__":

@@ -19,6 +19,10 @@ struct KernelVariant {
 
 extern const KernelVariant kKernelVariants[];
 extern const int kNumKernelVariants;
+// Plane-only kernels with the tree-sparse factorisation of M~ (same shapes as
+// entries of kKernelVariants; chosen by sim_options.gpu_factorization).
+extern const KernelVariant kTreeKernelVariants[];
+extern const int kNumTreeKernelVariants;
 
 // The multi-bin kernel: its family list (nvc, sb, ncr per kind index) and launcher.
 struct MultiFamily { int nvc, sb, ncr; };

@@ -243,7 +243,7 @@ __device__ __forceinline__ sv imul(const sinertia& J, const sv& V) {
 // ----------------------------------------------------------------------------
 // Per-variant LDS area.
 // ----------------------------------------------------------------------------
-template <int NVC, int SB, int NCR, bool BALL = false, bool SELF = false>
+template <int NVC, int SB, int NCR, bool BALL = false, bool SELF = false, bool TREE = false>
 struct alignas(16) GroupLds {
   static constexpr int NBC = 16 * SB;
   static constexpr int MST = NVC + 1;                 // padded row stride of the matrices
@@ -267,6 +267,12 @@ struct alignas(16) GroupLds {
   // built per launch; the step's bounding-sphere candidates among them
   uint16_t spair[SELF ? NBC * (NBC - 1) / 2 : 1];
   uint16_t scand[SELF ? NBC * (NBC - 1) / 2 : 1];
+  // tree-sparse factorisation: the negated inverse (rows of M~^-1 in natural
+  // column order), each DoF's path mask (itself and its ancestors) and the
+  // reciprocal diagonal of the factor
+  float X[TREE ? NVC * MST : 1];
+  unsigned pm[TREE ? NVC : 1];
+  float dinv[TREE ? NVC : 1];
 };
 
 // ----------------------------------------------------------------------------
@@ -669,15 +675,16 @@ struct WavesPerSimd {
 
 // One workgroup (one wave, four variants) of a bin: `block` is the
 // workgroup's index within the bin, lds_all the four variants' LDS areas.
-template <int NVC, int SB, int NCR, bool BALL = false, bool SELF = false>
+template <int NVC, int SB, int NCR, bool BALL = false, bool SELF = false, bool TREE = false>
 __device__ __forceinline__ void rollout_body(const BinArgs& a, const ModelParams& P, int block,
-                                             GroupLds<NVC, SB, NCR, BALL, SELF>* lds_all) {
+                                             GroupLds<NVC, SB, NCR, BALL, SELF, TREE>* lds_all) {
   constexpr int S = (NVC + 15) / 16;
   constexpr int NBC = 16 * SB;
   constexpr int MAXC = max_contacts(NBC, BALL, SELF);
   constexpr bool GEN = BALL || SELF;  // general contact entries and rows
   constexpr int CLW = GEN ? kListWordsBall : kListWords;
-  using L = GroupLds<NVC, SB, NCR, BALL, SELF>;
+  using L = GroupLds<NVC, SB, NCR, BALL, SELF, TREE>;
+  static_assert(!TREE || (NVC >= 8 && NVC <= 32), "path masks are 32-bit; the first six DoFs are held apart");
   constexpr int MST = L::MST;
 
   const int lane = threadIdx.x & 15;
@@ -757,6 +764,22 @@ __device__ __forceinline__ void rollout_body(const BinArgs& a, const ModelParams
     }
   }
   for (int j = lane; j < 2 * NBC + 4; j += 16) sh.lv[j] = lvl[j];
+  if constexpr (TREE) {
+    // path mask of every DoF (the DoF and its ancestors in the DoF tree): the
+    // free root's six DoFs form a chain, a hinge sits under its parent body's
+    // hinge and under the whole root, the ball's DoFs and the padding stand
+    // alone.  Ancestors carry lower indices (parents precede children).
+#pragma unroll
+    for (int t = 0; t < SB; ++t) {
+      const int b = lane + 16 * t;
+      if (b >= 1 && b < nb && r0 + b - 1 < NVC)
+        sh.pm[r0 + b - 1] = (r0 == 6 ? 0x3Fu : 0u) | (((ancS[t] & ~1u) >> 1) << r0);
+    }
+    for (int d = lane; d < NVC; d += 16) {
+      if (r0 == 6 && d < 6) sh.pm[d] = (2u << d) - 1u;
+      else if (d >= nvr) sh.pm[d] = 1u << d;
+    }
+  }
   int npairs = 0;  // row-uniform
   if (SELF) {
 #pragma unroll
@@ -1208,106 +1231,331 @@ __device__ __forceinline__ void rollout_body(const BinArgs& a, const ModelParams
       cS[s] = (d < nv) ? sh.cvec[d] : 0.f;
     }
 
-    // =====================================================================
-    // 3. inverse by a symmetric Gauss-Jordan sweep over the nv real pivots,
-    //    rows in registers, columns rotating by one per pivot (register
-    //    column j of step k holds original column (k + j) mod NVC).  The
-    //    pivot column is broadcast through a doubled LDS buffer.  Pivot row
-    //    k uses the symmetric column values: a_kj - (1 - 1/d) a_jk.
-    //    Result: -M~^-1 with register column j <-> column (nv + j) mod NVC.
-    //    Software-pipelined: the first updated column of step k is column 0
-    //    of step k + 1, so it is broadcast (and read back into the other
-    //    register set) before the rest of step k's updates, which hide the
-    //    LDS round trip; the arithmetic is that of the plain sweep.
-    // =====================================================================
-    {
-      float ckA[NVC], ckB[NVC];  // pivot column of the current / next step
-      // Store positions of the lane's rows in a broadcast buffer: row d at d
-      // and d + NVC; a slot past the last DoF writes both copies into the
-      // sink at 2 NVC + (d - NVC) < 2 NVC + 16, so the stores need no branch
-      // (a branch there splits the step and lets the compiler sink its
-      // updates below the next step's reads).
-      int cb_lo[S], cb_hi[S];
+    if constexpr (TREE) {
+      // ===================================================================
+      // 3. (tree-sparse alternative) M~ = L^T L with L lower triangular and
+      //    row i of L nonzero only on i's path (i and its ancestors), so
+      //    factoring from the last DoF to the first creates no fill-in
+      //    (Featherstone's branch-induced sparsity).  The factor overwrites
+      //    the lower triangle of the assembled matrix; each pivot's ancestor
+      //    rows are updated by their owner lanes along their own paths.  Then
+      //    every lane forms the column of M~^-1 of its own DoF c by two
+      //    triangular solves in its own row of X: L^T y = e_c (y lives on
+      //    c's path) and L x = y (x is row c too, M~^-1 being symmetric).
+      // ===================================================================
+      // The first six DoFs (the free root's chain, on every path) are held in
+      // registers or read in one batch; the hinge ancestors of a DoF are
+      // taken up to four at a time (one LDS round trip), any deeper rest one
+      // by one.
+      constexpr int R6 = 6;
+      constexpr unsigned kRootBits = (1u << R6) - 1u;
+      constexpr int HB = 4;
+      unsigned pmS[S];
 #pragma unroll
       for (int s = 0; s < S; ++s) {
         const int d = lane + 16 * s;
-        cb_lo[s] = d < NVC ? d : NVC + d;
-        cb_hi[s] = d < NVC ? d + NVC : NVC + d;
+        pmS[s] = d < nv ? sh.pm[d] : 0u;
       }
+      // first HB set bits of m (removed from m), with their validity
+      auto take = [](unsigned& m, int (&jj)[HB], bool (&ok)[HB]) {
 #pragma unroll
-      for (int s = 0; s < S; ++s) { sh.cb[0][cb_lo[s]] = Mi[s][0]; sh.cb[0][cb_hi[s]] = Mi[s][0]; }
-      wave_sync();
-#pragma unroll
-      for (int j = 0; j < NVC; ++j) ckA[j] = sh.cb[0][j];
-      auto pivot_step = [&](int k, const float (&ck)[NVC], float (&nck)[NVC]) {
-        const float pinv = recip(ck[0]);
-        float f[S];
-        bool piv[S];
+        for (int p = 0; p < HB; ++p) {
+          ok[p] = m != 0u;
+          jj[p] = ok[p] ? __builtin_ctz(m) : 0;
+          m &= m - 1u;
+        }
+      };
+#pragma unroll 1
+      for (int k = nv - 1; k >= 0; --k) {
+        const unsigned ak = sh.pm[k] & ~(1u << k);  // ancestors of k
+        const float lkk = sqrtf(sh.A[k * MST + k]);
+        const float r = recip(lkk);
+        float lk[S];
+        bool in[S];
 #pragma unroll
         for (int s = 0; s < S; ++s) {
-          piv[s] = (lane + 16 * s) == k;
-          f[s] = piv[s] ? 1.f - pinv : Mi[s][0] * pinv;
+          const int d = lane + 16 * s;
+          in[s] = (ak >> d) & 1u;
+          lk[s] = in[s] ? sh.A[k * MST + d] * r : 0.f;  // L[k][d]
+          if (in[s]) sh.A[k * MST + d] = lk[s];
+          if (d == k) {
+            sh.A[k * MST + k] = lkk;
+            sh.dinv[k] = r;
+          }
         }
-#pragma unroll
-        for (int s = 0; s < S; ++s) Mi[s][0] = fmaf(-f[s], ck[1], Mi[s][1]);
-        float* cbn = sh.cb[(k + 1) & 1];
-#pragma unroll
-        for (int s = 0; s < S; ++s) { cbn[cb_lo[s]] = Mi[s][0]; cbn[cb_hi[s]] = Mi[s][0]; }
         wave_sync();
+        // rows d of k's ancestors: A[d][j] -= L[k][d] L[k][j] along d's path
+        const float* rk = &sh.A[k * MST];
 #pragma unroll
-        for (int j = 0; j < NVC; ++j) nck[j] = cbn[k + 1 + j];  // k + 1 <= NVC: inside the doubled buffer
-        // keep the scheduler from hoisting the next step's chain above this
-        // step's updates (which would leave the reads' latency exposed)
-        __builtin_amdgcn_sched_barrier(0);
+        for (int s = 0; s < S; ++s) {
+          if (in[s]) {
+            const int d = lane + 16 * s;
+            float* rd = &sh.A[d * MST];
+            float a0[R6], b0[R6], ah[HB], bh[HB];
+            int jj[HB];
+            bool ok[HB];
+            unsigned mh = pmS[s] & ~kRootBits;
+            take(mh, jj, ok);
 #pragma unroll
-        for (int j = 2; j < NVC; ++j) {
+            for (int j = 0; j < R6; ++j) { a0[j] = rk[j]; b0[j] = rd[j]; }
 #pragma unroll
-          for (int s = 0; s < S; ++s) Mi[s][j - 1] = fmaf(-f[s], ck[j], Mi[s][j]);
+            for (int p = 0; p < HB; ++p) { ah[p] = rk[jj[p]]; bh[p] = rd[jj[p]]; }
+#pragma unroll
+            for (int j = 0; j < R6; ++j)
+              if ((pmS[s] >> j) & 1u) rd[j] = fmaf(-lk[s], a0[j], b0[j]);
+#pragma unroll
+            for (int p = 0; p < HB; ++p)
+              if (ok[p]) rd[jj[p]] = fmaf(-lk[s], ah[p], bh[p]);
+            while (mh) {
+              const int j = __builtin_ctz(mh);
+              mh &= mh - 1u;
+              rd[j] = fmaf(-lk[s], rk[j], rd[j]);
+            }
+          }
+        }
+        wave_sync();
+      }
+#pragma unroll
+      for (int s = 0; s < S; ++s) {
+        const int d = lane + 16 * s;
+        if (d < NVC) {
+#pragma unroll
+          for (int j = 0; j < NVC; ++j) sh.X[d * MST + j] = (j == d && d < nv) ? 1.f : 0.f;
+        }
+      }
+      // the factor's first six rows and reciprocal diagonal (uniform per variant)
+      float L6[R6][R6], di6[R6];
+      unsigned pm6[R6];
+#pragma unroll
+      for (int i = 0; i < R6; ++i) {
+        di6[i] = sh.dinv[i < nv ? i : 0];
+        pm6[i] = i < nv ? sh.pm[i] : 0u;
+#pragma unroll
+        for (int j = 0; j < i; ++j) L6[i][j] = sh.A[i * MST + j];
+      }
+      // L^T y = e_c, c the lane's DoF: y lives on c's path; its hinge part
+      // from c upwards with the root entries of the right-hand side kept in
+      // registers, then the six root entries
+      float y6[S][R6];
+#pragma unroll
+      for (int s = 0; s < S; ++s) {
+        const int d = lane + 16 * s;
+        float br[R6];
+#pragma unroll
+        for (int j = 0; j < R6; ++j) br[j] = (j == d) ? 1.f : 0.f;
+        if (d < nv) {
+          float* xr = &sh.X[d * MST];
+          const unsigned mr = pmS[s] & kRootBits;
+          unsigned mh = pmS[s] & ~kRootBits;
+          while (mh) {
+            const int i = 31 - __builtin_clz(mh);
+            mh &= ~(1u << i);
+            const float yi = xr[i] * sh.dinv[i];
+            xr[i] = yi;
+            const float* li = &sh.A[i * MST];
+#pragma unroll
+            for (int j = 0; j < R6; ++j)
+              if ((mr >> j) & 1u) br[j] = fmaf(-li[j], yi, br[j]);
+            unsigned an = mh;  // the rest of the path: i's hinge ancestors
+            float lh[HB], xh[HB];
+            int jj[HB];
+            bool ok[HB];
+            take(an, jj, ok);
+#pragma unroll
+            for (int p = 0; p < HB; ++p) { lh[p] = li[jj[p]]; xh[p] = xr[jj[p]]; }
+#pragma unroll
+            for (int p = 0; p < HB; ++p)
+              if (ok[p]) xr[jj[p]] = fmaf(-lh[p], yi, xh[p]);
+            while (an) {
+              const int j = __builtin_ctz(an);
+              an &= an - 1u;
+              xr[j] = fmaf(-li[j], yi, xr[j]);
+            }
+          }
         }
 #pragma unroll
-        for (int s = 0; s < S; ++s) Mi[s][NVC - 1] = piv[s] ? -pinv : f[s];
-        __builtin_amdgcn_sched_barrier(0);
-      };
-      // whole pairs of steps (no branch between a step's reads and their use,
-      // so the compiler keeps them ahead of the step's updates), then an odd
-      // last step
-      int k = 0;
+        for (int i = R6 - 1; i >= 0; --i) {
+          const bool on = d < nv && ((pmS[s] >> i) & 1u);
+          y6[s][i] = on ? br[i] * di6[i] : 0.f;
+#pragma unroll
+          for (int j = 0; j < i; ++j) br[j] = fmaf(-L6[i][j], y6[s][i], br[j]);
+        }
+      }
+      // L x = y over the DoFs in order: the root entries of x in registers,
+      // then each hinge DoF along its ancestors
+      int dr[S];
+#pragma unroll
+      for (int s = 0; s < S; ++s) dr[s] = (lane + 16 * s) < NVC ? lane + 16 * s : 0;
+      float x6[S][R6];
+#pragma unroll
+      for (int i = 0; i < R6; ++i) {
+#pragma unroll
+        for (int s = 0; s < S; ++s) {
+          float acc = y6[s][i];
+#pragma unroll
+          for (int j = 0; j < i; ++j)
+            if ((pm6[i] >> j) & 1u) acc = fmaf(-L6[i][j], x6[s][j], acc);
+          x6[s][i] = i < nv ? acc * di6[i] : 0.f;
+          if (lane + 16 * s < NVC) sh.X[dr[s] * MST + i] = x6[s][i];
+        }
+      }
 #pragma unroll 1
-      for (; k + 1 < nv; k += 2) {
-        pivot_step(k, ckA, ckB);
-        pivot_step(k + 1, ckB, ckA);
+      for (int i = R6; i < nv; ++i) {
+        const float* li = &sh.A[i * MST];
+        const float di = sh.dinv[i];
+        const unsigned pi = sh.pm[i];
+        float l0[R6];
+#pragma unroll
+        for (int j = 0; j < R6; ++j) l0[j] = li[j];
+        unsigned an = pi & ~kRootBits & ~(1u << i);
+        float lh[HB], xh[S][HB];
+        int jj[HB];
+        bool ok[HB];
+        take(an, jj, ok);
+        float acc[S];
+#pragma unroll
+        for (int s = 0; s < S; ++s) {
+          acc[s] = sh.X[dr[s] * MST + i];
+#pragma unroll
+          for (int p = 0; p < HB; ++p) xh[s][p] = sh.X[dr[s] * MST + jj[p]];
+        }
+#pragma unroll
+        for (int p = 0; p < HB; ++p) lh[p] = ok[p] ? li[jj[p]] : 0.f;
+#pragma unroll
+        for (int s = 0; s < S; ++s) {
+#pragma unroll
+          for (int j = 0; j < R6; ++j)
+            if ((pi >> j) & 1u) acc[s] = fmaf(-l0[j], x6[s][j], acc[s]);
+#pragma unroll
+          for (int p = 0; p < HB; ++p) acc[s] = fmaf(-lh[p], xh[s][p], acc[s]);
+        }
+        while (an) {
+          const int j = __builtin_ctz(an);
+          an &= an - 1u;
+          const float l = li[j];
+#pragma unroll
+          for (int s = 0; s < S; ++s) acc[s] = fmaf(-l, sh.X[dr[s] * MST + j], acc[s]);
+        }
+#pragma unroll
+        for (int s = 0; s < S; ++s)
+          if (lane + 16 * s < NVC) sh.X[dr[s] * MST + i] = acc[s] * di;
       }
-      if (k < nv) pivot_step(k, ckA, ckB);
-    }
-    // the assembled matrix is dead: keep the (negated, rotated) inverse in LDS
-    // for the clamp rows, which need single columns chosen at run time, and
-    // reload the registers in natural column order for the mat-vecs
-    wave_sync();
+      // registers and X hold the inverse negated, natural column order
 #pragma unroll
-    for (int s = 0; s < S; ++s) {
-      const int d = lane + 16 * s;
-      if (d < NVC) {
+      for (int s = 0; s < S; ++s) {
+        const int d = lane + 16 * s;
 #pragma unroll
-        for (int j = 0; j < NVC; ++j) sh.A[d * MST + j] = Mi[s][j];
+        for (int j = 0; j < NVC; ++j) {
+          Mi[s][j] = d < NVC ? -sh.X[dr[s] * MST + j] : 0.f;
+          if (d < NVC) sh.X[d * MST + j] = Mi[s][j];
+        }
+      }
+    } else {
+      // =====================================================================
+      // 3. inverse by a symmetric Gauss-Jordan sweep over the nv real pivots,
+      //    rows in registers, columns rotating by one per pivot (register
+      //    column j of step k holds original column (k + j) mod NVC).  The
+      //    pivot column is broadcast through a doubled LDS buffer.  Pivot row
+      //    k uses the symmetric column values: a_kj - (1 - 1/d) a_jk.
+      //    Result: -M~^-1 with register column j <-> column (nv + j) mod NVC.
+      //    Software-pipelined: the first updated column of step k is column 0
+      //    of step k + 1, so it is broadcast (and read back into the other
+      //    register set) before the rest of step k's updates, which hide the
+      //    LDS round trip; the arithmetic is that of the plain sweep.
+      // =====================================================================
+      {
+        float ckA[NVC], ckB[NVC];  // pivot column of the current / next step
+        // Store positions of the lane's rows in a broadcast buffer: row d at d
+        // and d + NVC; a slot past the last DoF writes both copies into the
+        // sink at 2 NVC + (d - NVC) < 2 NVC + 16, so the stores need no branch
+        // (a branch there splits the step and lets the compiler sink its
+        // updates below the next step's reads).
+        int cb_lo[S], cb_hi[S];
+  #pragma unroll
+        for (int s = 0; s < S; ++s) {
+          const int d = lane + 16 * s;
+          cb_lo[s] = d < NVC ? d : NVC + d;
+          cb_hi[s] = d < NVC ? d + NVC : NVC + d;
+        }
+  #pragma unroll
+        for (int s = 0; s < S; ++s) { sh.cb[0][cb_lo[s]] = Mi[s][0]; sh.cb[0][cb_hi[s]] = Mi[s][0]; }
+        wave_sync();
+  #pragma unroll
+        for (int j = 0; j < NVC; ++j) ckA[j] = sh.cb[0][j];
+        auto pivot_step = [&](int k, const float (&ck)[NVC], float (&nck)[NVC]) {
+          const float pinv = recip(ck[0]);
+          float f[S];
+          bool piv[S];
+  #pragma unroll
+          for (int s = 0; s < S; ++s) {
+            piv[s] = (lane + 16 * s) == k;
+            f[s] = piv[s] ? 1.f - pinv : Mi[s][0] * pinv;
+          }
+  #pragma unroll
+          for (int s = 0; s < S; ++s) Mi[s][0] = fmaf(-f[s], ck[1], Mi[s][1]);
+          float* cbn = sh.cb[(k + 1) & 1];
+  #pragma unroll
+          for (int s = 0; s < S; ++s) { cbn[cb_lo[s]] = Mi[s][0]; cbn[cb_hi[s]] = Mi[s][0]; }
+          wave_sync();
+  #pragma unroll
+          for (int j = 0; j < NVC; ++j) nck[j] = cbn[k + 1 + j];  // k + 1 <= NVC: inside the doubled buffer
+          // keep the scheduler from hoisting the next step's chain above this
+          // step's updates (which would leave the reads' latency exposed)
+          __builtin_amdgcn_sched_barrier(0);
+  #pragma unroll
+          for (int j = 2; j < NVC; ++j) {
+  #pragma unroll
+            for (int s = 0; s < S; ++s) Mi[s][j - 1] = fmaf(-f[s], ck[j], Mi[s][j]);
+          }
+  #pragma unroll
+          for (int s = 0; s < S; ++s) Mi[s][NVC - 1] = piv[s] ? -pinv : f[s];
+          __builtin_amdgcn_sched_barrier(0);
+        };
+        // whole pairs of steps (no branch between a step's reads and their use,
+        // so the compiler keeps them ahead of the step's updates), then an odd
+        // last step
+        int k = 0;
+  #pragma unroll 1
+        for (; k + 1 < nv; k += 2) {
+          pivot_step(k, ckA, ckB);
+          pivot_step(k + 1, ckB, ckA);
+        }
+        if (k < nv) pivot_step(k, ckA, ckB);
+      }
+      // the assembled matrix is dead: keep the (negated, rotated) inverse in LDS
+      // for the clamp rows, which need single columns chosen at run time, and
+      // reload the registers in natural column order for the mat-vecs
+      wave_sync();
+  #pragma unroll
+      for (int s = 0; s < S; ++s) {
+        const int d = lane + 16 * s;
+        if (d < NVC) {
+  #pragma unroll
+          for (int j = 0; j < NVC; ++j) sh.A[d * MST + j] = Mi[s][j];
+        }
+      }
+      wave_sync();
+  #pragma unroll
+      for (int s = 0; s < S; ++s) {
+        const int dr = (lane + 16 * s) < NVC ? lane + 16 * s : 0;
+  #pragma unroll
+        for (int c = 0; c < NVC; ++c) {
+          const int j = c - nv + (c < nv ? NVC : 0);  // register column of original column c
+          Mi[s][c] = sh.A[dr * MST + j];
+        }
       }
     }
-    wave_sync();
-#pragma unroll
-    for (int s = 0; s < S; ++s) {
-      const int dr = (lane + 16 * s) < NVC ? lane + 16 * s : 0;
-#pragma unroll
-      for (int c = 0; c < NVC; ++c) {
-        const int j = c - nv + (c < nv ? NVC : 0);  // register column of original column c
-        Mi[s][c] = sh.A[dr * MST + j];
-      }
-    }
+    // the negated inverse in LDS: rotated columns after the sweep, natural
+    // after the tree-sparse solves
+    const float* const Ainv = TREE ? &sh.X[0] : &sh.A[0];
     float Dd[S];  // own diagonal of M~^-1
 #pragma unroll
     for (int s = 0; s < S; ++s) {
       const int d = lane + 16 * s;
       int cidx = d - nv;
       cidx += (cidx < 0) ? NVC : 0;
-      Dd[s] = (d < nv) ? -sh.A[d * MST + cidx] : 0.f;
+      if (TREE) cidx = d < NVC ? d : 0;
+      Dd[s] = (d < nv) ? -Ainv[d * MST + cidx] : 0.f;
     }
 
     // =====================================================================
@@ -1473,11 +1721,12 @@ __device__ __forceinline__ void rollout_body(const BinArgs& a, const ModelParams
           dl = row_sum(dl);
           int cj = j - nv;
           cj += (cj < 0) ? NVC : 0;
+          if (TREE) cj = j;
           const float e = dt * dl;  // v+ -= dt M~^-1 e_j dl, inverse held negated
 #pragma unroll
           for (int s = 0; s < S; ++s) {
             const int d = lane + 16 * s;
-            const float mcol = sh.A[(d < NVC ? d : NVC - 1) * MST + cj];  // unmasked read
+            const float mcol = Ainv[(d < NVC ? d : NVC - 1) * MST + cj];  // unmasked read
             vp[s] = fmaf(d < NVC ? mcol : 0.f, e, vp[s]);
           }
           last = j;
@@ -1617,11 +1866,11 @@ __device__ __forceinline__ void rollout_body(const BinArgs& a, const ModelParams
   }
 }
 
-template <int NVC, int SB, int NCR, bool BALL = false, bool SELF = false>
+template <int NVC, int SB, int NCR, bool BALL = false, bool SELF = false, bool TREE = false>
 __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(WavesPerSimd<NVC, SB, NCR>::value)))
 void rollout_kernel(BinArgs a, ModelParams P) {
-  __shared__ GroupLds<NVC, SB, NCR, BALL, SELF> lds_all[kVarPerWave];
-  rollout_body<NVC, SB, NCR, BALL, SELF>(a, P, blockIdx.x, lds_all);
+  __shared__ GroupLds<NVC, SB, NCR, BALL, SELF, TREE> lds_all[kVarPerWave];
+  rollout_body<NVC, SB, NCR, BALL, SELF, TREE>(a, P, blockIdx.x, lds_all);
 }
 
 }  // namespace simk

@@ -31,6 +31,7 @@ std::string g_create_error;
 
 struct Bin {
   int nvc = 0, sb = 0, ncr = 0;
+  int tree = 0;  // 1: the kernel factors M~ tree-sparsely
   launch_fn fn = nullptr;
   std::vector<int> users;  // user index of each packed variant
   // packed host copies (uploaded by sim_bind)
@@ -294,6 +295,8 @@ int sim_create(const sim_model_desc* d, const sim_options* opts, sim_handle** ou
     if (o.time_launches && o.use_graph) return bad("time_launches and use_graph cannot be combined");
     if (o.host_factorization != SIM_FACTOR_DENSE && o.host_factorization != SIM_FACTOR_TREE)
       return bad("host_factorization must be SIM_FACTOR_DENSE or SIM_FACTOR_TREE");
+    if (o.gpu_factorization != SIM_FACTOR_DENSE && o.gpu_factorization != SIM_FACTOR_TREE)
+      return bad("gpu_factorization must be SIM_FACTOR_DENSE or SIM_FACTOR_TREE");
     auto cap_or_zero = [](int v) { return v == 0 || (v >= 8 && v <= kMaxNv && v % 4 == 0); };
     if (!cap_or_zero(o.min_nv_capacity)) return bad("min_nv_capacity must be 0 or a DoF capacity 8, 12, ..., 28");
     if (!cap_or_zero(o.slots32_min_nvc)) return bad("slots32_min_nvc must be 0 or a DoF capacity 8, 12, ..., 28");
@@ -408,6 +411,15 @@ int sim_create(const sim_model_desc* d, const sim_options* opts, sim_handle** ou
     const KernelVariant* kv = find_variant(b.nvc, b.sb, ncr_for(b.nvc), ball, self);
     b.ncr = kv->ncr;
     b.fn = kv->fn;
+    if (hp->opts.gpu_factorization == SIM_FACTOR_TREE && !ball && !self && !hp->opts.single_launch) {
+      for (int k = 0; k < kNumTreeKernelVariants; ++k) {
+        const KernelVariant& t = kTreeKernelVariants[k];
+        if (t.nvc == b.nvc && t.sb == b.sb && t.ncr == b.ncr) {
+          b.fn = t.fn;
+          b.tree = 1;
+        }
+      }
+    }
     for (int i = 0; i < n; ++i)
       if (keys[i] == kk) b.users.push_back(i);
     // within a bin, neighbours in a wave should share nv and tree depth
@@ -1049,6 +1061,14 @@ int sim_bins(const sim_handle* h, int32_t* n_bins, int32_t* info, int32_t max_bi
     info[4 * i + 2] = h->bins[i].ncr;
     info[4 * i + 3] = (int32_t)h->bins[i].users.size();
   }
+  return SIM_OK;
+}
+
+int sim_bin_factorization(const sim_handle* h, int32_t* n_bins, int32_t* factorization, int32_t max_bins) {
+  if (!h || !n_bins) return SIM_E_INVALID;
+  *n_bins = (int32_t)h->bins.size();
+  for (int i = 0; i < (int)h->bins.size() && i < max_bins && factorization; ++i)
+    factorization[i] = h->bins[i].tree ? SIM_FACTOR_TREE : SIM_FACTOR_DENSE;
   return SIM_OK;
 }
 

@@ -11,7 +11,11 @@ active rows (n_c contacts, n_clamp engaged actuator clamps), FMA = 2:
   + 70 nb + 60                            with a ball: ball-box tests, ball update
   + 12 nb (nb - 1) / 2                    with self-collision: bounding-sphere tests
 
-(nv counts the ball's six DoFs when there is one.)
+(nv counts the ball's six DoFs when there is one.)  With the tree-sparse
+factorisation (`factorization` "tree" for a variant) the factorisation and
+every solve are counted at the sparse algorithm's flops instead
+(`factor_solve_flops`): (2/3) nv^3 + 2 nv^2 becomes factor + solve, the
+contact rows' 6 nv^2 three solves and a clamp row's 2 nv^2 one solve.
 
 Padded lanes, bin capacities and the kernel's own extra work (for instance
 the explicit inverse) are not counted.  Bytes: model + state read once and
@@ -37,22 +41,29 @@ def depth_sums(pop):
     return D, dbar
 
 
-def flops_per_variant(pop, steps, rows_contact, rows_clamp, K=None):
+def flops_per_variant(pop, steps, rows_contact, rows_clamp, K=None, factorization="dense"):
     """Algorithmic flops of `steps` steps per variant given the counters
     (rows_contact = sum of active contacts over those steps, rows_clamp = sum
-    of engaged clamps)."""
+    of engaged clamps); factorization: "dense", "tree" or one of them per
+    variant."""
     K = int(pop.params["pgs_iters"] if K is None else K)
     nh = pop.n_hinges.astype(np.float64)
     nb = pop.n_bodies.astype(np.float64)
     nv = pop.nv.astype(np.float64)
     D, dbar = depth_sums(pop)
-    base = 156 * nh + 594 * nb + 60 * D + 72 * nh + (2.0 / 3.0) * nv ** 3 + 2 * nv ** 2 + 100
+    fac = np.broadcast_to(np.asarray(factorization), (pop.n_variants,))
+    factor, solve = (2.0 / 3.0) * nv ** 3, 2 * nv ** 2
+    if (fac == "tree").any():
+        tf, ts = factor_solve_flops(pop, "tree")
+        factor = np.where(fac == "tree", tf, factor)
+        solve = np.where(fac == "tree", ts, solve)
+    base = 156 * nh + 594 * nb + 60 * D + 72 * nh + factor + solve + 100
     if getattr(pop, "ball", None) is not None:
         base = base + 70 * nb + 60
     if getattr(pop, "self_collision", False):
         base = base + 12 * nb * (nb - 1) / 2        # bounding-sphere tests of every body pair
-    per_contact = 50 + 9 * dbar + 6 * nv ** 2 + 6 * nv + 12 * K * nv
-    per_clamp = 2 * nv ** 2 + 4 * K * nv
+    per_contact = 50 + 9 * dbar + 3 * solve + 6 * nv + 12 * K * nv
+    per_clamp = solve + 4 * K * nv
     return (base * steps + np.asarray(rows_contact, np.float64) * per_contact
             + np.asarray(rows_clamp, np.float64) * per_clamp)
 

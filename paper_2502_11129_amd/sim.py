@@ -19,7 +19,7 @@ SIM_ROOT_FREE, SIM_ROOT_FIXED = 0, 1
 SIM_HOST, SIM_DEVICE = 0, 1
 EXPORTED = ("sim_create", "sim_workspace_bytes", "sim_bind", "sim_step_batch", "sim_rollout", "sim_fitness",
             "sim_get_state", "sim_set_state", "sim_counters", "sim_rollout_split", "sim_rollout_host", "sim_bins",
-            "sim_variant_bins", "sim_launch_times", "sim_kernel_variants", "sim_split_allocation", "sim_plan_split", "sim_destroy", "sim_last_error")
+            "sim_variant_bins", "sim_bin_factorization", "sim_launch_times", "sim_kernel_variants", "sim_split_allocation", "sim_plan_split", "sim_destroy", "sim_last_error")
 
 _F = C.POINTER(C.c_float)
 _I32 = C.POINTER(C.c_int32)
@@ -38,16 +38,17 @@ class sim_options(C.Structure):
     _fields_ = [("contacts_in_registers", C.c_int32), ("use_graph", C.c_int32), ("steps_per_launch", C.c_int32),
                 ("streams", C.c_int32), ("min_body_slots", C.c_int32), ("ncr_by_nvc", C.c_int32 * 6),
                 ("time_launches", C.c_int32), ("single_launch", C.c_int32), ("host_factorization", C.c_int32),
-                ("min_nv_capacity", C.c_int32), ("slots32_min_nvc", C.c_int32)]
+                ("min_nv_capacity", C.c_int32), ("slots32_min_nvc", C.c_int32), ("gpu_factorization", C.c_int32)]
 
 
 NVC_CAPS = (8, 12, 16, 20, 24, 28)
 HOST_FACTORIZATIONS = ("dense", "tree")   # SIM_FACTOR_DENSE, SIM_FACTOR_TREE
+GPU_FACTORIZATIONS = HOST_FACTORIZATIONS
 
 
 def make_options(contacts_in_registers=0, use_graph=False, steps_per_launch=0, streams=0, min_body_slots=0,
                  ncr_by_nvc=None, time_launches=False, single_launch=False, host_factorization="dense",
-                 min_nv_capacity=0, slots32_min_nvc=0):
+                 min_nv_capacity=0, slots32_min_nvc=0, gpu_factorization="dense"):
     o = sim_options()
     o.contacts_in_registers = int(contacts_in_registers)
     o.use_graph = int(bool(use_graph))
@@ -59,6 +60,7 @@ def make_options(contacts_in_registers=0, use_graph=False, steps_per_launch=0, s
     o.host_factorization = HOST_FACTORIZATIONS.index(host_factorization)
     o.min_nv_capacity = int(min_nv_capacity)
     o.slots32_min_nvc = int(slots32_min_nvc)
+    o.gpu_factorization = GPU_FACTORIZATIONS.index(gpu_factorization)
     for nvc, v in (ncr_by_nvc or {}).items():
         o.ncr_by_nvc[NVC_CAPS.index(int(nvc))] = int(v)
     return o
@@ -113,6 +115,7 @@ def load():
     lib.sim_kernel_variants.argtypes = [_I32, _I32, C.c_int32]
     lib.sim_launch_times.argtypes = [P, _I32, _F, _I32, C.c_int32]
     lib.sim_variant_bins.argtypes = [P, _I32]
+    lib.sim_bin_factorization.argtypes = [P, _I32, _I32, C.c_int32]
     lib.sim_split_allocation.argtypes = [C.c_int32, _I32, C.POINTER(C.c_double), C.c_int32, C.c_double, _I32, _I32,
                                          C.POINTER(C.c_double), C.POINTER(C.c_double)]
     lib.sim_plan_split.argtypes = [P, C.c_int32, C.c_int32, C.c_int32, VP, C.POINTER(sim_split_plan)]
@@ -122,7 +125,7 @@ def load():
     lib.sim_last_error.restype = C.c_char_p
     for name in ("sim_workspace_bytes", "sim_bind", "sim_step_batch", "sim_rollout", "sim_fitness",
                  "sim_get_state", "sim_set_state", "sim_counters", "sim_bins", "sim_rollout_split",
-                 "sim_rollout_host", "sim_variant_bins", "sim_launch_times", "sim_kernel_variants", "sim_split_allocation", "sim_plan_split"):
+                 "sim_rollout_host", "sim_variant_bins", "sim_bin_factorization", "sim_launch_times", "sim_kernel_variants", "sim_split_allocation", "sim_plan_split"):
         getattr(lib, name).restype = I
     _lib = lib
     return lib
@@ -219,6 +222,13 @@ class Handle:
         info = np.zeros(4 * 64, np.int32)
         self._check(self.lib.sim_bins(self.h, C.byref(n), info.ctypes.data_as(_I32), 64))
         return [tuple(int(x) for x in info[4 * i:4 * i + 4]) for i in range(n.value)]
+
+    def bin_factorization(self):
+        """Per bin (sim_bins order): "dense" or "tree", the kernel's factorisation of M~."""
+        n = C.c_int32()
+        f = np.zeros(64, np.int32)
+        self._check(self.lib.sim_bin_factorization(self.h, C.byref(n), f.ctypes.data_as(_I32), 64))
+        return [GPU_FACTORIZATIONS[int(x)] for x in f[:n.value]]
 
     def variant_bins(self):
         out = np.zeros(self.n, np.int32)

@@ -1,6 +1,7 @@
 """C-ABI contract (host only, no device work): the library loads, exports every
 entry point declared in include/sim.h, validates descriptors before touching
 the device and packs variants into DoF bins."""
+import ctypes as C
 import os
 import re
 
@@ -136,3 +137,31 @@ def test_packing_options_min_nv_capacity_and_slots32_min_nvc():
     for bad in (dict(min_nv_capacity=10), dict(slots32_min_nvc=32), dict(min_nv_capacity=-4)):
         with pytest.raises(S.SimError):
             S.Handle(pop, **bad)
+
+
+def test_gpu_factorization_option_picks_the_tree_sparse_kernels_where_compiled():
+    """gpu_factorization = tree switches exactly the bins whose shape has a
+    tree-sparse kernel (plane-only, nv capacity 24, 32 bodies, 8 contacts in
+    registers); the others, and every bin of a single launch, keep the dense
+    sweep; the default is dense; other values are refused."""
+    pop = W.random_trees(512)
+    h = S.Handle(pop, min_body_slots=32, gpu_factorization="tree")
+    fac = h.bin_factorization()
+    assert len(fac) == len(h.bins())
+    for (nvc, slots, ncr, _), f in zip(h.bins(), fac):
+        assert f == ("tree" if (nvc, slots, ncr) == (24, 32, 8) else "dense")
+    assert "tree" in fac
+    h.close()
+    assert set(S.Handle(pop, min_body_slots=32).bin_factorization()) == {"dense"}
+    assert set(S.Handle(pop, min_body_slots=32, single_launch=True, gpu_factorization="tree")
+               .bin_factorization()) == {"dense"}
+    assert set(S.Handle(pop, min_body_slots=32, ncr_by_nvc={24: 2}, gpu_factorization="tree")
+               .bin_factorization()) == {"dense"}
+    assert set(S.Handle(W.box_and_ball(64), gpu_factorization="tree").bin_factorization()) == {"dense"}
+    o = S.make_options()
+    o.gpu_factorization = 2
+    desc, keep = S.make_desc(pop)
+    lib = S.load()
+    hh = C.c_void_p()
+    assert lib.sim_create(C.byref(desc), C.byref(o), C.byref(hh)) == S.SIM_E_INVALID
+    assert "gpu_factorization" in lib.sim_last_error(None).decode()

@@ -33,7 +33,7 @@ def _record(tmp_path, sha, steps=1000):
     src.write_text("// kernel source stand-in\n")
     (tmp_path / "profiles").mkdir()
     rec = {"kernel_source": "kernel.hpp", "kernel_source_sha256": sha, "scale": {"FETCH_SIZE": 2.0, "WRITE_SIZE": 1.0},
-           "per_launch_kib_by_steps_per_launch": {str(steps): {"rollout_kernel<24, 2, 8, false, false>": [100.0, 30.0]}}}
+           "per_launch_kib_by_steps_per_launch": {str(steps): {"rollout_kernel<24, 2, 8, false, false, false>": [100.0, 30.0]}}}
     (tmp_path / "profiles" / "rollout_traffic.json").write_text(json.dumps(rec))
     return hashlib.sha256(src.read_bytes()).hexdigest()
 
@@ -41,13 +41,13 @@ def _record(tmp_path, sha, steps=1000):
 def test_recorded_traffic_scales_and_refuses_stale_records(tmp_path, monkeypatch):
     monkeypatch.setattr(bench, "ROOT", str(tmp_path))
     good = _record(tmp_path, "0" * 64)
-    assert bench.recorded_traffic("rollout_kernel<24, 2, 8, false, false>", 1000) is None   # source changed
+    assert bench.recorded_traffic("rollout_kernel<24, 2, 8, false, false, false>", 1000) is None   # source changed
     (tmp_path / "profiles" / "rollout_traffic.json").unlink()
     (tmp_path / "profiles").rmdir()
     _record(tmp_path, good)
-    assert bench.recorded_traffic("rollout_kernel<24, 2, 8, false, false>", 1000) == (100.0 * 2.0 + 30.0) * 1024
-    assert bench.recorded_traffic("rollout_kernel<24, 2, 8, false, false>", 250) is None    # other launch length
-    assert bench.recorded_traffic("rollout_kernel<20, 2, 8, false, false>", 1000) is None   # kernel not profiled
+    assert bench.recorded_traffic("rollout_kernel<24, 2, 8, false, false, false>", 1000) == (100.0 * 2.0 + 30.0) * 1024
+    assert bench.recorded_traffic("rollout_kernel<24, 2, 8, false, false, false>", 250) is None    # other launch length
+    assert bench.recorded_traffic("rollout_kernel<20, 2, 8, false, false, false>", 1000) is None   # kernel not profiled
 
 
 def test_committed_traffic_record_names_profiled_kernels():
@@ -63,7 +63,7 @@ def test_committed_traffic_record_names_profiled_kernels():
 def test_committed_traffic_record_matches_the_kernel_source():
     """The record is re-taken whenever the rollout kernel changes: a stale
     record would silently drop the bench line's traffic figure."""
-    assert bench.recorded_traffic("rollout_kernel<24, 2, 8, false, false>", 1000) is not None
+    assert bench.recorded_traffic("rollout_kernel<24, 2, 8, false, false, false>", 1000) is not None
 
 
 def test_more_than_one_gpu_is_refused_with_a_message():

@@ -98,3 +98,21 @@ def test_tree_factorization_flop_count_closed_forms():
     d_fac, _ = FL.factor_solve_flops(W.quadrupeds(1), "dense")
     t_fac, _ = FL.factor_solve_flops(W.quadrupeds(1), "tree")
     assert t_fac[0] < d_fac[0] / 3                               # four limbs: branch-induced sparsity
+
+
+def test_step_flop_model_switches_to_the_sparse_counts_per_variant():
+    """With the tree-sparse factorisation a variant's factorisation and
+    solves (free velocity, three per contact, one per clamp) are counted at
+    the sparse algorithm's flops; the rest of the step is unchanged."""
+    from paper_2502_11129_amd import flops as FL
+    pop = W.quadrupeds(4)
+    nc, ncl, T = np.array([30, 0, 7, 12]), np.array([5, 0, 2, 9]), 10
+    dense = FL.flops_per_variant(pop, T, nc, ncl)
+    fac = np.array(["dense", "tree", "tree", "dense"])
+    mixed = FL.flops_per_variant(pop, T, nc, ncl, factorization=fac)
+    nv = pop.nv.astype(np.float64)
+    tf, ts = FL.factor_solve_flops(pop, "tree")
+    want = dense - (T * ((2 / 3) * nv ** 3 + 2 * nv ** 2 - tf - ts)
+                    + nc * 3 * (2 * nv ** 2 - ts) + ncl * (2 * nv ** 2 - ts))
+    np.testing.assert_allclose(mixed[1:3], want[1:3], rtol=1e-12)
+    np.testing.assert_array_equal(mixed[[0, 3]], dense[[0, 3]])

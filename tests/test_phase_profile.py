@@ -1,0 +1,18 @@
+"""The per-phase profiling build finds every phase mark in the current kernel
+source (host only: the instrumented text, no compilation)."""
+import os
+
+from paper_2502_11129_amd import phase_profile as P
+
+HDR = os.path.join(os.path.dirname(P.__file__), "csrc", "rollout_kernel.hpp")
+
+
+def test_every_phase_and_sub_phase_mark_is_found():
+    with open(HDR) as f:
+        src = f.read()
+    s = P.instrument(src)
+    assert s.count("s_memtime") == 8 + 7       # 7 phases + the step's end; 6 tree sub-phases + their end
+    assert s.count("_ph[") >= 7 and s.count("_sub[") >= 6
+    assert "static __device__ unsigned long long g_phase[16][8];" in s
+    # the plain source is untouched
+    assert "s_memtime" not in src

@@ -47,6 +47,7 @@ extern "C" {
 #define SIM_E_NOMEM (-2)   /* workspace smaller than sim_workspace_bytes()       */
 #define SIM_E_DEVICE (-3)  /* HIP runtime error (sticky for the handle)          */
 #define SIM_E_STATE (-4)   /* call out of order (e.g. step before sim_bind)      */
+#define SIM_E_HOST (-5)    /* host workers failed on some variants (host-only runs) */
 
 #define SIM_ROOT_FREE 0  /* 6-DoF floating core                                 */
 #define SIM_ROOT_FIXED 1 /* core welded to root_pose (tests)                    */
@@ -183,6 +184,10 @@ typedef struct {
  *                         bin under single_launch, keep the sweep
  *                         (sim_bin_factorization tells which).  The two agree
  *                         to rounding.
+ *  host_fault_items       for failure-handling tests: the first
+ *                         host_fault_items variants taken by the host workers
+ *                         of a host or split rollout fail as if their worker
+ *                         had raised an error (0 = none)
  */
 typedef struct {
   int32_t contacts_in_registers;
@@ -197,6 +202,7 @@ typedef struct {
   int32_t min_nv_capacity;
   int32_t slots32_min_nvc;
   int32_t gpu_factorization;
+  int32_t host_fault_items;
 } sim_options;
 
 #define SIM_FACTOR_DENSE 0
@@ -256,7 +262,8 @@ typedef struct {
   double combined_s; /* wall clock of the concurrent run, including the merge of host results */
   double gpu_s;      /* GPU share: first launch to completion (HIP events)                    */
   double host_s;     /* host share: first thread start to last thread end                     */
-  int32_t n_gpu, n_host, host_threads, reserved;
+  int32_t n_gpu, n_host, host_threads;
+  int32_t n_requeued; /* host-share variants no host worker finished, re-run on the GPU */
 } sim_split_times;
 
 /* Rollout of T steps with the population split between the GPU and host
@@ -266,14 +273,20 @@ typedef struct {
  * while the others run on the GPU; both start together.  When the call
  * returns (it synchronises `stream`), fitness, state and counters of every
  * variant are as after sim_rollout.  0 <= n_host <= n_variants;
- * host_threads >= 1.  `times` may be NULL. */
+ * host_threads >= 1.  `times` may be NULL.  A host worker that fails (an
+ * error raised while it simulates a variant, or a thread that cannot start)
+ * drops out and the others carry on; whatever no host worker finished is
+ * re-queued on the GPU after the GPU share (times->n_requeued), so the
+ * result still covers every variant. */
 int sim_rollout_split(sim_handle* h, int32_t T, int32_t n_host, int32_t host_threads, void* stream,
                       sim_split_times* times);
 
 /* Host-only rollout of every variant on host_threads CPU threads, without any
  * device work and without touching the device state (sim_bind not needed).
  * fitness: [n_variants] host floats, user order; may be NULL.  seconds: wall
- * clock of the run; may be NULL. */
+ * clock of the run; may be NULL.  If host workers fail on some variants
+ * there is no other device to take them: SIM_E_HOST, with the count in
+ * sim_last_error(h), and fitness is not written. */
 int sim_rollout_host(sim_handle* h, int32_t T, int32_t host_threads, float* fitness, double* seconds);
 
 /* Description of the packing: number of bins and, per bin, (nv capacity,
@@ -283,6 +296,19 @@ int sim_bins(const sim_handle* h, int32_t* n_bins, int32_t* info, int32_t max_bi
 /* Bin of every variant (user order), an index into the sim_bins order.
  * bin: [n_variants] ints.  Host only. */
 int sim_variant_bins(const sim_handle* h, int32_t* bin);
+
+/* Consecutive chunks of the population, in user order, such that a handle
+ * created for each chunk alone (same options) needs at most
+ * max_workspace_bytes of workspace: chunk c holds the variants
+ * [c ? chunk_end[c - 1] : 0, chunk_end[c]).  For populations whose workspace
+ * exceeds the device memory (the paper caps N per scene for that reason):
+ * create, bind and run one handle per chunk; per-variant results do not
+ * depend on the chunking.  chunk_end has max_chunks ints; *n_chunks receives
+ * the count.  Errors: SIM_E_NOMEM if one variant alone exceeds the cap;
+ * SIM_E_INVALID if max_chunks is too small (*n_chunks still receives the
+ * count).  Host only. */
+int sim_chunk_plan(const sim_handle* h, size_t max_workspace_bytes, int32_t* n_chunks, int32_t* chunk_end,
+                   int32_t max_chunks);
 
 /* Factorisation of M~ in each bin's kernel (sim_bins order):
  * SIM_FACTOR_DENSE or SIM_FACTOR_TREE (see sim_options.gpu_factorization).

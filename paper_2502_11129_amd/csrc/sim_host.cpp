@@ -3,6 +3,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <array>
 #include <atomic>
 #include <chrono>
 #include <cmath>
@@ -10,6 +11,7 @@
 #include <cstdio>
 #include <cstring>
 #include <memory>
+#include <stdexcept>
 #include <string>
 #include <vector>
 
@@ -48,6 +50,20 @@ struct Bin {
 };
 
 size_t align256(size_t x) { return (x + 255) & ~size_t(255); }
+
+long long ovf_stride_of(const Bin& b, int ball, int self) {
+  return ovf_floats(max_contacts(16 * b.sb, ball, self), b.nvc, (ball || self) ? kListWordsBall : kListWords);
+}
+
+// Workspace arrays of a bin (in layout order) and their bytes per variant;
+// the layout rounds every array up to 256 bytes.
+constexpr int kWsArrays = 15;
+void ws_bytes_per_variant(const Bin& b, int ball, int self, size_t (&per)[kWsArrays]) {
+  const size_t v[kWsArrays] = {HW_WORDS * 4, HF_WORDS * 4, (size_t)16 * b.sb * BW_WORDS * 4,
+                               (size_t)(2 * 16 * b.sb + 4) * 4, kQStride * 4, kVStride * 4, kQStride * 4,
+                               kVStride * 4, 8, 4, 8, 4, 16, (size_t)ovf_stride_of(b, ball, self) * 4, 16};
+  for (int i = 0; i < kWsArrays; ++i) per[i] = v[i];
+}
 
 }  // namespace
 
@@ -113,7 +129,29 @@ const KernelVariant* find_variant(int nvc, int sb, int ncr, int ball, int self) 
 // Launch every bin's kernel for n_steps (reset on the first chunk if asked).
 // Bins are independent: bin 0 runs on the caller's stream, every other bin on
 // a library stream forked from and joined back into the caller's stream.
-int launch_bin(sim_handle* h, Bin& b, int n_steps, bool reset, hipStream_t st, int count = -1) {
+// The bin's arguments for its packed variants [first, first + n).
+BinArgs sub_args(const Bin& b, int first, int n) {
+  BinArgs a = b.args;
+  const size_t f = (size_t)first;
+  a.n = n;
+  a.hdr += f * HW_WORDS;
+  a.hdrf += f * HF_WORDS;
+  a.body += f * 16 * b.sb * BW_WORDS;
+  a.lvl += f * b.lvl_stride;
+  a.q0 += f * kQStride;
+  a.v0 += f * kVStride;
+  a.q += f * kQStride;
+  a.v += f * kVStride;
+  a.k += f;
+  a.status += f;
+  a.xy0 += 2 * f;
+  a.fit += f;
+  a.cnt += 2 * f;
+  a.ovf += f * (size_t)b.ovf_stride;
+  return a;
+}
+
+int launch_bin(sim_handle* h, Bin& b, int n_steps, bool reset, hipStream_t st, int count = -1, int first_slot = 0) {
   if (count == 0) return SIM_OK;
   int done = 0;
   bool first = true;
@@ -125,7 +163,7 @@ int launch_bin(sim_handle* h, Bin& b, int n_steps, bool reset, hipStream_t st, i
   }
   while (first || done < n_steps) {
     const int chunk = std::min(h->steps_per_launch, n_steps - done);
-    BinArgs a = b.args;
+    BinArgs a = first_slot ? sub_args(b, first_slot, count) : b.args;
     a.n_steps = chunk;
     a.reset = (reset && first) ? 1 : 0;
     if (count >= 0) a.n = count;
@@ -213,23 +251,48 @@ HostVariantView host_view(const sim_handle* h, const Bin& b, size_t s) {
 }
 
 // Run the listed (bin, slot) pairs on host threads; returns wall seconds.
+// done[i] = 1 for every item that finished.  A worker whose item fails (an
+// exception: allocation, thread resources, or the injected test fault of
+// sim_options.host_fault_items) stops taking work; the others go on, and
+// what no worker finished is left to the caller (the split re-queues it on
+// the GPU).  A thread that cannot be started leaves its share to the rest.
 double run_host(const sim_handle* h, const std::vector<std::pair<int, int>>& work, int threads,
-                std::vector<HostVariantState>& out) {
+                std::vector<HostVariantState>& out, std::vector<char>& done) {
   out.assign(work.size(), HostVariantState());
+  done.assign(work.size(), 0);
   std::atomic<size_t> next(0);
+  const size_t faults = (size_t)std::max(0, h->opts.host_fault_items);
   auto t0 = std::chrono::steady_clock::now();
   auto body = [&]() {
     for (size_t i = next.fetch_add(1); i < work.size(); i = next.fetch_add(1)) {
-      const Bin& b = h->bins[work[i].first];
-      host_rollout(host_view(h, b, work[i].second), h->params, h->split_T, out[i]);
+      try {
+        if (i < faults) throw std::runtime_error("injected host worker fault");
+        const Bin& b = h->bins[work[i].first];
+        host_rollout(host_view(h, b, work[i].second), h->params, h->split_T, out[i]);
+        done[i] = 1;
+      } catch (...) {
+        return;  // this worker is out; its item stays undone
+      }
     }
   };
   const int nt = std::max(1, std::min<int>(threads, (int)work.size()));
   std::vector<std::thread> pool;
-  for (int t = 1; t < nt; ++t) pool.emplace_back(body);
+  for (int t = 1; t < nt; ++t) {
+    try {
+      pool.emplace_back(body);
+    } catch (...) {
+      break;
+    }
+  }
   body();
   for (auto& th : pool) th.join();
   return std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+}
+
+size_t count_undone(const std::vector<char>& done) {
+  size_t n = 0;
+  for (char c : done) n += c ? 0 : 1;
+  return n;
 }
 
 // Host share per bin: proportional to bin size, largest remainders, taken from the bin tails.
@@ -297,6 +360,7 @@ int sim_create(const sim_model_desc* d, const sim_options* opts, sim_handle** ou
       return bad("host_factorization must be SIM_FACTOR_DENSE or SIM_FACTOR_TREE");
     if (o.gpu_factorization != SIM_FACTOR_DENSE && o.gpu_factorization != SIM_FACTOR_TREE)
       return bad("gpu_factorization must be SIM_FACTOR_DENSE or SIM_FACTOR_TREE");
+    if (o.host_fault_items < 0) return bad("host_fault_items must be >= 0");
     auto cap_or_zero = [](int v) { return v == 0 || (v >= 8 && v <= kMaxNv && v % 4 == 0); };
     if (!cap_or_zero(o.min_nv_capacity)) return bad("min_nv_capacity must be 0 or a DoF capacity 8, 12, ..., 28");
     if (!cap_or_zero(o.slots32_min_nvc)) return bad("slots32_min_nvc must be 0 or a DoF capacity 8, 12, ..., 28");
@@ -536,7 +600,7 @@ int sim_create(const sim_model_desc* d, const sim_options* opts, sim_handle** ou
   auto take = [&](size_t bytes) { size_t o = off; off = align256(off + bytes); return o; };
   for (Bin& b : hp->bins) {
     const size_t m = b.users.size();
-    b.ovf_stride = ovf_floats(max_contacts(16 * b.sb, ball, self), b.nvc, (ball || self) ? kListWordsBall : kListWords);
+    b.ovf_stride = ovf_stride_of(b, ball, self);
     b.o_hdr = take(m * HW_WORDS * 4);
     b.o_hdrf = take(m * HF_WORDS * 4);
     b.o_body = take(m * 16 * b.sb * BW_WORDS * 4);
@@ -822,8 +886,12 @@ int sim_rollout_host(sim_handle* h, int32_t T, int32_t host_threads, float* fitn
   for (size_t bi = 0; bi < h->bins.size(); ++bi)
     for (size_t s2 = 0; s2 < h->bins[bi].users.size(); ++s2) work.push_back({(int)bi, (int)s2});
   std::vector<HostVariantState> out;
+  std::vector<char> done;
   h->split_T = T;
-  const double sec = run_host(h, work, host_threads, out);
+  const double sec = run_host(h, work, host_threads, out, done);
+  if (const size_t bad_n = count_undone(done))
+    return fail(h, SIM_E_HOST, "host workers failed; " + std::to_string(bad_n) + " of " +
+                                   std::to_string(work.size()) + " variants were not simulated");
   if (fitness)
     for (size_t i = 0; i < work.size(); ++i) {
       const Bin& b = h->bins[work[i].first];
@@ -858,10 +926,12 @@ int sim_rollout_split(sim_handle* h, int32_t T, int32_t n_host, int32_t host_thr
   if (!rc) rc = launch_all(h, T, true, st, &gc);
   if (!rc) rc = dev_check(h, hipEventRecord(e1, st), "event record");
   std::vector<HostVariantState> out;
+  std::vector<char> done;
   h->split_T = T;
   double host_s = 0.0;
-  if (!rc) host_s = run_host(h, work, host_threads, out);  // concurrent with the GPU launches above
+  if (!rc) host_s = run_host(h, work, host_threads, out, done);  // concurrent with the GPU launches above
   if (!rc) rc = dev_check(h, hipStreamSynchronize(st), "split sync");
+  const size_t n_requeued = rc ? 0 : count_undone(done);
   // merge: host results into the device state (contiguous tail of every bin)
   size_t wi = 0;
   for (size_t bi = 0; !rc && bi < h->bins.size(); ++bi) {
@@ -893,6 +963,30 @@ int sim_rollout_split(sim_handle* h, int32_t T, int32_t n_host, int32_t host_thr
     up(b.o_cnt + g * 16, cc.data(), nh * 16);
     if (!rc) rc = dev_check(h, hipStreamSynchronize(st), "merge sync");  // host vectors die here
   }
+  // re-queue: what no host worker finished runs on the GPU, one launch
+  // sequence per run of consecutive slots, over the merged (unfinished) slots
+  for (size_t bi = 0, wj = 0; !rc && n_requeued && bi < h->bins.size(); ++bi) {
+    Bin& b = h->bins[bi];
+    const int m = (int)b.users.size(), g = gc[bi];
+    std::vector<char> redo(m, 0);
+    for (int s2 = g; s2 < m; ++s2, ++wj) redo[s2] = done[wj] ? 0 : 1;
+    for (int s0 = g; !rc && s0 < m;) {
+      if (!redo[s0]) { ++s0; continue; }
+      int s1 = s0;
+      while (s1 < m && redo[s1]) ++s1;
+      for (int k = 0, first = 1; !rc && (first || k < T); first = 0) {
+        const int chunk = std::min(h->steps_per_launch, T - k);
+        BinArgs a = sub_args(b, s0, s1 - s0);
+        a.n_steps = chunk;
+        a.reset = first;
+        const hipError_t e = b.fn(a, h->params, st);
+        if (e != hipSuccess) rc = dev_check(h, e, "re-queue launch");
+        k += chunk;
+      }
+      s0 = s1;
+    }
+  }
+  if (!rc && n_requeued) rc = dev_check(h, hipStreamSynchronize(st), "re-queue sync");
   const double combined = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
   float gpu_ms = 0.f;
   if (!rc) rc = dev_check(h, hipEventElapsedTime(&gpu_ms, e0, e1), "event time");
@@ -906,7 +1000,7 @@ int sim_rollout_split(sim_handle* h, int32_t T, int32_t n_host, int32_t host_thr
     times->n_gpu = h->n - n_host;
     times->n_host = n_host;
     times->host_threads = host_threads;
-    times->reserved = 0;
+    times->n_requeued = (int32_t)n_requeued;
   }
   return SIM_OK;
 }
@@ -1043,10 +1137,13 @@ int sim_plan_split(sim_handle* h, int32_t T_pilot, int32_t host_threads, int32_t
     work.push_back({h->bin_of[user], h->slot_of[user]});
   }
   std::vector<HostVariantState> out;
+  std::vector<char> done;
   const int saved_T = h->split_T;
   h->split_T = T_pilot;
-  const double host_wall = run_host(h, work, host_threads, out);
+  const double host_wall = run_host(h, work, host_threads, out, done);
   h->split_T = saved_T;
+  if (const size_t bad_n = count_undone(done))
+    return fail(h, SIM_E_HOST, "host pilot: host workers failed on " + std::to_string(bad_n) + " variants");
   plan->host_s_per_variant = host_wall / take;
   return sim_split_allocation(h->n, plan->gpu_n, plan->gpu_s, np, plan->host_s_per_variant, &plan->n_host_paper,
                               &plan->n_host_makespan, &plan->makespan_paper_s, &plan->makespan_opt_s);
@@ -1061,6 +1158,52 @@ int sim_bins(const sim_handle* h, int32_t* n_bins, int32_t* info, int32_t max_bi
     info[4 * i + 2] = h->bins[i].ncr;
     info[4 * i + 3] = (int32_t)h->bins[i].users.size();
   }
+  return SIM_OK;
+}
+
+int sim_chunk_plan(const sim_handle* h, size_t max_workspace_bytes, int32_t* n_chunks, int32_t* chunk_end,
+                   int32_t max_chunks) {
+  if (!h || !n_chunks) return SIM_E_INVALID;
+  // a chunk's workspace: per bin present, every array rounded up to 256
+  // bytes; adding a variant adds its bin's per-variant bytes (and, for a bin
+  // new to the chunk, the rounding of that bin's arrays)
+  const size_t nb = h->bins.size();
+  std::vector<std::array<size_t, kWsArrays>> per(nb);
+  for (size_t bi = 0; bi < nb; ++bi) {
+    size_t p[kWsArrays];
+    ws_bytes_per_variant(h->bins[bi], h->ball, h->self, p);
+    for (int i = 0; i < kWsArrays; ++i) per[bi][i] = p[i];
+  }
+  std::vector<size_t> cnt(nb, 0);
+  auto grow = [&](int bi) {  // bytes added by one more variant of bin bi
+    size_t d = 0;
+    for (int i = 0; i < kWsArrays; ++i) d += align256((cnt[bi] + 1) * per[bi][i]) - align256(cnt[bi] * per[bi][i]);
+    return d;
+  };
+  std::vector<int32_t> ends;
+  size_t used = 0;
+  for (int i = 0; i < h->n; ++i) {
+    const int bi = h->bin_of[i];
+    if (used + grow(bi) > max_workspace_bytes) {
+      if (used == 0)
+        return fail(const_cast<sim_handle*>(h), SIM_E_NOMEM,
+                    "variant " + std::to_string(i) + " alone needs more workspace than the cap");
+      ends.push_back(i);  // close the chunk before variant i
+      std::fill(cnt.begin(), cnt.end(), 0);
+      used = 0;
+      if (grow(bi) > max_workspace_bytes)
+        return fail(const_cast<sim_handle*>(h), SIM_E_NOMEM,
+                    "variant " + std::to_string(i) + " alone needs more workspace than the cap");
+    }
+    used += grow(bi);
+    ++cnt[bi];
+  }
+  if (h->n > 0) ends.push_back(h->n);
+  *n_chunks = (int32_t)ends.size();
+  if ((int32_t)ends.size() > max_chunks || (!chunk_end && !ends.empty()))
+    return fail(const_cast<sim_handle*>(h), SIM_E_INVALID, "chunk_end holds fewer than " +
+                                                              std::to_string(ends.size()) + " entries");
+  std::copy(ends.begin(), ends.end(), chunk_end);
   return SIM_OK;
 }
 

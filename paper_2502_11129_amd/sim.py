@@ -14,12 +14,12 @@ import numpy as np
 _LIB_PATH = os.path.join(os.path.dirname(os.path.abspath(__file__)), "libsim.so")
 _lib = None
 
-SIM_OK, SIM_E_INVALID, SIM_E_NOMEM, SIM_E_DEVICE, SIM_E_STATE = 0, -1, -2, -3, -4
+SIM_OK, SIM_E_INVALID, SIM_E_NOMEM, SIM_E_DEVICE, SIM_E_STATE, SIM_E_HOST = 0, -1, -2, -3, -4, -5
 SIM_ROOT_FREE, SIM_ROOT_FIXED = 0, 1
 SIM_HOST, SIM_DEVICE = 0, 1
 EXPORTED = ("sim_create", "sim_workspace_bytes", "sim_bind", "sim_step_batch", "sim_rollout", "sim_fitness",
             "sim_get_state", "sim_set_state", "sim_counters", "sim_rollout_split", "sim_rollout_host", "sim_bins",
-            "sim_variant_bins", "sim_bin_factorization", "sim_launch_times", "sim_kernel_variants", "sim_split_allocation", "sim_plan_split", "sim_destroy", "sim_last_error")
+            "sim_variant_bins", "sim_bin_factorization", "sim_chunk_plan", "sim_launch_times", "sim_kernel_variants", "sim_split_allocation", "sim_plan_split", "sim_destroy", "sim_last_error")
 
 _F = C.POINTER(C.c_float)
 _I32 = C.POINTER(C.c_int32)
@@ -38,7 +38,8 @@ class sim_options(C.Structure):
     _fields_ = [("contacts_in_registers", C.c_int32), ("use_graph", C.c_int32), ("steps_per_launch", C.c_int32),
                 ("streams", C.c_int32), ("min_body_slots", C.c_int32), ("ncr_by_nvc", C.c_int32 * 6),
                 ("time_launches", C.c_int32), ("single_launch", C.c_int32), ("host_factorization", C.c_int32),
-                ("min_nv_capacity", C.c_int32), ("slots32_min_nvc", C.c_int32), ("gpu_factorization", C.c_int32)]
+                ("min_nv_capacity", C.c_int32), ("slots32_min_nvc", C.c_int32), ("gpu_factorization", C.c_int32),
+                ("host_fault_items", C.c_int32)]
 
 
 NVC_CAPS = (8, 12, 16, 20, 24, 28)
@@ -48,7 +49,7 @@ GPU_FACTORIZATIONS = HOST_FACTORIZATIONS
 
 def make_options(contacts_in_registers=0, use_graph=False, steps_per_launch=0, streams=0, min_body_slots=0,
                  ncr_by_nvc=None, time_launches=False, single_launch=False, host_factorization="dense",
-                 min_nv_capacity=0, slots32_min_nvc=0, gpu_factorization="dense"):
+                 min_nv_capacity=0, slots32_min_nvc=0, gpu_factorization="dense", host_fault_items=0):
     o = sim_options()
     o.contacts_in_registers = int(contacts_in_registers)
     o.use_graph = int(bool(use_graph))
@@ -61,6 +62,7 @@ def make_options(contacts_in_registers=0, use_graph=False, steps_per_launch=0, s
     o.min_nv_capacity = int(min_nv_capacity)
     o.slots32_min_nvc = int(slots32_min_nvc)
     o.gpu_factorization = GPU_FACTORIZATIONS.index(gpu_factorization)
+    o.host_fault_items = int(host_fault_items)
     for nvc, v in (ncr_by_nvc or {}).items():
         o.ncr_by_nvc[NVC_CAPS.index(int(nvc))] = int(v)
     return o
@@ -74,7 +76,7 @@ class sim_split_plan(C.Structure):
 
 class sim_split_times(C.Structure):
     _fields_ = [("combined_s", C.c_double), ("gpu_s", C.c_double), ("host_s", C.c_double),
-                ("n_gpu", C.c_int32), ("n_host", C.c_int32), ("host_threads", C.c_int32), ("reserved", C.c_int32)]
+                ("n_gpu", C.c_int32), ("n_host", C.c_int32), ("host_threads", C.c_int32), ("n_requeued", C.c_int32)]
 
 
 class SimError(RuntimeError):
@@ -116,6 +118,7 @@ def load():
     lib.sim_launch_times.argtypes = [P, _I32, _F, _I32, C.c_int32]
     lib.sim_variant_bins.argtypes = [P, _I32]
     lib.sim_bin_factorization.argtypes = [P, _I32, _I32, C.c_int32]
+    lib.sim_chunk_plan.argtypes = [P, SZ, _I32, _I32, C.c_int32]
     lib.sim_split_allocation.argtypes = [C.c_int32, _I32, C.POINTER(C.c_double), C.c_int32, C.c_double, _I32, _I32,
                                          C.POINTER(C.c_double), C.POINTER(C.c_double)]
     lib.sim_plan_split.argtypes = [P, C.c_int32, C.c_int32, C.c_int32, VP, C.POINTER(sim_split_plan)]
@@ -125,7 +128,7 @@ def load():
     lib.sim_last_error.restype = C.c_char_p
     for name in ("sim_workspace_bytes", "sim_bind", "sim_step_batch", "sim_rollout", "sim_fitness",
                  "sim_get_state", "sim_set_state", "sim_counters", "sim_bins", "sim_rollout_split",
-                 "sim_rollout_host", "sim_variant_bins", "sim_bin_factorization", "sim_launch_times", "sim_kernel_variants", "sim_split_allocation", "sim_plan_split"):
+                 "sim_rollout_host", "sim_variant_bins", "sim_bin_factorization", "sim_chunk_plan", "sim_launch_times", "sim_kernel_variants", "sim_split_allocation", "sim_plan_split"):
         getattr(lib, name).restype = I
     _lib = lib
     return lib
@@ -230,6 +233,17 @@ class Handle:
         self._check(self.lib.sim_bin_factorization(self.h, C.byref(n), f.ctypes.data_as(_I32), 64))
         return [GPU_FACTORIZATIONS[int(x)] for x in f[:n.value]]
 
+    def chunk_plan(self, max_workspace_bytes: int):
+        """Ends of consecutive chunks (user order) whose handles each fit the workspace cap."""
+        n = C.c_int32()
+        rc = self.lib.sim_chunk_plan(self.h, int(max_workspace_bytes), C.byref(n), None, 0)
+        if rc not in (SIM_OK, SIM_E_INVALID) or (rc == SIM_E_INVALID and n.value == 0):
+            self._check(rc)
+        ends = np.zeros(max(n.value, 1), np.int32)
+        self._check(self.lib.sim_chunk_plan(self.h, int(max_workspace_bytes), C.byref(n), ends.ctypes.data_as(_I32),
+                                            len(ends)))
+        return ends[:n.value].tolist()
+
     def variant_bins(self):
         out = np.zeros(self.n, np.int32)
         self._check(self.lib.sim_variant_bins(self.h, out.ctypes.data_as(_I32)))
@@ -330,7 +344,7 @@ class Simulator(Handle):
         t = sim_split_times()
         self._check(self.lib.sim_rollout_split(self.h, int(T), int(n_host), int(threads), self.stream(), C.byref(t)))
         return dict(combined_s=t.combined_s, gpu_s=t.gpu_s, host_s=t.host_s, n_gpu=t.n_gpu, n_host=t.n_host,
-                    host_threads=t.host_threads)
+                    host_threads=t.host_threads, n_requeued=t.n_requeued)
 
     def launch_times(self):
         """Per bin (sim_bins order): (milliseconds of its launches, number of launches) of the last run."""
@@ -358,3 +372,34 @@ class Simulator(Handle):
                                           b.ctypes.data_as(C.POINTER(C.c_uint64)),
                                           s.ctypes.data_as(C.POINTER(C.c_uint32)), SIM_HOST, self.stream()))
         return a, b, s
+
+
+def rollout_in_chunks(pop, T: int, max_workspace_bytes=None, device=None, **options):
+    """Rollout of T steps for a population of any size: consecutive chunks
+    (sim_chunk_plan) whose workspaces each fit max_workspace_bytes (default:
+    90 % of the device memory free now) are created, bound and run one after
+    another.  Returns dict(fitness, rows_contact, rows_clamp, status, chunks)
+    in user order; per-variant results equal those of one handle over the
+    whole population."""
+    import torch
+    dev = torch.device("cuda" if device is None else device)
+    if max_workspace_bytes is None:
+        free, _ = torch.cuda.mem_get_info(dev)
+        max_workspace_bytes = int(0.9 * free)
+    probe = Handle(pop, **options)
+    ends = probe.chunk_plan(max_workspace_bytes)
+    probe.close()
+    n = pop.n_variants
+    fit = np.zeros(n, np.float32)
+    rc, rl = np.zeros(n, np.uint64), np.zeros(n, np.uint64)
+    st = np.zeros(n, np.uint32)
+    start = 0
+    for e in ends:
+        sim = Simulator(pop.subset(np.arange(start, e)), device=dev, **options)
+        sim.rollout(T)
+        fit[start:e] = sim.fitness()
+        rc[start:e], rl[start:e], st[start:e] = sim.counters()
+        sim.close()
+        del sim
+        start = e
+    return dict(fitness=fit, rows_contact=rc, rows_clamp=rl, status=st, chunks=ends)

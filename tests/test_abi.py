@@ -165,3 +165,51 @@ def test_gpu_factorization_option_picks_the_tree_sparse_kernels_where_compiled()
     hh = C.c_void_p()
     assert lib.sim_create(C.byref(desc), C.byref(o), C.byref(hh)) == S.SIM_E_INVALID
     assert "gpu_factorization" in lib.sim_last_error(None).decode()
+
+
+def test_chunk_plan_keeps_every_chunk_within_the_workspace_cap():
+    """sim_chunk_plan cuts the population into consecutive chunks whose own
+    handles each fit the cap, and each chunk is as long as the cap allows;
+    a cap above the whole workspace gives one chunk, one below a single
+    variant's need is refused."""
+    pop = W.random_trees(300)
+    h = S.Handle(pop, min_body_slots=32)
+    total = h.workspace_bytes()
+    assert h.chunk_plan(total) == [pop.n_variants]
+    cap = total // 5
+    ends = h.chunk_plan(cap)
+    assert len(ends) >= 5 and ends[-1] == pop.n_variants
+    assert all(b > a for a, b in zip([0] + ends, ends))
+    start = 0
+    for e in ends:
+        sub = S.Handle(pop.subset(np.arange(start, e)), min_body_slots=32)
+        assert sub.workspace_bytes() <= cap
+        sub.close()
+        if e < pop.n_variants:             # one more variant would not fit
+            big = S.Handle(pop.subset(np.arange(start, e + 1)), min_body_slots=32)
+            assert big.workspace_bytes() > cap
+            big.close()
+        start = e
+    with pytest.raises(S.SimError) as ei:
+        h.chunk_plan(1024)
+    assert ei.value.code == S.SIM_E_NOMEM
+    h.close()
+
+
+def test_host_worker_failures_are_reported_not_fatal():
+    """A host worker that fails drops out and the others carry on; a
+    host-only rollout has no other device for what is left and reports how
+    many variants were not simulated (SIM_E_HOST); the count is exact."""
+    pop = W.random_trees(40)
+    ok = S.Handle(pop)
+    f, _ = ok.rollout_host(20, threads=4)
+    assert np.isfinite(f).all()
+    h = S.Handle(pop, host_fault_items=2)
+    with pytest.raises(S.SimError) as ei:
+        h.rollout_host(20, threads=4)      # two workers fail, two finish the rest
+    assert ei.value.code == S.SIM_E_HOST and "2 of 40" in str(ei.value)
+    with pytest.raises(S.SimError) as ei:
+        h.rollout_host(20, threads=1)      # the only worker fails at once
+    assert "40 of 40" in str(ei.value)
+    with pytest.raises(S.SimError):
+        S.Handle(pop, host_fault_items=-1)

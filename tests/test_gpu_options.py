@@ -76,3 +76,23 @@ def test_plan_split_measures_and_resets():
     assert (k == 0).all()
     np.testing.assert_array_equal(q, pop.q0.astype(np.float32))
     np.testing.assert_array_equal(v, pop.v0.astype(np.float32))
+
+
+def test_rollout_in_chunks_matches_one_handle():
+    """A population run as consecutive chunks that each fit a workspace cap
+    (a fifth of the whole) gives every variant the fitness, counters and
+    status of one handle over the whole population, bit for bit."""
+    from paper_2502_11129_amd.sim import Handle, Simulator, rollout_in_chunks
+    pop = W.random_trees(300)
+    T = 300
+    whole = Simulator(pop)
+    whole.rollout(T)
+    a, b, s = whole.counters()
+    cap = Handle(pop).workspace_bytes() // 5
+    r = rollout_in_chunks(pop, T, max_workspace_bytes=cap)
+    _say(f"[chunks] cap {cap} bytes: chunk ends {r['chunks']}")
+    assert len(r["chunks"]) >= 5
+    np.testing.assert_array_equal(r["fitness"], whole.fitness())
+    np.testing.assert_array_equal(r["rows_contact"], a)
+    np.testing.assert_array_equal(r["rows_clamp"], b)
+    np.testing.assert_array_equal(r["status"], s)

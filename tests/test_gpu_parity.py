@@ -351,3 +351,35 @@ def test_split_rollout_gpu_part_bitwise_host_part_within_bar():
     assert same.sum() >= 30          # the GPU share is bit-identical
     _, _, k = s.get_state()
     assert (k == 400).all()
+
+
+def test_split_rollout_requeues_a_failed_host_share_on_the_gpu():
+    """Host workers that fail (forced from the host: the first three
+    variants taken raise an error) drop out; the rest of the host share is
+    finished by the other workers and the three are re-run on the GPU, so
+    every variant has its result: re-queued and GPU-share variants bit for
+    bit the GPU-only rollout's, host-finished ones within the oracle bar.
+    With every worker failing, the whole host share is re-queued."""
+    pop = W.random_trees(64)
+    _say("[split re-queue] trees x64, 24 on 8 host threads, 3 forced failures, T=300")
+    g = _sim(pop)
+    g.rollout(300)
+    Fg = g.fitness()
+    qg, vg, kg = g.get_state()
+    s = _sim(pop, host_fault_items=3)
+    t = s.rollout_split(300, n_host=24, threads=8)
+    assert t["n_requeued"] == 3 and t["n_host"] == 24
+    Fs = s.fitness()
+    assert np.isfinite(Fs).all()
+    assert (Fs == Fg).sum() >= 40 + 3          # GPU share and re-queued variants
+    Fr, F32, Fp, margin = oracle_reference(pop, 300)
+    assert_gate(Fs.astype(np.float64), Fr, F32, Fp, say=_say, margin=margin)
+    _, _, k = s.get_state()
+    assert (k == 300).all()
+    a = _sim(pop, host_fault_items=24)
+    t = a.rollout_split(300, n_host=24, threads=1)
+    assert t["n_requeued"] == 24
+    q, v, k = a.get_state()
+    np.testing.assert_array_equal(a.fitness(), Fg)
+    np.testing.assert_array_equal(q, qg)
+    np.testing.assert_array_equal(v, vg)

@@ -135,13 +135,13 @@ def autotune(pop, T_pilot=1000, reps=3, log=None, cache=None, min_gain=0.01, due
     # kernels with fewer registers), every variant in 32-body kernels (fewer
     # bins), 32-body kernels only from 20 DoFs on with the smaller variants
     # merged into one 16-DoF, 16-body bin (whose kernels run two waves per
-    # SIMD), and the same with the 20-DoF variants in 16-body kernels with 2
+    # SIMD), and the same with the 20-DoF variants in 16-body kernels with 4
     # contacts in registers (also two waves per SIMD); a start that gives the
     # same bins as an earlier one is skipped
     results, seen = [], []
     for extra in (dict(min_body_slots=0), dict(min_body_slots=32),
                   dict(min_body_slots=32, slots32_min_nvc=20, min_nv_capacity=16),
-                  dict(min_body_slots=32, slots32_min_nvc=24, min_nv_capacity=16, ncr_by_nvc={16: 8, 20: 2})):
+                  dict(min_body_slots=32, slots32_min_nvc=24, min_nv_capacity=16, ncr_by_nvc={16: 8, 20: 4})):
         start_opts = dict(dict(streams=0, steps_per_launch=0, ncr_by_nvc={}), **extra)
         probe = S.Handle(pop, **start_opts)
         layout = sorted(tuple(b[:4]) for b in probe.bins())

@@ -20,7 +20,7 @@ namespace simk {
 // self-collision.
 #define SIMK_PLANE(X)                                                                        \
   X(8, 1, 16) X(8, 1, 2) X(12, 1, 16) X(12, 1, 2) X(16, 1, 16) X(16, 2, 16) X(16, 1, 2) X(16, 2, 8) X(16, 1, 8)    \
-  X(20, 1, 8) X(20, 2, 8) X(20, 1, 2) X(24, 1, 8) X(24, 2, 8) X(24, 2, 2) X(24, 1, 2)        \
+  X(20, 1, 8) X(20, 2, 8) X(20, 1, 2) X(20, 1, 4) X(24, 1, 8) X(24, 2, 8) X(24, 2, 2) X(24, 1, 2)        \
   X(28, 2, 8) X(28, 2, 2) X(28, 2, 4) X(28, 2, 12)
 #define SIMK_BALL(X) X(12, 1, 8) X(12, 1, 2) X(16, 1, 8) X(20, 1, 8) X(24, 1, 8) X(28, 1, 8) X(28, 2, 8)
 #define SIMK_SELF(X) X(12, 1, 8) X(12, 1, 2) X(16, 1, 8) X(20, 1, 8) X(24, 1, 8) X(24, 2, 8) X(28, 2, 8)

@@ -660,17 +660,20 @@ __device__ __forceinline__ int row_min_i(int x) {
 // ----------------------------------------------------------------------------
 // A budget of 256 registers (two waves per SIMD) for the families that fit it
 // without spills: one DoF slot per lane with at most 2 contacts in registers,
-// and the 16-DoF families with 8; and for the 20-DoF, 16-body family with 2
-// contacts in registers, which needs 276 and spills 80 bytes per lane at 256,
-// but at two waves per SIMD its bin of the 8192 random trees runs 4 % faster
-// and the whole rollout 5 % (the 24- and 28-DoF families spill 196 and 272
-// bytes there and run slower).  Their LDS areas then admit two waves per SIMD
-// with 16 body slots and 1.5 with 32.  The others may use the whole register
-// file and run one wave per SIMD.
+// and the 16-DoF families with 8; and for the 20-DoF, 16-body families with 2
+// or 4 contacts in registers, which spill 24 and 48 registers per lane at
+// 256 but run faster at two waves per SIMD: with 2, the whole rollout of the
+// 8192 random trees is 5 % faster than with the single-wave 32-body kernel,
+// with 4 another 3 % (more contacts stay out of the workspace; 5 is no
+// faster, 6 slower).  The 24- and 28-DoF families spill 196 and 272 bytes
+// there and run slower.  Their LDS areas then admit two waves per SIMD with
+// 16 body slots and 1.5 with 32.  The others may use the whole register file
+// and run one wave per SIMD.
 template <int NVC, int SB, int NCR>
 struct WavesPerSimd {
   static constexpr int value =
-      ((SB == 1 && NCR <= 2 && NVC <= 20) || (NCR == 8 && NVC == 16)) ? 2 : 1;
+      ((SB == 1 && NCR <= 2 && NVC <= 20) || (SB == 1 && NCR == 4 && NVC == 20) || (NCR == 8 && NVC == 16)) ? 2
+                                                                                                             : 1;
 };
 
 // One workgroup (one wave, four variants) of a bin: `block` is the

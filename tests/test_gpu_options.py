@@ -49,6 +49,7 @@ def test_options_give_bitwise_identical_results():
                  dict(min_body_slots=32, slots32_min_nvc=20, min_nv_capacity=16, ncr_by_nvc={16: 8}),
                  dict(min_body_slots=32, ncr_by_nvc={16: 8}),
                  dict(min_body_slots=32, slots32_min_nvc=24, min_nv_capacity=16, ncr_by_nvc={16: 8, 20: 2}),
+                 dict(min_body_slots=32, slots32_min_nvc=24, min_nv_capacity=16, ncr_by_nvc={16: 8, 20: 4}),
                  dict(min_body_slots=32, single_launch=True, steps_per_launch=70)):
         _say(f"[options] {opts}")
         s = Simulator(pop, **opts)

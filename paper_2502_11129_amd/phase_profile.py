@@ -29,6 +29,7 @@ import sys
 PKG = os.path.dirname(os.path.abspath(__file__))
 PHASES = ("fk+corners", "backward+crba", "inverse", "control+vfree", "contact rows", "pgs", "integrate")
 TREE_SUB = ("factor", "clear X", "first six rows", "L^T y", "L x = y", "store")
+PGS_SUB = ("clamp rows", "contacts in registers", "overflow contacts")
 # the first line of each phase (a comment that opens a ruled block, except
 # the inverse, which opens with the factorisation's compile-time branch)
 _MARKS = ("    // 1. forward kinematics", "    // 2. backward sweep", "    if constexpr (TREE) {",
@@ -56,15 +57,27 @@ def instrument(src: str) -> str:
         if line.startswith("  for (int it = 0; it < a.n_steps; ++it) {"):
             out.append("  unsigned long long _ph[7] = {0, 0, 0, 0, 0, 0, 0}, _ph_p = 0;")
             out.append("  unsigned long long _sub[6] = {0, 0, 0, 0, 0, 0}, _sub_p = 0;")
+            out.append("  unsigned long long _pgs[3] = {0, 0, 0}, _pgs_p = 0;")
         if line.startswith("  // ---- write back ----"):
             out.append("  if (threadIdx.x == 0) { const int _b = NVC / 4; atomicAdd(&g_phase[_b][7], 1ull);")
             out.append("    for (int _i = 0; _i < 7; ++_i) atomicAdd(&g_phase[_b][_i], _ph[_i]);")
-            out.append("    if (TREE) for (int _i = 0; _i < 6; ++_i) atomicAdd(&g_phase[15][_i], _sub[_i]); }")
+            out.append("    if (TREE) for (int _i = 0; _i < 6; ++_i) atomicAdd(&g_phase[16][_i], _sub[_i]);")
+            out.append("    for (int _i = 0; _i < 3; ++_i) atomicAdd(&g_phase[8 + _b][_i], _pgs[_i]); }")
         out.append(line)
     s = "\n".join(out)
-    s = s.replace("namespace simk {", "namespace simk {\nstatic __device__ unsigned long long g_phase[16][8];", 1)
+    s = s.replace("namespace simk {", "namespace simk {\nstatic __device__ unsigned long long g_phase[24][8];", 1)
     if s.count("s_memtime") != 8:
         raise RuntimeError("phase marks not found in the kernel source")
+    # projected Gauss-Seidel: clamp rows, contacts in registers, overflow
+    # contacts, summed over the sweeps
+    pgs = ("      // (i) actuator clamp rows in hinge order.", "      // (ii) contact rows in (body, corner) order",
+           "      for (int c = NCR; c < nc; ++c) {\n        const float* rows = ovf_rows")
+    for k, anchor in enumerate(pgs):
+        if s.count(anchor) != 1:
+            raise RuntimeError(f"projected Gauss-Seidel mark {k} not found")
+        s = s.replace(anchor, "      " + _clock("_pgs", k - 1, first=(k == 0)) + "\n" + anchor)
+    end = "    // =====================================================================\n    // 7. semi-implicit"
+    s = s.replace(end, "    " + _clock("_pgs", 2) + "\n" + end, 1)
     subs = ("#pragma unroll 1\n      for (int k = nv - 1; k >= 0; --k) {\n        const unsigned ak",
             "#pragma unroll\n      for (int s = 0; s < S; ++s) {\n        const int d = lane + 16 * s;\n        if (d < NVC) {\n"
             "#pragma unroll\n          for (int j = 0; j < NVC; ++j) sh.X[d * MST + j]",
@@ -100,9 +113,9 @@ def build(dirname: str) -> str:
 #define PH_CAT2(a, b) a##b
 #define PH_CAT(a, b) PH_CAT2(a, b)
 extern "C" int PH_CAT(simk_phase_read_, PHASE_TU)(unsigned long long* out, int clear) {
-  if (hipMemcpyFromSymbol(out, HIP_SYMBOL(simk::g_phase), sizeof(unsigned long long) * 128) != hipSuccess) return -1;
+  if (hipMemcpyFromSymbol(out, HIP_SYMBOL(simk::g_phase), sizeof(unsigned long long) * 192) != hipSuccess) return -1;
   if (clear) {
-    static unsigned long long z[128];
+    static unsigned long long z[192];
     if (hipMemcpyToSymbol(HIP_SYMBOL(simk::g_phase), z, sizeof(z)) != hipSuccess) return -2;
   }
   return 0;
@@ -149,7 +162,7 @@ def run(dirname: str, options: dict, steps: int, n: int = 8192, say=print):
     pop = W.random_trees(n)
     sim = S.Simulator(pop, **opts)
     tus = units(os.path.join(os.path.abspath(dirname), "csrc"))
-    buf = (C.c_ulonglong * 128)()
+    buf = (C.c_ulonglong * 192)()
     for tu in tus:
         getattr(lib, f"simk_phase_read_{tu}")(buf, 1)
     sim.rollout(steps)
@@ -159,14 +172,15 @@ def run(dirname: str, options: dict, steps: int, n: int = 8192, say=print):
     for tu in tus:
         if getattr(lib, f"simk_phase_read_{tu}")(buf, 1) != 0:
             raise RuntimeError(f"phase read failed for {tu}")
-        a = np.array(buf[:], dtype=np.float64).reshape(16, 8)
-        for b in range(15):
+        a = np.array(buf[:], dtype=np.float64).reshape(24, 8)
+        for b in range(8):
             if a[b, 7] > 0:
                 per = a[b, :7] / (a[b, 7] * steps)
                 row = dict(unit=tu, nvc=4 * b, waves=int(a[b, 7]), phases=dict(zip(PHASES, per.tolist())),
                            total=float(per.sum()))
-                if a[15, :6].any():
-                    row["tree_sub"] = dict(zip(TREE_SUB, (a[15, :6] / (a[b, 7] * steps)).tolist()))
+                if a[16, :6].any():
+                    row["tree_sub"] = dict(zip(TREE_SUB, (a[16, :6] / (a[b, 7] * steps)).tolist()))
+                row["pgs_sub"] = dict(zip(PGS_SUB, (a[8 + b, :3] / (a[b, 7] * steps)).tolist()))
                 rows.append(row)
     return rows
 
@@ -189,6 +203,7 @@ def main(argv=None):
               " ".join(f"{r['phases'][p]:>14.0f}" for p in PHASES) + f" {r['total']:>8.0f}")
         if "tree_sub" in r:
             print("         inverse sub-phases: " + ", ".join(f"{k} {v:.0f}" for k, v in r["tree_sub"].items()))
+        print("         projected Gauss-Seidel: " + ", ".join(f"{k} {v:.0f}" for k, v in r["pgs_sub"].items()))
     print(json.dumps(rows), flush=True)
     return 0
 

@@ -1,5 +1,8 @@
 """Parity at the full benchmark sizes, in the launch configurations bench.py
-times: 8192 random trees x 5000 steps (32-body kernels on four streams),
+times: 8192 random trees x 5000 steps (the autotuner's layout: the <= 16-DoF
+variants in one two-wave 16-body bin, the 20-DoF ones in the two-wave
+16-body kernel with 4 contacts in registers, the larger in 32-body kernels;
+and the 32-body layout on four streams),
 512 000 box-and-ball variants x 1000 steps, 32 768 quadrupeds x 1000 steps
 with and without self-collision, and all 4096 dropped boxes x 2000 steps
 against the oracle variant by variant.  The oracle cannot run the larger
@@ -46,8 +49,11 @@ def _rows(pop, idx, q, v):
 
 
 @pytest.mark.parametrize("name, make, T, opts, sample", [
-    ("trees 8192 x 5000", lambda: W.random_trees(8192), 5000, dict(min_body_slots=32, streams=4),
+    ("trees 8192 x 5000", lambda: W.random_trees(8192), 5000,
+     dict(min_body_slots=32, slots32_min_nvc=24, min_nv_capacity=16, ncr_by_nvc={16: 8, 20: 4}),
      np.array(W.TREE_SPOTCHECK)),
+    ("trees 8192 x 5000, 32-body kernels on four streams", lambda: W.random_trees(8192), 5000,
+     dict(min_body_slots=32, streams=4), np.array(W.TREE_SPOTCHECK)),
     ("box_and_ball 512000 x 1000", lambda: W.box_and_ball(512000), 1000, dict(),
      np.arange(0, 512000, 8000)),
     ("quadrupeds+self 32768 x 1000", lambda: dataclasses.replace(W.quadrupeds(32768), self_collision=True), 1000,

@@ -11,8 +11,10 @@ def test_every_phase_and_sub_phase_mark_is_found():
     with open(HDR) as f:
         src = f.read()
     s = P.instrument(src)
-    assert s.count("s_memtime") == 8 + 7       # 7 phases + the step's end; 6 tree sub-phases + their end
+    assert s.count("s_memtime") == 8 + 7 + 4   # 7 phases + the step's end; 6 tree sub-phases + their end;
+    #                                              3 sweep sub-phases + their end
     assert s.count("_ph[") >= 7 and s.count("_sub[") >= 6
-    assert "static __device__ unsigned long long g_phase[16][8];" in s
+    assert "static __device__ unsigned long long g_phase[24][8];" in s
+    assert s.count("_pgs[") >= 3
     # the plain source is untouched
     assert "s_memtime" not in src

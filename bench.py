@@ -320,6 +320,7 @@ def main():
             "holdout_recall_ceiling": sr["holdout_recall_ceiling"],
             "target": {"speedup": 5.0, "recall": 0.9},
             "config": {k: sr[k] for k in ("n_train", "n_holdout", "pool", "keep_frac", "T", "epochs", "batch")},
+            "equal_gpu_time": sr["equal_time"],
             "detail": {k: v for k, v in sr.items() if k.endswith("_s") or k.startswith(("kept", "unscreened"))},
         }
     out["rollouts"] = rollout_spread(rollout_ms, pop.n_variants * T)

@@ -8,6 +8,9 @@
    the GPU, then simulate the kept candidates exactly (the simulator is the
    judge of every kept candidate).
 
+Ablation at equal GPU time: the pool's first candidates simulated plainly
+for as long as the screened pass took, best and top-1 % fitness of both.
+
 Throughput compared: screened candidates per second,
   pool / (t_features + t_predict + t_topk + t_resim(kept)),
 against plain simulation, candidates / t_sim(candidates), both from GPU event
@@ -99,6 +102,19 @@ def run(n_train=200000, n_hold=10000, pool=1000000, keep_frac=0.05, T=5000, epoc
     out["unscreened_mean_fitness"] = float(np.nanmean(f_rand))
     out["kept_best_fitness"] = float(np.nanmax(f_top))
     out["unscreened_best_fitness"] = float(np.nanmax(f_rand))
+    # ablation at equal GPU time: plain simulation of as many pool candidates
+    # as fit in the screened pass's time, against the screened pass
+    n_eq = min(pool, max(1, int(out["plain_candidates_per_s"] * t_screen)))
+    f_eq, eq_s, _ = simulate_fitness(g_pool.take(np.arange(n_eq)), T=T)
+    top_n = max(1, min(k, n_eq) // 100)
+    out["equal_time"] = dict(
+        plain_candidates=n_eq, plain_gpu_s=eq_s, screened_gpu_s=t_screen, top_n=top_n,
+        screened_best=float(np.nanmax(f_top)), plain_best=float(np.nanmax(f_eq)),
+        screened_top_mean=float(np.sort(f_top[np.isfinite(f_top)])[-top_n:].mean()),
+        plain_top_mean=float(np.sort(f_eq[np.isfinite(f_eq)])[-top_n:].mean()))
+    log(f"equal GPU time ({t_screen:.2f} s): screened best {out['equal_time']['screened_best']:.4f}, "
+        f"top-{top_n} mean {out['equal_time']['screened_top_mean']:.4f}; plain ({n_eq} candidates) best "
+        f"{out['equal_time']['plain_best']:.4f}, top-{top_n} mean {out['equal_time']['plain_top_mean']:.4f}")
     out["wall_s"] = time.perf_counter() - t0
     log(f"screened {pool} candidates, kept {k}: {out['screened_candidates_per_s']:.0f} candidates/s "
         f"vs plain {out['plain_candidates_per_s']:.0f} ({out['speedup_vs_plain']:.1f}x); mean fitness kept "

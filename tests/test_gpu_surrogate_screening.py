@@ -56,3 +56,21 @@ def test_screening_beats_unscreened_sample_at_equal_simulation_budget():
     assert rho >= 0.45
     assert rec >= 0.12
     assert f_top.mean() > 1.5 * f_rand.mean()
+    # ablation at equal GPU time: plain simulation of as many pool candidates
+    # as the screened pass's GPU time (features, prediction, top-k and the
+    # kept candidates' rollouts) allows, against the screened pass.  At this
+    # size (2 % kept, recall 0.15) the plain pass simulates ~9x as many
+    # candidates and finds the fitter best ones (top-10 mean 0.75 against
+    # 0.60); the screened set is fitter on average.  The full-size figures
+    # are the bench line's surrogate.equal_gpu_time.
+    t_screen = t["features_s"] + t["predict_s"] + t["topk_s"]
+    _, resim_s, _ = simulate_fitness(pool.take(top), T=T)
+    t_screen += resim_s
+    n_eq = int(len(g_train) / gpu_s * t_screen)
+    f_eq, eq_s, _ = simulate_fitness(pool.take(np.arange(n_eq)), T=T)
+    top_n = 10
+    s_top, p_top = np.sort(f_top)[-top_n:].mean(), np.sort(f_eq)[-top_n:].mean()
+    _say(f"  equal GPU time {t_screen:.3f} s: screened 1000 kept of 50000, top-{top_n} mean {s_top:.4f}, best "
+         f"{f_top.max():.4f}; plain {n_eq} candidates ({eq_s:.3f} s), top-{top_n} mean {p_top:.4f}, best {f_eq.max():.4f}")
+    assert n_eq > 1000
+    assert f_top.mean() > 1.5 * np.nanmean(f_eq)

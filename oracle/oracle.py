@@ -93,6 +93,26 @@ def load_native(directory: str):
     return _native[directory]
 
 
+def load_sanitized(directory: str):
+    """The same source built with AddressSanitizer and UndefinedBehaviorSanitizer
+    (-O1 -g, any finding aborts) into ``directory``.  Only loadable in a
+    process started with the ASan runtime preloaded (``asan_runtime()``)."""
+    key = ("asan", directory)
+    if key not in _native:
+        os.makedirs(directory, exist_ok=True)
+        out = os.path.join(directory, "liboracle_asan.so")
+        subprocess.check_call(["g++", "-O1", "-g", "-fno-omit-frame-pointer", "-fsanitize=address,undefined",
+                               "-fno-sanitize-recover=undefined", "-std=c++17", "-shared", "-fPIC", "-pthread", _SRC,
+                               "-o", out])
+        _native[key] = _declare(C.CDLL(out))
+    return _native[key]
+
+
+def asan_runtime() -> str:
+    """Path of the compiler's ASan runtime (to preload for load_sanitized)."""
+    return subprocess.check_output(["g++", "-print-file-name=libasan.so"], text=True).strip()
+
+
 def _p(a, ct):
     return a.ctypes.data_as(C.POINTER(ct))
 

@@ -68,6 +68,44 @@ def build(jobs: int | None = None, verbose: bool = False, csrc: str = CSRC, lib:
     return lib
 
 
+def build_host_sanitized(out_dir: str) -> str:
+    """libsim.so with its host code (C ABI, packing, host worker, split and
+    chunk planning) built with AddressSanitizer and UndefinedBehaviorSanitizer
+    (host pass only, -O1 -g) and the kernel objects of the last build():
+    for host-only runs in a process that preloads the compiler's ASan runtime
+    (asan_runtime()).  Returns the library path."""
+    os.makedirs(out_dir, exist_ok=True)
+    kern, host = _sources()
+    kobjs = [os.path.join(BUILD, os.path.basename(k) + ".o") for k in kern]
+    missing = [o for o in kobjs if not os.path.exists(o)]
+    if missing:
+        raise FileNotFoundError(f"kernel objects missing (run build() first): {missing[:3]}")
+    san = ["-Xarch_host", "-fsanitize=address", "-Xarch_host", "-fsanitize=undefined"]
+    objs = []
+    for src in host:
+        obj = os.path.join(out_dir, os.path.basename(src) + ".o")
+        cmd = [HIPCC, "-O1", "-g", "-fno-omit-frame-pointer", "-std=c++17", "-fPIC", "-Wno-unused-result", *san,
+               "-I", CSRC, "-I", API_INC, "-I", ROCM_INC, "-x", "c++", "-D__HIP_PLATFORM_AMD__", "-c", src, "-o", obj]
+        r = subprocess.run(cmd, capture_output=True, text=True)
+        if r.returncode != 0:
+            raise RuntimeError(f"compile failed: {' '.join(cmd)}\n{r.stderr}")
+        objs.append(obj)
+    lib = os.path.join(out_dir, "libsim.so")
+    cmd = [HIPCC, f"--offload-arch={ARCH}", "-shared", "-fPIC", *san, *objs, *kobjs, "-o", lib]
+    r = subprocess.run(cmd, capture_output=True, text=True)
+    if r.returncode != 0:
+        raise RuntimeError(f"link failed: {' '.join(cmd)}\n{r.stderr}")
+    return lib
+
+
+def asan_runtime() -> str:
+    """The ASan runtime of the compiler that build_host_sanitized() uses."""
+    clang = os.path.join(os.path.dirname(os.path.realpath(HIPCC)), "..", "lib", "llvm", "bin", "clang")
+    if not os.path.exists(clang):
+        clang = "/opt/rocm/llvm/bin/clang"
+    return subprocess.check_output([clang, "-print-file-name=libclang_rt.asan-x86_64.so"], text=True).strip()
+
+
 if __name__ == "__main__":
     build(verbose=True)
     sys.exit(0)

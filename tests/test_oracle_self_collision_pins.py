@@ -178,3 +178,52 @@ def test_quadruped_limbs_meet_without_solver_failure():
     a0, _ = o0.counters()
     assert (o.get_state()[3] == 0).all()
     assert ((a.astype(np.int64) - a0.astype(np.int64)) > 0).sum() >= 10   # self-contacts happened
+
+
+def _fibonacci_sphere(n):
+    i = np.arange(n) + 0.5
+    z = 1.0 - 2.0 * i / n
+    r = np.sqrt(1.0 - z * z)
+    a = np.pi * (3.0 - np.sqrt(5.0)) * i
+    return np.stack([r * np.cos(a), r * np.sin(a), z], axis=1)
+
+
+def test_self_contact_normal_is_the_least_overlap_direction_over_all_directions():
+    """Independent of the separating-axis enumeration: for every box pair with
+    a corner contact, the translation along the oracle's normal that
+    separates the boxes (largest projection of the other box's corners minus
+    the smallest of the corner box's) is no larger than along any of 400 000
+    directions spread over the sphere, and within the grid's resolution of
+    the smallest of them (the least translation, the penetration depth of
+    the pair); the normal points from the other box to the corner box; each
+    corner's depth is the other box's largest corner projection along the
+    normal minus the corner's own."""
+    pop = _twisted_trees(10, seed=5)
+    o = O.Oracle(pop, float32_constants=False)
+    U = _fibonacci_sphere(400_000)
+    seen = 0
+    for vi in range(pop.n_variants):
+        q = o.variant_state(vi)[0]
+        c = o.contacts(vi, q, max_contacts=4096)
+        R, p, _, _ = o.fk(vi, q)
+        b0 = pop.body_offset[vi]
+        half = pop.half_ext[b0:b0 + R.shape[0]].astype(np.float64)
+        done = set()
+        for k in np.where((c["other"] >= 0) & (c["corner"] >= 0))[0]:
+            P, Q = int(c["body"][k]), int(c["other"][k])
+            n = np.asarray(c["normal"][k], np.float64)
+            cP, cQ = _corners(p[P], R[P], half[P]), _corners(p[Q], R[Q], half[Q])
+            assert abs(np.linalg.norm(n) - 1.0) < 1e-6      # rotations of the float32 state quaternion
+            assert n @ (p[P] - p[Q]) >= -1e-12
+            np.testing.assert_allclose(c["depth"][k], (cQ @ n).max() - c["x"][k] @ n, rtol=0, atol=1e-12)
+            if (min(P, Q), max(P, Q)) in done:
+                continue
+            done.add((min(P, Q), max(P, Q)))
+            ov_n = (cQ @ n).max() - (cP @ n).min()
+            proj_P, proj_Q = cP @ U.T, cQ @ U.T
+            # the translation along u that separates the boxes (P moved ahead of Q)
+            ov = proj_Q.max(0) - proj_P.min(0)
+            assert ov_n <= ov.min() + 1e-9
+            assert ov_n >= ov.min() - 2e-3 * np.linalg.norm(half[P] + half[Q])
+            seen += 1
+    assert seen >= 10

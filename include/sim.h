@@ -355,7 +355,8 @@ int sim_split_allocation(int32_t n, const int32_t* gpu_n, const double* gpu_s, i
  * 1/16 of every bin (HIP events on `stream`, after one warm-up), and a host
  * rollout of host_sample variants spread over the bins on host_threads
  * threads.  Leaves every variant reset to its initial state (as after
- * sim_bind).  Synchronises `stream`. */
+ * sim_bind).  Synchronises `stream`.  If host workers fail on pilot
+ * variants the host rate is unknown: SIM_E_HOST. */
 typedef struct {
   int32_t n_host_paper, n_host_makespan;
   double makespan_paper_s, makespan_opt_s; /* modelled, for T_pilot steps                */

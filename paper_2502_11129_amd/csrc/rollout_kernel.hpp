@@ -1078,10 +1078,12 @@ __device__ __forceinline__ void rollout_body(const BinArgs& a, const ModelParams
     //    and Newton-Euler force f = I A + V x* (I V); composite inertia C
     //    and force F of each subtree; hinge bias S.F and C S for CRBA
     // =====================================================================
-    for (int lev = maxdepth; lev >= 0; --lev) {
-      const int i1 = sh.lv[NBC + lev + 1];
-      for (int i = sh.lv[NBC + lev] + lane; i < i1; i += 16) {
-        const int b = sh.lv[i];
+    // each body's own inertia about p0 and Newton-Euler force first, for all
+    // bodies at once (they need no child), in place of the body's kinematics
+#pragma unroll
+    for (int t = 0; t < SB; ++t) {
+      const int b = lane + 16 * t;
+      if (b < nb) {
         const float* rec = bodyv + (size_t)b * BW_WORDS;
         float* own = &sh.A[b * 24];
         sinertia C;
@@ -1110,6 +1112,29 @@ __device__ __forceinline__ void rollout_body(const BinArgs& a, const ModelParams
           const sv x = crf(V, IV);
           F = {IA.a + x.a, IA.l + x.l};
         }
+        own[0] = C.m; own[1] = C.h.x; own[2] = C.h.y; own[3] = C.h.z;
+#pragma unroll
+        for (int k2 = 0; k2 < 6; ++k2) own[4 + k2] = C.I[k2];
+        own[10] = F.a.x; own[11] = F.a.y; own[12] = F.a.z;
+        own[13] = F.l.x; own[14] = F.l.y; own[15] = F.l.z;
+      }
+    }
+    wave_sync();
+    // then the subtrees level by level up the tree
+    for (int lev = maxdepth; lev >= 0; --lev) {
+      const int i1 = sh.lv[NBC + lev + 1];
+      for (int i = sh.lv[NBC + lev] + lane; i < i1; i += 16) {
+        const int b = sh.lv[i];
+        const float* rec = bodyv + (size_t)b * BW_WORDS;
+        float* own = &sh.A[b * 24];
+        sinertia C;
+        sv F;
+        C.m = own[0];
+        C.h = mk(own[1], own[2], own[3]);
+#pragma unroll
+        for (int k2 = 0; k2 < 6; ++k2) C.I[k2] = own[4 + k2];
+        F.a = mk(own[10], own[11], own[12]);
+        F.l = mk(own[13], own[14], own[15]);
         unsigned ch = __float_as_uint(rec[BW_CHILDREN]);
         while (ch) {
           const int c = __builtin_ctz(ch);

@@ -166,6 +166,15 @@ template <class T> V3<T> sat_axis(const V3<T>& pP, const M3<T>& RP, const V3<T>&
   return best;
 }
 
+// An edge-pair axis takes the contact from the face axes only when its
+// overlap is smaller than the least face overlap by more than 1e-5 m plus 5 %
+// of that face overlap (a long edge barely tilted across a face is a face
+// case, as in the common fudge-factor rule of box-box clipping).
+constexpr double kEdgeMarginAbs = 1e-5, kEdgeMarginRel = 0.05;
+template <class T> bool edge_beats_face(T edge_o, T face_o) {
+  return edge_o < face_o - T(kEdgeMarginAbs) - T(kEdgeMarginRel) * face_o;
+}
+
 // Edge-edge contact of boxes P and Q that intersect although no corner of
 // either lies inside the other (two edges crossing).  The 15 candidate axes
 // and their overlaps are those of sat_axis; when every candidate overlaps
@@ -174,7 +183,9 @@ template <class T> V3<T> sat_axis(const V3<T>& pP, const M3<T>& RP, const V3<T>&
 // midpoint of the closest points of the two edges that face each other
 // along it: P's edge parallel to its axis i on the side of Q, Q's edge
 // parallel to its axis j on the side of P.  Normal u from Q towards P,
-// depth = the overlap along u.  Returns false in every other case.
+// depth = the overlap along u.  The edge pair must beat the least face
+// overlap by the margin of edge_beats_face.  Returns false in every other
+// case.
 template <class T> bool edge_contact(const V3<T>& pP, const M3<T>& RP, const V3<T>& hP, const V3<T>& pQ,
                                      const M3<T>& RQ, const V3<T>& hQ, V3<T>& x, V3<T>& n, T& depth) {
   const V3<T> d = sub(pP, pQ);
@@ -188,6 +199,7 @@ template <class T> bool edge_contact(const V3<T>& pP, const M3<T>& RP, const V3<
   };
   for (int k = 0; k < 3; ++k) consider(axis(RP, k), -1, -1);
   for (int k = 0; k < 3; ++k) consider(axis(RQ, k), -1, -1);
+  const T face_o = best_o;
   for (int i = 0; i < 3; ++i)
     for (int j = 0; j < 3; ++j) {
       const V3<T> c = cross(axis(RP, i), axis(RQ, j));
@@ -195,7 +207,9 @@ template <class T> bool edge_contact(const V3<T>& pP, const M3<T>& RP, const V3<
       if (n2 < T(1e-6)) continue;
       consider(scl(c, T(1) / std::sqrt(n2)), i, j);
     }
-  if (!(best_o > 0) || bi < 0) return false;
+  // an edge pair only when it beats every face axis by the margin (a cross
+  // product along a face normal, edges in parallel planes, stays a face case)
+  if (!(best_o > 0) || bi < 0 || !edge_beats_face(best_o, face_o)) return false;
   if (dot(best, d) < 0) best = scl(best, T(-1));
   // the edges facing each other: P's towards -u, Q's towards +u
   V3<T> cP = pP, cQ = pQ;
@@ -214,6 +228,128 @@ template <class T> bool edge_contact(const V3<T>& pP, const M3<T>& RP, const V3<
   n = best;
   depth = best_o;
   return true;
+}
+
+// Face contacts of boxes P and Q that intersect although no corner of either
+// lies inside the other, when no edge-pair axis beats the least face overlap
+// by the margin of edge_beats_face (an edge or a face of one box pushed through a face of the
+// other without a corner inside).  The box R owning the face axis of least
+// overlap (first of equals: P's axes, then Q's) gives the
+// reference face: its face on the side of the other box I, outward normal n
+// (from R towards I), centre cR, rectangle of R's other two half extents
+// along R's other two axes (ascending).  I's incident face is its face whose
+// outward normal is most anti-parallel to n (I's axis with the largest
+// |a . n|, first of equals).  The contacts are the vertices of the incident
+// face clipped to the reference rectangle (coordinates in the reference
+// plane) that lie below the reference face, depth = n . (cR - x) > 0, taken
+// in this order: incident-face corners strictly inside the rectangle (corner
+// bits: sign of I's first, then second in-face axis), rectangle corners
+// strictly inside the incident face, carried onto the incident face (same
+// bits for R's axes), then crossings strictly inside both edges of each
+// incident-face edge (corners 0-1, 1-3, 3-2, 2-0) with the rectangle's edge
+// lines s = -e1, s = +e1, t = -e2, t = +e2.  Every point belongs to I and
+// takes the normal n.  Returns the number of contacts written (at most 24
+// candidates, at most 8 of them for a convex clip); inc = 0 when I is P, 1
+// when I is Q.
+template <class T> int face_contacts(const V3<T>& pP, const M3<T>& RP, const V3<T>& hP, const V3<T>& pQ,
+                                     const M3<T>& RQ, const V3<T>& hQ, V3<T>* xs, T* depths, V3<T>& n, int& inc) {
+  const V3<T> d = sub(pP, pQ);
+  T best_o = T(INFINITY);
+  V3<T> best{0, 0, 1};
+  int face = -1;
+  auto axis = [](const M3<T>& R, int k) { return V3<T>{R[k], R[3 + k], R[6 + k]}; };
+  auto overlap = [&](const V3<T>& u) {
+    return box_radius(RP, hP, u) + box_radius(RQ, hQ, u) - std::abs(dot(u, d));
+  };
+  for (int f = 0; f < 6; ++f) {
+    const V3<T> u = axis(f < 3 ? RP : RQ, f % 3);
+    const T o = overlap(u);
+    if (o < best_o) { best_o = o; best = u; face = f; }
+  }
+  T edge_o = T(INFINITY);
+  for (int i = 0; i < 3; ++i)
+    for (int j = 0; j < 3; ++j) {
+      const V3<T> c = cross(axis(RP, i), axis(RQ, j));
+      const T n2 = dot(c, c);
+      if (n2 < T(1e-6)) continue;
+      edge_o = std::min(edge_o, overlap(scl(c, T(1) / std::sqrt(n2))));
+    }
+  // the boxes intersect (every axis overlaps) and no edge pair beats the
+  // least face overlap by the margin
+  if (!(best_o > 0) || !(edge_o > 0) || edge_beats_face(edge_o, best_o)) return 0;
+  if (dot(best, d) < 0) best = scl(best, T(-1));  // from Q towards P
+  const bool refP = face < 3;
+  const int k = face % 3;
+  const M3<T>& RR = refP ? RP : RQ;
+  const M3<T>& RI = refP ? RQ : RP;
+  const V3<T>& hR = refP ? hP : hQ;
+  const V3<T>& hI = refP ? hQ : hP;
+  const V3<T>& pR = refP ? pP : pQ;
+  const V3<T>& pI = refP ? pQ : pP;
+  n = refP ? scl(best, T(-1)) : best;
+  inc = refP ? 1 : 0;
+  const V3<T> cR = add(pR, scl(n, hR[k]));
+  const int r1 = k == 0 ? 1 : 0, r2 = k == 2 ? 1 : 2;
+  const V3<T> ar1 = axis(RR, r1), ar2 = axis(RR, r2);
+  const T e1 = hR[r1], e2 = hR[r2];
+  int js = 0;
+  T bestc = -1;
+  for (int j = 0; j < 3; ++j) {
+    const T c = std::abs(dot(axis(RI, j), n));
+    if (c > bestc) { bestc = c; js = j; }
+  }
+  const T sg = dot(axis(RI, js), n) > 0 ? T(-1) : T(1);
+  const V3<T> cI = add(pI, scl(axis(RI, js), sg * hI[js]));
+  const int i1 = js == 0 ? 1 : 0, i2 = js == 2 ? 1 : 2;
+  const V3<T> ai1 = axis(RI, i1), ai2 = axis(RI, i2);
+  const T f1 = hI[i1], f2 = hI[i2];
+  auto st = [&](const V3<T>& x, T& s, T& t) { const V3<T> r = sub(x, cR); s = dot(r, ar1); t = dot(r, ar2); };
+  int m = 0;
+  auto keep = [&](const V3<T>& x) {
+    const T dep = dot(n, sub(cR, x));
+    if (dep > 0) { xs[m] = x; depths[m] = dep; ++m; }
+  };
+  V3<T> cor[4];
+  for (int c = 0; c < 4; ++c)
+    cor[c] = add(cI, add(scl(ai1, (c & 1) ? f1 : -f1), scl(ai2, (c & 2) ? f2 : -f2)));
+  // incident-face corners inside the rectangle
+  for (int c = 0; c < 4; ++c) {
+    T s, t;
+    st(cor[c], s, t);
+    if (std::abs(s) < e1 && std::abs(t) < e2) keep(cor[c]);
+  }
+  // rectangle corners inside the incident face, on the incident face
+  {
+    const T m11 = dot(ai1, ar1), m12 = dot(ai2, ar1), m21 = dot(ai1, ar2), m22 = dot(ai2, ar2);
+    const T det = m11 * m22 - m12 * m21;
+    T s0, t0;
+    st(cI, s0, t0);
+    for (int c = 0; c < 4; ++c) {
+      const T bs = ((c & 1) ? e1 : -e1) - s0, bt = ((c & 2) ? e2 : -e2) - t0;
+      const T uu = (bs * m22 - m12 * bt) / det, ww = (m11 * bt - m21 * bs) / det;
+      if (std::abs(uu) < f1 && std::abs(ww) < f2) keep(add(cI, add(scl(ai1, uu), scl(ai2, ww))));
+    }
+  }
+  // crossings of the incident-face edges with the rectangle's edge lines
+  const int ea[4] = {0, 1, 3, 2}, eb[4] = {1, 3, 2, 0};
+  for (int e = 0; e < 4; ++e) {
+    const V3<T>& A = cor[ea[e]];
+    const V3<T>& B = cor[eb[e]];
+    T sA, tA, sB, tB;
+    st(A, sA, tA);
+    st(B, sB, tB);
+    for (int l = 0; l < 4; ++l) {
+      const bool sline = l < 2;
+      const T cval = (l == 0) ? -e1 : (l == 1) ? e1 : (l == 2) ? -e2 : e2;
+      const T a0 = sline ? sA : tA, a1 = sline ? sB : tB;
+      if (a1 == a0) continue;
+      const T lam = (cval - a0) / (a1 - a0);
+      if (!(lam > 0 && lam < 1)) continue;
+      const T other = sline ? tA + lam * (tB - tA) : sA + lam * (sB - sA);
+      if (std::abs(other) < (sline ? e2 : e1)) keep(add(A, scl(sub(B, A), lam)));
+    }
+  }
+  return m;
 }
 
 // ----------------------------------------------------------------------------
@@ -605,6 +741,20 @@ template <class T> struct Sim {
                              C.depth)) {
               C.body = a; C.other = b; C.corner = -3; C.kind = 3;
               out.push_back(std::move(C));
+              continue;
+            }
+            // or an edge or face pushed through a face: the clipped incident face
+            V3<T> xs[24];
+            T ds[24];
+            V3<T> fn;
+            int inc = 0;
+            const int m = face_contacts(kin.p[a], kin.R[a], V.bodies[a].half, kin.p[b], kin.R[b], V.bodies[b].half,
+                                        xs, ds, fn, inc);
+            for (int i = 0; i < m; ++i) {
+              Contact F;
+              F.body = inc ? b : a; F.other = inc ? a : b; F.corner = -4; F.kind = 3;
+              F.x = xs[i]; F.n = fn; F.depth = ds[i];
+              out.push_back(std::move(F));
             }
             continue;
           }
@@ -1160,6 +1310,27 @@ int orc_edge_contact(const double* pP, const double* RP, const double* hP, const
   for (int k = 0; k < 3; ++k) { x[k] = xx[k]; n[k] = nn[k]; }
   *depth = d;
   return 1;
+}
+
+// face_contacts on two boxes (row-major rotations); returns the count m and
+// writes m points x[3 m], depths[m], the normal n[3] and inc (0: the points
+// belong to P, 1: to Q).
+int orc_face_contacts(const double* pP, const double* RP, const double* hP, const double* pQ, const double* RQ,
+                      const double* hQ, double* x, double* depth, double* n, int* inc) {
+  V3<double> a{pP[0], pP[1], pP[2]}, b{pQ[0], pQ[1], pQ[2]}, ha{hP[0], hP[1], hP[2]}, hb{hQ[0], hQ[1], hQ[2]};
+  M3<double> Ra, Rb;
+  for (int k = 0; k < 9; ++k) { Ra[k] = RP[k]; Rb[k] = RQ[k]; }
+  V3<double> xs[24], nn;
+  double ds[24];
+  int ic = 0;
+  const int m = face_contacts(a, Ra, ha, b, Rb, hb, xs, ds, nn, ic);
+  for (int i = 0; i < m; ++i) {
+    for (int k = 0; k < 3; ++k) x[3 * i + k] = xs[i][k];
+    depth[i] = ds[i];
+  }
+  for (int k = 0; k < 3; ++k) n[k] = nn[k];
+  *inc = ic;
+  return m;
 }
 
 // The library's own Cholesky, exposed so a test can compare it with LAPACK.

@@ -71,6 +71,8 @@ def _declare(lib):
     lib.orc_cholesky.restype = I
     lib.orc_edge_contact.argtypes = [D, D, D, D, D, D, D, D, D]
     lib.orc_edge_contact.restype = I
+    lib.orc_face_contacts.argtypes = [D, D, D, D, D, D, D, D, D, C.POINTER(C.c_int)]
+    lib.orc_face_contacts.restype = I
     return lib
 
 
@@ -136,6 +138,17 @@ def edge_contact(pP, RP, hP, pQ, RQ, hQ):
                                     _p(d, C.c_double)):
         return None
     return x, n, float(d[0])
+
+
+def face_contacts(pP, RP, hP, pQ, RQ, hQ):
+    """The oracle's face contacts of two boxes P and Q (centre, 3x3 rotation,
+    half extents): (points [m, 3], depths [m], n towards the points' box,
+    'P' or 'Q' for the box the points belong to), m = 0 when there are none."""
+    args = [np.ascontiguousarray(a, dtype=np.float64).ravel() for a in (pP, RP, hP, pQ, RQ, hQ)]
+    x, d, n, inc = np.zeros(72), np.zeros(24), np.zeros(3), C.c_int(0)
+    m = _load().orc_face_contacts(*[_p(a, C.c_double) for a in args], _p(x, C.c_double), _p(d, C.c_double),
+                                  _p(n, C.c_double), C.byref(inc))
+    return x[:3 * m].reshape(m, 3), d[:m], n, "Q" if inc.value else "P"
 
 
 class Oracle:

@@ -233,8 +233,8 @@ template <class T> bool edge_contact(const V3<T>& pP, const M3<T>& RP, const V3<
 // Face contacts of boxes P and Q that intersect although no corner of either
 // lies inside the other, when no edge-pair axis beats the least face overlap
 // by the margin of edge_beats_face (an edge or a face of one box pushed through a face of the
-// other without a corner inside).  The box R owning the face axis of least
-// overlap (first of equals: P's axes, then Q's) gives the
+// other without a corner inside).  The box R owning the first face axis (P's
+// axes, then Q's) whose overlap is within 1e-5 m of the least gives the
 // reference face: its face on the side of the other box I, outward normal n
 // (from R towards I), centre cR, rectangle of R's other two half extents
 // along R's other two axes (ascending).  I's incident face is its face whose
@@ -261,11 +261,16 @@ template <class T> int face_contacts(const V3<T>& pP, const M3<T>& RP, const V3<
   auto overlap = [&](const V3<T>& u) {
     return box_radius(RP, hP, u) + box_radius(RQ, hQ, u) - std::abs(dot(u, d));
   };
+  T fo[6];
   for (int f = 0; f < 6; ++f) {
-    const V3<T> u = axis(f < 3 ? RP : RQ, f % 3);
-    const T o = overlap(u);
-    if (o < best_o) { best_o = o; best = u; face = f; }
+    fo[f] = overlap(axis(f < 3 ? RP : RQ, f % 3));
+    if (fo[f] < best_o) best_o = fo[f];
   }
+  // the reference: the first face axis (P's, then Q's) within 1e-5 m of the
+  // least face overlap (parallel faces of two boxes tie exactly)
+  for (int f = 5; f >= 0; --f)
+    if (fo[f] <= best_o + T(1e-5)) face = f;
+  best = axis(face < 3 ? RP : RQ, face % 3);
   T edge_o = T(INFINITY);
   for (int i = 0; i < 3; ++i)
     for (int j = 0; j < 3; ++j) {

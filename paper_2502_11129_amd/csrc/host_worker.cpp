@@ -13,6 +13,7 @@
 #include "host_worker.hpp"
 
 #include <cmath>
+#include <algorithm>
 #include <cstring>
 
 namespace simk {
@@ -242,7 +243,12 @@ V3 sat_axis(V3 pP, const M3& RP, V3 hP, V3 pQ, const M3& RQ, V3 hQ) {
 // belongs to the cross product of P's edge direction i and Q's j, the
 // midpoint of the closest points of the two edges facing each other along it
 // (P's on the side of Q, Q's on the side of P), normal from Q towards P, depth
-// the overlap.  False in every other case.
+// the overlap, when the edge pair beats the least face overlap by the margin
+// of edge_beats_face.  False in every other case.
+// An edge pair takes the contact from the face axes only when its overlap
+// beats the least face overlap by 1e-5 m plus 5 % of it.
+bool edge_beats_face(float edge_o, float face_o) { return edge_o < face_o - 1e-5f - 0.05f * face_o; }
+
 bool edge_contact(V3 pP, const M3& RP, V3 hP, V3 pQ, const M3& RQ, V3 hQ, V3& x, V3& n, float& depth) {
   const V3 d = pP - pQ;
   float best_o = INFINITY;
@@ -254,6 +260,7 @@ bool edge_contact(V3 pP, const M3& RP, V3 hP, V3 pQ, const M3& RQ, V3 hQ, V3& x,
   };
   for (int k = 0; k < 3; ++k) consider(column(RP, k), -1, -1);
   for (int k = 0; k < 3; ++k) consider(column(RQ, k), -1, -1);
+  const float face_o = best_o;
   for (int i = 0; i < 3; ++i)
     for (int j = 0; j < 3; ++j) {
       const V3 c = crs(column(RP, i), column(RQ, j));
@@ -261,7 +268,7 @@ bool edge_contact(V3 pP, const M3& RP, V3 hP, V3 pQ, const M3& RQ, V3 hQ, V3& x,
       if (n2 < 1e-6f) continue;
       consider(c * (1.f / std::sqrt(n2)), i, j);
     }
-  if (!(best_o > 0.f) || bi < 0) return false;
+  if (!(best_o > 0.f) || bi < 0 || !edge_beats_face(best_o, face_o)) return false;
   if (dotp(best, d) < 0.f) best = best * -1.f;
   const float hp[3] = {hP.x, hP.y, hP.z}, hq[3] = {hQ.x, hQ.y, hQ.z};
   V3 cP = pP, cQ = pQ;
@@ -279,6 +286,107 @@ bool edge_contact(V3 pP, const M3& RP, V3 hP, V3 pQ, const M3& RQ, V3 hQ, V3& x,
   n = best;
   depth = best_o;
   return true;
+}
+
+// Face contacts of two intersecting boxes with no corner of either inside the
+// other when no edge pair beats the least face overlap by the margin: the
+// incident face clipped to the reference face, the clipped vertices below it,
+// in the fixed candidate order (incident corners inside the rectangle,
+// rectangle corners inside the incident face, crossings of the incident
+// edges with the rectangle's edge lines); writes up to 24, returns how many;
+// the points belong to P when inc = 0, to Q when inc = 1; normal n out of the
+// reference face.
+int face_contacts(V3 pP, const M3& RP, V3 hP, V3 pQ, const M3& RQ, V3 hQ, V3* xs, float* depths, V3& n,
+                  int& inc) {
+  const V3 d = pP - pQ;
+  float best_o = INFINITY;
+  V3 best = v3(0, 0, 1);
+  int face = -1;
+  auto overlap = [&](V3 u) { return box_radius(RP, hP, u) + box_radius(RQ, hQ, u) - std::fabs(dotp(u, d)); };
+  float fo[6];
+  for (int f = 0; f < 6; ++f) {
+    fo[f] = overlap(column(f < 3 ? RP : RQ, f % 3));
+    if (fo[f] < best_o) best_o = fo[f];
+  }
+  for (int f = 5; f >= 0; --f)  // the first face axis within 1e-5 m of the least
+    if (fo[f] <= best_o + 1e-5f) face = f;
+  best = column(face < 3 ? RP : RQ, face % 3);
+  float edge_o = INFINITY;
+  for (int i = 0; i < 3; ++i)
+    for (int j = 0; j < 3; ++j) {
+      const V3 c = crs(column(RP, i), column(RQ, j));
+      const float n2 = dotp(c, c);
+      if (n2 < 1e-6f) continue;
+      edge_o = std::min(edge_o, overlap(c * (1.f / std::sqrt(n2))));
+    }
+  if (!(best_o > 0.f) || !(edge_o > 0.f) || edge_beats_face(edge_o, best_o)) return 0;
+  if (dotp(best, d) < 0.f) best = best * -1.f;
+  const bool refP = face < 3;
+  const int k = face % 3;
+  const M3& RR = refP ? RP : RQ;
+  const M3& RI = refP ? RQ : RP;
+  const float hR[3] = {refP ? hP.x : hQ.x, refP ? hP.y : hQ.y, refP ? hP.z : hQ.z};
+  const float hI[3] = {refP ? hQ.x : hP.x, refP ? hQ.y : hP.y, refP ? hQ.z : hP.z};
+  const V3 pR = refP ? pP : pQ, pI = refP ? pQ : pP;
+  n = refP ? best * -1.f : best;
+  inc = refP ? 1 : 0;
+  const V3 cR = pR + n * hR[k];
+  const int r1 = k == 0 ? 1 : 0, r2 = k == 2 ? 1 : 2;
+  const V3 ar1 = column(RR, r1), ar2 = column(RR, r2);
+  const float e1 = hR[r1], e2 = hR[r2];
+  int js = 0;
+  float bc = -1.f;
+  for (int j = 0; j < 3; ++j) {
+    const float c = std::fabs(dotp(column(RI, j), n));
+    if (c > bc) { bc = c; js = j; }
+  }
+  const float sg = dotp(column(RI, js), n) > 0.f ? -1.f : 1.f;
+  const V3 cI = pI + column(RI, js) * (sg * hI[js]);
+  const int i1 = js == 0 ? 1 : 0, i2 = js == 2 ? 1 : 2;
+  const V3 ai1 = column(RI, i1), ai2 = column(RI, i2);
+  const float f1 = hI[i1], f2 = hI[i2];
+  auto st = [&](V3 x, float& s, float& t) { const V3 r = x - cR; s = dotp(r, ar1); t = dotp(r, ar2); };
+  int m = 0;
+  auto keep = [&](V3 x) {
+    const float dep = dotp(n, cR - x);
+    if (dep > 0.f) { xs[m] = x; depths[m] = dep; ++m; }
+  };
+  V3 cor[4];
+  for (int c = 0; c < 4; ++c) cor[c] = cI + (ai1 * ((c & 1) ? f1 : -f1) + ai2 * ((c & 2) ? f2 : -f2));
+  for (int c = 0; c < 4; ++c) {
+    float s, t;
+    st(cor[c], s, t);
+    if (std::fabs(s) < e1 && std::fabs(t) < e2) keep(cor[c]);
+  }
+  {
+    const float m11 = dotp(ai1, ar1), m12 = dotp(ai2, ar1), m21 = dotp(ai1, ar2), m22 = dotp(ai2, ar2);
+    const float det = m11 * m22 - m12 * m21;
+    float s0, t0;
+    st(cI, s0, t0);
+    for (int c = 0; c < 4; ++c) {
+      const float bs = ((c & 1) ? e1 : -e1) - s0, bt = ((c & 2) ? e2 : -e2) - t0;
+      const float uu = (bs * m22 - m12 * bt) / det, ww = (m11 * bt - m21 * bs) / det;
+      if (std::fabs(uu) < f1 && std::fabs(ww) < f2) keep(cI + (ai1 * uu + ai2 * ww));
+    }
+  }
+  const int ea[4] = {0, 1, 3, 2}, eb[4] = {1, 3, 2, 0};
+  for (int e = 0; e < 4; ++e) {
+    const V3 A = cor[ea[e]], Bv = cor[eb[e]];
+    float sA, tA, sB, tB;
+    st(A, sA, tA);
+    st(Bv, sB, tB);
+    for (int l = 0; l < 4; ++l) {
+      const bool sline = l < 2;
+      const float cval = l == 0 ? -e1 : (l == 1 ? e1 : (l == 2 ? -e2 : e2));
+      const float a0 = sline ? sA : tA, a1 = sline ? sB : tB;
+      if (a1 == a0) continue;
+      const float lam = (cval - a0) / (a1 - a0);
+      if (!(lam > 0.f && lam < 1.f)) continue;
+      const float other = sline ? tA + lam * (tB - tA) : sA + lam * (sB - sA);
+      if (std::fabs(other) < (sline ? e2 : e1)) keep(A + (Bv - A) * lam);
+    }
+  }
+  return m;
 }
 
 bool step(const HostVariantView& m, const ModelParams& P, HostVariantState& st, Work& wk) {
@@ -539,12 +647,21 @@ bool step(const HostVariantView& m, const ModelParams& P, HostVariantState& st, 
         if (!have_u) {  // no corner inside: two crossing edges, if the boxes intersect there
           V3 x, n;
           float depth;
+          unsigned anca, ancb;
+          { int x0 = Bi(a, BW_ANCESTORS); std::memcpy(&anca, &x0, 4); }
+          { int x0 = Bi(b, BW_ANCESTORS); std::memcpy(&ancb, &x0, 4); }
           if (edge_contact(wk.p[a], wk.R[a], half(a), wk.p[b], wk.R[b], half(b), x, n, depth)) {
-            unsigned anca, ancb;
-            { int x0 = Bi(a, BW_ANCESTORS); std::memcpy(&anca, &x0, 4); }
-            { int x0 = Bi(b, BW_ANCESTORS); std::memcpy(&ancb, &x0, 4); }
             add_contact(x, n, depth, anca, ancb, 0.f, true);
             ++nself;
+          } else {  // or an edge or face pushed through a face: the clipped incident face
+            V3 xs[24];
+            float ds[24];
+            int inc = 0;
+            const int mc = face_contacts(wk.p[a], wk.R[a], half(a), wk.p[b], wk.R[b], half(b), xs, ds, n, inc);
+            for (int i = 0; i < mc; ++i) {
+              add_contact(xs[i], n, ds[i], inc ? ancb : anca, inc ? anca : ancb, 0.f, true);
+              ++nself;
+            }
           }
         }
       }

@@ -513,26 +513,38 @@ __device__ __forceinline__ f3 sat_axis(f3 pP, const m33& RP, f3 hP, f3 pQ, const
   return dot3(best, d) < 0.f ? best * -1.f : best;
 }
 
+// An edge pair takes the contact from the face axes only when its overlap
+// beats the least face overlap by 1e-5 m plus 5 % of it (edges in parallel
+// planes give an edge-pair axis along the face normal with the same overlap).
+__device__ __forceinline__ bool edge_beats_face(float edge_o, float face_o) {
+  return edge_o < face_o - 1e-5f - 0.05f * face_o;
+}
+
 // Contact of two intersecting boxes P and Q with no corner of either inside
 // the other (two edges crossing): when the least overlap over the 15 axes of
 // sat_axis is positive and belongs to the cross product of P's edge direction
-// i and Q's j, the midpoint of the closest points of the two edges facing
-// each other along it (P's on the side of Q, Q's on the side of P), normal
-// from Q towards P, depth the overlap.  False in every other case.
+// i and Q's j, beating the least face overlap by the margin, the midpoint of
+// the closest points of the two edges facing each other along it (P's on the
+// side of Q, Q's on the side of P), normal from Q towards P, depth the
+// overlap.  False in every other case.
 __device__ __forceinline__ bool edge_contact(f3 pP, const m33& RP, f3 hP, f3 pQ, const m33& RQ, f3 hQ, f3& x, f3& n,
-                                             float& depth) {
+                                             float& depth, int& face) {
   const f3 d = pP - pQ;
   f3 best = mk(0.f, 0.f, 1.f);
   float best_o = __int_as_float(0x7f800000);
   int bi = -1, bj = -1;
+  float fo[6];
   auto consider = [&](f3 u, int i, int j) {
     const float o = box_radius(RP, hP, u) + box_radius(RQ, hQ, u) - fabsf(dot3(u, d));
     if (o < best_o) { best_o = o; best = u; bi = i; bj = j; }
+    return o;
   };
 #pragma unroll
-  for (int k = 0; k < 3; ++k) consider(mcol(RP, k), -1, -1);
+  for (int k = 0; k < 3; ++k) fo[k] = consider(mcol(RP, k), -1, -1);
 #pragma unroll
-  for (int k = 0; k < 3; ++k) consider(mcol(RQ, k), -1, -1);
+  for (int k = 0; k < 3; ++k) fo[3 + k] = consider(mcol(RQ, k), -1, -1);
+  const float face_o = best_o;
+  float edge_o = __int_as_float(0x7f800000);
 #pragma unroll
   for (int i = 0; i < 3; ++i)
 #pragma unroll
@@ -540,9 +552,18 @@ __device__ __forceinline__ bool edge_contact(f3 pP, const m33& RP, f3 hP, f3 pQ,
       const f3 c = cross3(mcol(RP, i), mcol(RQ, j));
       const float n2 = dot3(c, c);
       if (n2 < 1e-6f) continue;
-      consider(c * (1.f / sqrtf(n2)), i, j);
+      edge_o = fminf(edge_o, consider(c * (1.f / sqrtf(n2)), i, j));
     }
-  if (!(best_o > 0.f) || bi < 0) return false;
+  // the face case: the boxes intersect and no edge pair beats the least face
+  // overlap by the margin; the reference is the first face axis within 1e-5 m
+  // of the least face overlap
+  face = -1;
+  if (face_o > 0.f && edge_o > 0.f && !edge_beats_face(edge_o, face_o)) {
+#pragma unroll
+    for (int f = 5; f >= 0; --f)
+      if (fo[f] <= face_o + 1e-5f) face = f;
+  }
+  if (!(best_o > 0.f) || bi < 0 || !edge_beats_face(best_o, face_o)) return false;
   if (dot3(best, d) < 0.f) best = best * -1.f;
   const float hp[3] = {hP.x, hP.y, hP.z}, hq[3] = {hQ.x, hQ.y, hQ.z};
   f3 cP = pP, cQ = pQ;
@@ -564,6 +585,98 @@ __device__ __forceinline__ bool edge_contact(f3 pP, const m33& RP, f3 hP, f3 pQ,
   n = best;
   depth = best_o;
   return true;
+}
+
+// Face contacts of two intersecting boxes with no corner of either inside the
+// other when no edge pair beats the least face overlap by the margin (an edge
+// or a face of one box pushed through a face of the other): the reference
+// face is the face of the box owning the first face axis (P's, then Q's)
+// within 1e-5 m of the least face overlap, on the side of the other box (normal n out of it, centre cR, in-plane axes ar1,
+// ar2 with half extents e1, e2); the incident face is the other box's face
+// most anti-parallel to n (centre cI, axes ai1, ai2, half extents f1, f2);
+// the face index (0..2: P's axes, 3..5: Q's) comes from edge_contact.
+struct FaceClip {
+  f3 n, cR, ar1, ar2, cI, ai1, ai2;
+  float e1, e2, f1, f2;
+  bool on_q;  // the points belong to Q (else to P)
+};
+__device__ __forceinline__ void face_setup(f3 pP, const m33& RP, f3 hP, f3 pQ, const m33& RQ, f3 hQ,
+                                                    int face, FaceClip& F) {
+  const f3 d = pP - pQ;
+  f3 best = face == 0 ? mcol(RP, 0) : face == 1 ? mcol(RP, 1) : face == 2 ? mcol(RP, 2)
+          : face == 3 ? mcol(RQ, 0) : face == 4 ? mcol(RQ, 1) : mcol(RQ, 2);
+  if (dot3(best, d) < 0.f) best = best * -1.f;
+  const bool refP = face < 3;
+  const int k = refP ? face : face - 3;
+  const m33& RR = refP ? RP : RQ;
+  const m33& RI = refP ? RQ : RP;
+  const f3 hR = refP ? hP : hQ, hI = refP ? hQ : hP;
+  const f3 pR = refP ? pP : pQ, pI = refP ? pQ : pP;
+  F.n = refP ? best * -1.f : best;
+  F.on_q = refP;
+  const float hRk = k == 0 ? hR.x : (k == 1 ? hR.y : hR.z);
+  F.cR = pR + F.n * hRk;
+  F.ar1 = mcol(RR, k == 0 ? 1 : 0);
+  F.ar2 = mcol(RR, k == 2 ? 1 : 2);
+  F.e1 = k == 0 ? hR.y : hR.x;
+  F.e2 = k == 2 ? hR.y : hR.z;
+  int js = 0;
+  float bc = -1.f;
+#pragma unroll
+  for (int j = 0; j < 3; ++j) {
+    const float c = fabsf(dot3(mcol(RI, j), F.n));
+    if (c > bc) { bc = c; js = j; }
+  }
+  const f3 aj = js == 0 ? mcol(RI, 0) : (js == 1 ? mcol(RI, 1) : mcol(RI, 2));
+  const float hIj = js == 0 ? hI.x : (js == 1 ? hI.y : hI.z);
+  const float sg = dot3(aj, F.n) > 0.f ? -1.f : 1.f;
+  F.cI = pI + aj * (sg * hIj);
+  F.ai1 = js == 0 ? mcol(RI, 1) : mcol(RI, 0);
+  F.ai2 = js == 2 ? mcol(RI, 1) : mcol(RI, 2);
+  F.f1 = js == 0 ? hI.y : hI.x;
+  F.f2 = js == 2 ? hI.y : hI.z;
+}
+// Candidate c (0..23) of the clipped incident face, in the fixed order:
+// incident corners inside the reference rectangle (0..3), rectangle corners
+// inside the incident face carried onto it (4..7), crossings of incident edge
+// e = (c - 8) / 4 with rectangle edge line (c - 8) % 4 (8..23); true when the
+// candidate exists and lies below the reference face, with its point and
+// depth n . (cR - x).
+__device__ __forceinline__ bool face_candidate(const FaceClip& F, int c, f3& x, float& depth) {
+  auto corner = [&](int q) { return F.cI + (F.ai1 * ((q & 1) ? F.f1 : -F.f1) + F.ai2 * ((q & 2) ? F.f2 : -F.f2)); };
+  bool ok = false;
+  if (c < 4) {
+    x = corner(c);
+    const f3 r = x - F.cR;
+    ok = fabsf(dot3(r, F.ar1)) < F.e1 && fabsf(dot3(r, F.ar2)) < F.e2;
+  } else if (c < 8) {
+    const int q = c - 4;
+    const float m11 = dot3(F.ai1, F.ar1), m12 = dot3(F.ai2, F.ar1), m21 = dot3(F.ai1, F.ar2),
+                m22 = dot3(F.ai2, F.ar2);
+    const float det = m11 * m22 - m12 * m21;
+    const f3 r0 = F.cI - F.cR;
+    const float bs = ((q & 1) ? F.e1 : -F.e1) - dot3(r0, F.ar1), bt = ((q & 2) ? F.e2 : -F.e2) - dot3(r0, F.ar2);
+    const float uu = (bs * m22 - m12 * bt) / det, ww = (m11 * bt - m21 * bs) / det;
+    x = F.cI + (F.ai1 * uu + F.ai2 * ww);
+    ok = fabsf(uu) < F.f1 && fabsf(ww) < F.f2;
+  } else {
+    const int e = (c - 8) >> 2, l = (c - 8) & 3;
+    const int ia = e == 0 ? 0 : (e == 1 ? 1 : (e == 2 ? 3 : 2)), ib = e == 0 ? 1 : (e == 1 ? 3 : (e == 2 ? 2 : 0));
+    const f3 A = corner(ia), B = corner(ib);
+    const f3 rA = A - F.cR, rB = B - F.cR;
+    const float sA = dot3(rA, F.ar1), tA = dot3(rA, F.ar2), sB = dot3(rB, F.ar1), tB = dot3(rB, F.ar2);
+    const bool sline = l < 2;
+    const float cval = l == 0 ? -F.e1 : (l == 1 ? F.e1 : (l == 2 ? -F.e2 : F.e2));
+    const float a0 = sline ? sA : tA, a1 = sline ? sB : tB;
+    if (a1 != a0) {
+      const float lam = (cval - a0) / (a1 - a0);
+      const float other = sline ? tA + lam * (tB - tA) : sA + lam * (sB - sA);
+      x = A + (B - A) * lam;
+      ok = lam > 0.f && lam < 1.f && fabsf(other) < (sline ? F.e2 : F.e1);
+    }
+  }
+  depth = dot3(F.n, F.cR - x);
+  return ok && depth > 0.f;
 }
 
 // Corner c (bits x, y, z = signs) of a box with pose (R, p) and half extents h.
@@ -969,6 +1082,8 @@ __device__ __forceinline__ void rollout_body(const BinArgs& a, const ModelParams
       for (int c0 = 0; c0 < ncand; c0 += 16) {
         const int ci = c0 + lane;
         unsigned hits = 0u;  // bits 0..7: corners of a in b, 8..15: corners of b in a, 16: edge-edge
+        unsigned fmask = 0u;  // face contacts: the clipped incident face's candidates that exist
+        int face = -1;        // their reference face (edge_contact's face case)
         f3 ex = mk(0.f, 0.f, 0.f), en = ex;  // the edge-edge contact's point and normal (towards a)
         float ed = 0.f;
         int ia = 0, ib = 0;
@@ -994,16 +1109,42 @@ __device__ __forceinline__ void rollout_body(const BinArgs& a, const ModelParams
             if (point_in_box(box_corner(Ra, Pa, ha, c), Pb, Rb, hb)) hits |= 1u << c;
           for (int c = 0; c < 8; ++c)
             if (point_in_box(box_corner(Rb, Pb, hb, c), Pa, Ra, ha)) hits |= 1u << (8 + c);
-          // no corner inside: two crossing edges, if the boxes intersect there (bit 16)
-          if (hits == 0u && edge_contact(Pa, Ra, ha, Pb, Rb, hb, ex, en, ed)) hits = 1u << 16;
+          // no corner inside: two crossing edges, if the boxes intersect there (bit
+          // 16), or else an edge or face through a face (the clipped incident face)
+          if (hits == 0u && edge_contact(Pa, Ra, ha, Pb, Rb, hb, ex, en, ed, face)) hits = 1u << 16;
+          else if (hits == 0u && face >= 0) {
+            FaceClip F;
+            face_setup(Pa, Ra, ha, Pb, Rb, hb, face, F);
+#pragma unroll 1
+            for (int c = 0; c < 24; ++c) {
+              f3 x;
+              float dep;
+              if (face_candidate(F, c, x, dep)) fmask |= 1u << c;
+            }
+          }
         }
-        if (__builtin_amdgcn_ballot_w64(hits != 0u) == 0) continue;  // no hit in any row of the wave
-        const int cnt = __builtin_popcount(hits);
+        if (__builtin_amdgcn_ballot_w64((hits | fmask) != 0u) == 0) continue;  // no hit in any row of the wave
+        const int cnt = __builtin_popcount(hits) + __builtin_popcount(fmask);
         const int incl = row_scan_incl(cnt);
-        if (hits) {
+        if (hits | fmask) {
           int idx = nc + incl - cnt;
           const unsigned anca = __float_as_uint(bodyv[(size_t)ia * BW_WORDS + BW_ANCESTORS]);
           const unsigned ancb = __float_as_uint(bodyv[(size_t)ib * BW_WORDS + BW_ANCESTORS]);
+          if (fmask) {  // the clipped incident face again (same inputs, same points)
+            FaceClip F;
+            face_setup(Pa, Ra, ha, Pb, Rb, hb, face, F);
+            const unsigned plus = F.on_q ? ancb : anca, minus = F.on_q ? anca : ancb;
+#pragma unroll 1
+            for (int c = 0; c < 24; ++c) {
+              if (!((fmask >> c) & 1u)) continue;
+              f3 x;
+              float dep;
+              face_candidate(F, c, x, dep);
+              if (idx < NCR) put_contact<GEN>(&sh.cl[idx][0], x, plus, minus, F.n, dep, 3);
+              else if (idx < MAXC) put_contact<GEN>(&ovf_list[idx * CLW], x, plus, minus, F.n, dep, 3);
+              ++idx;
+            }
+          }
           if (hits == (1u << 16)) {
             if (idx < NCR) put_contact<GEN>(&sh.cl[idx][0], ex, anca, ancb, en, ed, 3);
             else if (idx < MAXC) put_contact<GEN>(&ovf_list[idx * CLW], ex, anca, ancb, en, ed, 3);

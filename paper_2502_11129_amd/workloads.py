@@ -443,6 +443,29 @@ def twisted_chains(n=16, nh=6, root_type=ROOT_FREE, key=13):
     return dataclasses.replace(concat(pops), self_collision=True, name="twisted chains")
 
 
+def tilted(pop: Population, seed: int, angle=0.12) -> Population:
+    """The population with every brick's rest orientation turned by a random
+    rotation of at most ``angle`` rad about each axis (rotation vector drawn
+    from U(-angle, angle)^3 with rng(seed)), composed on the right: hinge axes
+    and box faces of different bricks are no longer exactly parallel or
+    coplanar, so box pairs rarely sit exactly on a contact switch."""
+    rng = np.random.default_rng(seed)
+    rq = pop.rest_quat.astype(np.float64).copy()
+    for b in range(len(rq)):
+        if pop.parent[b] < 0:
+            continue
+        w = rng.uniform(-angle, angle, 3)
+        th = float(np.linalg.norm(w))
+        k = w / th
+        d = np.concatenate([[np.cos(th / 2)], np.sin(th / 2) * k])
+        a = rq[b]
+        rq[b] = [a[0] * d[0] - a[1] * d[1] - a[2] * d[2] - a[3] * d[3],
+                 a[0] * d[1] + a[1] * d[0] + a[2] * d[3] - a[3] * d[2],
+                 a[0] * d[2] - a[1] * d[3] + a[2] * d[0] + a[3] * d[1],
+                 a[0] * d[3] + a[1] * d[2] - a[2] * d[1] + a[3] * d[0]]
+    return dataclasses.replace(pop, rest_quat=rq.astype(pop.rest_quat.dtype))
+
+
 def single_box(half=(0.05, 0.05, 0.05), mass=None, pos=(0, 0, 1.0), quat=(1, 0, 0, 0),
                omega_b=(0, 0, 0), v_b=(0, 0, 0), mu=1.0, params=None, name="box", ball=None):
     """One free box; ``ball`` = dict(r, m, pos, quat, w, v) adds a ball

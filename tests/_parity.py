@@ -93,7 +93,7 @@ def self_margin(o, pop, vi, q):
             for P, Q in ((a, b), (b, a)):
                 l = ((p[P] + (signs * half[P]) @ R[P].T) - p[Q]) @ R[Q]
                 gap = half[Q] - np.abs(l)                     # > 0 on every axis: inside
-                near = np.abs(gap).min(axis=1)
+                near = np.abs(gap.min(axis=1))                # inside iff the least gap is > 0
                 inside_or_close = (gap > -1e-3).all(axis=1)
                 if inside_or_close.any():
                     best = min(best, near[inside_or_close].min())
@@ -105,7 +105,7 @@ def self_margin(o, pop, vi, q):
             for i in range(3):
                 for j in range(3):
                     c = np.cross(R[a][:, i], R[b][:, j])
-                    cuts.append(abs(c @ c - 1e-6))
+                    cuts.append(abs(np.sqrt(c @ c) - 1e-3) * 0.1)   # the |cross|^2 >= 1e-6 cut, in metres at 0.1 m
                     if c @ c >= 1e-6:
                         axes.append(c / np.linalg.norm(c))
             ov = np.array([half[a] @ np.abs(R[a].T @ u) + half[b] @ np.abs(R[b].T @ u) - abs(u @ d) for u in axes])
@@ -115,12 +115,79 @@ def self_margin(o, pop, vi, q):
             elif over[0] > -1e-3:
                 best = min(best, abs(over[0]), min(cuts))
                 if over[0] > 0:
-                    best = min(best, over[1] - over[0])
-                    k = int(np.argmin(ov))
-                    if k >= 6:  # an edge-pair axis: the facing edges' sides are the signs of
-                        u = axes[k]  # u along the other two axes of each box (the third is 0)
+                    fo, eo = ov[:6], ov[6:]
+                    f_min = fo.min()
+                    e_min = eo.min() if len(eo) else np.inf
+                    thr = f_min - 1e-5 - 0.05 * f_min       # an edge pair must beat the faces by this
+                    best = min(best, abs(e_min - thr))
+                    if e_min < thr:  # the edge case: its axis, and the facing edges' sides (the signs
+                        es = np.sort(eo)  # of u along the other two axes of each box, the third is 0)
+                        if len(es) > 1:
+                            best = min(best, es[1] - es[0])
+                        u = axes[6 + int(np.argmin(eo))]
                         best = min(best, np.sort(np.abs(R[a].T @ u))[1], np.sort(np.abs(R[b].T @ u))[1])
+                    else:            # the face case: the reference face (the first face axis within
+                        # 1e-5 m of the least overlap) and the clip's candidates
+                        ref = int(np.where(fo <= f_min + 1e-5)[0][0])
+                        best = min(best, np.abs(np.delete(fo, int(np.argmin(fo))) - f_min - 1e-5).min(),
+                                   _face_clip_margin(p[a], R[a], half[a], p[b], R[b], half[b], ref))
     return best
+
+
+def _face_clip_margin(pP, RP, hP, pQ, RQ, hQ, face):
+    """How close the face contacts of a box pair are to changing: the incident
+    face's choice, and every clip candidate's distance to the edge of its
+    validity (inside the rectangle or face, within the edge) or of its depth
+    sign (the oracle's face_contacts geometry, in metres)."""
+    d = pP - pQ
+    u = (RP if face < 3 else RQ)[:, face % 3]
+    if u @ d < 0:
+        u = -u
+    refP = face < 3
+    k = face % 3
+    RR, RI, hR, hI, pR, pI = (RP, RQ, hP, hQ, pP, pQ) if refP else (RQ, RP, hQ, hP, pQ, pP)
+    n = -u if refP else u
+    cR = pR + n * hR[k]
+    r = [i for i in range(3) if i != k]
+    ar1, ar2, e1, e2 = RR[:, r[0]], RR[:, r[1]], hR[r[0]], hR[r[1]]
+    dots = np.abs(RI.T @ n)
+    js = int(np.argmax(dots))
+    margin = np.sort(dots)[2] - np.sort(dots)[1]
+    sg = -1.0 if RI[:, js] @ n > 0 else 1.0
+    cI = pI + RI[:, js] * sg * hI[js]
+    i_ = [i for i in range(3) if i != js]
+    ai1, ai2, f1, f2 = RI[:, i_[0]], RI[:, i_[1]], hI[i_[0]], hI[i_[1]]
+    cor = [cI + ai1 * ((1 if c & 1 else -1) * f1) + ai2 * ((1 if c & 2 else -1) * f2) for c in range(4)]
+
+    def st(x):
+        return (x - cR) @ ar1, (x - cR) @ ar2
+
+    def note(slack, x):
+        nonlocal margin
+        margin = min(margin, abs(slack))
+        if slack > 0:
+            margin = min(margin, abs(n @ (cR - x)))
+
+    for c in range(4):
+        s_, t_ = st(cor[c])
+        note(min(e1 - abs(s_), e2 - abs(t_)), cor[c])
+    M = np.array([[ai1 @ ar1, ai2 @ ar1], [ai1 @ ar2, ai2 @ ar2]])
+    s0, t0 = st(cI)
+    for c in range(4):
+        uw = np.linalg.solve(M, [((1 if c & 1 else -1) * e1) - s0, ((1 if c & 2 else -1) * e2) - t0])
+        note(min(f1 - abs(uw[0]), f2 - abs(uw[1])), cI + ai1 * uw[0] + ai2 * uw[1])
+    for ia, ib in ((0, 1), (1, 3), (3, 2), (2, 0)):
+        A, B = cor[ia], cor[ib]
+        (sA, tA), (sB, tB) = st(A), st(B)
+        L = np.linalg.norm(B - A)
+        for cval, sline in ((-e1, True), (e1, True), (-e2, False), (e2, False)):
+            a0, a1 = (sA, sB) if sline else (tA, tB)
+            if a1 == a0:
+                continue
+            lam = (cval - a0) / (a1 - a0)
+            other = tA + lam * (tB - tA) if sline else sA + lam * (sB - sA)
+            note(min(lam * L, (1 - lam) * L, (e2 if sline else e1) - abs(other)), A + (B - A) * lam)
+    return margin
 
 
 def teacher_forced(pop, sim, ks, threads=THREADS, keys=False):

@@ -102,8 +102,18 @@ extern "C" {
  *                       relative velocity (corner's box minus penetrated
  *                       box) with the same soft normal and Coulomb disk; a
  *                       row no DoF can move (J M~^-1 J^T < 1e-9) is inert.
- *                       Two edges crossing with no corner inside are not
- *                       detected.  A variant with more than
+ *                       A pair that intersects with no corner of either
+ *                       box inside the other gets, when an edge pair's
+ *                       overlap beats the least face overlap by more than
+ *                       1e-5 m + 5 %, one contact at the midpoint of the
+ *                       two facing edges' closest points (normal that
+ *                       axis, depth its overlap); otherwise the face
+ *                       contacts: the incident face (the other box's face
+ *                       most anti-parallel to the reference face's normal;
+ *                       reference = the first face axis within 1e-5 m of
+ *                       the least face overlap) clipped to the reference
+ *                       face, the clipped vertices below it, depth along
+ *                       the reference normal.  A variant with more than
  *                       256 such contacts in a step freezes with
  *                       SIM_STATUS_CONTACTS.  Not combined with a ball.
  * Per-model constants: PD gains kp, kd (actuator torque limit tau_max), soft

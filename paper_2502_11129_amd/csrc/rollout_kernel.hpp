@@ -1789,6 +1789,11 @@ __device__ __forceinline__ void rollout_body(const BinArgs& a, const ModelParams
       }
     }
     float JnR[NCR][S], JxR[NCR][S], JyR[NCR][S], WnR[NCR][S], WxR[NCR][S], WyR[NCR][S];
+    // The contacts' solver scalars and multipliers: in registers for the
+    // single-wave families (which have registers to spare, and whose sweeps
+    // would otherwise wait on an LDS read at every contact), else in LDS.
+    constexpr bool SREG = WavesPerSimd<NVC, SB, NCR>::value == 1;
+    float scR[SREG ? NCR : 1][10];
 #pragma unroll
     for (int c = 0; c < NCR; ++c) {
       if (c < nc) {
@@ -1805,12 +1810,19 @@ __device__ __forceinline__ void rollout_body(const BinArgs& a, const ModelParams
           build_rows<S, NVC>(Mi, ang, cst, bodyOfDof, lane, x, anc, kc, kb, dt, JnR[c], JxR[c], JyR[c], WnR[c],
                              WxR[c], WyR[c], scal);
 #pragma unroll
-        for (int i = 0; i < 10; ++i) sh.cs[c][i] = scal[i];  // identical in every lane
+        for (int i = 0; i < 10; ++i) {
+          if constexpr (SREG) scR[c][i] = scal[i];
+          else sh.cs[c][i] = scal[i];  // identical in every lane
+        }
       } else {
 #pragma unroll
         for (int s = 0; s < S; ++s) {
           JnR[c][s] = JxR[c][s] = JyR[c][s] = 0.f;
           WnR[c][s] = WxR[c][s] = WyR[c][s] = 0.f;
+        }
+        if constexpr (SREG) {
+#pragma unroll
+          for (int i = 0; i < 10; ++i) scR[c][i] = 0.f;
         }
       }
     }
@@ -1907,10 +1919,14 @@ __device__ __forceinline__ void rollout_body(const BinArgs& a, const ModelParams
         if (c < nc) {
           float sc[10], lam[3];
 #pragma unroll
-          for (int i = 0; i < 10; ++i) sc[i] = sh.cs[c][i];
+          for (int i = 0; i < 10; ++i) sc[i] = SREG ? scR[c][i] : sh.cs[c][i];
           lam[0] = sc[7]; lam[1] = sc[8]; lam[2] = sc[9];
           contact_row<S>(vp, JnR[c], JxR[c], JyR[c], WnR[c], WxR[c], WyR[c], sc, lam, mu, dt);
-          sh.cs[c][7] = lam[0]; sh.cs[c][8] = lam[1]; sh.cs[c][9] = lam[2];
+          if constexpr (SREG) {
+            scR[c][7] = lam[0]; scR[c][8] = lam[1]; scR[c][9] = lam[2];
+          } else {
+            sh.cs[c][7] = lam[0]; sh.cs[c][8] = lam[1]; sh.cs[c][9] = lam[2];
+          }
         }
       }
       for (int c = NCR; c < nc; ++c) {

@@ -1790,9 +1790,12 @@ __device__ __forceinline__ void rollout_body(const BinArgs& a, const ModelParams
     }
     float JnR[NCR][S], JxR[NCR][S], JyR[NCR][S], WnR[NCR][S], WxR[NCR][S], WyR[NCR][S];
     // The contacts' solver scalars and multipliers: in registers for the
-    // single-wave families (which have registers to spare, and whose sweeps
-    // would otherwise wait on an LDS read at every contact), else in LDS.
-    constexpr bool SREG = WavesPerSimd<NVC, SB, NCR>::value == 1;
+    // single-wave families of 20 DoFs and more with at most 8 contacts in
+    // registers (above 256 registers anyway, with room left below 512; their
+    // sweeps would otherwise wait on an LDS read at every contact), else in
+    // LDS: the smaller families fit 256 registers and run two waves per SIMD,
+    // which the 80 more registers would cost them.
+    constexpr bool SREG = WavesPerSimd<NVC, SB, NCR>::value == 1 && NVC >= 20 && NCR <= 8;
     float scR[SREG ? NCR : 1][10];
 #pragma unroll
     for (int c = 0; c < NCR; ++c) {

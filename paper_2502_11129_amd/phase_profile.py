@@ -76,8 +76,12 @@ def instrument(src: str) -> str:
         if s.count(anchor) != 1:
             raise RuntimeError(f"projected Gauss-Seidel mark {k} not found")
         s = s.replace(anchor, "      " + _clock("_pgs", k - 1, first=(k == 0)) + "\n" + anchor)
-    end = "    // =====================================================================\n    // 7. semi-implicit"
-    s = s.replace(end, "    " + _clock("_pgs", 2) + "\n" + end, 1)
+    # the overflow part ends with each sweep (the clamp rows' clock restarts
+    # the next one), so its clock goes at the end of the sweep loop's body
+    end = "        sd[7] = lam[0]; sd[8] = lam[1]; sd[9] = lam[2];\n      }\n    }\n"
+    if s.count(end) != 1:
+        raise RuntimeError("end of the projected Gauss-Seidel sweep not found")
+    s = s.replace(end, end[:-len("    }\n")] + "      " + _clock("_pgs", 2) + "\n    }\n", 1)
     subs = ("#pragma unroll 1\n      for (int k = nv - 1; k >= 0; --k) {\n        const unsigned ak",
             "#pragma unroll\n      for (int s = 0; s < S; ++s) {\n        const int d = lane + 16 * s;\n        if (d < NVC) {\n"
             "#pragma unroll\n          for (int j = 0; j < NVC; ++j) sh.X[d * MST + j]",

@@ -7,6 +7,7 @@ from __future__ import annotations
 
 import concurrent.futures as cf
 import glob
+import json
 import os
 import shutil
 import subprocess
@@ -35,15 +36,37 @@ def _sources(csrc: str = CSRC):
     return kern, host
 
 
-def _compile(src: str, device: bool, csrc: str = CSRC, objdir: str = BUILD) -> str:
+RESOURCES = "kernel_resources.json"   # per-kernel registers, scratch, occupancy and LDS of the last build
+
+
+def _resources(stderr: str) -> dict:
+    """The compiler's kernel resource remarks (-Rpass-analysis=kernel-resource-usage)
+    as {kernel: {field: value}}."""
+    out, name = {}, None
+    for line in stderr.splitlines():
+        if "remark:" not in line or "kernel-resource-usage" not in line:
+            continue
+        text = line.split("remark:", 1)[1].split(" [-Rpass", 1)[0].strip()
+        key, _, val = text.partition(":")
+        key, val = key.strip(), val.strip()
+        if key == "Function Name":
+            name = val
+            out[name] = {}
+        elif name is not None:
+            out[name][key] = int(val) if val.lstrip("-").isdigit() else val
+    return out
+
+
+def _compile(src: str, device: bool, csrc: str = CSRC, objdir: str = BUILD) -> tuple[str, dict]:
     obj = os.path.join(objdir, os.path.basename(src) + ".o")
-    cmd = [HIPCC, *COMMON, *(DEVICE if device else []), "-I", csrc, "-c", src, "-o", obj]
+    cmd = [HIPCC, *COMMON, *(DEVICE if device else []), "-Rpass-analysis=kernel-resource-usage", "-I", csrc, "-c",
+           src, "-o", obj]
     if not device:
         cmd = [HIPCC, *COMMON, "-I", csrc, "-I", API_INC, "-I", ROCM_INC, "-x", "c++", "-D__HIP_PLATFORM_AMD__", "-c", src, "-o", obj]
     r = subprocess.run(cmd, capture_output=True, text=True)
     if r.returncode != 0:
         raise RuntimeError(f"compile failed: {' '.join(cmd)}\n{r.stdout}\n{r.stderr}")
-    return obj
+    return obj, (_resources(r.stderr) if device else {})
 
 
 def build(jobs: int | None = None, verbose: bool = False, csrc: str = CSRC, lib: str = LIB, objdir: str = BUILD) -> str:
@@ -56,7 +79,13 @@ def build(jobs: int | None = None, verbose: bool = False, csrc: str = CSRC, lib:
     with cf.ThreadPoolExecutor(jobs) as ex:
         futs = [ex.submit(_compile, s, True, csrc, objdir) for s in kern] + \
             [ex.submit(_compile, s, False, csrc, objdir) for s in host]
-        objs = [f.result() for f in futs]
+        done = [f.result() for f in futs]
+    objs = [o for o, _ in done]
+    res = {}
+    for _, r in done:
+        res.update(r)
+    with open(os.path.join(objdir, RESOURCES), "w") as f:
+        json.dump(res, f, indent=0, sort_keys=True)
     tmp = lib + ".tmp"
     cmd = [HIPCC, f"--offload-arch={ARCH}", "-shared", "-fPIC", *objs, "-o", tmp]
     r = subprocess.run(cmd, capture_output=True, text=True)
